@@ -1,0 +1,188 @@
+"""CPU FP64 oracle for maximum-Tsallis-entropy thresholding (arXiv 2012.10684).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU
+library never calls it and shares no code with it; the two meet only in the
+seeded input generator, which holds none of the method's arithmetic.
+
+All arithmetic lives in ``oracle.c`` (plain C, FP64, built with gcc without
+fast-math); this module only marshals numpy arrays through ctypes.
+
+Functions and the passages they follow:
+  bin_map / histogram -- Pre-processing section (linear map of levels onto L
+                         gray levels) and Thresholding section (histogram as
+                         the measurement space).
+  prefix              -- Tsallis-entropy section: p_i = c_i/N, P(t) = sum p_i,
+                         Q(t) = sum p_i^q (left-to-right sums).
+  search / objective  -- Tsallis-entropy section: class entropies H_j, the
+                         pseudo-additive objective and its arg max, extended to
+                         k thresholds by applying the composition rule
+                         recursively.
+  label               -- Algorithm 1 (thresholding kernel function),
+                         generalised to k thresholds.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MODE_DIRECT = 0
+MODE_PREFIX = 1
+MODE_KAPUR = 2
+
+OK = 0
+DEGENERATE = 1
+EMPTY = 2
+BADARG = 3
+
+
+def compile_source(src: str, out: str) -> str:
+    """Compile one C source into a shared library with gcc (-O2, IEEE
+    semantics, no contraction).  Used for oracle.c itself and, by the tests,
+    for deliberately mutated copies of it."""
+    tmp = out + ".tmp"
+    subprocess.run(
+        ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+         "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, src, "-lm"],
+        check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        compile_source(_SRC, _LIB)
+    return _LIB
+
+
+def load_library(path: str):
+    """Load an oracle-compatible shared library (the tests load mutants)."""
+    return _bind(ctypes.CDLL(path))
+
+
+def _bind(lib):
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.or_bin.argtypes = [i32, i32, i32, i32]
+    lib.or_bin.restype = i32
+    lib.or_bin_map.argtypes = [P, i64, i32, i32, i32, P]
+    lib.or_bin_map.restype = None
+    lib.or_histogram.argtypes = [P, i64, i32, i32, i32, P]
+    lib.or_histogram.restype = None
+    lib.or_prefix.argtypes = [P, i32, f64, P, P]
+    lib.or_prefix.restype = None
+    lib.or_search.argtypes = [P, i32, i32, f64, i32, P, P, P]
+    lib.or_search.restype = i32
+    lib.or_objective.argtypes = [P, i32, i32, f64, i32, P]
+    lib.or_objective.restype = f64
+    lib.or_label.argtypes = [P, i64, i32, i32, i32, P, i32, P]
+    lib.or_label.restype = None
+    return lib
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def bin_of(v: int, lo: int, hi: int, L: int, lib=None) -> int:
+    return int((lib or _load()).or_bin(int(v), int(lo), int(hi), int(L)))
+
+
+def bin_map(vox: np.ndarray, lo: int, hi: int, L: int, lib=None) -> np.ndarray:
+    v = np.ascontiguousarray(vox, dtype=np.int16).reshape(-1)
+    out = np.empty(v.size, dtype=np.int32)
+    (lib or _load()).or_bin_map(_ptr(v), v.size, lo, hi, L, _ptr(out))
+    return out
+
+
+def histogram(vox: np.ndarray, lo: int, hi: int, L: int, lib=None) -> np.ndarray:
+    v = np.ascontiguousarray(vox, dtype=np.int16).reshape(-1)
+    h = np.empty(L, dtype=np.uint32)
+    (lib or _load()).or_histogram(_ptr(v), v.size, lo, hi, L, _ptr(h))
+    return h
+
+
+def prefix(hist: np.ndarray, q: float, lib=None):
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    L = h.size
+    P = np.empty(L, dtype=np.float64)
+    Q = np.empty(L, dtype=np.float64)
+    (lib or _load()).or_prefix(_ptr(h), L, float(q), _ptr(P), _ptr(Q))
+    return P, Q
+
+
+class SearchResult:
+    """Oracle outcome for one problem: thresholds, objective S*, runner-up S."""
+
+    __slots__ = ("thr", "obj", "second", "status")
+
+    def __init__(self, thr, obj, second, status):
+        self.thr = thr
+        self.obj = obj
+        self.second = second
+        self.status = status
+
+    def rel_gap(self) -> float:
+        """(S* - S_2) / |S*|: relative gap to the best tuple other than thr."""
+        if self.status != OK or not np.isfinite(self.second):
+            return float("inf")
+        if self.obj == 0.0:
+            return 0.0 if self.second == 0.0 else float("inf")
+        return (self.obj - self.second) / abs(self.obj)
+
+    def __repr__(self):
+        return f"SearchResult(thr={self.thr.tolist()}, obj={self.obj!r}, second={self.second!r}, status={self.status})"
+
+
+def search(hist: np.ndarray, k: int, q: float, mode: int = MODE_PREFIX, lib=None) -> SearchResult:
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    thr = np.empty(k, dtype=np.int32)
+    best = ctypes.c_double()
+    second = ctypes.c_double()
+    st = (lib or _load()).or_search(_ptr(h), h.size, int(k), float(q), int(mode), _ptr(thr),
+                           ctypes.byref(best), ctypes.byref(second))
+    if st == BADARG:
+        raise ValueError(f"oracle.search: bad arguments L={h.size} k={k} q={q} mode={mode}")
+    return SearchResult(thr, best.value, second.value, st)
+
+
+def objective(hist: np.ndarray, thr, q: float, mode: int = MODE_PREFIX, lib=None) -> float:
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    t = np.ascontiguousarray(np.asarray(thr, dtype=np.int32).reshape(-1))
+    return float((lib or _load()).or_objective(_ptr(h), h.size, t.size, float(q), int(mode), _ptr(t)))
+
+
+def label(vox: np.ndarray, lo: int, hi: int, L: int, thr, lib=None) -> np.ndarray:
+    v = np.ascontiguousarray(vox, dtype=np.int16)
+    t = np.ascontiguousarray(np.asarray(thr, dtype=np.int32).reshape(-1))
+    out = np.empty(v.shape, dtype=np.uint8)
+    (lib or _load()).or_label(_ptr(v), v.size, lo, hi, L, _ptr(t), t.size, _ptr(out))
+    return out
+
+
+def segment(vox: np.ndarray, lo: int, hi: int, L: int, k: int, q: float, mode: int = MODE_PREFIX, lib=None):
+    """The whole path for one problem: histogram -> arg max -> labels."""
+    h = histogram(vox, lo, hi, L, lib=lib)
+    r = search(h, k, q, mode, lib=lib)
+    lab = label(vox, lo, hi, L, r.thr, lib=lib)
+    return h, r, lab
