@@ -1,0 +1,193 @@
+/*
+ * ts.h -- C ABI of the MI355X (gfx950) library for maximum-Tsallis-entropy
+ * threshold segmentation of CT volumes (Chang & Sheu, arXiv 2012.10684).
+ *
+ * The path is four calls, each following one step of the paper's statement of
+ * the problem:
+ *   ts_histogram        histogram of brightness levels, the "measurement
+ *                       space" of thresholding (Thresholding section), after
+ *                       the linear map of intensities onto gray levels
+ *                       (Pre-processing section);
+ *   ts_prefix           the probability set p_i and the class masses
+ *                       P(t) = sum_{i<=t} p_i, plus Q(t) = sum_{i<=t} p_i^q
+ *                       (Tsallis-entropy section, the sums defining H1, H2,
+ *                       P1, P2);
+ *   ts_threshold_search arg max of the pseudo-additive objective
+ *                       H1 + H2 + (1-q) H1 H2 (Tsallis-entropy section),
+ *                       extended to k = 1..3 thresholds by applying the
+ *                       composition rule recursively;
+ *   ts_label            the thresholding kernel function (Algorithm 1),
+ *                       extended to k thresholds.
+ *
+ * Conventions shared by every call
+ *  - Pointers are DEVICE pointers unless marked [host].  The caller allocates
+ *    and owns every buffer; no call allocates device memory.  Scratch memory
+ *    for the search is passed in as a workspace.
+ *  - Every call is asynchronous on `stream` (a hipStream_t, or NULL for the
+ *    default stream) and does not synchronise the host.
+ *  - Argument errors are detected on the host before any launch and returned
+ *    synchronously; nothing is launched then.  TS_ERR_HIP reports a failed
+ *    launch; faults inside kernels surface at the caller's next
+ *    synchronisation of the stream.  ts_last_error() gives a text for the
+ *    last non-OK status returned on the calling thread.
+ *  - The device contents of a ts_batch (pointers and offsets) cannot be
+ *    checked on the host: offsets must be non-decreasing with offs[0] = 0
+ *    and offs[nseg] = total, and every pointer must address at least its
+ *    problem's voxel count.  Violations are undefined behaviour.
+ *  - Results are bit-identical across runs, tunings and batch compositions.
+ */
+#ifndef TS_H
+#define TS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *ts_stream_t; /* a hipStream_t; NULL = the default stream */
+
+typedef enum {
+    TS_OK = 0,
+    TS_ERR_INVALID_ARG = 1, /* bad sizes, null pointers, bad q/k/window */
+    TS_ERR_UNSUPPORTED = 2, /* valid request the library does not implement (q == 1) */
+    TS_ERR_WORKSPACE = 3,   /* workspace smaller than ts_search_workspace_bytes() */
+    TS_ERR_HIP = 4          /* a HIP runtime call or kernel launch failed */
+} ts_status;
+
+/* [host] Intensity window and number of gray levels (bins).  A voxel v in
+ * [lo, hi] goes to bin floor((v - lo) * nbins / (hi - lo + 1)); v < lo goes
+ * to bin 0 and v > hi to bin nbins - 1.  Requires lo <= hi, both within
+ * int16, and 2 <= nbins <= 4096. */
+typedef struct {
+    int32_t lo;
+    int32_t hi;
+    int32_t nbins;
+} ts_binning;
+
+/* A batch of nseg independent problems (slices, slabs or volumes).  Problem s
+ * is the offs[s+1] - offs[s] contiguous int16 voxels at vox[s].
+ *   vox   device array [nseg] of device pointers (2-byte aligned);
+ *   offs  device array [nseg + 1], offs[0] = 0, non-decreasing;
+ *   nseg  number of problems (>= 0);
+ *   total [host] copy of offs[nseg] (sizes the launch). */
+typedef struct {
+    const int16_t *const *vox;
+    const int64_t *offs;
+    int32_t nseg;
+    int64_t total;
+} ts_batch;
+
+/* Search modes. */
+enum {
+    TS_SEARCH_FP32_TIECHECK = 0, /* FP32 exhaustive keys, then an FP64 re-check of every
+                                    tuple within the FP32 error bound (default; exact) */
+    TS_SEARCH_FP32_ONLY = 1,     /* FP32 keys only: first tuple with the largest FP32 key */
+    TS_SEARCH_FP64 = 2,          /* FP64 exhaustive keys */
+    TS_SEARCH_PLAIN = 3          /* one thread per tuple, all classes evaluated directly in
+                                    FP64, one launch per problem: the simple GPU form */
+};
+
+/* Per-problem outcome written by ts_threshold_search. */
+enum {
+    TS_PROBLEM_OK = 0,
+    TS_PROBLEM_DEGENERATE = 1, /* no valid tuple: fewer than k+1 occupied bins */
+    TS_PROBLEM_EMPTY = 2       /* the problem has no voxels */
+};
+
+/* [host] Optional launch shapes (NULL, or 0 in a field, selects the built-in
+ * default).  Tunings never change any output bit. */
+typedef struct {
+    int32_t hist_block;      /* threads per histogram workgroup: 64..1024, multiple of 64 */
+    int32_t hist_replicas;   /* LDS copies of every bin: 1, 2, 4, 8, 16 or 32 */
+    int32_t hist_wg_per_cu;  /* persistent histogram workgroups per compute unit: 1..16 */
+    int32_t label_block;     /* threads per label workgroup: 64..1024, multiple of 64 */
+    int32_t label_wg_per_cu; /* persistent label workgroups per compute unit: 1..32 */
+    int32_t search_cols;     /* threshold columns held per lane in a search tile: 1, 2 or 4 */
+    int32_t search_rows;     /* rows (first-threshold values) per k=2 search tile: 64..4096 */
+    int32_t min_chunk;       /* minimum voxels per streaming workgroup: >= 512 */
+} ts_tuning;
+
+/* ts_histogram -- per-problem histograms of gray levels (Thresholding
+ * section: histogram of brightness levels; Pre-processing section: linear
+ * map of intensities to gray levels, here the window rule of ts_binning).
+ *   batch  problems to count;
+ *   bin    [host] window and number of bins L;
+ *   hist   out: uint32 [nseg][L], overwritten; row s counts problem s.
+ *          Counts are exact (a problem may hold up to 2^32 - 1 voxels).
+ * Errors: TS_ERR_INVALID_ARG for nseg < 0, total < 0, null pointers when
+ * nseg > 0, or an invalid binning. */
+ts_status ts_histogram(ts_batch batch, ts_binning bin, uint32_t *hist, const ts_tuning *tune,
+                       ts_stream_t stream);
+
+/* ts_prefix -- probabilities and prefix sums (Tsallis-entropy section:
+ * p_i = c_i / N with N = sum c_i, class masses P(t) = sum_{i<=t} p_i, and
+ * Q(t) = sum_{i<=t} p_i^q, the sum whose differences give the class sums of
+ * p_i^q in H1 and H2).
+ *   hist   uint32 [nseg][nbins] from ts_histogram;
+ *   q      entropic index (the paper's alpha), finite, > 0;
+ *   P, Q   out: double [nseg][nbins].  P(t) = C(t)/N with C(t) the exact
+ *          integer count prefix (one rounding); P(nbins-1) = 1 exactly.
+ *          Q is summed so that an empty bin repeats the previous value bit
+ *          for bit.  A problem with N = 0 gets P = Q = 0.
+ * Errors: TS_ERR_INVALID_ARG for nseg < 0, nbins outside [2, 4096], null
+ * pointers when nseg > 0, q not finite or <= 0. */
+ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, double q, double *P, double *Q,
+                    ts_stream_t stream);
+
+/* [host] Bytes of workspace ts_threshold_search needs for these sizes
+ * (0 for invalid sizes). */
+size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t mode);
+
+/* ts_threshold_search -- exhaustive arg max of the Tsallis objective
+ * (Tsallis-entropy section: phi = arg max [H1 + H2 + (1-q) H1 H2]) over every
+ * tuple 0 <= t_1 < ... < t_k <= nbins-2 of thresholds.  Classes are
+ * [0,t_1], [t_1+1,t_2], ..., [t_k+1, nbins-1]; the k+1 class entropies are
+ * composed by the pseudo-additive rule applied recursively, which equals
+ * S = expm1(Lambda)/(1-q) with Lambda = sum_j [ln Q_j - q ln w_j] (Q_j the
+ * class sum of p_i^q, w_j the class mass).  A tuple with an empty class is
+ * invalid.  Ties go to the first tuple in lexicographic order.
+ *   P, Q    double [nseg][nbins] from ts_prefix with the same q;
+ *   k       1, 2 or 3;  q  finite, > 0, != 1 (q == 1 is TS_ERR_UNSUPPORTED);
+ *   mode    TS_SEARCH_*;
+ *   ws      device workspace of ws_bytes >= ts_search_workspace_bytes(...);
+ *           its contents on entry are ignored;
+ *   thr     out: int32 [nseg][k], ascending, or all -1 if no valid tuple;
+ *   obj     out: double [nseg], the objective S at thr in FP64 (NaN if none);
+ *   status  out: int32 [nseg], TS_PROBLEM_*.
+ * A degenerate or empty problem does not affect the others in the batch.
+ * Errors: TS_ERR_INVALID_ARG (sizes, pointers, k, q, mode),
+ * TS_ERR_UNSUPPORTED (q == 1), TS_ERR_WORKSPACE. */
+ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
+                              double q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr, double *obj,
+                              int32_t *status, const ts_tuning *tune, ts_stream_t stream);
+
+/* ts_label -- thresholding kernel function (Algorithm 1) with k thresholds:
+ * a voxel whose gray level (ts_binning rule) is b gets the label
+ * #{j : b > t_j} (0..k); for k = 1 this is 1 iff b >= T with T = t + 1.
+ *   batch  problems to label (same layout as for ts_histogram);
+ *   bin    [host] the binning used for the histogram;
+ *   thr    int32 [nseg][k] from ts_threshold_search.  A row that is not
+ *          strictly ascending within [0, nbins-2] (e.g. the all -1 row of a
+ *          degenerate problem) labels its whole problem 0;
+ *   out    device array [nseg] of device pointers; problem s writes
+ *          offs[s+1]-offs[s] uint8 labels at out[s], in voxel order.
+ * Errors: TS_ERR_INVALID_ARG for bad sizes, k, binning or null pointers. */
+ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k, uint8_t *const *out,
+                   const ts_tuning *tune, ts_stream_t stream);
+
+/* [host] Text describing the last non-OK status returned on this thread
+ * ("" if none).  The pointer stays valid until the next call on this thread. */
+const char *ts_last_error(void);
+
+/* [host] ABI version of this header (increments on incompatible change). */
+int32_t ts_abi_version(void);
+
+#define TS_ABI_VERSION 1
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TS_H */

@@ -1,0 +1,212 @@
+"""Python binding of libts (include/ts.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; PyTorch provides device
+memory (tensors) and the stream.  There is no fallback: if ``libts.so`` has
+not been built, importing this module raises ImportError.
+
+Functions mirror the C ABI:
+  histogram(batch, binning)          -> uint32 counts [nseg, L] (int32 storage)
+  prefix(hist, q)                    -> P, Q float64 [nseg, L]
+  threshold_search(P, Q, k, q, mode) -> thr int32 [nseg, k], obj float64 [nseg], status int32 [nseg]
+  label(batch, binning, thr, k)      -> one uint8 tensor per problem
+plus ``Batch`` (the device segment table) and ``segment`` (the four calls in
+order).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libts.so")
+
+TS_OK, TS_ERR_INVALID_ARG, TS_ERR_UNSUPPORTED, TS_ERR_WORKSPACE, TS_ERR_HIP = 0, 1, 2, 3, 4
+SEARCH_FP32_TIECHECK, SEARCH_FP32_ONLY, SEARCH_FP64, SEARCH_PLAIN = 0, 1, 2, 3
+PROBLEM_OK, PROBLEM_DEGENERATE, PROBLEM_EMPTY = 0, 1, 2
+
+
+class Binning(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32), ("hi", ctypes.c_int32), ("nbins", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"Binning(lo={self.lo}, hi={self.hi}, nbins={self.nbins})"
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("vox", ctypes.c_void_p), ("offs", ctypes.c_void_p), ("nseg", ctypes.c_int32),
+                ("total", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "hist_block", "hist_replicas", "hist_wg_per_cu", "label_block", "label_wg_per_cu",
+        "search_cols", "search_rows", "min_chunk")]
+
+    @classmethod
+    def from_dict(cls, d: Optional[dict]):
+        t = cls()
+        for k, v in (d or {}).items():
+            setattr(t, k, int(v))
+        return t
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class TsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libts status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    lib.ts_histogram.argtypes = [_Batch, Binning, P, P, P]
+    lib.ts_prefix.argtypes = [P, i32, i32, f64, P, P, P]
+    lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.ts_search_workspace_bytes.restype = sz
+    lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, f64, i32, P, sz, P, P, P, P, P]
+    lib.ts_label.argtypes = [_Batch, Binning, P, i32, P, P, P]
+    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label):
+        f.restype = ctypes.c_int
+    lib.ts_last_error.argtypes = []
+    lib.ts_last_error.restype = ctypes.c_char_p
+    lib.ts_abi_version.restype = ctypes.c_int32
+    if lib.ts_abi_version() != 1:
+        raise ImportError("libts ABI version mismatch")
+    return lib
+
+
+_lib = _load()
+
+
+def _check(st: int):
+    if st != TS_OK:
+        raise TsError(st, _lib.ts_last_error().decode())
+
+
+def _stream(stream) -> Optional[int]:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _tune(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        tune = Tuning.from_dict(tune)
+    return ctypes.byref(tune)
+
+
+class Batch:
+    """Device segment table for a batch of problems.
+
+    ``segments`` is a list of 1-D views (int16, CUDA) -- e.g. the slices of a
+    volume or whole volumes.  The table holds device pointers and the voxel
+    offsets; the tensors are kept alive by this object."""
+
+    def __init__(self, segments: Sequence[torch.Tensor], device=None):
+        segs = list(segments)
+        dev = device or (segs[0].device if segs else torch.device("cuda"))
+        for s in segs:
+            if s.dtype != torch.int16 or not s.is_cuda or not s.is_contiguous():
+                raise ValueError("segments must be contiguous int16 CUDA tensors")
+        self.segments = segs
+        self.sizes = [int(s.numel()) for s in segs]
+        offs = [0]
+        for n in self.sizes:
+            offs.append(offs[-1] + n)
+        self.total = offs[-1]
+        self.nseg = len(segs)
+        self.ptrs = torch.tensor([s.data_ptr() for s in segs] or [0], dtype=torch.int64).to(dev)
+        self.offs = torch.tensor(offs, dtype=torch.int64).to(dev)
+        self._c = _Batch(self.ptrs.data_ptr(), self.offs.data_ptr(), self.nseg, self.total)
+
+    @classmethod
+    def slices(cls, volume: torch.Tensor) -> "Batch":
+        """One problem per slice of a (Z, H, W) volume."""
+        v = volume.contiguous()
+        return cls([v[z].reshape(-1) for z in range(v.shape[0])])
+
+    @classmethod
+    def whole(cls, volumes: Iterable[torch.Tensor]) -> "Batch":
+        """One problem per volume."""
+        return cls([v.contiguous().reshape(-1) for v in volumes])
+
+
+def binning(lo: int, hi: int, nbins: int) -> Binning:
+    return Binning(int(lo), int(hi), int(nbins))
+
+
+def histogram(batch: Batch, bin: Binning, out: Optional[torch.Tensor] = None, tune=None, stream=None):
+    if out is None:
+        dev = batch.ptrs.device
+        out = torch.empty((batch.nseg, bin.nbins), dtype=torch.int32, device=dev)
+    _check(_lib.ts_histogram(batch._c, bin, _ptr(out), _tune(tune), _stream(stream)))
+    return out
+
+
+def prefix(hist: torch.Tensor, q: float, P=None, Q=None, stream=None):
+    nseg, L = hist.shape
+    if P is None:
+        P = torch.empty((nseg, L), dtype=torch.float64, device=hist.device)
+    if Q is None:
+        Q = torch.empty((nseg, L), dtype=torch.float64, device=hist.device)
+    _check(_lib.ts_prefix(_ptr(hist), nseg, L, float(q), _ptr(P), _ptr(Q), _stream(stream)))
+    return P, Q
+
+
+def workspace_bytes(nseg: int, nbins: int, k: int, mode: int = SEARCH_FP32_TIECHECK) -> int:
+    return int(_lib.ts_search_workspace_bytes(nseg, nbins, k, mode))
+
+
+def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q: float, mode: int = SEARCH_FP32_TIECHECK,
+                     ws: Optional[torch.Tensor] = None, out=None, tune=None, stream=None):
+    nseg, L = P.shape
+    need = workspace_bytes(nseg, L, k, mode)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=P.device)
+    if out is None:
+        thr = torch.empty((nseg, k), dtype=torch.int32, device=P.device)
+        obj = torch.empty(nseg, dtype=torch.float64, device=P.device)
+        status = torch.empty(nseg, dtype=torch.int32, device=P.device)
+    else:
+        thr, obj, status = out
+    _check(_lib.ts_threshold_search(_ptr(P), _ptr(Q), nseg, L, int(k), float(q), int(mode), _ptr(ws),
+                                    ws.numel(), _ptr(thr), _ptr(obj), _ptr(status), _tune(tune), _stream(stream)))
+    return thr, obj, status
+
+
+def label(batch: Batch, bin: Binning, thr: torch.Tensor, k: int, outs: Optional[List[torch.Tensor]] = None,
+          out_ptrs: Optional[torch.Tensor] = None, tune=None, stream=None):
+    dev = batch.ptrs.device
+    if outs is None:
+        outs = [torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes]
+    if out_ptrs is None:
+        out_ptrs = torch.tensor([o.data_ptr() for o in outs] or [0], dtype=torch.int64).to(dev)
+    _check(_lib.ts_label(batch._c, bin, _ptr(thr), int(k), _ptr(out_ptrs), _tune(tune), _stream(stream)))
+    return outs
+
+
+def segment(batch: Batch, bin: Binning, k: int, q: float, mode: int = SEARCH_FP32_TIECHECK, tune=None,
+            stream=None):
+    """histogram -> prefix -> search -> label for every problem of the batch."""
+    h = histogram(batch, bin, tune=tune, stream=stream)
+    P, Q = prefix(h, q, stream=stream)
+    thr, obj, status = threshold_search(P, Q, k, q, mode, tune=tune, stream=stream)
+    labels = label(batch, bin, thr, k, tune=tune, stream=stream)
+    return h, (P, Q), (thr, obj, status), labels
+
+
+def last_error() -> str:
+    return _lib.ts_last_error().decode()

@@ -1,0 +1,286 @@
+// api.hip -- the C ABI of libts: argument checks, tuning defaults, bin-map
+// constants and dispatch to the kernels.  See include/ts.h for the contract.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace ts {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ts_status fail(ts_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+ts_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(TS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return TS_OK;
+}
+
+int device_cu_count()
+{
+    static std::mutex mu;
+    static std::unordered_map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end())
+        return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        n = 256;
+    cache[dev] = n;
+    return n;
+}
+
+static bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
+{
+    ts_tuning z;
+    memset(&z, 0, sizeof(z));
+    if (!t)
+        t = &z;
+    // histogram: LDS = nbins * replicas * 4 bytes per workgroup
+    int rep_default = 32;
+    while (rep_default > 1 && (size_t)nbins * rep_default * 4 > 64 * 1024)
+        rep_default >>= 1;
+    o->hist_block = t->hist_block ? t->hist_block : 512;
+    o->hist_replicas = t->hist_replicas ? t->hist_replicas : rep_default;
+    o->hist_wg_per_cu = t->hist_wg_per_cu ? t->hist_wg_per_cu : 2;
+    o->label_block = t->label_block ? t->label_block : 256;
+    o->label_wg_per_cu = t->label_wg_per_cu ? t->label_wg_per_cu : 8;
+    o->search_cols = t->search_cols ? t->search_cols : 2;
+    o->search_rows = t->search_rows ? t->search_rows : 64;
+    o->min_chunk = t->min_chunk ? t->min_chunk : 8192;
+    if (o->hist_block < 64 || o->hist_block > 1024 || o->hist_block % 64)
+        return fail(TS_ERR_INVALID_ARG, "tuning: hist_block must be a multiple of 64 in [64, 1024]");
+    if (!pow2(o->hist_replicas) || o->hist_replicas > 32)
+        return fail(TS_ERR_INVALID_ARG, "tuning: hist_replicas must be 1, 2, 4, 8, 16 or 32");
+    if ((size_t)nbins * o->hist_replicas * 4 > 160 * 1024)
+        return fail(TS_ERR_INVALID_ARG, "tuning: nbins * hist_replicas * 4 exceeds the 160 KiB of LDS");
+    if (o->hist_wg_per_cu < 1 || o->hist_wg_per_cu > 16)
+        return fail(TS_ERR_INVALID_ARG, "tuning: hist_wg_per_cu must be in [1, 16]");
+    if (o->label_block < 64 || o->label_block > 1024 || o->label_block % 64)
+        return fail(TS_ERR_INVALID_ARG, "tuning: label_block must be a multiple of 64 in [64, 1024]");
+    if (o->label_wg_per_cu < 1 || o->label_wg_per_cu > 32)
+        return fail(TS_ERR_INVALID_ARG, "tuning: label_wg_per_cu must be in [1, 32]");
+    if (o->search_cols != 1 && o->search_cols != 2 && o->search_cols != 4)
+        return fail(TS_ERR_INVALID_ARG, "tuning: search_cols must be 1, 2 or 4");
+    if (o->search_rows < 64 || o->search_rows > 4096)
+        return fail(TS_ERR_INVALID_ARG, "tuning: search_rows must be in [64, 4096]");
+    if (o->min_chunk < 512)
+        return fail(TS_ERR_INVALID_ARG, "tuning: min_chunk must be >= 512");
+    return TS_OK;
+}
+
+// ---------------------------------------------------------------- bin map
+// The in-window offset d = v - lo (0 <= d < W) maps to floor(d * L / W).
+// Two integer forms are tried and kept only if they reproduce that floor for
+// every d in [0, W):
+//   narrow multiply: (d * mul) >> shift with mul < 2^24 and d * mul < 2^32;
+//   wide multiply:   hi32((d * L) * mul) >> shift.
+// Results are cached per (lo, hi, L).
+static bool check_map(uint32_t W, uint32_t L, uint64_t mul, uint32_t shift, bool wide)
+{
+    for (uint32_t d = 0; d < W; ++d) {
+        uint64_t want = (uint64_t)d * L / W;
+        uint64_t got;
+        if (wide)
+            got = (((uint64_t)(d * L) * mul) >> 32) >> shift;
+        else
+            got = ((uint64_t)d * mul) >> shift;
+        if (got != want)
+            return false;
+    }
+    return true;
+}
+
+ts_status make_binmap(const ts_binning &bin, BinMap *bm)
+{
+    if (bin.nbins < 2 || bin.nbins > MAX_BINS)
+        return fail(TS_ERR_INVALID_ARG, "binning: nbins must be in [2, 4096]");
+    if (bin.lo < -32768 || bin.hi > 32767 || bin.lo > bin.hi)
+        return fail(TS_ERR_INVALID_ARG, "binning: need -32768 <= lo <= hi <= 32767");
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, BinMap> cache;
+    uint64_t key = ((uint64_t)(uint16_t)bin.lo << 32) | ((uint64_t)(uint16_t)bin.hi << 16) | (uint64_t)bin.nbins;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *bm = it->second;
+            return TS_OK;
+        }
+    }
+    const uint32_t W = (uint32_t)(bin.hi - bin.lo + 1), L = (uint32_t)bin.nbins;
+    BinMap m;
+    m.lo = bin.lo;
+    m.hi = bin.hi;
+    m.L = bin.nbins;
+    m.narrow = W < L ? 1 : 0;
+    bool ok = false;
+    for (uint32_t s = 0; s < 32 && !ok; ++s) {
+        uint64_t num = ((uint64_t)L << s);
+        uint64_t mul = (num + W - 1) / W; // ceil(2^s L / W)
+        if (mul >= (1u << 24) || (uint64_t)(W - 1) * mul >= (1ull << 32))
+            break;
+        if (check_map(W, L, mul, s, false)) {
+            m.mul = (uint32_t)mul;
+            m.shift = s;
+            m.wide = 0;
+            ok = true;
+        }
+    }
+    for (uint32_t s = 0; s < 32 && !ok; ++s) {
+        if ((uint64_t)(W - 1) * L >= (1ull << 32))
+            break;
+        uint64_t mul = ((1ull << (32 + s)) / W) + 1; // floor(2^(32+s) / W) + 1
+        if (mul >= (1ull << 32))
+            break;
+        if (check_map(W, L, mul, s, true)) {
+            m.mul = (uint32_t)mul;
+            m.shift = s;
+            m.wide = 1;
+            ok = true;
+        }
+    }
+    if (!ok)
+        return fail(TS_ERR_UNSUPPORTED, "binning: no exact integer bin map found");
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = m;
+    *bm = m;
+    return TS_OK;
+}
+
+static ts_status check_batch(const ts_batch &b)
+{
+    if (b.nseg < 0 || b.total < 0)
+        return fail(TS_ERR_INVALID_ARG, "batch: nseg and total must be >= 0");
+    if (b.nseg > 0 && (!b.vox || !b.offs))
+        return fail(TS_ERR_INVALID_ARG, "batch: vox and offs must not be null when nseg > 0");
+    if (b.nseg == 0 && b.total != 0)
+        return fail(TS_ERR_INVALID_ARG, "batch: total must be 0 when nseg == 0");
+    return TS_OK;
+}
+
+} // namespace ts
+
+using namespace ts;
+
+extern "C" {
+
+int32_t ts_abi_version(void) { return TS_ABI_VERSION; }
+
+const char *ts_last_error(void) { return g_last_error.c_str(); }
+
+ts_status ts_histogram(ts_batch batch, ts_binning bin, uint32_t *hist, const ts_tuning *tune, ts_stream_t stream)
+{
+    ts_status st = check_batch(batch);
+    if (st != TS_OK)
+        return st;
+    BinMap bm;
+    if ((st = make_binmap(bin, &bm)) != TS_OK)
+        return st;
+    if (batch.nseg > 0 && !hist)
+        return fail(TS_ERR_INVALID_ARG, "ts_histogram: hist must not be null");
+    Tune t;
+    if ((st = resolve_tuning(tune, bin.nbins, &t)) != TS_OK)
+        return st;
+    if (batch.nseg == 0)
+        return TS_OK;
+    return launch_histogram(batch, bm, hist, t, (hipStream_t)stream);
+}
+
+ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, double q, double *P, double *Q,
+                    ts_stream_t stream)
+{
+    if (nseg < 0)
+        return fail(TS_ERR_INVALID_ARG, "ts_prefix: nseg must be >= 0");
+    if (nbins < 2 || nbins > MAX_BINS)
+        return fail(TS_ERR_INVALID_ARG, "ts_prefix: nbins must be in [2, 4096]");
+    if (!(q > 0.0) || !isfinite(q))
+        return fail(TS_ERR_INVALID_ARG, "ts_prefix: q must be finite and > 0");
+    if (nseg > 0 && (!hist || !P || !Q))
+        return fail(TS_ERR_INVALID_ARG, "ts_prefix: null pointer");
+    if (nseg == 0)
+        return TS_OK;
+    return launch_prefix(hist, nseg, nbins, q, P, Q, (hipStream_t)stream);
+}
+
+size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t mode)
+{
+    if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || k < 1 || k > 3 || mode < 0 || mode > 3)
+        return 0;
+    return search_workspace_bytes(nseg, nbins, k, mode, 4);
+}
+
+ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k, double q,
+                              int32_t mode, void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status,
+                              const ts_tuning *tune, ts_stream_t stream)
+{
+    if (nseg < 0)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nseg must be >= 0");
+    if (nbins < 2 || nbins > MAX_BINS)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nbins must be in [2, 4096]");
+    if (k < 1 || k > 3)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: k must be 1, 2 or 3");
+    if (nbins < k + 1)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nbins must be >= k + 1");
+    if (!(q > 0.0) || !isfinite(q))
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: q must be finite and > 0");
+    if (mode < 0 || mode > 3)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: unknown mode");
+    if (q == 1.0)
+        return fail(TS_ERR_UNSUPPORTED, "ts_threshold_search: q == 1 (Shannon/Kapur limit) is not implemented");
+    if (nseg > 0 && (!P || !Q || !thr || !obj || !status))
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: null pointer");
+    ts_status st;
+    Tune t;
+    if ((st = resolve_tuning(tune, nbins, &t)) != TS_OK)
+        return st;
+    size_t need = search_workspace_bytes(nseg, nbins, k, mode, 4);
+    if (nseg > 0 && (ws_bytes < need || (!ws && need > 0)))
+        return fail(TS_ERR_WORKSPACE, "ts_threshold_search: workspace too small (need " + std::to_string(need) +
+                                          " bytes, got " + std::to_string(ws_bytes) + ")");
+    if (nseg == 0)
+        return TS_OK;
+    return launch_search(P, Q, nseg, nbins, k, q, mode, ws, ws_bytes, thr, obj, status, t, (hipStream_t)stream);
+}
+
+ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k, uint8_t *const *out,
+                   const ts_tuning *tune, ts_stream_t stream)
+{
+    ts_status st = check_batch(batch);
+    if (st != TS_OK)
+        return st;
+    BinMap bm;
+    if ((st = make_binmap(bin, &bm)) != TS_OK)
+        return st;
+    if (k < 1 || k > 3)
+        return fail(TS_ERR_INVALID_ARG, "ts_label: k must be 1, 2 or 3");
+    if (batch.nseg > 0 && (!thr || !out))
+        return fail(TS_ERR_INVALID_ARG, "ts_label: null pointer");
+    Tune t;
+    if ((st = resolve_tuning(tune, bin.nbins, &t)) != TS_OK)
+        return st;
+    if (batch.nseg == 0)
+        return TS_OK;
+    return launch_label(batch, bm, thr, k, out, t, (hipStream_t)stream);
+}
+
+} // extern "C"

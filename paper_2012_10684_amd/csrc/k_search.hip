@@ -1,0 +1,833 @@
+// k_search.hip -- exhaustive arg max of the Tsallis objective over threshold
+// tuples (Tsallis-entropy section: phi = arg max [H1 + H2 + (1-q) H1 H2],
+// composed recursively for k = 2, 3).
+//
+// Objective in product/log form.  For a class (a, b] with mass w = P(b) - P(a)
+// and Q_j = Q(b) - Q(a):  1 + (1-q) H_j = Q_j / w^q, and the composition rule
+// multiplies these factors, so  S = expm1(Lambda) / (1 - q)  with
+// Lambda = sum_j [ln Q_j - q ln w_j].  S is strictly increasing in
+// Lambda / (1 - q) for q < 1 and for q > 1, hence arg max S = arg max of
+// sgn(1-q) * Lambda.  Each class therefore contributes one signed term
+//     g(a, b) = sgn(1-q) * (log Q_j - q log w_j)   in [0, |1-q| log L]
+// (the range follows from Q_j / w^q lying between 1 and m^(1-q) for a class of
+// m bins), and an empty class (w = 0) makes the tuple invalid (-inf, applied
+// after the sign).  The expm1 form avoids the cancellation of 1 - sum(p/w)^q
+// near q = 1; it is used once per problem, for the reported value.
+//
+// FP32 search with FP64 tie check (default mode):
+//   setup   one workgroup per problem: head(t) = g(-1, t), tail(t) = g(t, L-1)
+//           in FP32 (log2 units), and a per-problem bound delta on the
+//           difference between any FP32 key and the FP64 value computed from
+//           the same prefix sums;
+//   pairs   (k = 3) rows A_t2(t1) = head(t1) + g(t1, t2) and
+//           R_t2(t3) = g(t2, t3) + tail(t3), stored in the workspace;
+//   phase 1 every tuple's FP32 key, one tile per wavefront: lanes hold the
+//           last threshold(s) in registers, the earlier threshold is a
+//           wavefront-uniform loop whose operands come through scalar loads;
+//           wavefront max -> tile max, atomic max -> problem max M.
+//           k = 3 reuses the whole R row for every t1: one add and one max
+//           per tuple;
+//   phase 2 tiles whose max is >= M - 2 delta re-evaluate their tuples; every
+//           tuple with an FP32 key >= M - 2 delta is evaluated in FP64 and the
+//           best (FP64 value, then lexicographically first tuple) is kept.
+//           The FP64 arg max is always in that set, so the result is the FP64
+//           arg max;
+//   final   one workgroup per problem reduces the tile bests, writes the tuple,
+//           S = expm1(Lambda)/(1-q) and the status.
+// FP64 mode evaluates every key in FP64 directly (A/R rows in FP64 for k=3).
+// Plain mode is the simple form: one thread per tuple (rank decoded into the
+// tuple), every class evaluated from P and Q in global memory in FP64, a block
+// reduction and a second reduction pass, one problem per launch.
+#include <math.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace ts {
+
+// v_log_f32 error bound used in delta, in units of 2^-24 * max(1, |log2 x|);
+// the GPU test suite measures the instruction against FP64 log2.
+constexpr double LOG2_ERR_UNITS = 4.0;
+constexpr int PLAIN_BLOCKS = 65536;
+
+struct Meta {
+    int menc;    // ordered-int encoding of the problem's FP32 max key
+    float delta; // bound on |key32 - key64 / ln 2|
+    int pad0, pad1;
+};
+
+struct Best {
+    double rank; // value the arg max is taken over
+    double lam;  // FP64 signed Lambda (natural log) of the tuple
+    long long code;
+    long long pad;
+};
+
+__device__ __forceinline__ bool better(double r1, long long c1, double r2, long long c2)
+{
+    return r1 > r2 || (r1 == r2 && c1 < c2);
+}
+
+// ---------------------------------------------------------------- plan
+
+struct Plan {
+    int L, k, mode, cols, CW, Lp, T1;
+    int NB, NC, tiles; // column blocks, row groups, tiles per problem
+    size_t off_meta, off_head, off_tail, off_A, off_R, off_tmax, off_best, off_plain, bytes;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Plan make_plan(int nseg, int L, int k, int mode, int cols, int T1)
+{
+    Plan p;
+    p.L = L;
+    p.k = k;
+    p.mode = mode;
+    p.cols = cols;
+    p.CW = 64 * cols;
+    p.Lp = (L + 255) & ~255;
+    p.T1 = T1;
+    const int n = L - 1; // threshold positions 0..L-2
+    if (k == 1) {
+        p.NB = (n + p.CW - 1) / p.CW;
+        p.NC = 1;
+    } else if (k == 2) {
+        p.NB = (n + p.CW - 1) / p.CW;
+        p.NC = (std::max(L - 2, 1) + T1 - 1) / T1;
+    } else {
+        p.NB = (n + p.CW - 1) / p.CW;
+        p.NC = std::max(L - 3, 1); // one row per t2 in [1, L-3]
+    }
+    p.tiles = p.NB * p.NC;
+    const bool f64 = mode == TS_SEARCH_FP64;
+    const size_t es = f64 ? 8 : 4;
+    size_t o = 0;
+    p.off_meta = o;
+    o = align256(o + (size_t)nseg * sizeof(Meta));
+    p.off_head = o;
+    o = align256(o + (size_t)nseg * p.Lp * es);
+    p.off_tail = o;
+    o = align256(o + (size_t)nseg * p.Lp * es);
+    p.off_A = o;
+    p.off_R = o;
+    if (k == 3 && mode != TS_SEARCH_PLAIN) {
+        o = align256(o + (size_t)nseg * L * p.Lp * es);
+        p.off_R = o;
+        o = align256(o + (size_t)nseg * L * p.Lp * es);
+    }
+    p.off_tmax = o;
+    if (mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY)
+        o = align256(o + (size_t)nseg * p.tiles * sizeof(float));
+    p.off_best = o;
+    if (mode != TS_SEARCH_PLAIN)
+        o = align256(o + (size_t)nseg * p.tiles * sizeof(Best));
+    p.off_plain = o;
+    if (mode == TS_SEARCH_PLAIN)
+        o = align256(o + (size_t)PLAIN_BLOCKS * sizeof(Best));
+    p.bytes = o;
+    return p;
+}
+
+size_t search_workspace_bytes(int nseg, int L, int k, int mode, int)
+{
+    // the largest plan over every tuning the library accepts
+    size_t m = 0;
+    for (int cols : {1, 2, 4})
+        m = std::max(m, make_plan(nseg, L, k, mode, cols, 64).bytes);
+    return m;
+}
+
+// ---------------------------------------------------------------- class terms
+
+// Signed FP32 class term in log2 units from FP64 prefix differences.
+template <int SGN>
+__device__ __forceinline__ float cls32(double dP, double dQ, float nq, float gmax)
+{
+    const float lx = __builtin_amdgcn_logf((float)dQ);
+    const float ly = __builtin_amdgcn_logf((float)dP);
+    float g = fmaf(nq, ly, SGN > 0 ? lx : -lx); // nq = -sgn * q
+    g = __builtin_amdgcn_fmed3f(g, 0.0f, gmax);
+    return dP > 0.0 ? g : -INFINITY;
+}
+
+// Signed FP64 class term in natural-log units.
+__device__ __forceinline__ double cls64(double dP, double dQ, double q, double sgn, double hmax)
+{
+    if (!(dP > 0.0))
+        return -INFINITY;
+    double h = sgn * (log(dQ) - q * log(dP));
+    return fmin(fmax(h, 0.0), hmax);
+}
+
+// FP64 signed Lambda of the tuple t[0..k-1] directly from the prefix sums.
+__device__ __forceinline__ double lambda64(const double *P, const double *Q, int L, int k, const int *t, double q,
+                                           double sgn, double hmax)
+{
+    double acc = 0.0;
+    double pa = 0.0, qa = 0.0;
+    for (int j = 0; j <= k; ++j) {
+        const int b = j < k ? t[j] : L - 1;
+        const double pb = P[b], qb = Q[b];
+        acc += cls64(pb - pa, qb - qa, q, sgn, hmax);
+        pa = pb;
+        qa = qb;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ long long make_code(int k, const int *t)
+{
+    long long c = 0;
+    for (int j = 0; j < k; ++j)
+        c = (c << 12) | (long long)t[j];
+    return c;
+}
+
+__device__ __forceinline__ void wave_best(double &r, double &l, long long &c)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        double r2 = __shfl_xor(r, o, WAVE);
+        double l2 = __shfl_xor(l, o, WAVE);
+        long long c2 = __shfl_xor(c, o, WAVE);
+        if (better(r2, c2, r, c)) {
+            r = r2;
+            l = l2;
+            c = c2;
+        }
+    }
+}
+
+struct Args {
+    const double *P, *Q;
+    int nseg, L, Lp, k, mode;
+    double q, sgn, hmax; // hmax = |1-q| ln L
+    float nq, gmax;      // nq = -sgn * fl32(q), gmax = |1-q| log2 L (rounded up)
+    int CW, NB, NC, T1, tiles;
+    Meta *meta;
+    void *head, *tail, *A, *R;
+    float *tmax;
+    Best *best;
+};
+
+// ---------------------------------------------------------------- setup
+
+__global__ void __launch_bounds__(256) k_setup(Args a)
+{
+    const int s = blockIdx.x;
+    const double *P = a.P + (int64_t)s * a.L;
+    const double *Q = a.Q + (int64_t)s * a.L;
+    const int L = a.L;
+    __shared__ double red[256];
+
+    // smallest non-zero bin mass (for the magnitude bounds of delta)
+    double pmin = 1.0;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const double d = P[t] - (t ? P[t - 1] : 0.0);
+        if (d > 0.0)
+            pmin = fmin(pmin, d);
+    }
+    red[threadIdx.x] = pmin;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (threadIdx.x < o)
+            red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    pmin = red[0];
+
+    if (threadIdx.x == 0) {
+        Meta m;
+        m.menc = float_to_ordered(-INFINITY);
+        m.pad0 = m.pad1 = 0;
+        const double u = 0x1p-24;
+        const double q = a.q;
+        const double qtot = Q[L - 1];
+        const double qmin = pow(pmin, q);
+        double delta;
+        if (a.mode == TS_SEARCH_FP32_ONLY) {
+            delta = 0.0;
+        } else if (!(qtot > 0.0) || !(qmin > 1e-35) || qtot > 1e35) {
+            delta = INFINITY; // FP32 range exceeded: re-check every tuple in FP64
+        } else {
+            const double Ux = fmax(fabs(log2(qtot)), fabs(log2(qmin)) + 20.0);
+            const double Vy = fabs(log2(pmin));
+            const double gm = (double)a.gmax;
+            const double ec = (1.0 + q) * u * 1.5                                  // casts to FP32
+                              + LOG2_ERR_UNITS * u * (fmax(1.0, Ux) + q * fmax(1.0, Vy)) // v_log_f32
+                              + fabs((double)(-a.sgn * a.nq) - q) * Vy             // q rounded to FP32
+                              + u * (gm + 1.0);                                    // fma + clamp
+            const int kk = a.k;
+            delta = 2.0 * ((kk + 1) * ec + kk * (kk + 1) * u * (gm + 1.0)) + 1e-9 * (kk + 1) * (gm + 1.0);
+        }
+        m.delta = (float)delta;
+        if ((double)m.delta < delta)
+            m.delta = nextafterf(m.delta, INFINITY);
+        a.meta[s] = m;
+    }
+
+    const int Lp = a.Lp;
+    if (a.mode == TS_SEARCH_FP64) {
+        double *hd = (double *)a.head + (int64_t)s * Lp;
+        double *tl = (double *)a.tail + (int64_t)s * Lp;
+        const double pL = P[L - 1], qL = Q[L - 1];
+        for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
+            double h = -INFINITY, g = -INFINITY;
+            if (t <= L - 2) {
+                h = cls64(P[t], Q[t], a.q, a.sgn, a.hmax);
+                g = cls64(pL - P[t], qL - Q[t], a.q, a.sgn, a.hmax);
+            }
+            hd[t] = h;
+            tl[t] = g;
+        }
+    } else {
+        float *hd = (float *)a.head + (int64_t)s * Lp;
+        float *tl = (float *)a.tail + (int64_t)s * Lp;
+        const double pL = P[L - 1], qL = Q[L - 1];
+        for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
+            float h = -INFINITY, g = -INFINITY;
+            if (t <= L - 2) {
+                if (a.sgn > 0) {
+                    h = cls32<1>(P[t], Q[t], a.nq, a.gmax);
+                    g = cls32<1>(pL - P[t], qL - Q[t], a.nq, a.gmax);
+                } else {
+                    h = cls32<-1>(P[t], Q[t], a.nq, a.gmax);
+                    g = cls32<-1>(pL - P[t], qL - Q[t], a.nq, a.gmax);
+                }
+            }
+            hd[t] = h;
+            tl[t] = g;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- k = 3 rows
+
+template <int SGN>
+__global__ void __launch_bounds__(256) k_pairs32(Args a)
+{
+    const int s = blockIdx.x / (a.L - 3);
+    const int t2 = 1 + blockIdx.x % (a.L - 3); // rows 1 .. L-3
+    const int L = a.L, Lp = a.Lp;
+    const double *P = a.P + (int64_t)s * L;
+    const double *Q = a.Q + (int64_t)s * L;
+    const float *hd = (const float *)a.head + (int64_t)s * Lp;
+    const float *tl = (const float *)a.tail + (int64_t)s * Lp;
+    float *Ar = (float *)a.A + ((int64_t)s * L + t2) * Lp;
+    float *Rr = (float *)a.R + ((int64_t)s * L + t2) * Lp;
+    const double p2 = P[t2], q2 = Q[t2];
+    for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
+        float av = -INFINITY, rv = -INFINITY;
+        if (t < t2)
+            av = hd[t] + cls32<SGN>(p2 - P[t], q2 - Q[t], a.nq, a.gmax);
+        else if (t <= L - 2 && t > t2)
+            rv = cls32<SGN>(P[t] - p2, Q[t] - q2, a.nq, a.gmax) + tl[t];
+        Ar[t] = av;
+        Rr[t] = rv;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pairs64(Args a)
+{
+    const int s = blockIdx.x / (a.L - 3);
+    const int t2 = 1 + blockIdx.x % (a.L - 3);
+    const int L = a.L, Lp = a.Lp;
+    const double *P = a.P + (int64_t)s * L;
+    const double *Q = a.Q + (int64_t)s * L;
+    const double *hd = (const double *)a.head + (int64_t)s * Lp;
+    const double *tl = (const double *)a.tail + (int64_t)s * Lp;
+    double *Ar = (double *)a.A + ((int64_t)s * L + t2) * Lp;
+    double *Rr = (double *)a.R + ((int64_t)s * L + t2) * Lp;
+    const double p2 = P[t2], q2 = Q[t2];
+    for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
+        double av = -INFINITY, rv = -INFINITY;
+        if (t < t2)
+            av = hd[t] + cls64(p2 - P[t], q2 - Q[t], a.q, a.sgn, a.hmax);
+        else if (t <= L - 2 && t > t2)
+            rv = cls64(P[t] - p2, Q[t] - q2, a.q, a.sgn, a.hmax) + tl[t];
+        Ar[t] = av;
+        Rr[t] = rv;
+    }
+}
+
+// ---------------------------------------------------------------- tiles
+
+// Tile geometry.  k = 1: column block b.  k = 2: column block b of t2 and row
+// group c of t1 (T1 rows).  k = 3: row t2 (heaviest first) and column block b
+// of t3.  The wavefront index comes from readfirstlane so that every tile
+// quantity lives in scalar registers.
+struct Tile {
+    int s, tile, b, c, valid;
+};
+
+__device__ __forceinline__ Tile tile_of(const Args &a)
+{
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+    Tile t;
+    t.valid = g < (int64_t)a.nseg * a.tiles;
+    t.s = (int)(g / a.tiles);
+    t.tile = (int)(g % a.tiles);
+    t.b = t.tile % a.NB;
+    t.c = t.tile / a.NB;
+    return t;
+}
+
+// FP32 phase 1 / phase 2.  PHASE 1 writes the tile max and the problem max;
+// PHASE 2 keeps the best FP64 candidate at or above the threshold.
+template <int SGN, int COLS, int PHASE>
+__global__ void __launch_bounds__(256) k_tiles32(Args a)
+{
+    const Tile tl = tile_of(a);
+    if (!tl.valid)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int L = a.L, Lp = a.Lp, k = a.k;
+    const int s = tl.s;
+    const int64_t tid = (int64_t)s * a.tiles + tl.tile;
+    const double *P = a.P + (int64_t)s * L;
+    const double *Q = a.Q + (int64_t)s * L;
+    const float *hd = (const float *)a.head + (int64_t)s * Lp;
+    const float *tr = (const float *)a.tail + (int64_t)s * Lp;
+
+    float thr = -INFINITY;
+    if (PHASE == 2) {
+        const Meta m = a.meta[s];
+        const float M = ordered_to_float(m.menc);
+        if (!(a.tmax[tid] > -INFINITY) || M == -INFINITY) {
+            if (lane == 0)
+                a.best[tid] = Best{-INFINITY, -INFINITY, 0x7fffffffffffffffLL, 0};
+            return;
+        }
+        double t64 = (double)M - 2.0 * (double)m.delta;
+        thr = (float)t64;
+        if ((double)thr > t64)
+            thr = nextafterf(thr, -INFINITY);
+        if (a.tmax[tid] < thr) {
+            if (lane == 0)
+                a.best[tid] = Best{-INFINITY, -INFINITY, 0x7fffffffffffffffLL, 0};
+            return;
+        }
+    }
+    float acc = -INFINITY;
+    double br = -INFINITY, bl = -INFINITY;
+    long long bc = 0x7fffffffffffffffLL;
+
+    auto candidate = [&](float key, int t1, int t2, int t3) {
+        int t[3] = {t1, t2, t3};
+        int tt[3];
+        int kk = 0;
+        for (int j = 0; j < 3; ++j)
+            if (t[j] >= 0)
+                tt[kk++] = t[j];
+        const double lam = lambda64(P, Q, L, k, tt, a.q, a.sgn, a.hmax);
+        const double rank = a.mode == TS_SEARCH_FP32_ONLY ? (double)key : lam;
+        const long long code = make_code(k, tt);
+        if (better(rank, code, br, bc)) {
+            br = rank;
+            bl = lam;
+            bc = code;
+        }
+    };
+
+    if (k == 1) {
+#pragma unroll
+        for (int v = 0; v < COLS; ++v) {
+            const int t = tl.b * a.CW + v * 64 + lane;
+            const float key = hd[t] + tr[t]; // t < Lp: entries past L-2 are -inf
+            if (PHASE == 1)
+                acc = fmaxf(acc, key);
+            else if (key >= thr)
+                candidate(key, t, -1, -1);
+        }
+    } else if (k == 2) {
+        const int cbase = tl.b * a.CW;
+        const int r0 = tl.c * a.T1;
+        const int r1 = min(r0 + a.T1, min(L - 2, cbase + a.CW - 1));
+        double pc[COLS], qc[COLS];
+        float tc[COLS];
+        int t2v[COLS];
+#pragma unroll
+        for (int v = 0; v < COLS; ++v) {
+            const int t2 = cbase + v * 64 + lane;
+            t2v[v] = t2;
+            const int ti = min(t2, L - 1);
+            pc[v] = P[ti];
+            qc[v] = Q[ti];
+            tc[v] = tr[t2];
+        }
+        const int ra = min(r1, cbase);
+        for (int t1 = r0; t1 < ra; ++t1) { // all columns lie above t1
+            const double pr = P[t1], qr = Q[t1];
+            const float hr = hd[t1];
+#pragma unroll
+            for (int v = 0; v < COLS; ++v) {
+                const float key = (hr + cls32<SGN>(pc[v] - pr, qc[v] - qr, a.nq, a.gmax)) + tc[v];
+                if (PHASE == 1)
+                    acc = fmaxf(acc, key);
+                else if (key >= thr)
+                    candidate(key, t1, t2v[v], -1);
+            }
+        }
+        for (int t1 = max(r0, cbase); t1 < r1; ++t1) { // diagonal block: need t1 < t2
+            const double pr = P[t1], qr = Q[t1];
+            const float hr = hd[t1];
+#pragma unroll
+            for (int v = 0; v < COLS; ++v) {
+                const float key = (hr + cls32<SGN>(pc[v] - pr, qc[v] - qr, a.nq, a.gmax)) + tc[v];
+                if (t1 < t2v[v]) {
+                    if (PHASE == 1)
+                        acc = fmaxf(acc, key);
+                    else if (key >= thr)
+                        candidate(key, t1, t2v[v], -1);
+                }
+            }
+        }
+    } else {
+        const int t2 = L - 3 - tl.c; // heaviest rows first
+        const int cbase = tl.b * a.CW;
+        if (cbase + a.CW - 1 > t2 && cbase <= L - 2) {
+            const float *Ar = (const float *)a.A + ((int64_t)s * L + t2) * Lp;
+            const float *Rr = (const float *)a.R + ((int64_t)s * L + t2) * Lp;
+            float rc[COLS];
+#pragma unroll
+            for (int v = 0; v < COLS; ++v)
+                rc[v] = Rr[cbase + v * 64 + lane];
+            const int n1 = (t2 + 15) & ~15; // A row is -inf from t2 up to Lp
+            for (int t1 = 0; t1 < n1; t1 += 16) {
+                float av[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    av[u] = Ar[t1 + u];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+#pragma unroll
+                    for (int v = 0; v < COLS; ++v) {
+                        const float key = av[u] + rc[v];
+                        if (PHASE == 1)
+                            acc = fmaxf(acc, key);
+                        else if (key >= thr)
+                            candidate(key, t1 + u, t2, cbase + v * 64 + lane);
+                    }
+                }
+            }
+        }
+    }
+
+    if (PHASE == 1) {
+        acc = wave_max(acc);
+        if (lane == 0) {
+            a.tmax[tid] = acc;
+            if (acc > -INFINITY)
+                atomicMax(&a.meta[s].menc, float_to_ordered(acc));
+        }
+    } else {
+        wave_best(br, bl, bc);
+        if (lane == 0)
+            a.best[tid] = Best{br, bl, bc, 0};
+    }
+}
+
+// FP64 mode: exhaustive FP64 keys with the lexicographic tie rule.
+template <int COLS>
+__global__ void __launch_bounds__(256) k_tiles64(Args a)
+{
+    const Tile tl = tile_of(a);
+    if (!tl.valid)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int L = a.L, Lp = a.Lp, k = a.k;
+    const int s = tl.s;
+    const int64_t tid = (int64_t)s * a.tiles + tl.tile;
+    const double *P = a.P + (int64_t)s * L;
+    const double *Q = a.Q + (int64_t)s * L;
+    const double *hd = (const double *)a.head + (int64_t)s * Lp;
+    const double *tr = (const double *)a.tail + (int64_t)s * Lp;
+    double br = -INFINITY;
+    long long bc = 0x7fffffffffffffffLL;
+    auto offer = [&](double key, long long code) {
+        if (better(key, code, br, bc)) {
+            br = key;
+            bc = code;
+        }
+    };
+    if (k == 1) {
+        for (int v = 0; v < COLS; ++v) {
+            const int t = tl.b * a.CW + v * 64 + lane;
+            offer(hd[t] + tr[t], t);
+        }
+    } else if (k == 2) {
+        const int cbase = tl.b * a.CW;
+        const int r0 = tl.c * a.T1;
+        const int r1 = min(r0 + a.T1, min(L - 2, cbase + a.CW - 1));
+        for (int t1 = r0; t1 < r1; ++t1) {
+            const double pr = P[t1], qr = Q[t1], hr = hd[t1];
+            for (int v = 0; v < COLS; ++v) {
+                const int t2 = cbase + v * 64 + lane;
+                if (t1 < t2) {
+                    const int ti = min(t2, L - 1);
+                    const double key = (hr + cls64(P[ti] - pr, Q[ti] - qr, a.q, a.sgn, a.hmax)) + tr[t2];
+                    offer(key, ((long long)t1 << 12) | t2);
+                }
+            }
+        }
+    } else {
+        const int t2 = L - 3 - tl.c;
+        const int cbase = tl.b * a.CW;
+        if (cbase + a.CW - 1 > t2 && cbase <= L - 2) {
+            const double *Ar = (const double *)a.A + ((int64_t)s * L + t2) * Lp;
+            const double *Rr = (const double *)a.R + ((int64_t)s * L + t2) * Lp;
+            for (int v = 0; v < COLS; ++v) {
+                const int t3 = cbase + v * 64 + lane;
+                const double rc = Rr[t3];
+                double vb = -INFINITY;
+                int vt = 0;
+                for (int t1 = 0; t1 < t2; ++t1) { // t1 ascending: strict > keeps the first
+                    const double key = Ar[t1] + rc;
+                    if (key > vb) {
+                        vb = key;
+                        vt = t1;
+                    }
+                }
+                offer(vb, ((long long)vt << 24) | ((long long)t2 << 12) | t3);
+            }
+        }
+    }
+    double bl = br;
+    wave_best(br, bl, bc);
+    if (lane == 0)
+        a.best[tid] = Best{br, br, bc, 0};
+}
+
+// ---------------------------------------------------------------- final
+
+__global__ void __launch_bounds__(256) k_final(const Best *__restrict__ best, int per, const double *__restrict__ P,
+                                               int L, int k, double q, double sgn, int32_t *__restrict__ thr,
+                                               double *__restrict__ obj, int32_t *__restrict__ status, int s_base)
+{
+    const int s = s_base + blockIdx.x;
+    const Best *b = best + (int64_t)blockIdx.x * per;
+    double br = -INFINITY, bl = -INFINITY;
+    long long bc = 0x7fffffffffffffffLL;
+    for (int i = threadIdx.x; i < per; i += blockDim.x) {
+        const Best x = b[i];
+        if (better(x.rank, x.code, br, bc)) {
+            br = x.rank;
+            bl = x.lam;
+            bc = x.code;
+        }
+    }
+    wave_best(br, bl, bc);
+    __shared__ double sr[4], sl[4];
+    __shared__ long long sc[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sr[w] = br;
+        sl[w] = bl;
+        sc[w] = bc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+            if (better(sr[i], sc[i], br, bc)) {
+                br = sr[i];
+                bl = sl[i];
+                bc = sc[i];
+            }
+        if (br == -INFINITY) {
+            for (int j = 0; j < k; ++j)
+                thr[(int64_t)s * k + j] = -1;
+            obj[s] = NAN;
+            status[s] = P[(int64_t)s * L + L - 1] > 0.0 ? TS_PROBLEM_DEGENERATE : TS_PROBLEM_EMPTY;
+        } else {
+            for (int j = k - 1; j >= 0; --j) {
+                thr[(int64_t)s * k + j] = (int32_t)(bc & 4095);
+                bc >>= 12;
+            }
+            obj[s] = expm1(sgn * bl) / (1.0 - q);
+            status[s] = TS_PROBLEM_OK;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- plain
+
+__device__ __forceinline__ int64_t binom(int64_t x, int r)
+{
+    if (x < r)
+        return 0;
+    if (r == 1)
+        return x;
+    if (r == 2)
+        return x * (x - 1) / 2;
+    return x * (x - 1) * (x - 2) / 6;
+}
+
+// largest x with binom(x, r) <= v
+__device__ __forceinline__ int64_t inv_binom(int64_t v, int r)
+{
+    double est;
+    if (r == 1)
+        return v;
+    if (r == 2)
+        est = floor(sqrt(2.0 * (double)v)) + 1.0;
+    else
+        est = floor(cbrt(6.0 * (double)v)) + 2.0;
+    int64_t x = (int64_t)est;
+    while (binom(x, r) > v)
+        --x;
+    while (binom(x + 1, r) <= v)
+        ++x;
+    return x;
+}
+
+__global__ void __launch_bounds__(256) k_plain(const double *__restrict__ P, const double *__restrict__ Q, int L,
+                                               int k, int64_t ntup, double q, double sgn, double hmax,
+                                               Best *__restrict__ out)
+{
+    double br = -INFINITY, bl = -INFINITY;
+    long long bc = 0x7fffffffffffffffLL;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ntup;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        // combinatorial number system: r = C(t_k, k) + ... + C(t_1, 1)
+        int t[3];
+        int64_t v = r;
+        for (int j = k; j >= 1; --j) {
+            const int64_t x = inv_binom(v, j);
+            t[j - 1] = (int)x;
+            v -= binom(x, j);
+        }
+        const double lam = lambda64(P, Q, L, k, t, q, sgn, hmax);
+        const long long code = make_code(k, t);
+        if (better(lam, code, br, bc)) {
+            br = lam;
+            bl = lam;
+            bc = code;
+        }
+    }
+    wave_best(br, bl, bc);
+    __shared__ double sr[4];
+    __shared__ long long sc[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sr[w] = br;
+        sc[w] = bc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+            if (better(sr[i], sc[i], br, bc)) {
+                br = sr[i];
+                bc = sc[i];
+            }
+        out[blockIdx.x] = Best{br, br, bc, 0};
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+template <int SGN>
+static void launch_tiles32(int cols, int phase, dim3 g, hipStream_t st, const Args &a)
+{
+#define TS_TILES(C)                                                                                                 \
+    if (phase == 1)                                                                                                 \
+        hipLaunchKernelGGL((k_tiles32<SGN, C, 1>), g, dim3(256), 0, st, a);                                         \
+    else                                                                                                            \
+        hipLaunchKernelGGL((k_tiles32<SGN, C, 2>), g, dim3(256), 0, st, a);
+    if (cols == 1) {
+        TS_TILES(1)
+    } else if (cols == 2) {
+        TS_TILES(2)
+    } else {
+        TS_TILES(4)
+    }
+#undef TS_TILES
+}
+
+ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, double q, int mode, void *ws,
+                        size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t, hipStream_t st)
+{
+    (void)ws_bytes;
+    const Plan p = make_plan(nseg, L, k, mode, t.search_cols, t.search_rows);
+    char *base = (char *)ws;
+    Args a;
+    a.P = P;
+    a.Q = Q;
+    a.nseg = nseg;
+    a.L = L;
+    a.Lp = p.Lp;
+    a.k = k;
+    a.mode = mode;
+    a.q = q;
+    a.sgn = q < 1.0 ? 1.0 : -1.0;
+    a.hmax = fabs(1.0 - q) * log((double)L);
+    const float q32 = (float)q;
+    a.nq = (float)(-a.sgn) * q32;
+    {
+        double gm = fabs(1.0 - q) * log2((double)L);
+        float g = (float)gm;
+        if ((double)g < gm)
+            g = nextafterf(g, INFINITY);
+        a.gmax = g;
+    }
+    a.CW = p.CW;
+    a.NB = p.NB;
+    a.NC = p.NC;
+    a.T1 = p.T1;
+    a.tiles = p.tiles;
+    a.meta = (Meta *)(base + p.off_meta);
+    a.head = base + p.off_head;
+    a.tail = base + p.off_tail;
+    a.A = base + p.off_A;
+    a.R = base + p.off_R;
+    a.tmax = (float *)(base + p.off_tmax);
+    a.best = (Best *)(base + p.off_best);
+
+    if (mode == TS_SEARCH_PLAIN) {
+        const int64_t n = L - 1;
+        const int64_t ntup = k == 1 ? n : (k == 2 ? n * (n - 1) / 2 : n * (n - 1) * (n - 2) / 6);
+        const int blocks = (int)std::min<int64_t>(PLAIN_BLOCKS, std::max<int64_t>(1, (ntup + 255) / 256));
+        Best *pb = (Best *)(base + p.off_plain);
+        for (int s = 0; s < nseg; ++s) {
+            hipLaunchKernelGGL(k_plain, dim3(blocks), dim3(256), 0, st, P + (int64_t)s * L, Q + (int64_t)s * L, L,
+                               k, ntup, q, a.sgn, a.hmax, pb);
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, pb, blocks, P, L, k, q, a.sgn, thr, obj, status,
+                               s);
+        }
+        return check_launch("ts_threshold_search (plain)");
+    }
+
+    hipLaunchKernelGGL(k_setup, dim3(nseg), dim3(256), 0, st, a);
+    if (k == 3) {
+        dim3 g((unsigned)((int64_t)(L - 3) * nseg));
+        if (mode == TS_SEARCH_FP64)
+            hipLaunchKernelGGL(k_pairs64, g, dim3(256), 0, st, a);
+        else if (a.sgn > 0)
+            hipLaunchKernelGGL(k_pairs32<1>, g, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_pairs32<-1>, g, dim3(256), 0, st, a);
+    }
+    const int64_t waves = (int64_t)nseg * p.tiles;
+    dim3 g((unsigned)((waves + 3) / 4));
+    if (mode == TS_SEARCH_FP64) {
+        if (t.search_cols == 1)
+            hipLaunchKernelGGL(k_tiles64<1>, g, dim3(256), 0, st, a);
+        else if (t.search_cols == 2)
+            hipLaunchKernelGGL(k_tiles64<2>, g, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_tiles64<4>, g, dim3(256), 0, st, a);
+    } else {
+        for (int phase = 1; phase <= 2; ++phase) {
+            if (a.sgn > 0)
+                launch_tiles32<1>(t.search_cols, phase, g, st, a);
+            else
+                launch_tiles32<-1>(t.search_cols, phase, g, st, a);
+        }
+    }
+    hipLaunchKernelGGL(k_final, dim3(nseg), dim3(256), 0, st, a.best, p.tiles, P, L, k, q, a.sgn, thr, obj, status, 0);
+    return check_launch("ts_threshold_search");
+}
+
+} // namespace ts

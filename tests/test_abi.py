@@ -1,0 +1,142 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol include/ts.h
+declares, sizes workspaces, and rejects bad arguments before any launch
+(no GPU is touched by these calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ts.h")
+LIB = os.path.join(ROOT, "paper_2012_10684_amd", "libts.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ts_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libts.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for n in ("ts_histogram", "ts_prefix", "ts_threshold_search", "ts_label", "ts_search_workspace_bytes",
+              "ts_last_error", "ts_abi_version"):
+        assert n in names, names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for n in declared_functions():
+        assert n in exported, f"{n} declared in ts.h but not exported"
+        getattr(lib, n)
+
+
+class Binning(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32), ("hi", ctypes.c_int32), ("nbins", ctypes.c_int32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("vox", ctypes.c_void_p), ("offs", ctypes.c_void_p), ("nseg", ctypes.c_int32),
+                ("total", ctypes.c_int64)]
+
+
+def _bind(lib):
+    P, i32, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    lib.ts_histogram.argtypes = [Batch, Binning, P, P, P]
+    lib.ts_prefix.argtypes = [P, i32, i32, f64, P, P, P]
+    lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.ts_search_workspace_bytes.restype = sz
+    lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, f64, i32, P, sz, P, P, P, P, P]
+    lib.ts_label.argtypes = [Batch, Binning, P, i32, P, P, P]
+    lib.ts_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def test_abi_version(lib):
+    lib.ts_abi_version.restype = ctypes.c_int32
+    assert lib.ts_abi_version() == 1
+
+
+def test_workspace_sizes(lib):
+    _bind(lib)
+    ws = lib.ts_search_workspace_bytes
+    assert ws(1, 4096, 1, 0) > 0
+    assert ws(300, 256, 2, 0) >= 300 * 256 * 8  # head + tail rows
+    assert ws(1, 1024, 3, 0) >= 2 * 1024 * 1024 * 4  # k = 3 pair rows
+    assert ws(1, 1024, 3, 2) >= 2 * 1024 * 1024 * 8  # FP64 rows
+    assert ws(10, 256, 2, 0) > ws(5, 256, 2, 0)
+    for bad in [(-1, 256, 1, 0), (1, 1, 1, 0), (1, 4097, 1, 0), (1, 256, 0, 0), (1, 256, 4, 0), (1, 256, 1, 7)]:
+        assert ws(*bad) == 0, bad
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("hist_neg_nseg", 1), ("hist_bad_bins", 1), ("hist_lo_gt_hi", 1), ("hist_null", 1), ("hist_bad_tune", 1),
+    ("prefix_q0", 1), ("prefix_qnan", 1), ("prefix_bins", 1), ("prefix_null", 1),
+    ("search_k0", 1), ("search_k4", 1), ("search_q1", 2), ("search_mode", 1), ("search_ws", 3),
+    ("search_bins_lt_k1", 1), ("search_null", 1),
+    ("label_k", 1), ("label_null", 1), ("label_total_without_seg", 1),
+])
+def test_argument_errors(lib, case, expect):
+    _bind(lib)
+    ok_bin = Binning(-1024, 3071, 1024)
+    b1 = Batch(FAKE, FAKE, 1, 10)
+    sx = None
+    T = ctypes.c_void_p
+    if case == "hist_neg_nseg":
+        st = lib.ts_histogram(Batch(FAKE, FAKE, -1, 0), ok_bin, FAKE, None, sx)
+    elif case == "hist_bad_bins":
+        st = lib.ts_histogram(b1, Binning(0, 10, 4097), FAKE, None, sx)
+    elif case == "hist_lo_gt_hi":
+        st = lib.ts_histogram(b1, Binning(10, 0, 16), FAKE, None, sx)
+    elif case == "hist_null":
+        st = lib.ts_histogram(Batch(None, FAKE, 1, 10), ok_bin, FAKE, None, sx)
+    elif case == "hist_bad_tune":
+        tune = (ctypes.c_int32 * 8)(100, 0, 0, 0, 0, 0, 0, 0)  # block not a multiple of 64
+        st = lib.ts_histogram(b1, ok_bin, FAKE, ctypes.cast(tune, T), sx)
+    elif case == "prefix_q0":
+        st = lib.ts_prefix(FAKE, 1, 256, 0.0, FAKE, FAKE, sx)
+    elif case == "prefix_qnan":
+        st = lib.ts_prefix(FAKE, 1, 256, float("nan"), FAKE, FAKE, sx)
+    elif case == "prefix_bins":
+        st = lib.ts_prefix(FAKE, 1, 1, 0.8, FAKE, FAKE, sx)
+    elif case == "prefix_null":
+        st = lib.ts_prefix(None, 1, 256, 0.8, FAKE, FAKE, sx)
+    elif case in ("search_k0", "search_k4", "search_q1", "search_mode", "search_ws", "search_bins_lt_k1",
+                  "search_null"):
+        k = {"search_k0": 0, "search_k4": 4}.get(case, 2)
+        q = 1.0 if case == "search_q1" else 0.8
+        mode = 9 if case == "search_mode" else 0
+        L = 2 if case == "search_bins_lt_k1" else 256
+        ws_bytes = 16 if case == "search_ws" else 1 << 40
+        P = None if case == "search_null" else FAKE
+        st = lib.ts_threshold_search(P, FAKE, 1, L, k, q, mode, FAKE, ws_bytes, FAKE, FAKE, FAKE, None, sx)
+    elif case == "label_k":
+        st = lib.ts_label(b1, ok_bin, FAKE, 0, FAKE, None, sx)
+    elif case == "label_null":
+        st = lib.ts_label(b1, ok_bin, None, 1, FAKE, None, sx)
+    elif case == "label_total_without_seg":
+        st = lib.ts_label(Batch(None, None, 0, 5), ok_bin, FAKE, 1, FAKE, None, sx)
+    assert st == expect, (case, st, lib.ts_last_error())
+    assert lib.ts_last_error(), "an error text must be set"
+
+
+def test_empty_batch_is_a_no_op(lib):
+    _bind(lib)
+    ok_bin = Binning(-1024, 3071, 256)
+    assert lib.ts_histogram(Batch(None, None, 0, 0), ok_bin, None, None, None) == 0
+    assert lib.ts_label(Batch(None, None, 0, 0), ok_bin, None, 1, None, None, None) == 0
+    assert lib.ts_prefix(None, 0, 256, 0.8, None, None, None) == 0
+    assert lib.ts_threshold_search(None, None, 0, 256, 2, 0.8, 0, None, 0, None, None, None, None, None) == 0

@@ -1,0 +1,239 @@
+"""GPU parity of every step of the path against the CPU oracle, element by
+element on seeded inputs: histograms and labels bit-exact, P bit-exact, Q to
+summation-order rounding, thresholds identical (up to the stated tie rule) and
+objectives within 1e-5 relative.  Sizes span several tiles with ragged tails;
+edge cases cover empty, one-voxel and unaligned problems, degenerate
+histograms, exact ties and narrow windows."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import check_choice, say, to_dev, u32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2012_10684_amd import api, synth  # noqa: E402
+
+WINDOWS = [(-1024, 3071, 4096), (-1024, 3071, 1024), (-1024, -200, 256), (-1024, 3071, 512),
+           (-5, 7, 13), (100, 100, 4), (-32768, 32767, 4096), (3, 1000, 7), (-1024, -1000, 256)]
+MODES = [api.SEARCH_FP32_TIECHECK, api.SEARCH_FP64, api.SEARCH_PLAIN]
+
+
+def ragged_segments(rng, base: torch.Tensor):
+    """Views of one buffer at assorted offsets and lengths (incl. empty,
+    one voxel, unaligned starts, lengths not a multiple of 8)."""
+    sizes = [0, 1, 7, 8, 9, 63, 1000, 4097, 65537, 0, 3, 262144]
+    segs, pos = [], 0
+    for n in sizes:
+        pos += int(rng.integers(0, 9))  # misalign the start
+        segs.append(base[pos:pos + n])
+        pos += n
+    return segs
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    rng = np.random.default_rng(101)
+    host = synth.make_volume(synth.rng_for(9, 1), 2, 512).reshape(-1)[:400000].copy()
+    host[:50] = np.arange(-32768, 32767, 1311)[:50]  # extreme values
+    base = to_dev(host)
+    segs = ragged_segments(rng, base)
+    return host, base, segs
+
+
+@pytest.mark.parametrize("win", WINDOWS, ids=lambda w: f"{w[0]}_{w[1]}_{w[2]}")
+def test_histogram_ragged_batch(ragged, win):
+    host, base, segs = ragged
+    lo, hi, L = win
+    b = api.Batch(segs)
+    h = u32(api.histogram(b, api.binning(lo, hi, L)))
+    torch.cuda.synchronize()
+    for i, s in enumerate(segs):
+        want = oracle.histogram(s.cpu().numpy(), lo, hi, L)
+        assert np.array_equal(h[i], want), (win, i, s.numel())
+        assert int(h[i].sum()) == s.numel()
+
+
+@pytest.mark.parametrize("win", WINDOWS, ids=lambda w: f"{w[0]}_{w[1]}_{w[2]}")
+def test_histogram_every_int16(win):
+    lo, hi, L = win
+    allv = np.arange(-32768, 32768, dtype=np.int64).astype(np.int16)
+    h = u32(api.histogram(api.Batch([to_dev(allv)]), api.binning(lo, hi, L)))[0]
+    assert np.array_equal(h, oracle.histogram(allv, lo, hi, L)), win
+
+
+@pytest.mark.parametrize("tune", [None, dict(hist_replicas=1, hist_block=64), dict(hist_replicas=4, hist_block=1024),
+                                  dict(hist_wg_per_cu=1, min_chunk=512)], ids=["default", "r1b64", "r4b1024", "small"])
+def test_histogram_tuning_invariant(ragged, tune):
+    host, base, segs = ragged
+    b = api.Batch(segs)
+    binn = api.binning(-1024, -200, 256)
+    ref = u32(api.histogram(b, binn))
+    got = u32(api.histogram(b, binn, tune=tune))
+    assert np.array_equal(ref, got)
+
+
+def _prefix_case(rng, L):
+    h = rng.integers(0, 1000, L).astype(np.uint32)
+    h[rng.random(L) < 0.4] = 0
+    return h
+
+
+@pytest.mark.parametrize("q", [0.3, 0.8, 1.5, 2.5])
+def test_prefix(q):
+    rng = np.random.default_rng(7)
+    hs = [_prefix_case(rng, 1024) for _ in range(5)]
+    hs.append(np.zeros(1024, np.uint32))  # empty problem
+    one = np.zeros(1024, np.uint32)
+    one[512] = 7
+    hs.append(one)
+    H = np.stack(hs)
+    P, Q = api.prefix(to_dev(H.view(np.int32)), q)
+    P, Q = P.cpu().numpy(), Q.cpu().numpy()
+    for i, h in enumerate(hs):
+        Po, Qo = oracle.prefix(h, q)
+        assert np.array_equal(P[i], Po), i  # one rounding of an exact count ratio
+        tol = 1024 * 2.0 ** -52 * np.maximum(Qo, 1e-300)
+        assert np.all(np.abs(Q[i] - Qo) <= tol), (i, np.max(np.abs(Q[i] - Qo) / np.maximum(Qo, 1e-300)))
+        z = np.nonzero(h == 0)[0]
+        z = z[z > 0]
+        assert np.array_equal(Q[i][z], Q[i][z - 1]), "an empty bin must repeat Q bit for bit"
+        if h.sum():
+            assert P[i][-1] == 1.0
+
+
+def _search_all(H: np.ndarray, k: int, q: float, mode: int, tune=None):
+    P, Q = api.prefix(to_dev(H.view(np.int32)), q)
+    thr, obj, st = api.threshold_search(P, Q, k, q, mode, tune=tune)
+    torch.cuda.synchronize()
+    return thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+
+
+def _random_hists(rng, n, L, zero_frac=0.3, hi=50):
+    H = rng.integers(0, hi, (n, L)).astype(np.uint32)
+    H[rng.random((n, L)) < zero_frac] = 0
+    return H
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["fp32tie", "fp64", "plain"])
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("q", [0.3, 0.8, 1.5, 3.0])
+def test_search_small_random(mode, k, q):
+    rng = np.random.default_rng(1000 * k + int(q * 10) + mode)
+    for L in (k + 1, k + 2, 13, 64, 130):
+        H = _random_hists(rng, 6, L)
+        thr, obj, st = _search_all(H, k, q, mode)
+        for i in range(len(H)):
+            check_choice(H[i], k, q, thr[i], obj[i], st[i], mode=oracle.MODE_DIRECT)
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["fp32tie", "fp64", "plain"])
+def test_search_edge_cases(mode):
+    L = 40
+    cases = []
+    cases.append(np.zeros(L, np.uint32))  # empty
+    one = np.zeros(L, np.uint32)
+    one[17] = 9
+    cases.append(one)  # one occupied bin: degenerate for every k
+    for occ in ([0, 39], [3, 4, 30], [1, 2, 3, 38]):  # exactly k+1 occupied bins for k = 1, 2, 3
+        h = np.zeros(L, np.uint32)
+        h[occ] = 5
+        cases.append(h)
+    cases.append(np.full(L, 3, np.uint32))  # uniform: exact ties everywhere
+    half = np.arange(1, L // 2 + 1, dtype=np.uint32)
+    cases.append(np.concatenate([half, half[::-1]]))  # symmetric
+    H = np.stack(cases)
+    for k in (1, 2, 3):
+        for q in (0.5, 1.5):
+            thr, obj, st = _search_all(H, k, q, mode)
+            for i in range(len(H)):
+                check_choice(H[i], k, q, thr[i], obj[i], st[i], mode=oracle.MODE_DIRECT)
+
+
+def test_search_exact_ties_first_tuple():
+    # runs of empty bins: every tuple moving a threshold inside a run ties
+    # exactly; the first in lexicographic order must win
+    L = 64
+    h = np.zeros(L, np.uint32)
+    h[[2, 3, 20, 21, 22, 50, 51, 60]] = [5, 9, 4, 4, 7, 3, 8, 2]
+    for k in (1, 2, 3):
+        for mode in MODES:
+            thr, obj, st = _search_all(h[None], k, 0.8, mode)
+            r = oracle.search(h, k, 0.8, oracle.MODE_DIRECT)
+            assert thr[0].tolist() == r.thr.tolist(), (k, mode, thr[0], r)
+
+
+@pytest.mark.parametrize("tune", [dict(search_cols=1), dict(search_cols=4), dict(search_cols=2, search_rows=256)],
+                         ids=["c1", "c4", "c2r256"])
+def test_search_tuning_invariant(tune):
+    rng = np.random.default_rng(5)
+    for k in (1, 2, 3):
+        H = _random_hists(rng, 5, 300, zero_frac=0.2, hi=5000)
+        a = _search_all(H, k, 0.8, api.SEARCH_FP32_TIECHECK)
+        b = _search_all(H, k, 0.8, api.SEARCH_FP32_TIECHECK, tune=tune)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y, equal_nan=True)
+
+
+def test_search_fp32_only_mode_is_close():
+    rng = np.random.default_rng(11)
+    H = _random_hists(rng, 8, 256, zero_frac=0.1, hi=10000)
+    thr, obj, st = _search_all(H, 2, 0.8, api.SEARCH_FP32_ONLY)
+    for i in range(len(H)):
+        r = oracle.search(H[i], 2, 0.8)
+        s = oracle.objective(H[i], thr[i], 0.8)
+        assert s >= r.obj - 1e-4 * abs(r.obj)  # FP32 keys: near-optimal, not necessarily exact
+        assert abs(obj[i] - s) <= 1e-10 * abs(s)  # reported value is the FP64 objective of that tuple
+
+
+def test_label_ragged(ragged):
+    host, base, segs = ragged
+    rng = np.random.default_rng(3)
+    for lo, hi, L in WINDOWS:
+        for k in (1, 2, 3):
+            thr = np.stack([np.sort(rng.choice(L - 1, k, replace=False)) for _ in segs]).astype(np.int32)
+            thr[1] = -1  # degenerate row
+            if len(segs) > 4 and k >= 2:
+                thr[4, :2] = [5, 5]  # not strictly ascending: labels 0
+            b = api.Batch(segs)
+            outs = api.label(b, api.binning(lo, hi, L), to_dev(thr), k)
+            torch.cuda.synchronize()
+            for i, s in enumerate(segs):
+                want = oracle.label(s.cpu().numpy(), lo, hi, L, thr[i])
+                if i == 4 and k >= 2:
+                    want = np.zeros_like(want)
+                assert np.array_equal(outs[i].cpu().numpy(), want), (lo, hi, L, k, i)
+
+
+def test_label_misaligned_output():
+    v = to_dev(synth.workload_slice(3).reshape(-1))
+    out_buf = torch.empty(v.numel() + 16, dtype=torch.uint8, device=v.device)
+    out = out_buf[3:3 + v.numel()]  # output phase differs from the input phase
+    thr = to_dev(np.array([[1100]], np.int32))
+    api.label(api.Batch([v]), api.binning(-1024, 3071, 4096), thr, 1, outs=[out])
+    want = oracle.label(v.cpu().numpy(), -1024, 3071, 4096, [1100])
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_determinism_and_batch_invariance():
+    vol = synth.make_volume(synth.rng_for(9, 2), 24, 256)
+    dv = to_dev(vol)
+    binn = api.binning(-1024, -200, 256)
+    whole = api.Batch.slices(dv)
+    r1 = api.segment(whole, binn, 2, 0.8)
+    r2 = api.segment(whole, binn, 2, 0.8)
+    torch.cuda.synchronize()
+    assert torch.equal(r1[0], r2[0]) and torch.equal(r1[2][0], r2[2][0])
+    assert torch.equal(r1[2][1], r2[2][1])
+    for a, b in zip(r1[3], r2[3]):
+        assert torch.equal(a, b)
+    # each slice alone gives the same bits as inside the batch
+    for z in (0, 7, 23):
+        one = api.segment(api.Batch([dv[z].reshape(-1)]), binn, 2, 0.8)
+        assert torch.equal(one[0][0], r1[0][z])
+        assert torch.equal(one[2][0][0], r1[2][0][z]) and torch.equal(one[2][1][0], r1[2][1][z])
+        assert torch.equal(one[3][0], r1[3][z])

@@ -1,0 +1,84 @@
+"""GPU parity on the five workloads at their full sizes, in the launch
+configuration the benchmark times, against the oracle (all outputs where the
+oracle finishes in seconds, sampled problems otherwise)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import check_choice, say, to_dev, u32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2012_10684_amd import api, synth  # noqa: E402
+
+
+def test_single_slice_4096_bins_k1():
+    """One 512x512 slice, 4096 bins over [-1024, 3071], k = 1, q = 0.8."""
+    for idx in range(3):
+        s = synth.workload_slice(idx)
+        binn = api.binning(-1024, 3071, 4096)
+        h, _, (thr, obj, st), labels = api.segment(api.Batch([to_dev(s.reshape(-1))]), binn, 1, 0.8)
+        torch.cuda.synchronize()
+        hh = oracle.histogram(s, -1024, 3071, 4096)
+        assert np.array_equal(u32(h)[0], hh)
+        exact, r = check_choice(hh, 1, 0.8, thr.cpu().numpy()[0], float(obj[0]), int(st[0]))
+        say(f"slice {idx}: gpu {thr.cpu().numpy()[0].tolist()} oracle {r.thr.tolist()} gap {r.rel_gap():.3g}")
+        want = oracle.label(s.reshape(-1), -1024, 3071, 4096, r.thr if exact else thr.cpu().numpy()[0])
+        assert np.array_equal(labels[0].cpu().numpy(), want)
+
+
+@pytest.fixture(scope="module")
+def volume300():
+    say("generating the 512x512x300 volume")
+    return synth.workload_volume300(0)
+
+
+@pytest.mark.parametrize("q", [0.5, 0.8, 1.5])
+def test_volume300_per_slice_k2(volume300, q):
+    """Per-slice 256-bin histograms over [-1024, -200], k = 2, every slice."""
+    vol = volume300
+    dv = to_dev(vol)
+    b = api.Batch.slices(dv)
+    binn = api.binning(-1024, -200, 256)
+    h, _, (thr, obj, st), labels = api.segment(b, binn, 2, q)
+    torch.cuda.synchronize()
+    H = u32(h)
+    thr, obj, st = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+    exact = 0
+    for z in range(vol.shape[0]):
+        hz = oracle.histogram(vol[z], -1024, -200, 256)
+        assert np.array_equal(H[z], hz), z
+        ex, r = check_choice(hz, 2, q, thr[z], obj[z], st[z])
+        exact += ex
+        if z % 50 == 0:
+            lab = labels[z].cpu().numpy()
+            assert np.array_equal(lab, oracle.label(vol[z].reshape(-1), -1024, -200, 256, thr[z]))
+    say(f"q={q}: {exact}/{vol.shape[0]} slices with identical thresholds")
+    # every label, against the oracle's labels for the GPU thresholds (which
+    # the loop above showed to be the oracle's choice up to the tie rule)
+    allv = vol.reshape(vol.shape[0], -1)
+    for z in range(vol.shape[0]):
+        want = oracle.label(allv[z], -1024, -200, 256, thr[z])
+        assert np.array_equal(labels[z].cpu().numpy(), want), z
+
+
+def test_volume600_whole_k3():
+    """Whole-volume 1024-bin histogram of 512x512x600, k = 3, q = 0.8."""
+    say("generating the 512x512x600 volume")
+    vol = synth.workload_volume600(0)
+    dv = to_dev(vol)
+    b = api.Batch([dv.reshape(-1)])
+    binn = api.binning(-1024, 3071, 1024)
+    h, _, (thr, obj, st), labels = api.segment(b, binn, 3, 0.8)
+    torch.cuda.synchronize()
+    hh = oracle.histogram(vol, -1024, 3071, 1024)
+    assert np.array_equal(u32(h)[0], hh)
+    say("oracle search k=3 L=1024")
+    ex, r = check_choice(hh, 3, 0.8, thr.cpu().numpy()[0], float(obj[0]), int(st[0]))
+    say(f"gpu {thr.cpu().numpy()[0].tolist()} oracle {r.thr.tolist()} S {float(obj[0])!r} vs {r.obj!r}")
+    want = oracle.label(vol.reshape(-1), -1024, 3071, 1024, thr.cpu().numpy()[0])
+    assert np.array_equal(labels[0].cpu().numpy(), want)
