@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the Tsallis-threshold segmentation path on one MI355X.
+
+Workload: one 512x512x300 int16 CT-like volume (seeded synthetic four-tissue
+mixture with branching airway tubes); per-slice 256-bin histograms over the
+HU window [-1024, -200]; per-slice exhaustive k = 2 threshold search for
+q = 0.5, 0.8 and 1.5 (FP32 keys + FP64 tie check); per-slice labels for each
+q.  One step is the whole path over the volume:
+    ts_histogram (300 problems) + 3 x [ts_prefix + ts_threshold_search + ts_label].
+Inputs are resident in HBM before timing starts; every output buffer and the
+workspace are allocated once, so a step only launches kernels.
+
+Prints one JSON line: voxels/s over the whole step (the value), tuples/s,
+per-kernel times from HIP events recorded on the launch stream, the roofline
+of the dominant kernel and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+Z, H, W = 300, 512, 512
+LO, HI, L = -1024, -200, 256
+K = 2
+QS = (0.5, 0.8, 1.5)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slices", type=int, default=300, help="slices in the oracle's timed sample")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only run device-to-device copies of 256 MiB (reference kernel for the PMC byte counters)")
+    return ap.parse_args()
+
+
+def src_hash(name: str) -> str:
+    p = os.path.join(ROOT, "paper_2012_10684_amd", "csrc", name)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kernel_file: str):
+    """HBM traffic per launch from the committed PMC summary, if it was taken
+    on the current source of that kernel (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel_file)
+    if not e or e.get("src_sha") != src_hash(kernel_file):
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(vol, nslices: int):
+    import numpy as np
+    import oracle
+
+    sample = vol[:nslices]
+    t0 = time.perf_counter()
+    for z in range(sample.shape[0]):
+        h = oracle.histogram(sample[z], LO, HI, L)
+        for q in QS:
+            r = oracle.search(h, K, q, oracle.MODE_PREFIX)
+            oracle.label(sample[z].reshape(-1), LO, HI, L, r.thr)
+    dt = time.perf_counter() - t0
+    nvox = int(np.prod(sample.shape))
+    return {"value": nvox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nslices} of the 300 slices: oracle histogram + 3 x (prefix-mode k=2 search + labels), "
+                      f"{dt:.2f} s single-threaded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+              f"(the per-slice problems are independent: see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2012_10684_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.calibrate:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": a.numel(), "bytes_written": b.numel(), "launches": 5}))
+        return
+    vol = synth.workload_volume300(0)
+    dv = torch.from_numpy(vol).to(dev)
+    batch = api.Batch.slices(dv)
+    binn = api.binning(LO, HI, L)
+    nseg = batch.nseg
+    hist = torch.empty((nseg, L), dtype=torch.int32, device=dev)
+    PQ = [(torch.empty((nseg, L), dtype=torch.float64, device=dev),
+           torch.empty((nseg, L), dtype=torch.float64, device=dev)) for _ in QS]
+    ws = torch.empty(api.workspace_bytes(nseg, L, K), dtype=torch.uint8, device=dev)
+    res = [(torch.empty((nseg, K), dtype=torch.int32, device=dev), torch.empty(nseg, dtype=torch.float64, device=dev),
+            torch.empty(nseg, dtype=torch.int32, device=dev)) for _ in QS]
+    outs = [[torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes] for _ in QS]
+    optrs = [torch.tensor([o.data_ptr() for o in oq], dtype=torch.int64).to(dev) for oq in outs]
+    stream = torch.cuda.current_stream()
+    names = ["histogram"] + [f"{n}_q{q}" for q in QS for n in ("prefix", "search", "label")]
+
+    def step(ev=None):
+        i = 0
+
+        def mark():
+            nonlocal i
+            if ev is not None:
+                ev[i].record(stream)
+                i += 1
+
+        mark()
+        api.histogram(batch, binn, out=hist, stream=stream)
+        mark()
+        for j, q in enumerate(QS):
+            api.prefix(hist, q, P=PQ[j][0], Q=PQ[j][1], stream=stream)
+            mark()
+            api.threshold_search(PQ[j][0], PQ[j][1], K, q, api.SEARCH_FP32_TIECHECK, ws=ws, out=res[j], stream=stream)
+            mark()
+            api.label(batch, binn, res[j][0], K, outs=outs[j], out_ptrs=optrs[j], stream=stream)
+            mark()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    nev = 1 + len(names)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(events[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    per = {n: 0.0 for n in names}
+    for s in range(args.steps):
+        for i, n in enumerate(names):
+            per[n] += events[s][i].elapsed_time(events[s][i + 1]) * 1e-3
+    per = {n: v / args.steps for n, v in per.items()}
+
+    nvox = Z * H * W
+    tuples = len(QS) * nseg * ((L - 1) * (L - 2) // 2)
+    label_t = [per[f"label_q{q}"] for q in QS]
+    hist_t = per["histogram"]
+    search_t = [per[f"search_q{q}"] for q in QS]
+    kernels = {"label": sum(label_t), "histogram": hist_t, "search": sum(search_t),
+               "prefix": sum(per[f"prefix_q{q}"] for q in QS)}
+    dominant = max(kernels, key=kernels.get)
+    if dominant == "label":
+        avg = sum(label_t) / len(label_t)
+        alg = 3 * nvox
+        src = "k_label.hip"
+    else:
+        avg = hist_t
+        alg = 2 * nvox
+        src = "k_histogram.hip"
+    achieved = alg / avg / 1e9
+    traffic = load_traffic(src)
+    # correctness guard: every problem found a valid tuple, every label pass wrote labels in [0, K]
+    st_ok = all(int((r[2] != 0).sum()) == 0 for r in res)
+    line = {
+        "metric": "voxels/s end-to-end (+ Tsallis tuples/s; % HBM peak of the dominant kernel)",
+        "value": nvox * args.steps / dt,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "volume 512x512x300 int16, per-slice 256-bin histograms over [-1024,-200], "
+                               "per-slice k=2 exhaustive search for q in {0.5,0.8,1.5} (FP32 keys + FP64 tie check), "
+                               "per-slice labels for each q",
+                   "problems": nseg, "voxels": nvox, "bins": L, "k": K, "q": list(QS)},
+        "tuples_per_s": tuples * args.steps / dt,
+        "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
+        "roofline": {"bound": "hbm", "kernel": src.replace(".hip", ""), "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6},
+        "histogram_gbs": 2 * nvox / hist_t / 1e9,
+        "label_gbs": 3 * nvox / (sum(label_t) / len(label_t)) / 1e9,
+        "all_problems_ok": bool(st_ok),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(vol, args.cpu_slices)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
