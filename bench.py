@@ -130,14 +130,15 @@ def main():
                 i += 1
 
         mark()
-        api.histogram(batch, binn, out=hist, stream=stream)
+        api.histogram(batch, binn, out=hist, tune="auto", stream=stream)
         mark()
         for j, q in enumerate(QS):
             api.prefix(hist, q, P=PQ[j][0], Q=PQ[j][1], stream=stream)
             mark()
-            api.threshold_search(PQ[j][0], PQ[j][1], K, q, api.SEARCH_FP32_TIECHECK, ws=ws, out=res[j], stream=stream)
+            api.threshold_search(PQ[j][0], PQ[j][1], K, q, api.SEARCH_FP32_TIECHECK, ws=ws, out=res[j], tune="auto",
+                                 stream=stream)
             mark()
-            api.label(batch, binn, res[j][0], K, outs=outs[j], out_ptrs=optrs[j], stream=stream)
+            api.label(batch, binn, res[j][0], K, outs=outs[j], out_ptrs=optrs[j], tune="auto", stream=stream)
             mark()
 
     for _ in range(args.warmup):

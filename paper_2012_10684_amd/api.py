@@ -43,7 +43,7 @@ class _Batch(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "hist_block", "hist_replicas", "hist_wg_per_cu", "label_block", "label_wg_per_cu",
-        "search_cols", "search_rows", "min_chunk")]
+        "search_cols", "search_rows", "min_chunk", "search_path", "search_block")]
 
     @classmethod
     def from_dict(cls, d: Optional[dict]):
@@ -100,9 +100,18 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _tune(tune):
+def _tune(tune, key_fn=None):
+    """None: library defaults; "auto": the autotuner's cached shapes for this
+    size class (defaults if none); a dict or Tuning: those shapes."""
     if tune is None:
         return None
+    if isinstance(tune, str):
+        if tune != "auto":
+            raise ValueError(f"unknown tuning {tune!r}")
+        from . import autotune
+        tune = autotune.lookup(key_fn(autotune)) if key_fn else None
+        if not tune:
+            return None
     if isinstance(tune, dict):
         tune = Tuning.from_dict(tune)
     return ctypes.byref(tune)
@@ -152,7 +161,8 @@ def histogram(batch: Batch, bin: Binning, out: Optional[torch.Tensor] = None, tu
     if out is None:
         dev = batch.ptrs.device
         out = torch.empty((batch.nseg, bin.nbins), dtype=torch.int32, device=dev)
-    _check(_lib.ts_histogram(batch._c, bin, _ptr(out), _tune(tune), _stream(stream)))
+    t = _tune(tune, lambda a: a.key_histogram(batch.nseg, batch.total, bin.nbins))
+    _check(_lib.ts_histogram(batch._c, bin, _ptr(out), t, _stream(stream)))
     return out
 
 
@@ -182,8 +192,9 @@ def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q: float, mode: i
         status = torch.empty(nseg, dtype=torch.int32, device=P.device)
     else:
         thr, obj, status = out
+    t = _tune(tune, lambda a: a.key_search(nseg, L, k, mode))
     _check(_lib.ts_threshold_search(_ptr(P), _ptr(Q), nseg, L, int(k), float(q), int(mode), _ptr(ws),
-                                    ws.numel(), _ptr(thr), _ptr(obj), _ptr(status), _tune(tune), _stream(stream)))
+                                    ws.numel(), _ptr(thr), _ptr(obj), _ptr(status), t, _stream(stream)))
     return thr, obj, status
 
 
@@ -194,7 +205,8 @@ def label(batch: Batch, bin: Binning, thr: torch.Tensor, k: int, outs: Optional[
         outs = [torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes]
     if out_ptrs is None:
         out_ptrs = torch.tensor([o.data_ptr() for o in outs] or [0], dtype=torch.int64).to(dev)
-    _check(_lib.ts_label(batch._c, bin, _ptr(thr), int(k), _ptr(out_ptrs), _tune(tune), _stream(stream)))
+    t = _tune(tune, lambda a: a.key_label(batch.nseg, batch.total, k))
+    _check(_lib.ts_label(batch._c, bin, _ptr(thr), int(k), _ptr(out_ptrs), t, _stream(stream)))
     return outs
 
 

@@ -65,8 +65,10 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
     o->label_block = t->label_block ? t->label_block : 256;
     o->label_wg_per_cu = t->label_wg_per_cu ? t->label_wg_per_cu : 8;
     o->search_cols = t->search_cols ? t->search_cols : 2;
-    o->search_rows = t->search_rows ? t->search_rows : 64;
+    o->search_rows = t->search_rows ? t->search_rows : 32;
     o->min_chunk = t->min_chunk ? t->min_chunk : 8192;
+    o->search_path = t->search_path;
+    o->search_block = t->search_block ? t->search_block : 512;
     if (o->hist_block < 64 || o->hist_block > 1024 || o->hist_block % 64)
         return fail(TS_ERR_INVALID_ARG, "tuning: hist_block must be a multiple of 64 in [64, 1024]");
     if (!pow2(o->hist_replicas) || o->hist_replicas > 32)
@@ -81,10 +83,14 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
         return fail(TS_ERR_INVALID_ARG, "tuning: label_wg_per_cu must be in [1, 32]");
     if (o->search_cols != 1 && o->search_cols != 2 && o->search_cols != 4)
         return fail(TS_ERR_INVALID_ARG, "tuning: search_cols must be 1, 2 or 4");
-    if (o->search_rows < 64 || o->search_rows > 4096)
-        return fail(TS_ERR_INVALID_ARG, "tuning: search_rows must be in [64, 4096]");
+    if (o->search_rows < 32 || o->search_rows > 4096 || o->search_rows % 4)
+        return fail(TS_ERR_INVALID_ARG, "tuning: search_rows must be a multiple of 4 in [32, 4096]");
     if (o->min_chunk < 512)
         return fail(TS_ERR_INVALID_ARG, "tuning: min_chunk must be >= 512");
+    if (o->search_path < 0 || o->search_path > 2)
+        return fail(TS_ERR_INVALID_ARG, "tuning: search_path must be 0, 1 or 2");
+    if (o->search_block != 256 && o->search_block != 512 && o->search_block != 1024)
+        return fail(TS_ERR_INVALID_ARG, "tuning: search_block must be 256, 512 or 1024");
     return TS_OK;
 }
 

@@ -25,6 +25,7 @@ struct Tune {
     int label_block, label_wg_per_cu;
     int search_cols, search_rows;
     int min_chunk;
+    int search_path, search_block;
 };
 ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *out);
 
@@ -40,18 +41,48 @@ struct BinMap {
 };
 ts_status make_binmap(const ts_binning &bin, BinMap *bm);
 
-__device__ __forceinline__ int bin_of(int v, const BinMap &bm)
+// MAP selects the multiply at compile time: bit 0 = wide, bit 1 = narrow
+// window (values above hi need the explicit select).
+template <int MAP>
+__device__ __forceinline__ int bin_of_t(int v, const BinMap &bm)
 {
     int vc = min(max(v, bm.lo), bm.hi);
     uint32_t d = (uint32_t)(vc - bm.lo);
     uint32_t b;
-    if (bm.wide)
+    if (MAP & 1)
         b = __umulhi(d * (uint32_t)bm.L, bm.mul) >> bm.shift;
     else
         b = __umul24(d, bm.mul) >> bm.shift;
-    if (bm.narrow && v > bm.hi)
+    if ((MAP & 2) && v > bm.hi)
         b = (uint32_t)(bm.L - 1);
     return (int)b;
+}
+
+__device__ __forceinline__ int bin_of(int v, const BinMap &bm)
+{
+    switch ((bm.wide ? 1 : 0) | (bm.narrow ? 2 : 0)) {
+    case 0: return bin_of_t<0>(v, bm);
+    case 1: return bin_of_t<1>(v, bm);
+    case 2: return bin_of_t<2>(v, bm);
+    default: return bin_of_t<3>(v, bm);
+    }
+}
+
+inline int map_kind(const BinMap &bm) { return (bm.wide ? 1 : 0) | (bm.narrow ? 2 : 0); }
+
+// Pointers read from a device table are generic; the voxel and label arrays
+// always live in global memory, and saying so lets the compiler use global
+// (not flat) loads and stores, which do not wait on LDS traffic.
+#define TS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const TS_GLOBAL T *gp(const T *p)
+{
+    return (const TS_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ TS_GLOBAL T *gpw(T *p)
+{
+    return (TS_GLOBAL T *)p;
 }
 
 // ---------------------------------------------------------------- batch walk

@@ -32,7 +32,7 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n)
         p[i] = 0u;
 }
 
-template <int R>
+template <int R, int MAP>
 __device__ __forceinline__ void count8(uint32_t *lds, const v4i &w, const BinMap &bm, uint32_t rep)
 {
     const uint32_t u[4] = {(uint32_t)w.x, (uint32_t)w.y, (uint32_t)w.z, (uint32_t)w.w};
@@ -40,8 +40,8 @@ __device__ __forceinline__ void count8(uint32_t *lds, const v4i &w, const BinMap
     for (int j = 0; j < 4; ++j) {
         int v0 = (int)(int16_t)(u[j] & 0xffffu);
         int v1 = (int)(int16_t)(u[j] >> 16);
-        atomicAdd(&lds[bin_of(v0, bm) * R + rep], 1u);
-        atomicAdd(&lds[bin_of(v1, bm) * R + rep], 1u);
+        atomicAdd(&lds[bin_of_t<MAP>(v0, bm) * R + rep], 1u);
+        atomicAdd(&lds[bin_of_t<MAP>(v1, bm) * R + rep], 1u);
     }
 }
 
@@ -62,7 +62,7 @@ __device__ void flush(uint32_t *lds, int L, uint32_t *__restrict__ hist_row)
     __syncthreads();
 }
 
-template <int R>
+template <int R, int MAP>
 __global__ void __launch_bounds__(1024) k_histogram(const int16_t *const *__restrict__ vox,
                                                     const int64_t *__restrict__ offs, int nseg, int64_t total,
                                                     int64_t chunk, BinMap bm, uint32_t *__restrict__ hist)
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(1024) k_histogram(const int16_t *const *__rest
             ++s;
         const int64_t s0 = offs[s];
         const int64_t s1 = min(offs[s + 1], end);
-        const int16_t *base = vox[s];
+        const TS_GLOBAL int16_t *base = gp(vox[s]);
         int64_t i0 = pos - s0, i1 = s1 - s0; // local element range [i0, i1)
         // elements before the first 16-byte aligned one
         const uintptr_t a0 = (uintptr_t)(base + i0);
@@ -94,44 +94,75 @@ __global__ void __launch_bounds__(1024) k_histogram(const int16_t *const *__rest
         if (head > i1 - i0)
             head = i1 - i0;
         if (threadIdx.x < head)
-            atomicAdd(&lds[bin_of(base[i0 + threadIdx.x], bm) * R + rep], 1u);
-        const int64_t vb = i0 + head;            // first aligned element
-        const int64_t nvec = (i1 - vb) >> 3;     // whole 8-element vectors
-        const v4i *vp = reinterpret_cast<const v4i *>(base + vb);
+            atomicAdd(&lds[bin_of_t<MAP>(base[i0 + threadIdx.x], bm) * R + rep], 1u);
+        const int64_t vb = i0 + head;        // first aligned element
+        const int64_t nvec = (i1 - vb) >> 3; // whole 8-element vectors
+        const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(base + vb);
+        const int64_t st = blockDim.x;
         int64_t j = threadIdx.x;
-        const int64_t stepv = blockDim.x;
-        for (; j + 3 * stepv < nvec; j += 4 * stepv) {
-            v4i w0 = __builtin_nontemporal_load(vp + j);
-            v4i w1 = __builtin_nontemporal_load(vp + j + stepv);
-            v4i w2 = __builtin_nontemporal_load(vp + j + 2 * stepv);
-            v4i w3 = __builtin_nontemporal_load(vp + j + 3 * stepv);
-            count8<R>(lds, w0, bm, rep);
-            count8<R>(lds, w1, bm, rep);
-            count8<R>(lds, w2, bm, rep);
-            count8<R>(lds, w3, bm, rep);
+        // groups of four vectors per thread; the next group is in flight
+        // while the current one is counted
+        bool have = j + 3 * st < nvec;
+        v4i a0v = {0, 0, 0, 0}, a1v = a0v, a2v = a0v, a3v = a0v;
+        if (have) {
+            a0v = __builtin_nontemporal_load(vp + j);
+            a1v = __builtin_nontemporal_load(vp + j + st);
+            a2v = __builtin_nontemporal_load(vp + j + 2 * st);
+            a3v = __builtin_nontemporal_load(vp + j + 3 * st);
         }
-        for (; j < nvec; j += stepv) {
-            v4i w = __builtin_nontemporal_load(vp + j);
-            count8<R>(lds, w, bm, rep);
+        while (have) {
+            const int64_t jn = j + 4 * st;
+            const bool nxt = jn + 3 * st < nvec;
+            v4i b0 = a0v, b1 = a1v, b2 = a2v, b3 = a3v;
+            if (nxt) {
+                b0 = __builtin_nontemporal_load(vp + jn);
+                b1 = __builtin_nontemporal_load(vp + jn + st);
+                b2 = __builtin_nontemporal_load(vp + jn + 2 * st);
+                b3 = __builtin_nontemporal_load(vp + jn + 3 * st);
+            }
+            count8<R, MAP>(lds, a0v, bm, rep);
+            count8<R, MAP>(lds, a1v, bm, rep);
+            count8<R, MAP>(lds, a2v, bm, rep);
+            count8<R, MAP>(lds, a3v, bm, rep);
+            a0v = b0;
+            a1v = b1;
+            a2v = b2;
+            a3v = b3;
+            j = jn;
+            have = nxt;
         }
+        for (; j < nvec; j += st)
+            count8<R, MAP>(lds, __builtin_nontemporal_load(vp + j), bm, rep);
         const int64_t tb = vb + (nvec << 3); // tail elements [tb, i1)
         if (threadIdx.x < i1 - tb)
-            atomicAdd(&lds[bin_of(base[tb + threadIdx.x], bm) * R + rep], 1u);
+            atomicAdd(&lds[bin_of_t<MAP>(base[tb + threadIdx.x], bm) * R + rep], 1u);
         pos = s0 + i1;
         flush<R>(lds, L, hist + (int64_t)s * L);
         ++s;
     }
 }
 
+template <int R, int MAP>
+static void launch_rm(int grid, int block, size_t lds, hipStream_t st, const ts_batch &b, int64_t chunk,
+                      const BinMap &bm, uint32_t *hist)
+{
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_histogram<R, MAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipLaunchKernelGGL((k_histogram<R, MAP>), dim3(grid), dim3(block), lds, st, b.vox, b.offs, b.nseg, b.total,
+                       chunk, bm, hist);
+}
+
 template <int R>
 static void launch_r(int grid, int block, size_t lds, hipStream_t st, const ts_batch &b, int64_t chunk,
                      const BinMap &bm, uint32_t *hist)
 {
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_histogram<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    hipLaunchKernelGGL(k_histogram<R>, dim3(grid), dim3(block), lds, st, b.vox, b.offs, b.nseg, b.total, chunk,
-                       bm, hist);
+    switch (map_kind(bm)) {
+    case 0: launch_rm<R, 0>(grid, block, lds, st, b, chunk, bm, hist); break;
+    case 1: launch_rm<R, 1>(grid, block, lds, st, b, chunk, bm, hist); break;
+    case 2: launch_rm<R, 2>(grid, block, lds, st, b, chunk, bm, hist); break;
+    default: launch_rm<R, 3>(grid, block, lds, st, b, chunk, bm, hist); break;
+    }
 }
 
 ts_status launch_histogram(const ts_batch &b, const BinMap &bm, uint32_t *hist, const Tune &t, hipStream_t st)

@@ -85,8 +85,8 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
             ++s;
         const int64_t s0 = offs[s];
         const int64_t s1 = min(offs[s + 1], end);
-        const int16_t *src = vox[s];
-        uint8_t *dst = out[s];
+        const TS_GLOBAL int16_t *src = gp(vox[s]);
+        TS_GLOBAL uint8_t *dst = gpw(out[s]);
         const Cuts cuts = make_cuts(thr + (int64_t)s * k, k, bm);
         const int64_t i0 = pos - s0, i1 = s1 - s0;
         const uintptr_t ain = (uintptr_t)(src + i0), aout = (uintptr_t)(dst + i0);
@@ -99,17 +99,34 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
                 dst[i0 + threadIdx.x] = (uint8_t)lab1(src[i0 + threadIdx.x], cuts);
             const int64_t vb = i0 + head;
             const int64_t nvec = (i1 - vb) >> 3;
-            const v4i *vp = reinterpret_cast<const v4i *>(src + vb);
-            v2u *op = reinterpret_cast<v2u *>(dst + vb);
-            const int64_t stepv = blockDim.x;
+            const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(src + vb);
+            TS_GLOBAL v2u *op = reinterpret_cast<TS_GLOBAL v2u *>(dst + vb);
+            const int64_t st = blockDim.x;
             int64_t j = threadIdx.x;
-            for (; j + stepv < nvec; j += 2 * stepv) {
-                v4i w0 = __builtin_nontemporal_load(vp + j);
-                v4i w1 = __builtin_nontemporal_load(vp + j + stepv);
-                __builtin_nontemporal_store(lab8(w0, cuts), op + j);
-                __builtin_nontemporal_store(lab8(w1, cuts), op + j + stepv);
+            // pairs of vectors per thread; the next pair is in flight while
+            // the current one is labelled and stored
+            bool have = j + st < nvec;
+            v4i a0 = {0, 0, 0, 0}, a1 = a0;
+            if (have) {
+                a0 = __builtin_nontemporal_load(vp + j);
+                a1 = __builtin_nontemporal_load(vp + j + st);
             }
-            for (; j < nvec; j += stepv)
+            while (have) {
+                const int64_t jn = j + 2 * st;
+                const bool nxt = jn + st < nvec;
+                v4i b0 = a0, b1 = a1;
+                if (nxt) {
+                    b0 = __builtin_nontemporal_load(vp + jn);
+                    b1 = __builtin_nontemporal_load(vp + jn + st);
+                }
+                __builtin_nontemporal_store(lab8(a0, cuts), op + j);
+                __builtin_nontemporal_store(lab8(a1, cuts), op + j + st);
+                a0 = b0;
+                a1 = b1;
+                j = jn;
+                have = nxt;
+            }
+            for (; j < nvec; j += st)
                 __builtin_nontemporal_store(lab8(__builtin_nontemporal_load(vp + j), cuts), op + j);
             const int64_t tb = vb + (nvec << 3);
             if (threadIdx.x < i1 - tb)

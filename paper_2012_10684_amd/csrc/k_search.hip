@@ -135,7 +135,7 @@ size_t search_workspace_bytes(int nseg, int L, int k, int mode, int)
     // the largest plan over every tuning the library accepts
     size_t m = 0;
     for (int cols : {1, 2, 4})
-        m = std::max(m, make_plan(nseg, L, k, mode, cols, 64).bytes);
+        m = std::max(m, make_plan(nseg, L, k, mode, cols, 32).bytes);
     return m;
 }
 
@@ -214,61 +214,97 @@ struct Args {
 
 // ---------------------------------------------------------------- setup
 
-__global__ void __launch_bounds__(256) k_setup(Args a)
+// Smallest non-zero bin mass of one problem (block-wide minimum; every
+// thread returns the result).  red must hold blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_pmin(const double *P, int L, double *red)
 {
-    const int s = blockIdx.x;
-    const double *P = a.P + (int64_t)s * a.L;
-    const double *Q = a.Q + (int64_t)s * a.L;
-    const int L = a.L;
-    __shared__ double red[256];
-
-    // smallest non-zero bin mass (for the magnitude bounds of delta)
     double pmin = 1.0;
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const double d = P[t] - (t ? P[t - 1] : 0.0);
         if (d > 0.0)
             pmin = fmin(pmin, d);
     }
-    red[threadIdx.x] = pmin;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        pmin = fmin(pmin, __shfl_xor(pmin, o, WAVE));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = pmin;
     __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-        if (threadIdx.x < o)
-            red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
-        __syncthreads();
-    }
     pmin = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+        pmin = fmin(pmin, red[i]);
+    __syncthreads();
+    return pmin;
+}
 
+// Bound on |key32 - key64 / ln 2| over every tuple of one problem, where
+// key32 is the FP32 key and key64 the FP64 value from the same prefix sums.
+// Per class term: the two casts to FP32 (2^-24 relative each), the error of
+// v_log_f32 on both logs, q rounded to FP32, the fma rounding; then k
+// additions of terms bounded by gmax.  Magnitudes: |log2 w| <= |log2 pmin|,
+// |log2 Q_j| <= max(|log2 Q_tot|, |log2 pmin^q|) (+20 of margin for the
+// rounding of small prefix differences).  Doubled for safety.  Infinity
+// when the FP32 range is exceeded (every tuple is then re-checked in FP64).
+__device__ __forceinline__ float problem_delta(const Args &a, double pmin, double qtot)
+{
+    if (a.mode == TS_SEARCH_FP32_ONLY)
+        return 0.0f;
+    const double u = 0x1p-24;
+    const double q = a.q;
+    const double qmin = pow(pmin, q);
+    double delta;
+    if (!(qtot > 0.0) || !(qmin > 1e-35) || qtot > 1e35) {
+        delta = INFINITY;
+    } else {
+        const double Ux = fmax(fabs(log2(qtot)), fabs(log2(qmin)) + 20.0);
+        const double Vy = fabs(log2(pmin));
+        const double gm = (double)a.gmax;
+        const double ec = (1.0 + q) * u * 1.5                                            // casts to FP32
+                          + LOG2_ERR_UNITS * u * (fmax(1.0, Ux) + q * fmax(1.0, Vy))     // v_log_f32
+                          + fabs((double)(-a.sgn * a.nq) - q) * Vy                       // q rounded to FP32
+                          + u * (gm + 1.0);                                              // fma + clamp
+        const int kk = a.k;
+        delta = 2.0 * ((kk + 1) * ec + kk * (kk + 1) * u * (gm + 1.0)) + 1e-9 * (kk + 1) * (gm + 1.0);
+    }
+    float d = (float)delta;
+    if ((double)d < delta)
+        d = nextafterf(d, INFINITY);
+    return d;
+}
+
+// FP32 head(t) = g(-1, t) and tail(t) = g(t, L-1) for t in [0, Lp); entries
+// past L-2 are -inf.
+template <int SGN>
+__device__ __forceinline__ void head_tail32(const Args &a, const double *P, const double *Q, float *hd, float *tl)
+{
+    const int L = a.L;
+    const double pL = P[L - 1], qL = Q[L - 1];
+    for (int t = threadIdx.x; t < a.Lp; t += blockDim.x) {
+        float h = -INFINITY, g = -INFINITY;
+        if (t <= L - 2) {
+            h = cls32<SGN>(P[t], Q[t], a.nq, a.gmax);
+            g = cls32<SGN>(pL - P[t], qL - Q[t], a.nq, a.gmax);
+        }
+        hd[t] = h;
+        tl[t] = g;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_setup(Args a)
+{
+    const int s = blockIdx.x;
+    const double *P = a.P + (int64_t)s * a.L;
+    const double *Q = a.Q + (int64_t)s * a.L;
+    const int L = a.L, Lp = a.Lp;
+    __shared__ double red[4];
+    const double pmin = block_pmin(P, L, red);
     if (threadIdx.x == 0) {
         Meta m;
         m.menc = float_to_ordered(-INFINITY);
         m.pad0 = m.pad1 = 0;
-        const double u = 0x1p-24;
-        const double q = a.q;
-        const double qtot = Q[L - 1];
-        const double qmin = pow(pmin, q);
-        double delta;
-        if (a.mode == TS_SEARCH_FP32_ONLY) {
-            delta = 0.0;
-        } else if (!(qtot > 0.0) || !(qmin > 1e-35) || qtot > 1e35) {
-            delta = INFINITY; // FP32 range exceeded: re-check every tuple in FP64
-        } else {
-            const double Ux = fmax(fabs(log2(qtot)), fabs(log2(qmin)) + 20.0);
-            const double Vy = fabs(log2(pmin));
-            const double gm = (double)a.gmax;
-            const double ec = (1.0 + q) * u * 1.5                                  // casts to FP32
-                              + LOG2_ERR_UNITS * u * (fmax(1.0, Ux) + q * fmax(1.0, Vy)) // v_log_f32
-                              + fabs((double)(-a.sgn * a.nq) - q) * Vy             // q rounded to FP32
-                              + u * (gm + 1.0);                                    // fma + clamp
-            const int kk = a.k;
-            delta = 2.0 * ((kk + 1) * ec + kk * (kk + 1) * u * (gm + 1.0)) + 1e-9 * (kk + 1) * (gm + 1.0);
-        }
-        m.delta = (float)delta;
-        if ((double)m.delta < delta)
-            m.delta = nextafterf(m.delta, INFINITY);
+        m.delta = problem_delta(a, pmin, Q[L - 1]);
         a.meta[s] = m;
     }
-
-    const int Lp = a.Lp;
     if (a.mode == TS_SEARCH_FP64) {
         double *hd = (double *)a.head + (int64_t)s * Lp;
         double *tl = (double *)a.tail + (int64_t)s * Lp;
@@ -282,24 +318,10 @@ __global__ void __launch_bounds__(256) k_setup(Args a)
             hd[t] = h;
             tl[t] = g;
         }
+    } else if (a.sgn > 0) {
+        head_tail32<1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp);
     } else {
-        float *hd = (float *)a.head + (int64_t)s * Lp;
-        float *tl = (float *)a.tail + (int64_t)s * Lp;
-        const double pL = P[L - 1], qL = Q[L - 1];
-        for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
-            float h = -INFINITY, g = -INFINITY;
-            if (t <= L - 2) {
-                if (a.sgn > 0) {
-                    h = cls32<1>(P[t], Q[t], a.nq, a.gmax);
-                    g = cls32<1>(pL - P[t], qL - Q[t], a.nq, a.gmax);
-                } else {
-                    h = cls32<-1>(P[t], Q[t], a.nq, a.gmax);
-                    g = cls32<-1>(pL - P[t], qL - Q[t], a.nq, a.gmax);
-                }
-            }
-            hd[t] = h;
-            tl[t] = g;
-        }
+        head_tail32<-1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp);
     }
 }
 
@@ -375,147 +397,218 @@ __device__ __forceinline__ Tile tile_of(const Args &a)
     return t;
 }
 
-// FP32 phase 1 / phase 2.  PHASE 1 writes the tile max and the problem max;
-// PHASE 2 keeps the best FP64 candidate at or above the threshold.
+struct Cand {
+    double r, l; // rank, FP64 signed Lambda
+    long long c; // lexicographic code
+};
+
+// Everything a tile body reads for one problem.
+struct TileCtx {
+    const double *P, *Q; // prefix sums of the problem
+    const float *hd, *tr; // head / tail rows (LDS or global)
+    const float *A, *R;   // k = 3 rows of the problem (global)
+    int L, Lp, mode, CW, T1;
+    double q, sgn, hmax;
+    float nq, gmax;
+};
+
+__device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *hd, const float *tr)
+{
+    TileCtx x;
+    x.P = a.P + (int64_t)s * a.L;
+    x.Q = a.Q + (int64_t)s * a.L;
+    x.hd = hd;
+    x.tr = tr;
+    x.A = (const float *)a.A + (int64_t)s * a.L * a.Lp;
+    x.R = (const float *)a.R + (int64_t)s * a.L * a.Lp;
+    x.L = a.L;
+    x.Lp = a.Lp;
+    x.mode = a.mode;
+    x.CW = a.CW;
+    x.T1 = a.T1;
+    x.q = a.q;
+    x.sgn = a.sgn;
+    x.hmax = a.hmax;
+    x.nq = a.nq;
+    x.gmax = a.gmax;
+    return x;
+}
+
+// Phase 1 folds every key into acc; phase 2 evaluates every key >= thr in
+// FP64 and keeps the best (rank, then first tuple).
+template <int PHASE, int K>
+__device__ __forceinline__ void take(const TileCtx &x, float key, float thr, float &acc, Cand &b, int t1, int t2,
+                                     int t3)
+{
+    if (PHASE == 1) {
+        acc = fmaxf(acc, key);
+    } else if (key >= thr) {
+        const int t[3] = {t1, t2, t3};
+        const double lam = lambda64(x.P, x.Q, x.L, K, t, x.q, x.sgn, x.hmax);
+        const double rank = x.mode == TS_SEARCH_FP32_ONLY ? (double)key : lam;
+        const long long code = make_code(K, t);
+        if (better(rank, code, b.r, b.c)) {
+            b.r = rank;
+            b.l = lam;
+            b.c = code;
+        }
+    }
+}
+
+template <int COLS, int PHASE>
+__device__ __forceinline__ void tile_k1(const TileCtx &x, int b, float thr, float &acc, Cand &best)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < COLS; ++v) {
+        const int t = b * x.CW + v * 64 + lane; // t < Lp: entries past L-2 are -inf
+        take<PHASE, 1>(x, x.hd[t] + x.tr[t], thr, acc, best, t, 0, 0);
+    }
+}
+
+// Rows [t1b, t1e) of a k = 2 tile; MASK keeps only t1 < t2.  Four rows are
+// loaded together so the scalar loads and the transcendental latencies of
+// consecutive rows overlap.
+template <int SGN, int COLS, int PHASE, bool MASK>
+__device__ __forceinline__ void rows_k2(const TileCtx &x, int t1b, int t1e, const double (&pc)[COLS],
+                                        const double (&qc)[COLS], const float (&tc)[COLS], const int (&t2v)[COLS],
+                                        float thr, float &acc, Cand &best)
+{
+    int t1 = t1b;
+    for (; t1 + 4 <= t1e; t1 += 4) {
+        double pr[4], qr[4];
+        float hr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pr[u] = x.P[t1 + u];
+            qr[u] = x.Q[t1 + u];
+            hr[u] = x.hd[t1 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int v = 0; v < COLS; ++v) {
+                const float key = (hr[u] + cls32<SGN>(pc[v] - pr[u], qc[v] - qr[u], x.nq, x.gmax)) + tc[v];
+                if (!MASK || t1 + u < t2v[v])
+                    take<PHASE, 2>(x, key, thr, acc, best, t1 + u, t2v[v], 0);
+            }
+        }
+    }
+    for (; t1 < t1e; ++t1) {
+        const double pr = x.P[t1], qr = x.Q[t1];
+        const float hr = x.hd[t1];
+#pragma unroll
+        for (int v = 0; v < COLS; ++v) {
+            const float key = (hr + cls32<SGN>(pc[v] - pr, qc[v] - qr, x.nq, x.gmax)) + tc[v];
+            if (!MASK || t1 < t2v[v])
+                take<PHASE, 2>(x, key, thr, acc, best, t1, t2v[v], 0);
+        }
+    }
+}
+
 template <int SGN, int COLS, int PHASE>
+__device__ __forceinline__ void tile_k2(const TileCtx &x, int b, int c, float thr, float &acc, Cand &best)
+{
+    const int lane = threadIdx.x & 63;
+    const int L = x.L;
+    const int cbase = b * x.CW;
+    const int r0 = c * x.T1;
+    const int r1 = min(r0 + x.T1, min(L - 2, cbase + x.CW - 1));
+    if (r0 >= r1)
+        return;
+    double pc[COLS], qc[COLS];
+    float tc[COLS];
+    int t2v[COLS];
+#pragma unroll
+    for (int v = 0; v < COLS; ++v) {
+        const int t2 = cbase + v * 64 + lane;
+        t2v[v] = t2;
+        const int ti = min(t2, L - 1);
+        pc[v] = x.P[ti];
+        qc[v] = x.Q[ti];
+        tc[v] = x.tr[t2]; // -inf past L-2
+    }
+    const int ra = min(r1, cbase);
+    rows_k2<SGN, COLS, PHASE, false>(x, r0, ra, pc, qc, tc, t2v, thr, acc, best); // every t2 > t1
+    rows_k2<SGN, COLS, PHASE, true>(x, max(r0, cbase), r1, pc, qc, tc, t2v, thr, acc, best);
+}
+
+template <int COLS, int PHASE>
+__device__ __forceinline__ void tile_k3(const TileCtx &x, int b, int c, float thr, float &acc, Cand &best)
+{
+    const int lane = threadIdx.x & 63;
+    const int t2 = x.L - 3 - c; // heaviest rows first
+    const int cbase = b * x.CW;
+    if (!(cbase + x.CW - 1 > t2 && cbase <= x.L - 2))
+        return;
+    const float *Ar = x.A + (int64_t)t2 * x.Lp;
+    const float *Rr = x.R + (int64_t)t2 * x.Lp;
+    float rc[COLS];
+#pragma unroll
+    for (int v = 0; v < COLS; ++v)
+        rc[v] = Rr[cbase + v * 64 + lane]; // -inf where t3 <= t2 or t3 > L-2
+    const int n1 = (t2 + 15) & ~15;        // the A row is -inf from t2 up to Lp
+    for (int t1 = 0; t1 < n1; t1 += 16) {
+        float av[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            av[u] = Ar[t1 + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+#pragma unroll
+            for (int v = 0; v < COLS; ++v)
+                take<PHASE, 3>(x, av[u] + rc[v], thr, acc, best, t1 + u, t2, cbase + v * 64 + lane);
+        }
+    }
+}
+
+template <int SGN, int COLS, int PHASE, int K>
+__device__ __forceinline__ void tile_body(const TileCtx &x, int b, int c, float thr, float &acc, Cand &best)
+{
+    if (K == 1)
+        tile_k1<COLS, PHASE>(x, b, thr, acc, best);
+    else if (K == 2)
+        tile_k2<SGN, COLS, PHASE>(x, b, c, thr, acc, best);
+    else
+        tile_k3<COLS, PHASE>(x, b, c, thr, acc, best);
+}
+
+__device__ __forceinline__ float phase2_threshold(float M, float delta)
+{
+    const double t64 = (double)M - 2.0 * (double)delta;
+    float t = (float)t64;
+    if ((double)t > t64)
+        t = nextafterf(t, -INFINITY);
+    return t;
+}
+
+// Multi-launch path, one tile per wavefront.  PHASE 1 writes the tile max and
+// the problem max; PHASE 2 re-checks tiles whose max reaches the threshold.
+template <int SGN, int COLS, int PHASE, int K>
 __global__ void __launch_bounds__(256) k_tiles32(Args a)
 {
     const Tile tl = tile_of(a);
     if (!tl.valid)
         return;
     const int lane = threadIdx.x & 63;
-    const int L = a.L, Lp = a.Lp, k = a.k;
     const int s = tl.s;
     const int64_t tid = (int64_t)s * a.tiles + tl.tile;
-    const double *P = a.P + (int64_t)s * L;
-    const double *Q = a.Q + (int64_t)s * L;
-    const float *hd = (const float *)a.head + (int64_t)s * Lp;
-    const float *tr = (const float *)a.tail + (int64_t)s * Lp;
-
+    const TileCtx x = make_ctx(a, s, (const float *)a.head + (int64_t)s * a.Lp, (const float *)a.tail + (int64_t)s * a.Lp);
     float thr = -INFINITY;
     if (PHASE == 2) {
         const Meta m = a.meta[s];
         const float M = ordered_to_float(m.menc);
-        if (!(a.tmax[tid] > -INFINITY) || M == -INFINITY) {
-            if (lane == 0)
-                a.best[tid] = Best{-INFINITY, -INFINITY, 0x7fffffffffffffffLL, 0};
-            return;
-        }
-        double t64 = (double)M - 2.0 * (double)m.delta;
-        thr = (float)t64;
-        if ((double)thr > t64)
-            thr = nextafterf(thr, -INFINITY);
-        if (a.tmax[tid] < thr) {
+        const float tm = a.tmax[tid];
+        thr = phase2_threshold(M, m.delta);
+        if (!(tm > -INFINITY) || M == -INFINITY || tm < thr) {
             if (lane == 0)
                 a.best[tid] = Best{-INFINITY, -INFINITY, 0x7fffffffffffffffLL, 0};
             return;
         }
     }
     float acc = -INFINITY;
-    double br = -INFINITY, bl = -INFINITY;
-    long long bc = 0x7fffffffffffffffLL;
-
-    auto candidate = [&](float key, int t1, int t2, int t3) {
-        int t[3] = {t1, t2, t3};
-        int tt[3];
-        int kk = 0;
-        for (int j = 0; j < 3; ++j)
-            if (t[j] >= 0)
-                tt[kk++] = t[j];
-        const double lam = lambda64(P, Q, L, k, tt, a.q, a.sgn, a.hmax);
-        const double rank = a.mode == TS_SEARCH_FP32_ONLY ? (double)key : lam;
-        const long long code = make_code(k, tt);
-        if (better(rank, code, br, bc)) {
-            br = rank;
-            bl = lam;
-            bc = code;
-        }
-    };
-
-    if (k == 1) {
-#pragma unroll
-        for (int v = 0; v < COLS; ++v) {
-            const int t = tl.b * a.CW + v * 64 + lane;
-            const float key = hd[t] + tr[t]; // t < Lp: entries past L-2 are -inf
-            if (PHASE == 1)
-                acc = fmaxf(acc, key);
-            else if (key >= thr)
-                candidate(key, t, -1, -1);
-        }
-    } else if (k == 2) {
-        const int cbase = tl.b * a.CW;
-        const int r0 = tl.c * a.T1;
-        const int r1 = min(r0 + a.T1, min(L - 2, cbase + a.CW - 1));
-        double pc[COLS], qc[COLS];
-        float tc[COLS];
-        int t2v[COLS];
-#pragma unroll
-        for (int v = 0; v < COLS; ++v) {
-            const int t2 = cbase + v * 64 + lane;
-            t2v[v] = t2;
-            const int ti = min(t2, L - 1);
-            pc[v] = P[ti];
-            qc[v] = Q[ti];
-            tc[v] = tr[t2];
-        }
-        const int ra = min(r1, cbase);
-        for (int t1 = r0; t1 < ra; ++t1) { // all columns lie above t1
-            const double pr = P[t1], qr = Q[t1];
-            const float hr = hd[t1];
-#pragma unroll
-            for (int v = 0; v < COLS; ++v) {
-                const float key = (hr + cls32<SGN>(pc[v] - pr, qc[v] - qr, a.nq, a.gmax)) + tc[v];
-                if (PHASE == 1)
-                    acc = fmaxf(acc, key);
-                else if (key >= thr)
-                    candidate(key, t1, t2v[v], -1);
-            }
-        }
-        for (int t1 = max(r0, cbase); t1 < r1; ++t1) { // diagonal block: need t1 < t2
-            const double pr = P[t1], qr = Q[t1];
-            const float hr = hd[t1];
-#pragma unroll
-            for (int v = 0; v < COLS; ++v) {
-                const float key = (hr + cls32<SGN>(pc[v] - pr, qc[v] - qr, a.nq, a.gmax)) + tc[v];
-                if (t1 < t2v[v]) {
-                    if (PHASE == 1)
-                        acc = fmaxf(acc, key);
-                    else if (key >= thr)
-                        candidate(key, t1, t2v[v], -1);
-                }
-            }
-        }
-    } else {
-        const int t2 = L - 3 - tl.c; // heaviest rows first
-        const int cbase = tl.b * a.CW;
-        if (cbase + a.CW - 1 > t2 && cbase <= L - 2) {
-            const float *Ar = (const float *)a.A + ((int64_t)s * L + t2) * Lp;
-            const float *Rr = (const float *)a.R + ((int64_t)s * L + t2) * Lp;
-            float rc[COLS];
-#pragma unroll
-            for (int v = 0; v < COLS; ++v)
-                rc[v] = Rr[cbase + v * 64 + lane];
-            const int n1 = (t2 + 15) & ~15; // A row is -inf from t2 up to Lp
-            for (int t1 = 0; t1 < n1; t1 += 16) {
-                float av[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    av[u] = Ar[t1 + u];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-#pragma unroll
-                    for (int v = 0; v < COLS; ++v) {
-                        const float key = av[u] + rc[v];
-                        if (PHASE == 1)
-                            acc = fmaxf(acc, key);
-                        else if (key >= thr)
-                            candidate(key, t1 + u, t2, cbase + v * 64 + lane);
-                    }
-                }
-            }
-        }
-    }
-
+    Cand best = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL};
+    tile_body<SGN, COLS, PHASE, K>(x, tl.b, tl.c, thr, acc, best);
     if (PHASE == 1) {
         acc = wave_max(acc);
         if (lane == 0) {
@@ -524,9 +617,101 @@ __global__ void __launch_bounds__(256) k_tiles32(Args a)
                 atomicMax(&a.meta[s].menc, float_to_ordered(acc));
         }
     } else {
-        wave_best(br, bl, bc);
+        wave_best(best.r, best.l, best.c);
         if (lane == 0)
-            a.best[tid] = Best{br, bl, bc, 0};
+            a.best[tid] = Best{best.r, best.l, best.c, 0};
+    }
+}
+
+// Write one problem's result from its best candidate.
+__device__ __forceinline__ void write_result(const Cand &b, int s, const double *P, int L, int k, double q, double sgn,
+                                             int32_t *thr, double *obj, int32_t *status)
+{
+    if (b.r == -INFINITY) {
+        for (int j = 0; j < k; ++j)
+            thr[(int64_t)s * k + j] = -1;
+        obj[s] = NAN;
+        status[s] = P[(int64_t)s * L + L - 1] > 0.0 ? TS_PROBLEM_DEGENERATE : TS_PROBLEM_EMPTY;
+    } else {
+        long long c = b.c;
+        for (int j = k - 1; j >= 0; --j) {
+            thr[(int64_t)s * k + j] = (int32_t)(c & 4095);
+            c >>= 12;
+        }
+        obj[s] = expm1(sgn * b.l) / (1.0 - q);
+        status[s] = TS_PROBLEM_OK;
+    }
+}
+
+// Single-launch path: one workgroup per problem does the setup, phase 1,
+// phase 2 and the final reduction; head/tail rows and tile maxima stay in LDS.
+constexpr int FUSED_THREADS = 1024; // upper bound; the launch picks 256, 512 or 1024
+constexpr int FUSED_MAX_L = 4096;
+constexpr int FUSED_MAX_TILES = 1024;
+
+template <int SGN, int COLS, int K>
+__global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__restrict__ thr_out,
+                                                         double *__restrict__ obj, int32_t *__restrict__ status)
+{
+    __shared__ float hd[FUSED_MAX_L], tr[FUSED_MAX_L];
+    __shared__ float tmax[FUSED_MAX_TILES];
+    __shared__ double red[FUSED_THREADS / 64];
+    __shared__ float wmax[FUSED_THREADS / 64];
+    __shared__ double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
+    __shared__ long long wc[FUSED_THREADS / 64];
+    __shared__ float sdelta;
+    const int s = blockIdx.x;
+    const double *P = a.P + (int64_t)s * a.L;
+    const double *Q = a.Q + (int64_t)s * a.L;
+    const double pmin = block_pmin(P, a.L, red);
+    head_tail32<SGN>(a, P, Q, hd, tr);
+    if (threadIdx.x == 0)
+        sdelta = problem_delta(a, pmin, Q[a.L - 1]);
+    __syncthreads();
+    const TileCtx x = make_ctx(a, s, hd, tr);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nw = blockDim.x >> 6;
+    Cand best = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL};
+    float wm = -INFINITY;
+    for (int tile = w; tile < a.tiles; tile += nw) {
+        float acc = -INFINITY;
+        tile_body<SGN, COLS, 1, K>(x, tile % a.NB, tile / a.NB, 0.0f, acc, best);
+        acc = wave_max(acc);
+        if (lane == 0)
+            tmax[tile] = acc;
+        wm = fmaxf(wm, acc);
+    }
+    if (lane == 0)
+        wmax[w] = wm;
+    __syncthreads();
+    float M = -INFINITY;
+    for (int i = 0; i < nw; ++i)
+        M = fmaxf(M, wmax[i]);
+    if (M > -INFINITY) {
+        const float thr = phase2_threshold(M, sdelta);
+        for (int tile = w; tile < a.tiles; tile += nw) {
+            if (tmax[tile] >= thr) {
+                float acc = -INFINITY;
+                tile_body<SGN, COLS, 2, K>(x, tile % a.NB, tile / a.NB, thr, acc, best);
+            }
+        }
+    }
+    wave_best(best.r, best.l, best.c);
+    if (lane == 0) {
+        wr[w] = best.r;
+        wl[w] = best.l;
+        wc[w] = best.c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < nw; ++i)
+            if (better(wr[i], wc[i], best.r, best.c)) {
+                best.r = wr[i];
+                best.l = wl[i];
+                best.c = wc[i];
+            }
+        write_result(best, s, a.P, a.L, K, a.q, a.sgn, thr_out, obj, status);
     }
 }
 
@@ -636,19 +821,7 @@ __global__ void __launch_bounds__(256) k_final(const Best *__restrict__ best, in
                 bl = sl[i];
                 bc = sc[i];
             }
-        if (br == -INFINITY) {
-            for (int j = 0; j < k; ++j)
-                thr[(int64_t)s * k + j] = -1;
-            obj[s] = NAN;
-            status[s] = P[(int64_t)s * L + L - 1] > 0.0 ? TS_PROBLEM_DEGENERATE : TS_PROBLEM_EMPTY;
-        } else {
-            for (int j = k - 1; j >= 0; --j) {
-                thr[(int64_t)s * k + j] = (int32_t)(bc & 4095);
-                bc >>= 12;
-            }
-            obj[s] = expm1(sgn * bl) / (1.0 - q);
-            status[s] = TS_PROBLEM_OK;
-        }
+        write_result(Cand{br, bl, bc}, s, P, L, k, q, sgn, thr, obj, status);
     }
 }
 
@@ -728,22 +901,42 @@ __global__ void __launch_bounds__(256) k_plain(const double *__restrict__ P, con
 
 // ---------------------------------------------------------------- dispatch
 
-template <int SGN>
-static void launch_tiles32(int cols, int phase, dim3 g, hipStream_t st, const Args &a)
+template <int SGN, int COLS, int K>
+static void launch_phases(dim3 g, hipStream_t st, const Args &a)
 {
-#define TS_TILES(C)                                                                                                 \
-    if (phase == 1)                                                                                                 \
-        hipLaunchKernelGGL((k_tiles32<SGN, C, 1>), g, dim3(256), 0, st, a);                                         \
-    else                                                                                                            \
-        hipLaunchKernelGGL((k_tiles32<SGN, C, 2>), g, dim3(256), 0, st, a);
-    if (cols == 1) {
-        TS_TILES(1)
-    } else if (cols == 2) {
-        TS_TILES(2)
-    } else {
-        TS_TILES(4)
+    hipLaunchKernelGGL((k_tiles32<SGN, COLS, 1, K>), g, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_tiles32<SGN, COLS, 2, K>), g, dim3(256), 0, st, a);
+}
+
+template <int SGN, int COLS>
+static void launch_fp32(int fused_block, int k, dim3 g, int nseg, hipStream_t st, const Args &a, int32_t *thr,
+                        double *obj, int32_t *status)
+{
+    if (fused_block) {
+        if (k == 1)
+            hipLaunchKernelGGL((k_fused<SGN, COLS, 1>), dim3(nseg), dim3(fused_block), 0, st, a, thr, obj, status);
+        else
+            hipLaunchKernelGGL((k_fused<SGN, COLS, 2>), dim3(nseg), dim3(fused_block), 0, st, a, thr, obj, status);
+        return;
     }
-#undef TS_TILES
+    if (k == 1)
+        launch_phases<SGN, COLS, 1>(g, st, a);
+    else if (k == 2)
+        launch_phases<SGN, COLS, 2>(g, st, a);
+    else
+        launch_phases<SGN, COLS, 3>(g, st, a);
+}
+
+template <int SGN>
+static void launch_fp32_cols(int cols, int fused, int k, dim3 g, int nseg, hipStream_t st, const Args &a,
+                             int32_t *thr, double *obj, int32_t *status)
+{
+    if (cols == 1)
+        launch_fp32<SGN, 1>(fused, k, g, nseg, st, a, thr, obj, status);
+    else if (cols == 2)
+        launch_fp32<SGN, 2>(fused, k, g, nseg, st, a, thr, obj, status);
+    else
+        launch_fp32<SGN, 4>(fused, k, g, nseg, st, a, thr, obj, status);
 }
 
 ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, double q, int mode, void *ws,
@@ -799,18 +992,29 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
         return check_launch("ts_threshold_search (plain)");
     }
 
-    hipLaunchKernelGGL(k_setup, dim3(nseg), dim3(256), 0, st, a);
-    if (k == 3) {
-        dim3 g((unsigned)((int64_t)(L - 3) * nseg));
-        if (mode == TS_SEARCH_FP64)
-            hipLaunchKernelGGL(k_pairs64, g, dim3(256), 0, st, a);
-        else if (a.sgn > 0)
-            hipLaunchKernelGGL(k_pairs32<1>, g, dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL(k_pairs32<-1>, g, dim3(256), 0, st, a);
-    }
+    const bool fp32 = mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY;
+    // one workgroup per problem when that fills the chip or the problem is small
+    const bool can_fuse = fp32 && p.tiles <= FUSED_MAX_TILES && p.Lp <= FUSED_MAX_L && (k == 1 || (k == 2 && L <= 1024));
+    const bool fused = can_fuse && (t.search_path == 1 || (t.search_path == 0 && (k == 1 || nseg >= 128)));
     const int64_t waves = (int64_t)nseg * p.tiles;
     dim3 g((unsigned)((waves + 3) / 4));
+    if (fused) {
+        if (a.sgn > 0)
+            launch_fp32_cols<1>(t.search_cols, t.search_block, k, g, nseg, st, a, thr, obj, status);
+        else
+            launch_fp32_cols<-1>(t.search_cols, t.search_block, k, g, nseg, st, a, thr, obj, status);
+        return check_launch("ts_threshold_search");
+    }
+    hipLaunchKernelGGL(k_setup, dim3(nseg), dim3(256), 0, st, a);
+    if (k == 3) {
+        dim3 gp((unsigned)((int64_t)(L - 3) * nseg));
+        if (mode == TS_SEARCH_FP64)
+            hipLaunchKernelGGL(k_pairs64, gp, dim3(256), 0, st, a);
+        else if (a.sgn > 0)
+            hipLaunchKernelGGL(k_pairs32<1>, gp, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_pairs32<-1>, gp, dim3(256), 0, st, a);
+    }
     if (mode == TS_SEARCH_FP64) {
         if (t.search_cols == 1)
             hipLaunchKernelGGL(k_tiles64<1>, g, dim3(256), 0, st, a);
@@ -818,13 +1022,10 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
             hipLaunchKernelGGL(k_tiles64<2>, g, dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL(k_tiles64<4>, g, dim3(256), 0, st, a);
+    } else if (a.sgn > 0) {
+        launch_fp32_cols<1>(t.search_cols, 0, k, g, nseg, st, a, thr, obj, status);
     } else {
-        for (int phase = 1; phase <= 2; ++phase) {
-            if (a.sgn > 0)
-                launch_tiles32<1>(t.search_cols, phase, g, st, a);
-            else
-                launch_tiles32<-1>(t.search_cols, phase, g, st, a);
-        }
+        launch_fp32_cols<-1>(t.search_cols, 0, k, g, nseg, st, a, thr, obj, status);
     }
     hipLaunchKernelGGL(k_final, dim3(nseg), dim3(256), 0, st, a.best, p.tiles, P, L, k, q, a.sgn, thr, obj, status, 0);
     return check_launch("ts_threshold_search");

@@ -104,7 +104,7 @@ def test_argument_errors(lib, case, expect):
     elif case == "hist_null":
         st = lib.ts_histogram(Batch(None, FAKE, 1, 10), ok_bin, FAKE, None, sx)
     elif case == "hist_bad_tune":
-        tune = (ctypes.c_int32 * 8)(100, 0, 0, 0, 0, 0, 0, 0)  # block not a multiple of 64
+        tune = (ctypes.c_int32 * 10)(100, 0, 0, 0, 0, 0, 0, 0, 0, 0)  # block not a multiple of 64
         st = lib.ts_histogram(b1, ok_bin, FAKE, ctypes.cast(tune, T), sx)
     elif case == "prefix_q0":
         st = lib.ts_prefix(FAKE, 1, 256, 0.0, FAKE, FAKE, sx)

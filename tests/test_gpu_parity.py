@@ -237,3 +237,27 @@ def test_determinism_and_batch_invariance():
         assert torch.equal(one[0][0], r1[0][z])
         assert torch.equal(one[2][0][0], r1[2][0][z]) and torch.equal(one[2][1][0], r1[2][1][z])
         assert torch.equal(one[3][0], r1[3][z])
+
+
+@pytest.mark.parametrize("q", [0.5, 1.5])
+def test_fused_and_tiled_search_paths_agree(q):
+    """The one-workgroup-per-problem kernel and the one-launch-per-phase
+    kernels, forced through the tuning, give the same bits; so do batches of
+    >= 128 problems (automatic choice: one workgroup per problem) and
+    sub-batches of 5 (automatic choice: one launch per phase)."""
+    rng = np.random.default_rng(77)
+    for k, L in ((1, 300), (2, 300), (2, 1000)):
+        H = _random_hists(rng, 140, L, zero_frac=0.15, hi=3000)
+        big = _search_all(H, k, q, api.SEARCH_FP32_TIECHECK)
+        for path in (1, 2):
+            for tb in ((256, 1024) if path == 1 else (512,)):
+                forced = _search_all(H, k, q, api.SEARCH_FP32_TIECHECK,
+                                     tune=dict(search_path=path, search_block=tb, search_cols=1 + (tb == 1024)))
+                for x, y in zip(forced, big):
+                    assert np.array_equal(x, y, equal_nan=True), (k, L, path, tb)
+        for i0 in (0, 64, 135):
+            small = _search_all(H[i0:i0 + 5], k, q, api.SEARCH_FP32_TIECHECK)
+            for x, y in zip(small, big):
+                assert np.array_equal(x, y[i0:i0 + 5], equal_nan=True), (k, L, i0)
+        for i in range(0, 140, 23):
+            check_choice(H[i], k, q, big[0][i], big[1][i], big[2][i])
