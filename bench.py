@@ -27,10 +27,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-Z, H, W = 300, 512, 512
-LO, HI, L = -1024, -200, 256
-K = 2
-QS = (0.5, 0.8, 1.5)
+
+# name -> (description, per-slice?, window lo, hi, bins, k, q values)
+WORKLOADS = {
+    "volume300": ("volume 512x512x300 int16, per-slice 256-bin histograms over [-1024,-200], per-slice k=2 "
+                  "exhaustive search for q in {0.5,0.8,1.5} (FP32 keys + FP64 tie check), per-slice labels for each q",
+                  True, -1024, -200, 256, 2, (0.5, 0.8, 1.5)),
+    "volume600": ("volume 512x512x600 int16, whole-volume 1024-bin histogram over [-1024,3071], k=3 exhaustive "
+                  "search (177,910,271 tuples), q=0.8, labels", False, -1024, 3071, 1024, 3, (0.8,)),
+    "slice": ("one 512x512 int16 slice, 4096-bin histogram over [-1024,3071], k=1, q=0.8, labels",
+              False, -1024, 3071, 4096, 1, (0.8,)),
+}
 
 
 def parse():
@@ -39,6 +46,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="volume300", choices=sorted(WORKLOADS),
+                    help="volume300 is the benchmark's workload; the others report the same fields")
     ap.add_argument("--cpu-slices", type=int, default=300, help="slices in the oracle's timed sample")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run device-to-device copies of 256 MiB (reference kernel for the PMC byte counters)")
@@ -64,22 +73,31 @@ def load_traffic(kernel_file: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(vol, nslices: int):
+def cpu_baseline(vol, nslices: int, wl):
     import numpy as np
     import oracle
 
-    sample = vol[:nslices]
+    _, per_slice, LO, HI, L, K, QS = wl
     t0 = time.perf_counter()
-    for z in range(sample.shape[0]):
-        h = oracle.histogram(sample[z], LO, HI, L)
+    if per_slice:
+        sample = vol[:nslices]
+        for z in range(sample.shape[0]):
+            h = oracle.histogram(sample[z], LO, HI, L)
+            for q in QS:
+                r = oracle.search(h, K, q, oracle.MODE_PREFIX)
+                oracle.label(sample[z].reshape(-1), LO, HI, L, r.thr)
+        what = f"{sample.shape[0]} of the {vol.shape[0]} slices: oracle histogram + {len(QS)} x (prefix-mode k={K} search + labels)"
+    else:
+        sample = vol
+        h = oracle.histogram(sample, LO, HI, L)
         for q in QS:
             r = oracle.search(h, K, q, oracle.MODE_PREFIX)
-            oracle.label(sample[z].reshape(-1), LO, HI, L, r.thr)
+            oracle.label(sample.reshape(-1), LO, HI, L, r.thr)
+        what = f"the whole input: oracle histogram + prefix-mode k={K} search + labels"
     dt = time.perf_counter() - t0
     nvox = int(np.prod(sample.shape))
     return {"value": nvox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nslices} of the 300 slices: oracle histogram + 3 x (prefix-mode k=2 search + labels), "
-                      f"{dt:.2f} s single-threaded"}
+            "sample": f"{what}, {dt:.2f} s single-threaded"}
 
 
 def main():
@@ -104,9 +122,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": a.numel(), "bytes_written": b.numel(), "launches": 5}))
         return
-    vol = synth.workload_volume300(0)
+    wl = WORKLOADS[args.workload]
+    desc, per_slice, LO, HI, L, K, QS = wl
+    vol = {"volume300": lambda: synth.workload_volume300(0), "volume600": lambda: synth.workload_volume600(0),
+           "slice": lambda: synth.workload_slice(0)[None]}[args.workload]()
     dv = torch.from_numpy(vol).to(dev)
-    batch = api.Batch.slices(dv)
+    batch = api.Batch.slices(dv) if per_slice else api.Batch([dv.reshape(-1)])
     binn = api.binning(LO, HI, L)
     nseg = batch.nseg
     hist = torch.empty((nseg, L), dtype=torch.int32, device=dev)
@@ -159,8 +180,10 @@ def main():
             per[n] += events[s][i].elapsed_time(events[s][i + 1]) * 1e-3
     per = {n: v / args.steps for n, v in per.items()}
 
-    nvox = Z * H * W
-    tuples = len(QS) * nseg * ((L - 1) * (L - 2) // 2)
+    nvox = int(vol.size)
+    n = L - 1
+    per_problem = {1: n, 2: n * (n - 1) // 2, 3: n * (n - 1) * (n - 2) // 6}[K]
+    tuples = len(QS) * nseg * per_problem
     label_t = [per[f"label_q{q}"] for q in QS]
     hist_t = per["histogram"]
     search_t = [per[f"search_q{q}"] for q in QS]
@@ -192,10 +215,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "volume 512x512x300 int16, per-slice 256-bin histograms over [-1024,-200], "
-                               "per-slice k=2 exhaustive search for q in {0.5,0.8,1.5} (FP32 keys + FP64 tie check), "
-                               "per-slice labels for each q",
-                   "problems": nseg, "voxels": nvox, "bins": L, "k": K, "q": list(QS)},
+        "config": {"workload": desc, "problems": nseg, "voxels": nvox, "bins": L, "k": K, "q": list(QS)},
         "tuples_per_s": tuples * args.steps / dt,
         "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
         "roofline": {"bound": "hbm", "kernel": src.replace(".hip", ""), "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -207,7 +227,7 @@ def main():
         "all_problems_ok": bool(st_ok),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(vol, args.cpu_slices)
+        line["cpu_baseline"] = cpu_baseline(vol, args.cpu_slices, wl)
     print(json.dumps(line), flush=True)
 
 

@@ -21,7 +21,7 @@ from typing import Iterable, List, Optional, Sequence
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libts.so")
+LIB_PATH = os.environ.get("TS_LIBRARY", os.path.join(_HERE, "libts.so"))
 
 TS_OK, TS_ERR_INVALID_ARG, TS_ERR_UNSUPPORTED, TS_ERR_WORKSPACE, TS_ERR_HIP = 0, 1, 2, 3, 4
 SEARCH_FP32_TIECHECK, SEARCH_FP32_ONLY, SEARCH_FP64, SEARCH_PLAIN = 0, 1, 2, 3

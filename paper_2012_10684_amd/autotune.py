@@ -76,8 +76,8 @@ def label_space() -> Iterable[dict]:
 
 
 def search_space(L: int, k: int) -> Iterable[dict]:
-    for c, r in itertools.product((1, 2, 4), (32, 64, 128)):
-        if k == 3 and r != 32:
+    for c, r in itertools.product((1, 2, 4), (16, 32, 64)):
+        if k == 3 and r != 16:
             continue  # rows per tile only shape k = 2 tiles
         yield dict(search_cols=c, search_rows=r, search_path=2)
         if k == 1 or (k == 2 and L <= 1024):

@@ -65,7 +65,7 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
     o->label_block = t->label_block ? t->label_block : 256;
     o->label_wg_per_cu = t->label_wg_per_cu ? t->label_wg_per_cu : 8;
     o->search_cols = t->search_cols ? t->search_cols : 2;
-    o->search_rows = t->search_rows ? t->search_rows : 32;
+    o->search_rows = t->search_rows ? t->search_rows : 16;
     o->min_chunk = t->min_chunk ? t->min_chunk : 8192;
     o->search_path = t->search_path;
     o->search_block = t->search_block ? t->search_block : 512;
@@ -83,8 +83,8 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
         return fail(TS_ERR_INVALID_ARG, "tuning: label_wg_per_cu must be in [1, 32]");
     if (o->search_cols != 1 && o->search_cols != 2 && o->search_cols != 4)
         return fail(TS_ERR_INVALID_ARG, "tuning: search_cols must be 1, 2 or 4");
-    if (o->search_rows < 32 || o->search_rows > 4096 || o->search_rows % 4)
-        return fail(TS_ERR_INVALID_ARG, "tuning: search_rows must be a multiple of 4 in [32, 4096]");
+    if (o->search_rows < 16 || o->search_rows > 4096 || o->search_rows % 4)
+        return fail(TS_ERR_INVALID_ARG, "tuning: search_rows must be a multiple of 4 in [16, 4096]");
     if (o->min_chunk < 512)
         return fail(TS_ERR_INVALID_ARG, "tuning: min_chunk must be >= 512");
     if (o->search_path < 0 || o->search_path > 2)

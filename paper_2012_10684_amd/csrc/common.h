@@ -102,12 +102,50 @@ __device__ __forceinline__ int find_segment(const int64_t *offs, int nseg, int64
 }
 
 // ---------------------------------------------------------------- reductions
+// Wavefront reductions with DPP lane moves (full-rate VALU; no LDS round
+// trips): swaps within quads, mirrors within half-rows and rows, then the
+// row broadcasts of lanes 15 and 31 leave the result in lane 63, which is
+// read back as a wavefront-uniform value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xF, false);
+}
+
 __device__ __forceinline__ float wave_max(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v = fmaxf(v, __shfl_xor(v, o, WAVE));
-    return v;
+#define TS_DPP_MAX(C, M) v = fmaxf(v, __int_as_float(dpp_i32<C, M>(__float_as_int(v))))
+    TS_DPP_MAX(0xB1, 0xF);  // quad_perm [1,0,3,2]
+    TS_DPP_MAX(0x4E, 0xF);  // quad_perm [2,3,0,1]
+    TS_DPP_MAX(0x141, 0xF); // row_half_mirror
+    TS_DPP_MAX(0x140, 0xF); // row_mirror
+    TS_DPP_MAX(0x142, 0xA); // row_bcast15 into rows 1 and 3
+    TS_DPP_MAX(0x143, 0xC); // row_bcast31 into rows 2 and 3
+#undef TS_DPP_MAX
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+template <int C, int M>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i32<C, M>((int)(b & 0xffffffffLL));
+    const int hi = dpp_i32<C, M>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_min_f64(double v)
+{
+    v = fmin(v, dpp_f64<0xB1, 0xF>(v));
+    v = fmin(v, dpp_f64<0x4E, 0xF>(v));
+    v = fmin(v, dpp_f64<0x141, 0xF>(v));
+    v = fmin(v, dpp_f64<0x140, 0xF>(v));
+    v = fmin(v, dpp_f64<0x142, 0xA>(v));
+    v = fmin(v, dpp_f64<0x143, 0xC>(v));
+    const long long b = __double_as_longlong(v);
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // order-preserving map of a float onto int32 (for atomicMax on floats)

@@ -50,6 +50,15 @@ namespace ts {
 // the GPU test suite measures the instruction against FP64 log2.
 constexpr double LOG2_ERR_UNITS = 4.0;
 constexpr int PLAIN_BLOCKS = 65536;
+constexpr int K3_THREADS = 256;                // k = 3 rows kernel
+constexpr int K3_COLS = 4;                     // columns per lane
+constexpr int K3_CHUNK = K3_THREADS * K3_COLS; // columns per workgroup
+constexpr int K3_GROUP = 32;                   // rows per recorded maximum
+constexpr int FUSED_THREADS = 1024; // upper bound; the launch picks 256, 512 or 1024
+constexpr int FUSED_MAX_L = 4096;  // k = 1
+constexpr int FUSED_MAX_L2 = 1024; // k = 2 (P and Q staged in LDS)
+constexpr int FUSED_MAX_TILES = 4096;
+
 
 struct Meta {
     int menc;    // ordered-int encoding of the problem's FP32 max key
@@ -74,7 +83,7 @@ __device__ __forceinline__ bool better(double r1, long long c1, double r2, long 
 struct Plan {
     int L, k, mode, cols, CW, Lp, T1;
     int NB, NC, tiles; // column blocks, row groups, tiles per problem
-    size_t off_meta, off_head, off_tail, off_A, off_R, off_tmax, off_best, off_plain, bytes;
+    size_t off_meta, off_hl, off_head, off_tail, off_A, off_R, off_tmax, off_best, off_plain, bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -96,9 +105,14 @@ static Plan make_plan(int nseg, int L, int k, int mode, int cols, int T1)
     } else if (k == 2) {
         p.NB = (n + p.CW - 1) / p.CW;
         p.NC = (std::max(L - 2, 1) + T1 - 1) / T1;
-    } else {
+    } else if (mode == TS_SEARCH_FP64 || mode == TS_SEARCH_PLAIN) {
         p.NB = (n + p.CW - 1) / p.CW;
         p.NC = std::max(L - 3, 1); // one row per t2 in [1, L-3]
+    } else {
+        // (row t2, chunk of K3_CHUNK columns, wavefront) tiles of k_rows3
+        p.NC = (std::max(L - 3, 1) + K3_CHUNK - 1) / K3_CHUNK; // chunks per row
+        p.NB = K3_THREADS / 64 * std::max(L - 3, 1);          // wavefronts per chunk x rows
+        p.T1 = (L + K3_GROUP - 1) / K3_GROUP;                 // row groups per wavefront tile
     }
     p.tiles = p.NB * p.NC;
     const bool f64 = mode == TS_SEARCH_FP64;
@@ -106,20 +120,23 @@ static Plan make_plan(int nseg, int L, int k, int mode, int cols, int T1)
     size_t o = 0;
     p.off_meta = o;
     o = align256(o + (size_t)nseg * sizeof(Meta));
+    p.off_hl = o;
+    if (mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY)
+        o = align256(o + (size_t)nseg * p.Lp * sizeof(float4));
     p.off_head = o;
     o = align256(o + (size_t)nseg * p.Lp * es);
     p.off_tail = o;
     o = align256(o + (size_t)nseg * p.Lp * es);
     p.off_A = o;
     p.off_R = o;
-    if (k == 3 && mode != TS_SEARCH_PLAIN) {
+    if (k == 3 && mode == TS_SEARCH_FP64) {
         o = align256(o + (size_t)nseg * L * p.Lp * es);
         p.off_R = o;
         o = align256(o + (size_t)nseg * L * p.Lp * es);
     }
     p.off_tmax = o;
     if (mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY)
-        o = align256(o + (size_t)nseg * p.tiles * sizeof(float));
+        o = align256(o + (size_t)nseg * p.tiles * (k == 3 ? p.T1 : 1) * sizeof(float));
     p.off_best = o;
     if (mode != TS_SEARCH_PLAIN)
         o = align256(o + (size_t)nseg * p.tiles * sizeof(Best));
@@ -135,21 +152,34 @@ size_t search_workspace_bytes(int nseg, int L, int k, int mode, int)
     // the largest plan over every tuning the library accepts
     size_t m = 0;
     for (int cols : {1, 2, 4})
-        m = std::max(m, make_plan(nseg, L, k, mode, cols, 32).bytes);
+        m = std::max(m, make_plan(nseg, L, k, mode, cols, 16).bytes);
     return m;
 }
 
 // ---------------------------------------------------------------- class terms
 
-// Signed FP32 class term in log2 units from FP64 prefix differences.
-template <int SGN>
-__device__ __forceinline__ float cls32(double dP, double dQ, float nq, float gmax)
+// Each FP64 prefix value X is also kept as a pair of floats, hi = fl32(X) and
+// lo = fl32(X - hi) (x, y: P; z, w: Q), so a class difference is formed in
+// FP32 as (hi_b - hi_a) + (lo_b - lo_a), within 2^-23 relative (plus
+// 2^-46 X_max / difference) of the FP64 difference, at FP32 rate.
+__device__ __forceinline__ float4 split_hl(double P, double Q)
 {
-    const float lx = __builtin_amdgcn_logf((float)dQ);
-    const float ly = __builtin_amdgcn_logf((float)dP);
+    const float ph = (float)P, qh = (float)Q;
+    return make_float4(ph, (float)(P - (double)ph), qh, (float)(Q - (double)qh));
+}
+
+// Signed FP32 class term in log2 units for the class (a, b] from the split
+// prefixes at b and a (a = -1: all zero).  Valid iff the class mass is > 0.
+template <int SGN>
+__device__ __forceinline__ float cls32(const float4 &hb, const float4 &ha, float nq, float gmax)
+{
+    const float dp = (hb.x - ha.x) + (hb.y - ha.y);
+    const float dq = (hb.z - ha.z) + (hb.w - ha.w);
+    const float lx = __builtin_amdgcn_logf(dq);
+    const float ly = __builtin_amdgcn_logf(dp);
     float g = fmaf(nq, ly, SGN > 0 ? lx : -lx); // nq = -sgn * q
     g = __builtin_amdgcn_fmed3f(g, 0.0f, gmax);
-    return dP > 0.0 ? g : -INFINITY;
+    return dp > 0.0f ? g : -INFINITY;
 }
 
 // Signed FP64 class term in natural-log units.
@@ -162,19 +192,31 @@ __device__ __forceinline__ double cls64(double dP, double dQ, double q, double s
 }
 
 // FP64 signed Lambda of the tuple t[0..k-1] directly from the prefix sums.
-__device__ __forceinline__ double lambda64(const double *P, const double *Q, int L, int k, const int *t, double q,
-                                           double sgn, double hmax)
+template <int K>
+__device__ __forceinline__ double lambda64_k(const double *P, const double *Q, int L, const int *t, double q,
+                                             double sgn, double hmax)
 {
     double acc = 0.0;
     double pa = 0.0, qa = 0.0;
-    for (int j = 0; j <= k; ++j) {
-        const int b = j < k ? t[j] : L - 1;
+#pragma unroll
+    for (int j = 0; j <= K; ++j) {
+        const int b = j < K ? t[j] : L - 1;
         const double pb = P[b], qb = Q[b];
         acc += cls64(pb - pa, qb - qa, q, sgn, hmax);
         pa = pb;
         qa = qb;
     }
     return acc;
+}
+
+__device__ __forceinline__ double lambda64(const double *P, const double *Q, int L, int k, const int *t, double q,
+                                           double sgn, double hmax)
+{
+    if (k == 1)
+        return lambda64_k<1>(P, Q, L, t, q, sgn, hmax);
+    if (k == 2)
+        return lambda64_k<2>(P, Q, L, t, q, sgn, hmax);
+    return lambda64_k<3>(P, Q, L, t, q, sgn, hmax);
 }
 
 __device__ __forceinline__ long long make_code(int k, const int *t)
@@ -185,19 +227,42 @@ __device__ __forceinline__ long long make_code(int k, const int *t)
     return c;
 }
 
+// Best (rank desc, code asc) candidate of the wavefront, returned in every
+// lane.  DPP moves as in wave_max; skipped when no lane holds a candidate.
+template <int C, int M>
+__device__ __forceinline__ void best_step(double &r, double &l, long long &c)
+{
+    const double r2 = dpp_f64<C, M>(r);
+    const double l2 = dpp_f64<C, M>(l);
+    const long long c2 = __double_as_longlong(dpp_f64<C, M>(__longlong_as_double(c)));
+    if (better(r2, c2, r, c)) {
+        r = r2;
+        l = l2;
+        c = c2;
+    }
+}
+
+__device__ __forceinline__ double readlane63_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ void wave_best(double &r, double &l, long long &c)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        double r2 = __shfl_xor(r, o, WAVE);
-        double l2 = __shfl_xor(l, o, WAVE);
-        long long c2 = __shfl_xor(c, o, WAVE);
-        if (better(r2, c2, r, c)) {
-            r = r2;
-            l = l2;
-            c = c2;
-        }
-    }
+    if (!__any(r > -INFINITY))
+        return; // no lane holds a candidate
+    best_step<0xB1, 0xF>(r, l, c);
+    best_step<0x4E, 0xF>(r, l, c);
+    best_step<0x141, 0xF>(r, l, c);
+    best_step<0x140, 0xF>(r, l, c);
+    best_step<0x142, 0xA>(r, l, c);
+    best_step<0x143, 0xC>(r, l, c);
+    r = readlane63_f64(r);
+    l = readlane63_f64(l);
+    c = __double_as_longlong(readlane63_f64(__longlong_as_double(c)));
 }
 
 struct Args {
@@ -207,6 +272,7 @@ struct Args {
     float nq, gmax;      // nq = -sgn * fl32(q), gmax = |1-q| log2 L (rounded up)
     int CW, NB, NC, T1, tiles;
     Meta *meta;
+    float4 *hl; // [nseg][Lp] split prefixes (multi-launch paths)
     void *head, *tail, *A, *R;
     float *tmax;
     Best *best;
@@ -214,80 +280,125 @@ struct Args {
 
 // ---------------------------------------------------------------- setup
 
-// Smallest non-zero bin mass of one problem (block-wide minimum; every
-// thread returns the result).  red must hold blockDim.x / 64 doubles.
-__device__ __forceinline__ double block_pmin(const double *P, int L, double *red)
+// Smallest positive step of P and of Q over consecutive bins of one problem
+// (block-wide minima; every thread returns them).  red holds 2 doubles per
+// wavefront.  Any positive class mass is >= pmin, and any positive
+// difference of stored Q values is >= dqmin (a difference of two stored
+// non-decreasing prefix values is at least the largest step between them).
+struct Steps {
+    double pmin, dqmin;
+};
+
+__device__ __forceinline__ Steps block_steps(const double *P, const double *Q, int L, double *red)
 {
-    double pmin = 1.0;
+    double pm = 1.0, qm = INFINITY;
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
-        const double d = P[t] - (t ? P[t - 1] : 0.0);
-        if (d > 0.0)
-            pmin = fmin(pmin, d);
+        const double dp = P[t] - (t ? P[t - 1] : 0.0);
+        const double dq = Q[t] - (t ? Q[t - 1] : 0.0);
+        if (dp > 0.0)
+            pm = fmin(pm, dp);
+        if (dq > 0.0)
+            qm = fmin(qm, dq);
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        pmin = fmin(pmin, __shfl_xor(pmin, o, WAVE));
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = pmin;
+    pm = wave_min_f64(pm);
+    qm = wave_min_f64(qm);
+    const int nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = pm;
+        red[nw + (threadIdx.x >> 6)] = qm;
+    }
     __syncthreads();
-    pmin = red[0];
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
-        pmin = fmin(pmin, red[i]);
+    Steps r = {red[0], red[nw]};
+    for (int i = 1; i < nw; ++i) {
+        r.pmin = fmin(r.pmin, red[i]);
+        r.dqmin = fmin(r.dqmin, red[nw + i]);
+    }
     __syncthreads();
-    return pmin;
+    return r;
 }
 
 // Bound on |key32 - key64 / ln 2| over every tuple of one problem, where
 // key32 is the FP32 key and key64 the FP64 value from the same prefix sums.
 // Per class term: the two casts to FP32 (2^-24 relative each), the error of
-// v_log_f32 on both logs, q rounded to FP32, the fma rounding; then k
-// additions of terms bounded by gmax.  Magnitudes: |log2 w| <= |log2 pmin|,
-// |log2 Q_j| <= max(|log2 Q_tot|, |log2 pmin^q|) (+20 of margin for the
-// rounding of small prefix differences).  Doubled for safety.  Infinity
-// when the FP32 range is exceeded (every tuple is then re-checked in FP64).
-__device__ __forceinline__ float problem_delta(const Args &a, double pmin, double qtot)
+// v_log_f32 on both logs (LOG2_ERR_UNITS * 2^-24 * max(1, |log2 x|)), q
+// rounded to FP32, the fma; then k additions of terms bounded by gmax.
+// Magnitudes: |log2 w| <= |log2 pmin| and |log2 Q_j| <= max(|log2 Q_tot|,
+// |log2 dqmin|) for every valid class (see block_steps); they are taken from
+// v_log_f32 and inflated by 1 % + 1.  The result is doubled.  Infinity when a
+// class sum could leave the normal FP32 range: every tuple is then re-checked
+// in FP64.
+__device__ __forceinline__ float problem_delta(const Args &a, Steps st, double qtot)
 {
     if (a.mode == TS_SEARCH_FP32_ONLY)
         return 0.0f;
-    const double u = 0x1p-24;
-    const double q = a.q;
-    const double qmin = pow(pmin, q);
-    double delta;
-    if (!(qtot > 0.0) || !(qmin > 1e-35) || qtot > 1e35) {
-        delta = INFINITY;
-    } else {
-        const double Ux = fmax(fabs(log2(qtot)), fabs(log2(qmin)) + 20.0);
-        const double Vy = fabs(log2(pmin));
-        const double gm = (double)a.gmax;
-        const double ec = (1.0 + q) * u * 1.5                                            // casts to FP32
-                          + LOG2_ERR_UNITS * u * (fmax(1.0, Ux) + q * fmax(1.0, Vy))     // v_log_f32
-                          + fabs((double)(-a.sgn * a.nq) - q) * Vy                       // q rounded to FP32
-                          + u * (gm + 1.0);                                              // fma + clamp
-        const int kk = a.k;
-        delta = 2.0 * ((kk + 1) * ec + kk * (kk + 1) * u * (gm + 1.0)) + 1e-9 * (kk + 1) * (gm + 1.0);
-    }
-    float d = (float)delta;
-    if ((double)d < delta)
-        d = nextafterf(d, INFINITY);
-    return d;
+    if (!(qtot > 0.0) || !(st.dqmin > 1e-36) || !(st.pmin > 1e-36) || qtot > 1e36)
+        return INFINITY;
+    const float u = 0x1p-24f;
+    const float q = (float)a.q;
+    const float lq = fmaxf(fabsf(__builtin_amdgcn_logf((float)qtot)), fabsf(__builtin_amdgcn_logf((float)st.dqmin)));
+    const float lp = fabsf(__builtin_amdgcn_logf((float)st.pmin));
+    const float Ux = lq * 1.01f + 1.0f, Vy = lp * 1.01f + 1.0f;
+    const float gm = a.gmax;
+    // split FP32 differences: relative error <= 2u + 4u^2 X_max / (smallest difference)
+    const float rp = 2.0f * u + 4.0f * u * u / (float)st.pmin;
+    const float rq = 2.0f * u + 4.0f * u * u * (float)(qtot / st.dqmin);
+    if (!(rp < 1e-3f) || !(rq < 1e-3f))
+        return INFINITY;
+    const float ec = (rq + q * rp) * 1.5f                                    // FP32 class sums
+                     + (float)LOG2_ERR_UNITS * u * (Ux + q * Vy)            // v_log_f32
+                     + (float)fabs((double)(-a.sgn * a.nq) - a.q) * Vy      // q rounded to FP32
+                     + u * (gm + 1.0f);                                     // fma + clamp
+    const float kk = (float)a.k;
+    const float d = 2.0f * ((kk + 1.0f) * ec + kk * (kk + 1.0f) * u * (gm + 1.0f)) + 1e-9f * (kk + 1.0f) * (gm + 1.0f);
+    return d * 1.0001f;
 }
 
 // FP32 head(t) = g(-1, t) and tail(t) = g(t, L-1) for t in [0, Lp); entries
 // past L-2 are -inf.
 template <int SGN>
-__device__ __forceinline__ void head_tail32(const Args &a, const double *P, const double *Q, float *hd, float *tl)
+__device__ __forceinline__ Steps head_tail32(const Args &a, const double *P, const double *Q, float *hd, float *tl,
+                                             float4 *hl, double *red)
 {
     const int L = a.L;
-    const double pL = P[L - 1], qL = Q[L - 1];
+    const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const double PL = P[L - 1], QL = Q[L - 1];
+    const float4 last = split_hl(PL, QL);
+    double pm = 1.0, qm = INFINITY;
     for (int t = threadIdx.x; t < a.Lp; t += blockDim.x) {
+        const int ti = min(t, L - 1);
+        const double p = P[ti], q = Q[ti];
+        const double p0 = ti ? P[ti - 1] : 0.0, q0 = ti ? Q[ti - 1] : 0.0;
+        if (t < L) {
+            if (p - p0 > 0.0)
+                pm = fmin(pm, p - p0);
+            if (q - q0 > 0.0)
+                qm = fmin(qm, q - q0);
+        }
+        const float4 h4 = split_hl(p, q);
         float h = -INFINITY, g = -INFINITY;
         if (t <= L - 2) {
-            h = cls32<SGN>(P[t], Q[t], a.nq, a.gmax);
-            g = cls32<SGN>(pL - P[t], qL - Q[t], a.nq, a.gmax);
+            h = cls32<SGN>(h4, zero, a.nq, a.gmax);
+            g = cls32<SGN>(last, h4, a.nq, a.gmax);
         }
         hd[t] = h;
         tl[t] = g;
+        if (hl)
+            hl[t] = h4;
     }
+    pm = wave_min_f64(pm);
+    qm = wave_min_f64(qm);
+    const int nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = pm;
+        red[nw + (threadIdx.x >> 6)] = qm;
+    }
+    __syncthreads();
+    Steps r = {red[0], red[nw]};
+    for (int i = 1; i < nw; ++i) {
+        r.pmin = fmin(r.pmin, red[i]);
+        r.dqmin = fmin(r.dqmin, red[nw + i]);
+    }
+    return r;
 }
 
 __global__ void __launch_bounds__(256) k_setup(Args a)
@@ -296,13 +407,21 @@ __global__ void __launch_bounds__(256) k_setup(Args a)
     const double *P = a.P + (int64_t)s * a.L;
     const double *Q = a.Q + (int64_t)s * a.L;
     const int L = a.L, Lp = a.Lp;
-    __shared__ double red[4];
-    const double pmin = block_pmin(P, L, red);
+    __shared__ double red[8];
+    Steps stp;
+    if (a.mode == TS_SEARCH_FP64)
+        stp = block_steps(P, Q, L, red);
+    else if (a.sgn > 0)
+        stp = head_tail32<1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
+                             a.hl + (int64_t)s * Lp, red);
+    else
+        stp = head_tail32<-1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
+                              a.hl + (int64_t)s * Lp, red);
     if (threadIdx.x == 0) {
         Meta m;
         m.menc = float_to_ordered(-INFINITY);
         m.pad0 = m.pad1 = 0;
-        m.delta = problem_delta(a, pmin, Q[L - 1]);
+        m.delta = problem_delta(a, stp, Q[L - 1]);
         a.meta[s] = m;
     }
     if (a.mode == TS_SEARCH_FP64) {
@@ -318,38 +437,10 @@ __global__ void __launch_bounds__(256) k_setup(Args a)
             hd[t] = h;
             tl[t] = g;
         }
-    } else if (a.sgn > 0) {
-        head_tail32<1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp);
-    } else {
-        head_tail32<-1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp);
     }
 }
 
 // ---------------------------------------------------------------- k = 3 rows
-
-template <int SGN>
-__global__ void __launch_bounds__(256) k_pairs32(Args a)
-{
-    const int s = blockIdx.x / (a.L - 3);
-    const int t2 = 1 + blockIdx.x % (a.L - 3); // rows 1 .. L-3
-    const int L = a.L, Lp = a.Lp;
-    const double *P = a.P + (int64_t)s * L;
-    const double *Q = a.Q + (int64_t)s * L;
-    const float *hd = (const float *)a.head + (int64_t)s * Lp;
-    const float *tl = (const float *)a.tail + (int64_t)s * Lp;
-    float *Ar = (float *)a.A + ((int64_t)s * L + t2) * Lp;
-    float *Rr = (float *)a.R + ((int64_t)s * L + t2) * Lp;
-    const double p2 = P[t2], q2 = Q[t2];
-    for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
-        float av = -INFINITY, rv = -INFINITY;
-        if (t < t2)
-            av = hd[t] + cls32<SGN>(p2 - P[t], q2 - Q[t], a.nq, a.gmax);
-        else if (t <= L - 2 && t > t2)
-            rv = cls32<SGN>(P[t] - p2, Q[t] - q2, a.nq, a.gmax) + tl[t];
-        Ar[t] = av;
-        Rr[t] = rv;
-    }
-}
 
 __global__ void __launch_bounds__(256) k_pairs64(Args a)
 {
@@ -406,15 +497,18 @@ struct Cand {
 struct TileCtx {
     const double *P, *Q; // prefix sums of the problem
     const float *hd, *tr; // head / tail rows (LDS or global)
+    const float4 *hl;     // split prefixes (LDS or global)
     const float *A, *R;   // k = 3 rows of the problem (global)
     int L, Lp, mode, CW, T1;
     double q, sgn, hmax;
     float nq, gmax;
 };
 
-__device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *hd, const float *tr)
+__device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *hd, const float *tr,
+                                            const float4 *hl)
 {
     TileCtx x;
+    x.hl = hl;
     x.P = a.P + (int64_t)s * a.L;
     x.Q = a.Q + (int64_t)s * a.L;
     x.hd = hd;
@@ -444,7 +538,7 @@ __device__ __forceinline__ void take(const TileCtx &x, float key, float thr, flo
         acc = fmaxf(acc, key);
     } else if (key >= thr) {
         const int t[3] = {t1, t2, t3};
-        const double lam = lambda64(x.P, x.Q, x.L, K, t, x.q, x.sgn, x.hmax);
+        const double lam = lambda64_k<K>(x.P, x.Q, x.L, t, x.q, x.sgn, x.hmax);
         const double rank = x.mode == TS_SEARCH_FP32_ONLY ? (double)key : lam;
         const long long code = make_code(K, t);
         if (better(rank, code, b.r, b.c)) {
@@ -469,41 +563,46 @@ __device__ __forceinline__ void tile_k1(const TileCtx &x, int b, float thr, floa
 // Rows [t1b, t1e) of a k = 2 tile; MASK keeps only t1 < t2.  Four rows are
 // loaded together so the scalar loads and the transcendental latencies of
 // consecutive rows overlap.
-template <int SGN, int COLS, int PHASE, bool MASK>
-__device__ __forceinline__ void rows_k2(const TileCtx &x, int t1b, int t1e, const double (&pc)[COLS],
-                                        const double (&qc)[COLS], const float (&tc)[COLS], const int (&t2v)[COLS],
-                                        float thr, float &acc, Cand &best)
+// Rows [t1b, t1e) of a k = 2 tile; MASK keeps only t1 < t2.  Rows go in
+// groups of R: the group's row operands are all loaded before any of its
+// tuples is evaluated, so one load latency covers R x COLS class terms.
+template <int SGN, int COLS, int PHASE, bool MASK, int R>
+__device__ __forceinline__ void rows_k2_group(const TileCtx &x, int t1, const float4 (&hc)[COLS],
+                                              const float (&tc)[COLS], const int (&t2v)[COLS], float thr, float &acc,
+                                              Cand &best)
 {
-    int t1 = t1b;
-    for (; t1 + 4 <= t1e; t1 += 4) {
-        double pr[4], qr[4];
-        float hr[4];
+    float4 hr[R];
+    float hdr[R];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            pr[u] = x.P[t1 + u];
-            qr[u] = x.Q[t1 + u];
-            hr[u] = x.hd[t1 + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-#pragma unroll
-            for (int v = 0; v < COLS; ++v) {
-                const float key = (hr[u] + cls32<SGN>(pc[v] - pr[u], qc[v] - qr[u], x.nq, x.gmax)) + tc[v];
-                if (!MASK || t1 + u < t2v[v])
-                    take<PHASE, 2>(x, key, thr, acc, best, t1 + u, t2v[v], 0);
-            }
-        }
+    for (int u = 0; u < R; ++u) {
+        hr[u] = x.hl[t1 + u];
+        hdr[u] = x.hd[t1 + u];
     }
-    for (; t1 < t1e; ++t1) {
-        const double pr = x.P[t1], qr = x.Q[t1];
-        const float hr = x.hd[t1];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
 #pragma unroll
         for (int v = 0; v < COLS; ++v) {
-            const float key = (hr + cls32<SGN>(pc[v] - pr, qc[v] - qr, x.nq, x.gmax)) + tc[v];
-            if (!MASK || t1 < t2v[v])
-                take<PHASE, 2>(x, key, thr, acc, best, t1, t2v[v], 0);
+            const float key = (hdr[u] + cls32<SGN>(hc[v], hr[u], x.nq, x.gmax)) + tc[v];
+            if (!MASK || t1 + u < t2v[v])
+                take<PHASE, 2>(x, key, thr, acc, best, t1 + u, t2v[v], 0);
         }
     }
+}
+
+template <int SGN, int COLS, int PHASE, bool MASK>
+__device__ __forceinline__ void rows_k2(const TileCtx &x, int t1b, int t1e, const float4 (&hc)[COLS],
+                                        const float (&tc)[COLS], const int (&t2v)[COLS], float thr, float &acc,
+                                        Cand &best)
+{
+    int t1 = t1b;
+    for (; t1 + 8 <= t1e; t1 += 8)
+        rows_k2_group<SGN, COLS, PHASE, MASK, 8>(x, t1, hc, tc, t2v, thr, acc, best);
+    if (t1 + 4 <= t1e) {
+        rows_k2_group<SGN, COLS, PHASE, MASK, 4>(x, t1, hc, tc, t2v, thr, acc, best);
+        t1 += 4;
+    }
+    for (; t1 < t1e; ++t1)
+        rows_k2_group<SGN, COLS, PHASE, MASK, 1>(x, t1, hc, tc, t2v, thr, acc, best);
 }
 
 template <int SGN, int COLS, int PHASE>
@@ -516,50 +615,19 @@ __device__ __forceinline__ void tile_k2(const TileCtx &x, int b, int c, float th
     const int r1 = min(r0 + x.T1, min(L - 2, cbase + x.CW - 1));
     if (r0 >= r1)
         return;
-    double pc[COLS], qc[COLS];
+    float4 hc[COLS];
     float tc[COLS];
     int t2v[COLS];
 #pragma unroll
     for (int v = 0; v < COLS; ++v) {
         const int t2 = cbase + v * 64 + lane;
         t2v[v] = t2;
-        const int ti = min(t2, L - 1);
-        pc[v] = x.P[ti];
-        qc[v] = x.Q[ti];
+        hc[v] = x.hl[min(t2, L - 1)];
         tc[v] = x.tr[t2]; // -inf past L-2
     }
     const int ra = min(r1, cbase);
-    rows_k2<SGN, COLS, PHASE, false>(x, r0, ra, pc, qc, tc, t2v, thr, acc, best); // every t2 > t1
-    rows_k2<SGN, COLS, PHASE, true>(x, max(r0, cbase), r1, pc, qc, tc, t2v, thr, acc, best);
-}
-
-template <int COLS, int PHASE>
-__device__ __forceinline__ void tile_k3(const TileCtx &x, int b, int c, float thr, float &acc, Cand &best)
-{
-    const int lane = threadIdx.x & 63;
-    const int t2 = x.L - 3 - c; // heaviest rows first
-    const int cbase = b * x.CW;
-    if (!(cbase + x.CW - 1 > t2 && cbase <= x.L - 2))
-        return;
-    const float *Ar = x.A + (int64_t)t2 * x.Lp;
-    const float *Rr = x.R + (int64_t)t2 * x.Lp;
-    float rc[COLS];
-#pragma unroll
-    for (int v = 0; v < COLS; ++v)
-        rc[v] = Rr[cbase + v * 64 + lane]; // -inf where t3 <= t2 or t3 > L-2
-    const int n1 = (t2 + 15) & ~15;        // the A row is -inf from t2 up to Lp
-    for (int t1 = 0; t1 < n1; t1 += 16) {
-        float av[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            av[u] = Ar[t1 + u];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-#pragma unroll
-            for (int v = 0; v < COLS; ++v)
-                take<PHASE, 3>(x, av[u] + rc[v], thr, acc, best, t1 + u, t2, cbase + v * 64 + lane);
-        }
-    }
+    rows_k2<SGN, COLS, PHASE, false>(x, r0, ra, hc, tc, t2v, thr, acc, best); // every t2 > t1
+    rows_k2<SGN, COLS, PHASE, true>(x, max(r0, cbase), r1, hc, tc, t2v, thr, acc, best);
 }
 
 template <int SGN, int COLS, int PHASE, int K>
@@ -567,10 +635,8 @@ __device__ __forceinline__ void tile_body(const TileCtx &x, int b, int c, float 
 {
     if (K == 1)
         tile_k1<COLS, PHASE>(x, b, thr, acc, best);
-    else if (K == 2)
-        tile_k2<SGN, COLS, PHASE>(x, b, c, thr, acc, best);
     else
-        tile_k3<COLS, PHASE>(x, b, c, thr, acc, best);
+        tile_k2<SGN, COLS, PHASE>(x, b, c, thr, acc, best);
 }
 
 __device__ __forceinline__ float phase2_threshold(float M, float delta)
@@ -593,7 +659,8 @@ __global__ void __launch_bounds__(256) k_tiles32(Args a)
     const int lane = threadIdx.x & 63;
     const int s = tl.s;
     const int64_t tid = (int64_t)s * a.tiles + tl.tile;
-    const TileCtx x = make_ctx(a, s, (const float *)a.head + (int64_t)s * a.Lp, (const float *)a.tail + (int64_t)s * a.Lp);
+    const TileCtx x = make_ctx(a, s, (const float *)a.head + (int64_t)s * a.Lp, (const float *)a.tail + (int64_t)s * a.Lp,
+                               a.hl + (int64_t)s * a.Lp);
     float thr = -INFINITY;
     if (PHASE == 2) {
         const Meta m = a.meta[s];
@@ -623,6 +690,174 @@ __global__ void __launch_bounds__(256) k_tiles32(Args a)
     }
 }
 
+// k = 3, one workgroup per (problem, row t2, chunk of 1024 columns).  The A
+// row head(t1) + g(t1, t2), t1 < t2, is built in LDS; lane columns are
+// t3 = t2 + 1 + c for c in the chunk, each holding R(t3) = g(t2, t3) + tail(t3)
+// in a register.  Every tuple's key is A[t1] + R[t3]: one add, and one max3 per
+// two tuples.  Tiles are (row, chunk, wavefront); rows are visited from the
+// middle outwards so the heaviest rows (t2 (L - t2) tuples) start first.
+
+__device__ __forceinline__ int k3_row(int r, int L)
+{
+    const int lo = 1, hi = L - 3, mid = (lo + hi) / 2;
+    const int off = (r + 1) / 2;
+    const int t2 = (r & 1) ? mid + off : mid - off;
+    return t2; // r in [0, L-3) visits every row in [1, L-3] once
+}
+
+// Rows t1 in [g0, g1) of one wavefront: key = A[t1] + R[t3] (g0, g1 multiples
+// of 8; A is -inf from t2 up to the padded end).
+template <int COLS, int PHASE>
+__device__ __forceinline__ void rows3_loop(const TileCtx &x, const float *Arow, int g0, int g1,
+                                           const float (&r)[K3_COLS], int t2, const int (&t3v)[K3_COLS], float thr,
+                                           float &acc, Cand &best)
+{
+    const float4 *A4 = reinterpret_cast<const float4 *>(Arow);
+    float acc0 = -INFINITY, acc1 = -INFINITY;
+    for (int t1 = g0; t1 < g1; t1 += 8) {
+        const float4 u0 = A4[t1 >> 2], u1 = A4[(t1 >> 2) + 1];
+        const float av[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+        if (PHASE == 1) {
+#pragma unroll
+            for (int v = 0; v < COLS; ++v) {
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    const float m = __builtin_fmaxf(av[u] + r[v], av[u + 1] + r[v]);
+                    if (v & 1)
+                        acc1 = __builtin_fmaxf(acc1, m);
+                    else
+                        acc0 = __builtin_fmaxf(acc0, m);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int v = 0; v < COLS; ++v) {
+                    float unused = 0.0f;
+                    take<2, 3>(x, av[u] + r[v], thr, unused, best, t1 + u, t2, t3v[v]);
+                }
+        }
+    }
+    acc = fmaxf(acc, fmaxf(acc0, acc1));
+}
+
+// k = 3, one workgroup per (problem, row t2, chunk of 1024 columns).  The A
+// row head(t1) + g(t1, t2), t1 < t2, is built in LDS; column c of the chunk is
+// t3 = t2 + 1 + c, held by lane c % 64 of wavefront (c / 64) % 4 as
+// R(t3) = g(t2, t3) + tail(t3) in a register, so the valid columns of a short
+// row are spread over all four wavefronts (and SIMDs).  Every tuple's key is
+// A[t1] + R[t3]: one add, and one max3 per two tuples.  Phase 1 records the
+// wavefront max of every group of K3_GROUP rows; phase 2 re-checks only groups
+// whose max reaches the threshold.  Rows are visited from the middle
+// outwards so the heaviest rows (t2 (L - t2) tuples) start first.
+template <int SGN, int PHASE>
+__global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
+{
+    __shared__ float Arow[FUSED_MAX_L + 16];
+    const int L = a.L;
+    const int nrow = L - 3, nch = a.NC; // NC = column chunks per row
+    const int ng = a.T1;                // row groups per wavefront tile
+    const int64_t bid = blockIdx.x;
+    const int s = (int)(bid / ((int64_t)nrow * nch));
+    const int rem = (int)(bid % ((int64_t)nrow * nch));
+    const int t2 = k3_row(rem / nch, L);
+    const int chunk = rem % nch;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t tid0 = (((int64_t)s * nrow + (t2 - 1)) * nch + chunk) * (K3_THREADS / 64);
+    const int ncols = L - 2 - t2;
+    const int c0 = chunk * K3_CHUNK;
+    const int n1 = (t2 + 7) & ~7;
+    const int ngr = (n1 + K3_GROUP - 1) / K3_GROUP; // groups used by this row
+    const TileCtx x = make_ctx(a, s, (const float *)a.head + (int64_t)s * a.Lp, (const float *)a.tail + (int64_t)s * a.Lp,
+                               a.hl + (int64_t)s * a.Lp);
+    const Best none = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL, 0};
+    float *gmax_w = a.tmax + (tid0 + w) * ng; // this wavefront's group maxima
+    if (c0 >= ncols) { // empty chunk (whole workgroup)
+        if (PHASE == 1) {
+            for (int i = threadIdx.x; i < (K3_THREADS / 64) * ng; i += K3_THREADS)
+                a.tmax[tid0 * ng + i] = -INFINITY;
+        } else if (threadIdx.x < K3_THREADS / 64) {
+            a.best[tid0 + threadIdx.x] = none;
+        }
+        return;
+    }
+    float thr = -INFINITY;
+    if (PHASE == 2) {
+        const Meta m = a.meta[s];
+        const float M = ordered_to_float(m.menc);
+        thr = phase2_threshold(M, m.delta);
+        bool any = false;
+        for (int i = threadIdx.x; i < (K3_THREADS / 64) * ng; i += K3_THREADS) {
+            const float tm = a.tmax[tid0 * ng + i];
+            any = any || (tm > -INFINITY && tm >= thr);
+        }
+        any = __syncthreads_or(any) && M > -INFINITY;
+        if (!any) {
+            if (threadIdx.x < K3_THREADS / 64)
+                a.best[tid0 + threadIdx.x] = none;
+            return;
+        }
+    }
+    const float4 h2 = x.hl[t2];
+    for (int t1 = threadIdx.x; t1 < n1; t1 += K3_THREADS)
+        Arow[t1] = t1 < t2 ? x.hd[t1] + cls32<SGN>(h2, x.hl[t1], x.nq, x.gmax) : -INFINITY;
+    float r[K3_COLS];
+    int t3v[K3_COLS];
+    int nv = 0; // column blocks of this wavefront holding a valid column
+#pragma unroll
+    for (int v = 0; v < K3_COLS; ++v) {
+        const int cb = c0 + v * K3_THREADS + w * 64;
+        const int c = cb + lane;
+        const int t3 = t2 + 1 + c;
+        t3v[v] = t3;
+        r[v] = c < ncols ? cls32<SGN>(x.hl[t3], h2, x.nq, x.gmax) + x.tr[t3] : -INFINITY;
+        nv += cb < ncols ? 1 : 0;
+    }
+    __syncthreads();
+    Cand best = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL};
+    float wmax = -INFINITY;
+    for (int g = 0; g < ngr; ++g) {
+        const int g0 = g * K3_GROUP, g1 = min(n1, g0 + K3_GROUP);
+        if (PHASE == 2 && !(gmax_w[g] >= thr))
+            continue;
+        float acc = -INFINITY;
+        if (nv > 2)
+            rows3_loop<4, PHASE>(x, Arow, g0, g1, r, t2, t3v, thr, acc, best);
+        else if (nv == 2)
+            rows3_loop<2, PHASE>(x, Arow, g0, g1, r, t2, t3v, thr, acc, best);
+        else if (nv == 1)
+            rows3_loop<1, PHASE>(x, Arow, g0, g1, r, t2, t3v, thr, acc, best);
+        if (PHASE == 1) {
+            acc = wave_max(acc);
+            if (lane == 0)
+                gmax_w[g] = acc;
+            wmax = fmaxf(wmax, acc);
+        }
+    }
+    if (PHASE == 1) {
+        for (int g = ngr + lane; g < ng; g += 64)
+            gmax_w[g] = -INFINITY;
+        // one atomic per workgroup for the problem max
+        __shared__ float wm[K3_THREADS / 64];
+        if (lane == 0)
+            wm[w] = wmax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = wm[0];
+            for (int i = 1; i < K3_THREADS / 64; ++i)
+                m = fmaxf(m, wm[i]);
+            if (m > -INFINITY)
+                atomicMax(&a.meta[s].menc, float_to_ordered(m));
+        }
+    } else {
+        wave_best(best.r, best.l, best.c);
+        if (lane == 0)
+            a.best[tid0 + w] = Best{best.r, best.l, best.c, 0};
+    }
+}
+
 // Write one problem's result from its best candidate.
 __device__ __forceinline__ void write_result(const Cand &b, int s, const double *P, int L, int k, double q, double sgn,
                                              int32_t *thr, double *obj, int32_t *status)
@@ -645,17 +880,15 @@ __device__ __forceinline__ void write_result(const Cand &b, int s, const double 
 
 // Single-launch path: one workgroup per problem does the setup, phase 1,
 // phase 2 and the final reduction; head/tail rows and tile maxima stay in LDS.
-constexpr int FUSED_THREADS = 1024; // upper bound; the launch picks 256, 512 or 1024
-constexpr int FUSED_MAX_L = 4096;
-constexpr int FUSED_MAX_TILES = 1024;
 
 template <int SGN, int COLS, int K>
 __global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__restrict__ thr_out,
                                                          double *__restrict__ obj, int32_t *__restrict__ status)
 {
     __shared__ float hd[FUSED_MAX_L], tr[FUSED_MAX_L];
+    __shared__ float4 hls[FUSED_MAX_L2];
     __shared__ float tmax[FUSED_MAX_TILES];
-    __shared__ double red[FUSED_THREADS / 64];
+    __shared__ double red[2 * (FUSED_THREADS / 64)];
     __shared__ float wmax[FUSED_THREADS / 64];
     __shared__ double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
     __shared__ long long wc[FUSED_THREADS / 64];
@@ -663,12 +896,11 @@ __global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__rest
     const int s = blockIdx.x;
     const double *P = a.P + (int64_t)s * a.L;
     const double *Q = a.Q + (int64_t)s * a.L;
-    const double pmin = block_pmin(P, a.L, red);
-    head_tail32<SGN>(a, P, Q, hd, tr);
+    const Steps stp = head_tail32<SGN>(a, P, Q, hd, tr, K == 2 ? hls : nullptr, red); // k = 2: split prefixes in LDS
     if (threadIdx.x == 0)
-        sdelta = problem_delta(a, pmin, Q[a.L - 1]);
+        sdelta = problem_delta(a, stp, Q[a.L - 1]);
     __syncthreads();
-    const TileCtx x = make_ctx(a, s, hd, tr);
+    const TileCtx x = make_ctx(a, s, hd, tr, hls);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nw = blockDim.x >> 6;
@@ -788,15 +1020,30 @@ __global__ void __launch_bounds__(256) k_tiles64(Args a)
 
 // ---------------------------------------------------------------- final
 
-__global__ void __launch_bounds__(256) k_final(const Best *__restrict__ best, int per, const double *__restrict__ P,
-                                               int L, int k, double q, double sgn, int32_t *__restrict__ thr,
-                                               double *__restrict__ obj, int32_t *__restrict__ status, int s_base)
+__global__ void __launch_bounds__(1024) k_final(const Best *__restrict__ best, int per, const double *__restrict__ P,
+                                                int L, int k, double q, double sgn, int32_t *__restrict__ thr,
+                                                double *__restrict__ obj, int32_t *__restrict__ status, int s_base)
 {
     const int s = s_base + blockIdx.x;
     const Best *b = best + (int64_t)blockIdx.x * per;
     double br = -INFINITY, bl = -INFINITY;
     long long bc = 0x7fffffffffffffffLL;
-    for (int i = threadIdx.x; i < per; i += blockDim.x) {
+    int i = threadIdx.x;
+    const int st = blockDim.x;
+    for (; i + 3 * st < per; i += 4 * st) { // four loads in flight per thread
+        Best x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            x[u] = b[i + u * st];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (better(x[u].rank, x[u].code, br, bc)) {
+                br = x[u].rank;
+                bl = x[u].lam;
+                bc = x[u].code;
+            }
+    }
+    for (; i < per; i += st) {
         const Best x = b[i];
         if (better(x.rank, x.code, br, bc)) {
             br = x.rank;
@@ -805,8 +1052,8 @@ __global__ void __launch_bounds__(256) k_final(const Best *__restrict__ best, in
         }
     }
     wave_best(br, bl, bc);
-    __shared__ double sr[4], sl[4];
-    __shared__ long long sc[4];
+    __shared__ double sr[16], sl[16];
+    __shared__ long long sc[16];
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         sr[w] = br;
@@ -815,11 +1062,11 @@ __global__ void __launch_bounds__(256) k_final(const Best *__restrict__ best, in
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
-            if (better(sr[i], sc[i], br, bc)) {
-                br = sr[i];
-                bl = sl[i];
-                bc = sc[i];
+        for (int j = 1; j < (int)(blockDim.x >> 6); ++j)
+            if (better(sr[j], sc[j], br, bc)) {
+                br = sr[j];
+                bl = sl[j];
+                bc = sc[j];
             }
         write_result(Cand{br, bl, bc}, s, P, L, k, q, sgn, thr, obj, status);
     }
@@ -921,10 +1168,8 @@ static void launch_fp32(int fused_block, int k, dim3 g, int nseg, hipStream_t st
     }
     if (k == 1)
         launch_phases<SGN, COLS, 1>(g, st, a);
-    else if (k == 2)
-        launch_phases<SGN, COLS, 2>(g, st, a);
     else
-        launch_phases<SGN, COLS, 3>(g, st, a);
+        launch_phases<SGN, COLS, 2>(g, st, a); // k = 3 uses k_rows3
 }
 
 template <int SGN>
@@ -971,6 +1216,7 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
     a.T1 = p.T1;
     a.tiles = p.tiles;
     a.meta = (Meta *)(base + p.off_meta);
+    a.hl = (float4 *)(base + p.off_hl);
     a.head = base + p.off_head;
     a.tail = base + p.off_tail;
     a.A = base + p.off_A;
@@ -986,7 +1232,7 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
         for (int s = 0; s < nseg; ++s) {
             hipLaunchKernelGGL(k_plain, dim3(blocks), dim3(256), 0, st, P + (int64_t)s * L, Q + (int64_t)s * L, L,
                                k, ntup, q, a.sgn, a.hmax, pb);
-            hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, pb, blocks, P, L, k, q, a.sgn, thr, obj, status,
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, pb, blocks, P, L, k, q, a.sgn, thr, obj, status,
                                s);
         }
         return check_launch("ts_threshold_search (plain)");
@@ -994,7 +1240,8 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
 
     const bool fp32 = mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY;
     // one workgroup per problem when that fills the chip or the problem is small
-    const bool can_fuse = fp32 && p.tiles <= FUSED_MAX_TILES && p.Lp <= FUSED_MAX_L && (k == 1 || (k == 2 && L <= 1024));
+    const bool can_fuse = fp32 && p.tiles <= FUSED_MAX_TILES && p.Lp <= FUSED_MAX_L &&
+                          (k == 1 || (k == 2 && L <= FUSED_MAX_L2));
     const bool fused = can_fuse && (t.search_path == 1 || (t.search_path == 0 && (k == 1 || nseg >= 128)));
     const int64_t waves = (int64_t)nseg * p.tiles;
     dim3 g((unsigned)((waves + 3) / 4));
@@ -1006,14 +1253,22 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
         return check_launch("ts_threshold_search");
     }
     hipLaunchKernelGGL(k_setup, dim3(nseg), dim3(256), 0, st, a);
-    if (k == 3) {
+    if (k == 3 && mode == TS_SEARCH_FP64) {
         dim3 gp((unsigned)((int64_t)(L - 3) * nseg));
-        if (mode == TS_SEARCH_FP64)
-            hipLaunchKernelGGL(k_pairs64, gp, dim3(256), 0, st, a);
-        else if (a.sgn > 0)
-            hipLaunchKernelGGL(k_pairs32<1>, gp, dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL(k_pairs32<-1>, gp, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_pairs64, gp, dim3(256), 0, st, a);
+    }
+    if (k == 3 && fp32) {
+        dim3 gr((unsigned)((int64_t)(L - 3) * p.NC * nseg));
+        if (a.sgn > 0) {
+            hipLaunchKernelGGL((k_rows3<1, 1>), gr, dim3(K3_THREADS), 0, st, a);
+            hipLaunchKernelGGL((k_rows3<1, 2>), gr, dim3(K3_THREADS), 0, st, a);
+        } else {
+            hipLaunchKernelGGL((k_rows3<-1, 1>), gr, dim3(K3_THREADS), 0, st, a);
+            hipLaunchKernelGGL((k_rows3<-1, 2>), gr, dim3(K3_THREADS), 0, st, a);
+        }
+        hipLaunchKernelGGL(k_final, dim3(nseg), dim3(1024), 0, st, a.best, p.tiles, P, L, k, q, a.sgn, thr, obj, status,
+                           0);
+        return check_launch("ts_threshold_search");
     }
     if (mode == TS_SEARCH_FP64) {
         if (t.search_cols == 1)
@@ -1027,7 +1282,7 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
     } else {
         launch_fp32_cols<-1>(t.search_cols, 0, k, g, nseg, st, a, thr, obj, status);
     }
-    hipLaunchKernelGGL(k_final, dim3(nseg), dim3(256), 0, st, a.best, p.tiles, P, L, k, q, a.sgn, thr, obj, status, 0);
+    hipLaunchKernelGGL(k_final, dim3(nseg), dim3(1024), 0, st, a.best, p.tiles, P, L, k, q, a.sgn, thr, obj, status, 0);
     return check_launch("ts_threshold_search");
 }
 

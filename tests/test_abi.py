@@ -75,7 +75,7 @@ def test_workspace_sizes(lib):
     ws = lib.ts_search_workspace_bytes
     assert ws(1, 4096, 1, 0) > 0
     assert ws(300, 256, 2, 0) >= 300 * 256 * 8  # head + tail rows
-    assert ws(1, 1024, 3, 0) >= 2 * 1024 * 1024 * 4  # k = 3 pair rows
+    assert 0 < ws(1, 1024, 3, 0) < ws(1, 1024, 3, 2)  # FP32 k = 3 builds its rows in LDS
     assert ws(1, 1024, 3, 2) >= 2 * 1024 * 1024 * 8  # FP64 rows
     assert ws(10, 256, 2, 0) > ws(5, 256, 2, 0)
     for bad in [(-1, 256, 1, 0), (1, 1, 1, 0), (1, 4097, 1, 0), (1, 256, 0, 0), (1, 256, 4, 0), (1, 256, 1, 7)]:

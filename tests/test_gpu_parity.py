@@ -261,3 +261,15 @@ def test_fused_and_tiled_search_paths_agree(q):
                 assert np.array_equal(x, y[i0:i0 + 5], equal_nan=True), (k, L, i0)
         for i in range(0, 140, 23):
             check_choice(H[i], k, q, big[0][i], big[1][i], big[2][i])
+
+
+@pytest.mark.parametrize("q", [0.8, 1.5])
+def test_search_k3_column_chunks(q):
+    """k = 3 rows longer than one 1024-column chunk (L = 1100), two problems
+    in one batch, against the oracle (prefix mode)."""
+    rng = np.random.default_rng(91)
+    H = _random_hists(rng, 2, 1100, zero_frac=0.25, hi=4000)
+    H[0, 500:540] = 0  # a run of empty bins
+    thr, obj, st = _search_all(H, 3, q, api.SEARCH_FP32_TIECHECK)
+    for i in range(2):
+        check_choice(H[i], 3, q, thr[i], obj[i], st[i])
