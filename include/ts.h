@@ -18,6 +18,7 @@
  *                       composition rule recursively;
  *   ts_label            the thresholding kernel function (Algorithm 1),
  *                       extended to k thresholds.
+ *   ts_label_sets       ts_label for several threshold sets in one pass.
  *
  * Conventions shared by every call
  *  - Pointers are DEVICE pointers unless marked [host].  The caller allocates
@@ -47,6 +48,10 @@ extern "C" {
 #endif
 
 typedef void *ts_stream_t; /* a hipStream_t; NULL = the default stream */
+
+/* Largest number of entropic indices q that ts_prefix and
+ * ts_threshold_search take in one call. */
+#define TS_MAX_Q 8
 
 typedef enum {
     TS_OK = 0,
@@ -127,21 +132,25 @@ ts_status ts_histogram(ts_batch batch, ts_binning bin, uint32_t *hist, const ts_
 /* ts_prefix -- probabilities and prefix sums (Tsallis-entropy section:
  * p_i = c_i / N with N = sum c_i, class masses P(t) = sum_{i<=t} p_i, and
  * Q(t) = sum_{i<=t} p_i^q, the sum whose differences give the class sums of
- * p_i^q in H1 and H2).
+ * p_i^q in H1 and H2), for nq entropic indices at once (the experiments
+ * section compares several q on the same image).
  *   hist   uint32 [nseg][nbins] from ts_histogram;
- *   q      entropic index (the paper's alpha), finite, > 0;
- *   P, Q   out: double [nseg][nbins].  P(t) = C(t)/N with C(t) the exact
+ *   nq, q  [host] nq (1..TS_MAX_Q) entropic indices (the paper's alpha),
+ *          each finite and > 0;
+ *   P      out: double [nseg][nbins], P(t) = C(t)/N with C(t) the exact
  *          integer count prefix (one rounding); P(nbins-1) = 1 exactly.
- *          Q is summed so that an empty bin repeats the previous value bit
- *          for bit.  A problem with N = 0 gets P = Q = 0.
- * Errors: TS_ERR_INVALID_ARG for nseg < 0, nbins outside [2, 4096], null
- * pointers when nseg > 0, q not finite or <= 0. */
-ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, double q, double *P, double *Q,
-                    ts_stream_t stream);
+ *          P does not depend on q;
+ *   Q      out: double [nq][nseg][nbins], row (j, s) for q[j].  Q is summed
+ *          so that an empty bin repeats the previous value bit for bit.
+ *          A problem with N = 0 gets P = Q = 0.
+ * Errors: TS_ERR_INVALID_ARG for nseg < 0, nbins outside [2, 4096], nq out
+ * of range, null pointers when nseg > 0, a q not finite or <= 0. */
+ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q, double *P,
+                    double *Q, ts_stream_t stream);
 
 /* [host] Bytes of workspace ts_threshold_search needs for these sizes
  * (0 for invalid sizes). */
-size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t mode);
+size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq, int32_t mode);
 
 /* ts_threshold_search -- exhaustive arg max of the Tsallis objective
  * (Tsallis-entropy section: phi = arg max [H1 + H2 + (1-q) H1 H2]) over every
@@ -150,21 +159,25 @@ size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t
  * composed by the pseudo-additive rule applied recursively, which equals
  * S = expm1(Lambda)/(1-q) with Lambda = sum_j [ln Q_j - q ln w_j] (Q_j the
  * class sum of p_i^q, w_j the class mass).  A tuple with an empty class is
- * invalid.  Ties go to the first tuple in lexicographic order.
- *   P, Q    double [nseg][nbins] from ts_prefix with the same q;
- *   k       1, 2 or 3;  q  finite, > 0, != 1 (q == 1 is TS_ERR_UNSUPPORTED);
+ * invalid.  Ties go to the first tuple in lexicographic order.  The nq x nseg
+ * problems (one per entropic index and histogram) are searched in one pass.
+ *   P, Q    double [nseg][nbins] and [nq][nseg][nbins] from ts_prefix with
+ *           the same q array;
+ *   k       1, 2 or 3;
+ *   nq, q   [host] nq (1..TS_MAX_Q) entropic indices, each finite, > 0 and
+ *           != 1 (q == 1 is TS_ERR_UNSUPPORTED);
  *   mode    TS_SEARCH_*;
  *   ws      device workspace of ws_bytes >= ts_search_workspace_bytes(...);
  *           its contents on entry are ignored;
- *   thr     out: int32 [nseg][k], ascending, or all -1 if no valid tuple;
- *   obj     out: double [nseg], the objective S at thr in FP64 (NaN if none);
- *   status  out: int32 [nseg], TS_PROBLEM_*.
+ *   thr     out: int32 [nq][nseg][k], ascending, or all -1 if no valid tuple;
+ *   obj     out: double [nq][nseg], the objective S at thr in FP64 (NaN if none);
+ *   status  out: int32 [nq][nseg], TS_PROBLEM_*.
  * A degenerate or empty problem does not affect the others in the batch.
- * Errors: TS_ERR_INVALID_ARG (sizes, pointers, k, q, mode),
+ * Errors: TS_ERR_INVALID_ARG (sizes, pointers, k, nq, q, mode),
  * TS_ERR_UNSUPPORTED (q == 1), TS_ERR_WORKSPACE. */
 ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
-                              double q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr, double *obj,
-                              int32_t *status, const ts_tuning *tune, ts_stream_t stream);
+                              int32_t nq, const double *q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr,
+                              double *obj, int32_t *status, const ts_tuning *tune, ts_stream_t stream);
 
 /* ts_label -- thresholding kernel function (Algorithm 1) with k thresholds:
  * a voxel whose gray level (ts_binning rule) is b gets the label
@@ -180,6 +193,23 @@ ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, in
 ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k, uint8_t *const *out,
                    const ts_tuning *tune, ts_stream_t stream);
 
+/* Largest number of threshold sets ts_label_sets takes in one call. */
+#define TS_MAX_LABEL_SETS 4
+
+/* ts_label_sets -- ts_label for several threshold sets of one batch (e.g.
+ * the thresholds found for several entropic indices q, Section 4), in one
+ * pass over the voxels: each voxel is read once and one label is written
+ * per set.  Labels are bit-identical to nsets separate ts_label calls.
+ *   nsets  1..TS_MAX_LABEL_SETS;
+ *   thr    [host] array of nsets device pointers, each int32 [nseg][k]
+ *          (same rules as ts_label's thr);
+ *   out    [host] array of nsets device arrays [nseg] of device pointers
+ *          (same layout as ts_label's out).  The outputs of different sets
+ *          must not overlap.
+ * Errors: as ts_label, and TS_ERR_INVALID_ARG for nsets out of range. */
+ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int32_t *const *thr, int32_t k,
+                        uint8_t *const *const *out, const ts_tuning *tune, ts_stream_t stream);
+
 /* [host] Text describing the last non-OK status returned on this thread
  * ("" if none).  The pointer stays valid until the next call on this thread. */
 const char *ts_last_error(void);
@@ -187,7 +217,7 @@ const char *ts_last_error(void);
 /* [host] ABI version of this header (increments on incompatible change). */
 int32_t ts_abi_version(void);
 
-#define TS_ABI_VERSION 1
+#define TS_ABI_VERSION 2
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,10 @@ Functions mirror the C ABI:
   histogram(batch, binning)          -> uint32 counts [nseg, L] (int32 storage)
   prefix(hist, q)                    -> P, Q float64 [nseg, L]
   threshold_search(P, Q, k, q, mode) -> thr int32 [nseg, k], obj float64 [nseg], status int32 [nseg]
+  (q may also be a sequence of up to MAX_Q values: Q, thr, obj and status
+  then get a leading [nq] dimension and every q is handled by one launch)
   label(batch, binning, thr, k)      -> one uint8 tensor per problem
+  label_sets(batch, binning, thrs, k) -> one list of uint8 tensors per threshold set
 plus ``Batch`` (the device segment table) and ``segment`` (the four calls in
 order).
 """
@@ -23,6 +26,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TS_LIBRARY", os.path.join(_HERE, "libts.so"))
 
+ABI_VERSION = 2
+MAX_Q = 8
 TS_OK, TS_ERR_INVALID_ARG, TS_ERR_UNSUPPORTED, TS_ERR_WORKSPACE, TS_ERR_HIP = 0, 1, 2, 3, 4
 SEARCH_FP32_TIECHECK, SEARCH_FP32_ONLY, SEARCH_FP64, SEARCH_PLAIN = 0, 1, 2, 3
 PROBLEM_OK, PROBLEM_DEGENERATE, PROBLEM_EMPTY = 0, 1, 2
@@ -68,17 +73,18 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     lib.ts_histogram.argtypes = [_Batch, Binning, P, P, P]
-    lib.ts_prefix.argtypes = [P, i32, i32, f64, P, P, P]
-    lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.ts_prefix.argtypes = [P, i32, i32, i32, P, P, P, P]
+    lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
     lib.ts_search_workspace_bytes.restype = sz
-    lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, f64, i32, P, sz, P, P, P, P, P]
+    lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, sz, P, P, P, P, P]
     lib.ts_label.argtypes = [_Batch, Binning, P, i32, P, P, P]
-    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label):
+    lib.ts_label_sets.argtypes = [_Batch, Binning, i32, P, i32, P, P, P]
+    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets):
         f.restype = ctypes.c_int
     lib.ts_last_error.argtypes = []
     lib.ts_last_error.restype = ctypes.c_char_p
     lib.ts_abi_version.restype = ctypes.c_int32
-    if lib.ts_abi_version() != 1:
+    if lib.ts_abi_version() != ABI_VERSION:
         raise ImportError("libts ABI version mismatch")
     return lib
 
@@ -166,34 +172,53 @@ def histogram(batch: Batch, bin: Binning, out: Optional[torch.Tensor] = None, tu
     return out
 
 
-def prefix(hist: torch.Tensor, q: float, P=None, Q=None, stream=None):
+def _qs(q):
+    """(tuple of q values, batched?) for a scalar or a sequence."""
+    if isinstance(q, (int, float)):
+        return (float(q),), False
+    qs = tuple(float(x) for x in q)
+    return qs, True
+
+
+def _qarr(qs):
+    return (ctypes.c_double * len(qs))(*qs) if qs else None
+
+
+def prefix(hist: torch.Tensor, q, P=None, Q=None, stream=None):
+    """P [nseg, L] and Q: [nseg, L] for a scalar q, [nq, nseg, L] for a sequence."""
     nseg, L = hist.shape
+    qs, batched = _qs(q)
     if P is None:
         P = torch.empty((nseg, L), dtype=torch.float64, device=hist.device)
     if Q is None:
-        Q = torch.empty((nseg, L), dtype=torch.float64, device=hist.device)
-    _check(_lib.ts_prefix(_ptr(hist), nseg, L, float(q), _ptr(P), _ptr(Q), _stream(stream)))
+        Q = torch.empty(((len(qs),) if batched else ()) + (nseg, L), dtype=torch.float64, device=hist.device)
+    _check(_lib.ts_prefix(_ptr(hist), nseg, L, len(qs), _qarr(qs), _ptr(P), _ptr(Q), _stream(stream)))
     return P, Q
 
 
-def workspace_bytes(nseg: int, nbins: int, k: int, mode: int = SEARCH_FP32_TIECHECK) -> int:
-    return int(_lib.ts_search_workspace_bytes(nseg, nbins, k, mode))
+def workspace_bytes(nseg: int, nbins: int, k: int, mode: int = SEARCH_FP32_TIECHECK, nq: int = 1) -> int:
+    return int(_lib.ts_search_workspace_bytes(nseg, nbins, k, nq, mode))
 
 
-def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q: float, mode: int = SEARCH_FP32_TIECHECK,
+def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q, mode: int = SEARCH_FP32_TIECHECK,
                      ws: Optional[torch.Tensor] = None, out=None, tune=None, stream=None):
+    """thr [.., nseg, k], obj and status [.., nseg]; the leading [nq] dimension
+    is present when q is a sequence."""
     nseg, L = P.shape
-    need = workspace_bytes(nseg, L, k, mode)
+    qs, batched = _qs(q)
+    nq = len(qs)
+    lead = (nq,) if batched else ()
+    need = workspace_bytes(nseg, L, k, mode, nq)
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=P.device)
     if out is None:
-        thr = torch.empty((nseg, k), dtype=torch.int32, device=P.device)
-        obj = torch.empty(nseg, dtype=torch.float64, device=P.device)
-        status = torch.empty(nseg, dtype=torch.int32, device=P.device)
+        thr = torch.empty(lead + (nseg, k), dtype=torch.int32, device=P.device)
+        obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=P.device)
+        status = torch.empty(lead + (nseg,), dtype=torch.int32, device=P.device)
     else:
         thr, obj, status = out
-    t = _tune(tune, lambda a: a.key_search(nseg, L, k, mode))
-    _check(_lib.ts_threshold_search(_ptr(P), _ptr(Q), nseg, L, int(k), float(q), int(mode), _ptr(ws),
+    t = _tune(tune, lambda a: a.key_search(nseg * nq, L, k, mode))
+    _check(_lib.ts_threshold_search(_ptr(P), _ptr(Q), nseg, L, int(k), nq, _qarr(qs), int(mode), _ptr(ws),
                                     ws.numel(), _ptr(thr), _ptr(obj), _ptr(status), t, _stream(stream)))
     return thr, obj, status
 
@@ -207,6 +232,27 @@ def label(batch: Batch, bin: Binning, thr: torch.Tensor, k: int, outs: Optional[
         out_ptrs = torch.tensor([o.data_ptr() for o in outs] or [0], dtype=torch.int64).to(dev)
     t = _tune(tune, lambda a: a.key_label(batch.nseg, batch.total, k))
     _check(_lib.ts_label(batch._c, bin, _ptr(thr), int(k), _ptr(out_ptrs), t, _stream(stream)))
+    return outs
+
+
+MAX_LABEL_SETS = 4
+
+
+def label_sets(batch: Batch, bin: Binning, thrs: Sequence[torch.Tensor], k: int,
+               outs: Optional[List[List[torch.Tensor]]] = None, out_ptrs: Optional[Sequence[torch.Tensor]] = None,
+               tune=None, stream=None):
+    """Labels for several threshold sets (each int32 [nseg, k]) in one pass."""
+    dev = batch.ptrs.device
+    n = len(thrs)
+    if outs is None:
+        outs = [[torch.empty(m, dtype=torch.uint8, device=dev) for m in batch.sizes] for _ in range(n)]
+    if out_ptrs is None:
+        out_ptrs = [torch.tensor([o.data_ptr() for o in oq] or [0], dtype=torch.int64).to(dev) for oq in outs]
+    thr_arr = (ctypes.c_void_p * max(n, 1))(*[t.data_ptr() for t in thrs])
+    out_arr = (ctypes.c_void_p * max(n, 1))(*[p.data_ptr() for p in out_ptrs])
+    t = _tune(tune, lambda a: a.key_label(batch.nseg, batch.total, k, n))
+    _check(_lib.ts_label_sets(batch._c, bin, n, ctypes.cast(thr_arr, ctypes.c_void_p), int(k),
+                              ctypes.cast(out_arr, ctypes.c_void_p), t, _stream(stream)))
     return outs
 
 

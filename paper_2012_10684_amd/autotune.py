@@ -55,8 +55,9 @@ def key_histogram(nseg: int, total: int, L: int) -> str:
     return f"{_arch()}|histogram|L={L}|nseg=2^{_p2(nseg)}|vox=2^{_p2(total)}"
 
 
-def key_label(nseg: int, total: int, k: int) -> str:
-    return f"{_arch()}|label|k={k}|nseg=2^{_p2(nseg)}|vox=2^{_p2(total)}"
+def key_label(nseg: int, total: int, k: int, nsets: int = 1) -> str:
+    sets = "" if nsets == 1 else f"|sets={nsets}"
+    return f"{_arch()}|label|k={k}{sets}|nseg=2^{_p2(nseg)}|vox=2^{_p2(total)}"
 
 
 def key_search(nseg: int, L: int, k: int, mode: int) -> str:
@@ -153,10 +154,19 @@ class Autotuner:
         return self._sweep(key, label_space(),
                            lambda t: api.label(batch, binn, thr, k, outs=outs, out_ptrs=optrs, tune=t or None), reps)
 
-    def tune_search(self, P: torch.Tensor, Q: torch.Tensor, k: int, q: float, mode: int, ws: torch.Tensor, out,
+    def tune_label_sets(self, batch: api.Batch, binn: api.Binning, thrs, k: int, outs, optrs,
+                        reps: int = 10) -> dict:
+        key = key_label(batch.nseg, batch.total, k, len(thrs))
+        return self._sweep(key, label_space(),
+                           lambda t: api.label_sets(batch, binn, thrs, k, outs=outs, out_ptrs=optrs,
+                                                    tune=t or None), reps)
+
+    def tune_search(self, P: torch.Tensor, Q: torch.Tensor, k: int, q, mode: int, ws: torch.Tensor, out,
                     reps: int = 10) -> dict:
+        """q: one value, or a sequence searched in one launch (key over nq x nseg problems)."""
         nseg, L = P.shape
-        key = key_search(nseg, L, k, mode)
+        nq = 1 if isinstance(q, (int, float)) else len(q)
+        key = key_search(nseg * nq, L, k, mode)
         return self._sweep(key, search_space(L, k),
                            lambda t: api.threshold_search(P, Q, k, q, mode, ws=ws, out=out, tune=t or None), reps)
 
@@ -193,16 +203,21 @@ def _tune_workload(name: str, tuner: Autotuner):
     binn = api.binning(lo, hi, L)
     hist = api.histogram(batch, binn)
     tuner.tune_histogram(batch, binn, hist)
-    for q in qs:
-        P, Q = api.prefix(hist, q)
-        ws = torch.empty(api.workspace_bytes(batch.nseg, L, k), dtype=torch.uint8, device=dev)
-        out = (torch.empty((batch.nseg, k), dtype=torch.int32, device=dev),
-               torch.empty(batch.nseg, dtype=torch.float64, device=dev),
-               torch.empty(batch.nseg, dtype=torch.int32, device=dev))
-        tuner.tune_search(P, Q, k, q, api.SEARCH_FP32_TIECHECK, ws, out)
-    outs = [torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes]
-    optrs = torch.tensor([o.data_ptr() for o in outs], dtype=torch.int64).to(dev)
-    tuner.tune_label(batch, binn, out[0], k, outs, optrs)
+    # every q of the workload in one search launch, as the benchmark runs it
+    nq = len(qs)
+    P, Q = api.prefix(hist, qs)
+    ws = torch.empty(api.workspace_bytes(batch.nseg, L, k, api.SEARCH_FP32_TIECHECK, nq), dtype=torch.uint8,
+                     device=dev)
+    out = (torch.empty((nq, batch.nseg, k), dtype=torch.int32, device=dev),
+           torch.empty((nq, batch.nseg), dtype=torch.float64, device=dev),
+           torch.empty((nq, batch.nseg), dtype=torch.int32, device=dev))
+    tuner.tune_search(P, Q, k, qs, api.SEARCH_FP32_TIECHECK, ws, out)
+    thrs = [out[0][j] for j in range(nq)]
+    outs = [[torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes] for _ in thrs]
+    optrs = [torch.tensor([o.data_ptr() for o in oq], dtype=torch.int64).to(dev) for oq in outs]
+    tuner.tune_label(batch, binn, thrs[0], k, outs[0], optrs[0])
+    if len(thrs) > 1:
+        tuner.tune_label_sets(batch, binn, thrs, k, outs, optrs)
 
 
 def main(argv=None):

@@ -212,32 +212,52 @@ ts_status ts_histogram(ts_batch batch, ts_binning bin, uint32_t *hist, const ts_
     return launch_histogram(batch, bm, hist, t, (hipStream_t)stream);
 }
 
-ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, double q, double *P, double *Q,
-                    ts_stream_t stream)
+// Checks nq and the q values of a prefix or search call (fn names the call).
+static ts_status check_q(const char *fn, int32_t nq, const double *q, bool search)
+{
+    if (nq < 1 || nq > TS_MAX_Q)
+        return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": nq must be 1.." + std::to_string(TS_MAX_Q));
+    if (!q)
+        return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": null q array");
+    for (int j = 0; j < nq; ++j) {
+        if (!(q[j] > 0.0) || !isfinite(q[j]))
+            return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": q must be finite and > 0");
+    }
+    if (search)
+        for (int j = 0; j < nq; ++j)
+            if (q[j] == 1.0)
+                return fail(TS_ERR_UNSUPPORTED, std::string(fn) + ": q == 1 (Shannon/Kapur limit) is not implemented");
+    return TS_OK;
+}
+
+ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q, double *P,
+                    double *Q, ts_stream_t stream)
 {
     if (nseg < 0)
         return fail(TS_ERR_INVALID_ARG, "ts_prefix: nseg must be >= 0");
     if (nbins < 2 || nbins > MAX_BINS)
         return fail(TS_ERR_INVALID_ARG, "ts_prefix: nbins must be in [2, 4096]");
-    if (!(q > 0.0) || !isfinite(q))
-        return fail(TS_ERR_INVALID_ARG, "ts_prefix: q must be finite and > 0");
+    ts_status st;
+    if ((st = check_q("ts_prefix", nq, q, false)) != TS_OK)
+        return st;
     if (nseg > 0 && (!hist || !P || !Q))
         return fail(TS_ERR_INVALID_ARG, "ts_prefix: null pointer");
     if (nseg == 0)
         return TS_OK;
-    return launch_prefix(hist, nseg, nbins, q, P, Q, (hipStream_t)stream);
+    return launch_prefix(hist, nseg, nbins, nq, q, P, Q, (hipStream_t)stream);
 }
 
-size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t mode)
+size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq, int32_t mode)
 {
-    if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || k < 1 || k > 3 || mode < 0 || mode > 3)
+    if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || k < 1 || k > 3 || nq < 1 || nq > TS_MAX_Q || mode < 0 ||
+        mode > 3)
         return 0;
-    return search_workspace_bytes(nseg, nbins, k, mode, 4);
+    return search_workspace_bytes(nseg * nq, nbins, k, mode, 4);
 }
 
-ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k, double q,
-                              int32_t mode, void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status,
-                              const ts_tuning *tune, ts_stream_t stream)
+ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k, int32_t nq,
+                              const double *q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr, double *obj,
+                              int32_t *status, const ts_tuning *tune, ts_stream_t stream)
 {
     if (nseg < 0)
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nseg must be >= 0");
@@ -247,29 +267,30 @@ ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, in
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: k must be 1, 2 or 3");
     if (nbins < k + 1)
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nbins must be >= k + 1");
-    if (!(q > 0.0) || !isfinite(q))
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: q must be finite and > 0");
     if (mode < 0 || mode > 3)
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: unknown mode");
-    if (q == 1.0)
-        return fail(TS_ERR_UNSUPPORTED, "ts_threshold_search: q == 1 (Shannon/Kapur limit) is not implemented");
+    ts_status st;
+    if ((st = check_q("ts_threshold_search", nq, q, true)) != TS_OK)
+        return st;
+    if ((int64_t)nseg * nq > 0x7fffffff / 2)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: too many problems");
     if (nseg > 0 && (!P || !Q || !thr || !obj || !status))
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: null pointer");
-    ts_status st;
     Tune t;
     if ((st = resolve_tuning(tune, nbins, &t)) != TS_OK)
         return st;
-    size_t need = search_workspace_bytes(nseg, nbins, k, mode, 4);
+    size_t need = search_workspace_bytes(nseg * nq, nbins, k, mode, 4);
     if (nseg > 0 && (ws_bytes < need || (!ws && need > 0)))
         return fail(TS_ERR_WORKSPACE, "ts_threshold_search: workspace too small (need " + std::to_string(need) +
                                           " bytes, got " + std::to_string(ws_bytes) + ")");
     if (nseg == 0)
         return TS_OK;
-    return launch_search(P, Q, nseg, nbins, k, q, mode, ws, ws_bytes, thr, obj, status, t, (hipStream_t)stream);
+    return launch_search(P, Q, nseg, nbins, k, nq, q, mode, ws, ws_bytes, thr, obj, status, t, (hipStream_t)stream);
 }
 
-ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k, uint8_t *const *out,
-                   const ts_tuning *tune, ts_stream_t stream)
+static ts_status label_common(const char *fn, ts_batch batch, ts_binning bin, int32_t nsets,
+                              const int32_t *const *thr, int32_t k, uint8_t *const *const *out, const ts_tuning *tune,
+                              ts_stream_t stream)
 {
     ts_status st = check_batch(batch);
     if (st != TS_OK)
@@ -278,15 +299,38 @@ ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k
     if ((st = make_binmap(bin, &bm)) != TS_OK)
         return st;
     if (k < 1 || k > 3)
-        return fail(TS_ERR_INVALID_ARG, "ts_label: k must be 1, 2 or 3");
-    if (batch.nseg > 0 && (!thr || !out))
-        return fail(TS_ERR_INVALID_ARG, "ts_label: null pointer");
+        return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": k must be 1, 2 or 3");
+    if (nsets < 1 || nsets > TS_MAX_LABEL_SETS)
+        return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": nsets must be 1.." + std::to_string(TS_MAX_LABEL_SETS));
+    LabelSets sets = {};
+    if (batch.nseg > 0) {
+        if (!thr || !out)
+            return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": null pointer");
+        for (int u = 0; u < nsets; ++u) {
+            if (!thr[u] || !out[u])
+                return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": null pointer");
+            sets.thr[u] = thr[u];
+            sets.out[u] = out[u];
+        }
+    }
     Tune t;
     if ((st = resolve_tuning(tune, bin.nbins, &t)) != TS_OK)
         return st;
     if (batch.nseg == 0)
         return TS_OK;
-    return launch_label(batch, bm, thr, k, out, t, (hipStream_t)stream);
+    return launch_label(batch, bm, sets, nsets, k, t, (hipStream_t)stream);
+}
+
+ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k, uint8_t *const *out,
+                   const ts_tuning *tune, ts_stream_t stream)
+{
+    return label_common("ts_label", batch, bin, 1, &thr, k, &out, tune, stream);
+}
+
+ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int32_t *const *thr, int32_t k,
+                        uint8_t *const *const *out, const ts_tuning *tune, ts_stream_t stream)
+{
+    return label_common("ts_label_sets", batch, bin, nsets, thr, k, out, tune, stream);
 }
 
 } // extern "C"

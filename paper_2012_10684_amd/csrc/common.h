@@ -161,14 +161,20 @@ __device__ __forceinline__ float ordered_to_float(int e)
 
 // ---------------------------------------------------------------- launches
 ts_status launch_histogram(const ts_batch &b, const BinMap &bm, uint32_t *hist, const Tune &t, hipStream_t s);
-ts_status launch_prefix(const uint32_t *hist, int nseg, int L, double q, double *P, double *Q, hipStream_t s);
-ts_status launch_label(const ts_batch &b, const BinMap &bm, const int32_t *thr, int k, uint8_t *const *out,
-                       const Tune &t, hipStream_t s);
+ts_status launch_prefix(const uint32_t *hist, int nseg, int L, int nq, const double *q, double *P, double *Q,
+                        hipStream_t s);
+// Threshold rows and output tables of the sets labelled by one launch.
+struct LabelSets {
+    const int32_t *thr[TS_MAX_LABEL_SETS];
+    uint8_t *const *out[TS_MAX_LABEL_SETS];
+};
+ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &sets, int nsets, int k, const Tune &t,
+                       hipStream_t st);
 
 struct SearchPlan;
 size_t search_workspace_bytes(int nseg, int L, int k, int mode, int cols);
-ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, double q, int mode, void *ws,
-                        size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t,
-                        hipStream_t s);
+ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, int nq, const double *q, int mode,
+                        void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t,
+                        hipStream_t st);
 
 } // namespace ts

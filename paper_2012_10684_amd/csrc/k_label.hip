@@ -69,10 +69,52 @@ __device__ __forceinline__ v2u lab8(const v4i &w, const Cuts &c)
     return r;
 }
 
+// Up to TS_MAX_LABEL_SETS threshold sets labelled in one pass: each 16-byte
+// load of 8 voxels feeds one 8-byte store per set.
+template <int NS>
+__device__ __forceinline__ void label_vec(const TS_GLOBAL v4i *vp, TS_GLOBAL v2u *const (&op)[NS],
+                                          const Cuts (&cuts)[NS], int64_t nvec)
+{
+    const int64_t st = blockDim.x;
+    int64_t j = threadIdx.x;
+    // pairs of vectors per thread; the next pair is in flight while the
+    // current one is labelled and stored
+    bool have = j + st < nvec;
+    v4i a0 = {0, 0, 0, 0}, a1 = a0;
+    if (have) {
+        a0 = __builtin_nontemporal_load(vp + j);
+        a1 = __builtin_nontemporal_load(vp + j + st);
+    }
+    while (have) {
+        const int64_t jn = j + 2 * st;
+        const bool nxt = jn + st < nvec;
+        v4i b0 = a0, b1 = a1;
+        if (nxt) {
+            b0 = __builtin_nontemporal_load(vp + jn);
+            b1 = __builtin_nontemporal_load(vp + jn + st);
+        }
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            __builtin_nontemporal_store(lab8(a0, cuts[u]), op[u] + j);
+            __builtin_nontemporal_store(lab8(a1, cuts[u]), op[u] + j + st);
+        }
+        a0 = b0;
+        a1 = b1;
+        j = jn;
+        have = nxt;
+    }
+    for (; j < nvec; j += st) {
+        const v4i a = __builtin_nontemporal_load(vp + j);
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            __builtin_nontemporal_store(lab8(a, cuts[u]), op[u] + j);
+    }
+}
+
+template <int NS>
 __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict__ vox,
                                                 const int64_t *__restrict__ offs, int nseg, int64_t total,
-                                                int64_t chunk, BinMap bm, const int32_t *__restrict__ thr, int k,
-                                                uint8_t *const *__restrict__ out)
+                                                int64_t chunk, BinMap bm, LabelSets sets, int k)
 {
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = min(total, beg + chunk);
@@ -86,62 +128,59 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
         const int64_t s0 = offs[s];
         const int64_t s1 = min(offs[s + 1], end);
         const TS_GLOBAL int16_t *src = gp(vox[s]);
-        TS_GLOBAL uint8_t *dst = gpw(out[s]);
-        const Cuts cuts = make_cuts(thr + (int64_t)s * k, k, bm);
+        TS_GLOBAL uint8_t *dst[NS];
+        Cuts cuts[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            dst[u] = gpw(sets.out[u][s]);
+            cuts[u] = make_cuts(sets.thr[u] + (int64_t)s * k, k, bm);
+        }
         const int64_t i0 = pos - s0, i1 = s1 - s0;
-        const uintptr_t ain = (uintptr_t)(src + i0), aout = (uintptr_t)(dst + i0);
-        // element phase of 16-byte input alignment and of 8-byte output alignment
+        const uintptr_t ain = (uintptr_t)(src + i0);
+        // element phase of 16-byte input alignment; every output must have
+        // the same phase for 8-byte alignment
         const int64_t hin = (int64_t)(((16u - (ain & 15u)) & 15u) >> 1);
-        const int64_t hout = (int64_t)((8u - (aout & 7u)) & 7u);
-        if ((ain & 1u) == 0 && hin == hout) {
-            int64_t head = min(hin, i1 - i0);
-            if (threadIdx.x < head)
-                dst[i0 + threadIdx.x] = (uint8_t)lab1(src[i0 + threadIdx.x], cuts);
+        bool vec = (ain & 1u) == 0;
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            vec = vec && (int64_t)((8u - ((uintptr_t)(dst[u] + i0) & 7u)) & 7u) == hin;
+        if (vec) {
+            const int64_t head = min(hin, i1 - i0);
+            if (threadIdx.x < head) {
+                const int v = src[i0 + threadIdx.x];
+#pragma unroll
+                for (int u = 0; u < NS; ++u)
+                    dst[u][i0 + threadIdx.x] = (uint8_t)lab1(v, cuts[u]);
+            }
             const int64_t vb = i0 + head;
             const int64_t nvec = (i1 - vb) >> 3;
-            const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(src + vb);
-            TS_GLOBAL v2u *op = reinterpret_cast<TS_GLOBAL v2u *>(dst + vb);
-            const int64_t st = blockDim.x;
-            int64_t j = threadIdx.x;
-            // pairs of vectors per thread; the next pair is in flight while
-            // the current one is labelled and stored
-            bool have = j + st < nvec;
-            v4i a0 = {0, 0, 0, 0}, a1 = a0;
-            if (have) {
-                a0 = __builtin_nontemporal_load(vp + j);
-                a1 = __builtin_nontemporal_load(vp + j + st);
-            }
-            while (have) {
-                const int64_t jn = j + 2 * st;
-                const bool nxt = jn + st < nvec;
-                v4i b0 = a0, b1 = a1;
-                if (nxt) {
-                    b0 = __builtin_nontemporal_load(vp + jn);
-                    b1 = __builtin_nontemporal_load(vp + jn + st);
-                }
-                __builtin_nontemporal_store(lab8(a0, cuts), op + j);
-                __builtin_nontemporal_store(lab8(a1, cuts), op + j + st);
-                a0 = b0;
-                a1 = b1;
-                j = jn;
-                have = nxt;
-            }
-            for (; j < nvec; j += st)
-                __builtin_nontemporal_store(lab8(__builtin_nontemporal_load(vp + j), cuts), op + j);
+            TS_GLOBAL v2u *op[NS];
+#pragma unroll
+            for (int u = 0; u < NS; ++u)
+                op[u] = reinterpret_cast<TS_GLOBAL v2u *>(dst[u] + vb);
+            label_vec<NS>(reinterpret_cast<const TS_GLOBAL v4i *>(src + vb), op, cuts, nvec);
             const int64_t tb = vb + (nvec << 3);
-            if (threadIdx.x < i1 - tb)
-                dst[tb + threadIdx.x] = (uint8_t)lab1(src[tb + threadIdx.x], cuts);
+            if (threadIdx.x < i1 - tb) {
+                const int v = src[tb + threadIdx.x];
+#pragma unroll
+                for (int u = 0; u < NS; ++u)
+                    dst[u][tb + threadIdx.x] = (uint8_t)lab1(v, cuts[u]);
+            }
         } else {
-            for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
-                dst[i] = (uint8_t)lab1(src[i], cuts);
+            for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+                const int v = src[i];
+#pragma unroll
+                for (int u = 0; u < NS; ++u)
+                    dst[u][i] = (uint8_t)lab1(v, cuts[u]);
+            }
         }
         pos = s0 + i1;
         ++s;
     }
 }
 
-ts_status launch_label(const ts_batch &b, const BinMap &bm, const int32_t *thr, int k, uint8_t *const *out,
-                       const Tune &t, hipStream_t st)
+ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &sets, int nsets, int k, const Tune &t,
+                       hipStream_t st)
 {
     if (b.total == 0)
         return TS_OK;
@@ -152,8 +191,13 @@ ts_status launch_label(const ts_batch &b, const BinMap &bm, const int32_t *thr, 
     int64_t chunk = (b.total + grid - 1) / grid;
     chunk = (chunk + 63) & ~(int64_t)63;
     grid = (b.total + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_label, dim3((unsigned)grid), dim3(t.label_block), 0, st, b.vox, b.offs, b.nseg, b.total,
-                       chunk, bm, thr, k, out);
+    const dim3 g((unsigned)grid), blk(t.label_block);
+    switch (nsets) {
+    case 1: hipLaunchKernelGGL(k_label<1>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
+    case 2: hipLaunchKernelGGL(k_label<2>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
+    case 3: hipLaunchKernelGGL(k_label<3>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
+    default: hipLaunchKernelGGL(k_label<4>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
+    }
     return check_launch("ts_label");
 }
 

@@ -13,7 +13,9 @@
 //    chunk, so Q(t) == Q(t-1) bit for bit whenever bin t is empty: tuples
 //    that differ only inside a run of empty bins see identical class sums
 //    and tie exactly, as in exact arithmetic;
-//  * results are staged in LDS and written with coalesced stores.
+//  * results are staged in LDS and written with coalesced stores;
+//  * one workgroup per (q index, histogram): all q of a call in one launch.
+//    P does not depend on q and is written by the workgroups of q_0.
 #include "common.h"
 
 namespace ts {
@@ -28,8 +30,12 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__restrict__ hist, int L, double q,
-                                                           double *__restrict__ P, double *__restrict__ Q)
+struct QList {
+    double q[TS_MAX_Q];
+};
+
+__global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__restrict__ hist, int nseg, int L,
+                                                           QList ql, double *__restrict__ P, double *__restrict__ Q)
 {
     extern __shared__ double smem[];
     double *pq = smem;                        // [L]: p^q, then Q
@@ -37,10 +43,12 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
     uint32_t *cnt = (uint32_t *)(smem + 2 * L); // [L]: counts
     __shared__ uint64_t wsum[PREFIX_THREADS / 64];
 
-    const int s = blockIdx.x;
+    const int s = blockIdx.x % nseg, j = blockIdx.x / nseg;
+    const double q = ql.q[j];
+    const bool wp = j == 0; // P is written once
     const uint32_t *h = hist + (int64_t)s * L;
     double *Ps = P + (int64_t)s * L;
-    double *Qs = Q + (int64_t)s * L;
+    double *Qs = Q + (int64_t)blockIdx.x * L;
     const int lane = threadIdx.x & 63;
 
     uint64_t c = 0;
@@ -60,7 +68,8 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
         N += wsum[w];
     if (N == 0) {
         for (int i = threadIdx.x; i < L; i += blockDim.x) {
-            Ps[i] = 0.0;
+            if (wp)
+                Ps[i] = 0.0;
             Qs[i] = 0.0;
         }
         return;
@@ -107,17 +116,22 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
     }
     __syncthreads();
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
-        Ps[i] = sp[i];
+        if (wp)
+            Ps[i] = sp[i];
         Qs[i] = pq[i];
     }
 }
 
-ts_status launch_prefix(const uint32_t *hist, int nseg, int L, double q, double *P, double *Q, hipStream_t st)
+ts_status launch_prefix(const uint32_t *hist, int nseg, int L, int nq, const double *q, double *P, double *Q,
+                        hipStream_t st)
 {
+    QList ql;
+    for (int j = 0; j < TS_MAX_Q; ++j)
+        ql.q[j] = q[j < nq ? j : 0];
     const size_t lds = (size_t)L * (2 * sizeof(double) + sizeof(uint32_t));
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)k_prefix, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_prefix, dim3(nseg), dim3(PREFIX_THREADS), lds, st, hist, L, q, P, Q);
+    hipLaunchKernelGGL(k_prefix, dim3((unsigned)(nseg * nq)), dim3(PREFIX_THREADS), lds, st, hist, nseg, L, ql, P, Q);
     return check_launch("ts_prefix");
 }
 

@@ -171,13 +171,13 @@ __device__ __forceinline__ float4 split_hl(double P, double Q)
 // Signed FP32 class term in log2 units for the class (a, b] from the split
 // prefixes at b and a (a = -1: all zero).  Valid iff the class mass is > 0.
 template <int SGN>
-__device__ __forceinline__ float cls32(const float4 &hb, const float4 &ha, float nq, float gmax)
+__device__ __forceinline__ float cls32(const float4 &hb, const float4 &ha, float mq, float gmax)
 {
     const float dp = (hb.x - ha.x) + (hb.y - ha.y);
     const float dq = (hb.z - ha.z) + (hb.w - ha.w);
     const float lx = __builtin_amdgcn_logf(dq);
     const float ly = __builtin_amdgcn_logf(dp);
-    float g = fmaf(nq, ly, SGN > 0 ? lx : -lx); // nq = -sgn * q
+    float g = fmaf(mq, ly, SGN > 0 ? lx : -lx); // mq = -sgn * q
     g = __builtin_amdgcn_fmed3f(g, 0.0f, gmax);
     return dp > 0.0f ? g : -INFINITY;
 }
@@ -265,11 +265,18 @@ __device__ __forceinline__ void wave_best(double &r, double &l, long long &c)
     c = __double_as_longlong(readlane63_f64(__longlong_as_double(c)));
 }
 
+// Constants of one entropic index q.
+struct QConst {
+    double q, sgn, hmax; // hmax = |1-q| ln L
+    float mq, gmax;      // mq = -sgn * fl32(q), gmax = |1-q| log2 L (rounded up)
+};
+
+// Problem p of a launch uses index q_{p / nseg}, P row p % nseg and Q row p;
+// every per-problem output and workspace row is indexed by p.
 struct Args {
     const double *P, *Q;
-    int nseg, L, Lp, k, mode;
-    double q, sgn, hmax; // hmax = |1-q| ln L
-    float nq, gmax;      // nq = -sgn * fl32(q), gmax = |1-q| log2 L (rounded up)
+    int nseg, nprob, L, Lp, k, mode;
+    QConst qc[TS_MAX_Q];
     int CW, NB, NC, T1, tiles;
     Meta *meta;
     float4 *hl; // [nseg][Lp] split prefixes (multi-launch paths)
@@ -327,18 +334,18 @@ __device__ __forceinline__ Steps block_steps(const double *P, const double *Q, i
 // v_log_f32 and inflated by 1 % + 1.  The result is doubled.  Infinity when a
 // class sum could leave the normal FP32 range: every tuple is then re-checked
 // in FP64.
-__device__ __forceinline__ float problem_delta(const Args &a, Steps st, double qtot)
+__device__ __forceinline__ float problem_delta(const Args &a, const QConst &c, Steps st, double qtot)
 {
     if (a.mode == TS_SEARCH_FP32_ONLY)
         return 0.0f;
     if (!(qtot > 0.0) || !(st.dqmin > 1e-36) || !(st.pmin > 1e-36) || qtot > 1e36)
         return INFINITY;
     const float u = 0x1p-24f;
-    const float q = (float)a.q;
+    const float q = (float)c.q;
     const float lq = fmaxf(fabsf(__builtin_amdgcn_logf((float)qtot)), fabsf(__builtin_amdgcn_logf((float)st.dqmin)));
     const float lp = fabsf(__builtin_amdgcn_logf((float)st.pmin));
     const float Ux = lq * 1.01f + 1.0f, Vy = lp * 1.01f + 1.0f;
-    const float gm = a.gmax;
+    const float gm = c.gmax;
     // split FP32 differences: relative error <= 2u + 4u^2 X_max / (smallest difference)
     const float rp = 2.0f * u + 4.0f * u * u / (float)st.pmin;
     const float rq = 2.0f * u + 4.0f * u * u * (float)(qtot / st.dqmin);
@@ -346,7 +353,7 @@ __device__ __forceinline__ float problem_delta(const Args &a, Steps st, double q
         return INFINITY;
     const float ec = (rq + q * rp) * 1.5f                                    // FP32 class sums
                      + (float)LOG2_ERR_UNITS * u * (Ux + q * Vy)            // v_log_f32
-                     + (float)fabs((double)(-a.sgn * a.nq) - a.q) * Vy      // q rounded to FP32
+                     + (float)fabs((double)(-c.sgn * c.mq) - c.q) * Vy      // q rounded to FP32
                      + u * (gm + 1.0f);                                     // fma + clamp
     const float kk = (float)a.k;
     const float d = 2.0f * ((kk + 1.0f) * ec + kk * (kk + 1.0f) * u * (gm + 1.0f)) + 1e-9f * (kk + 1.0f) * (gm + 1.0f);
@@ -356,8 +363,8 @@ __device__ __forceinline__ float problem_delta(const Args &a, Steps st, double q
 // FP32 head(t) = g(-1, t) and tail(t) = g(t, L-1) for t in [0, Lp); entries
 // past L-2 are -inf.
 template <int SGN>
-__device__ __forceinline__ Steps head_tail32(const Args &a, const double *P, const double *Q, float *hd, float *tl,
-                                             float4 *hl, double *red)
+__device__ __forceinline__ Steps head_tail32(const Args &a, const QConst &c, const double *P, const double *Q,
+                                             float *hd, float *tl, float4 *hl, double *red)
 {
     const int L = a.L;
     const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -377,8 +384,8 @@ __device__ __forceinline__ Steps head_tail32(const Args &a, const double *P, con
         const float4 h4 = split_hl(p, q);
         float h = -INFINITY, g = -INFINITY;
         if (t <= L - 2) {
-            h = cls32<SGN>(h4, zero, a.nq, a.gmax);
-            g = cls32<SGN>(last, h4, a.nq, a.gmax);
+            h = cls32<SGN>(h4, zero, c.mq, c.gmax);
+            g = cls32<SGN>(last, h4, c.mq, c.gmax);
         }
         hd[t] = h;
         tl[t] = g;
@@ -403,25 +410,26 @@ __device__ __forceinline__ Steps head_tail32(const Args &a, const double *P, con
 
 __global__ void __launch_bounds__(256) k_setup(Args a)
 {
-    const int s = blockIdx.x;
-    const double *P = a.P + (int64_t)s * a.L;
+    const int s = blockIdx.x; // problem
+    const QConst &c = a.qc[s / a.nseg];
+    const double *P = a.P + (int64_t)(s % a.nseg) * a.L;
     const double *Q = a.Q + (int64_t)s * a.L;
     const int L = a.L, Lp = a.Lp;
     __shared__ double red[8];
     Steps stp;
     if (a.mode == TS_SEARCH_FP64)
         stp = block_steps(P, Q, L, red);
-    else if (a.sgn > 0)
-        stp = head_tail32<1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
+    else if (c.sgn > 0)
+        stp = head_tail32<1>(a, c, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
                              a.hl + (int64_t)s * Lp, red);
     else
-        stp = head_tail32<-1>(a, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
+        stp = head_tail32<-1>(a, c, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
                               a.hl + (int64_t)s * Lp, red);
     if (threadIdx.x == 0) {
         Meta m;
         m.menc = float_to_ordered(-INFINITY);
         m.pad0 = m.pad1 = 0;
-        m.delta = problem_delta(a, stp, Q[L - 1]);
+        m.delta = problem_delta(a, c, stp, Q[L - 1]);
         a.meta[s] = m;
     }
     if (a.mode == TS_SEARCH_FP64) {
@@ -431,8 +439,8 @@ __global__ void __launch_bounds__(256) k_setup(Args a)
         for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
             double h = -INFINITY, g = -INFINITY;
             if (t <= L - 2) {
-                h = cls64(P[t], Q[t], a.q, a.sgn, a.hmax);
-                g = cls64(pL - P[t], qL - Q[t], a.q, a.sgn, a.hmax);
+                h = cls64(P[t], Q[t], c.q, c.sgn, c.hmax);
+                g = cls64(pL - P[t], qL - Q[t], c.q, c.sgn, c.hmax);
             }
             hd[t] = h;
             tl[t] = g;
@@ -447,7 +455,8 @@ __global__ void __launch_bounds__(256) k_pairs64(Args a)
     const int s = blockIdx.x / (a.L - 3);
     const int t2 = 1 + blockIdx.x % (a.L - 3);
     const int L = a.L, Lp = a.Lp;
-    const double *P = a.P + (int64_t)s * L;
+    const QConst &c = a.qc[s / a.nseg];
+    const double *P = a.P + (int64_t)(s % a.nseg) * L;
     const double *Q = a.Q + (int64_t)s * L;
     const double *hd = (const double *)a.head + (int64_t)s * Lp;
     const double *tl = (const double *)a.tail + (int64_t)s * Lp;
@@ -457,9 +466,9 @@ __global__ void __launch_bounds__(256) k_pairs64(Args a)
     for (int t = threadIdx.x; t < Lp; t += blockDim.x) {
         double av = -INFINITY, rv = -INFINITY;
         if (t < t2)
-            av = hd[t] + cls64(p2 - P[t], q2 - Q[t], a.q, a.sgn, a.hmax);
+            av = hd[t] + cls64(p2 - P[t], q2 - Q[t], c.q, c.sgn, c.hmax);
         else if (t <= L - 2 && t > t2)
-            rv = cls64(P[t] - p2, Q[t] - q2, a.q, a.sgn, a.hmax) + tl[t];
+            rv = cls64(P[t] - p2, Q[t] - q2, c.q, c.sgn, c.hmax) + tl[t];
         Ar[t] = av;
         Rr[t] = rv;
     }
@@ -480,7 +489,7 @@ __device__ __forceinline__ Tile tile_of(const Args &a)
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
     Tile t;
-    t.valid = g < (int64_t)a.nseg * a.tiles;
+    t.valid = g < (int64_t)a.nprob * a.tiles;
     t.s = (int)(g / a.tiles);
     t.tile = (int)(g % a.tiles);
     t.b = t.tile % a.NB;
@@ -501,7 +510,7 @@ struct TileCtx {
     const float *A, *R;   // k = 3 rows of the problem (global)
     int L, Lp, mode, CW, T1;
     double q, sgn, hmax;
-    float nq, gmax;
+    float mq, gmax;
 };
 
 __device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *hd, const float *tr,
@@ -509,7 +518,8 @@ __device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *h
 {
     TileCtx x;
     x.hl = hl;
-    x.P = a.P + (int64_t)s * a.L;
+    const QConst &c = a.qc[s / a.nseg];
+    x.P = a.P + (int64_t)(s % a.nseg) * a.L;
     x.Q = a.Q + (int64_t)s * a.L;
     x.hd = hd;
     x.tr = tr;
@@ -520,11 +530,11 @@ __device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *h
     x.mode = a.mode;
     x.CW = a.CW;
     x.T1 = a.T1;
-    x.q = a.q;
-    x.sgn = a.sgn;
-    x.hmax = a.hmax;
-    x.nq = a.nq;
-    x.gmax = a.gmax;
+    x.q = c.q;
+    x.sgn = c.sgn;
+    x.hmax = c.hmax;
+    x.mq = c.mq;
+    x.gmax = c.gmax;
     return x;
 }
 
@@ -582,7 +592,7 @@ __device__ __forceinline__ void rows_k2_group(const TileCtx &x, int t1, const fl
     for (int u = 0; u < R; ++u) {
 #pragma unroll
         for (int v = 0; v < COLS; ++v) {
-            const float key = (hdr[u] + cls32<SGN>(hc[v], hr[u], x.nq, x.gmax)) + tc[v];
+            const float key = (hdr[u] + cls32<SGN>(hc[v], hr[u], x.mq, x.gmax)) + tc[v];
             if (!MASK || t1 + u < t2v[v])
                 take<PHASE, 2>(x, key, thr, acc, best, t1 + u, t2v[v], 0);
         }
@@ -651,11 +661,8 @@ __device__ __forceinline__ float phase2_threshold(float M, float delta)
 // Multi-launch path, one tile per wavefront.  PHASE 1 writes the tile max and
 // the problem max; PHASE 2 re-checks tiles whose max reaches the threshold.
 template <int SGN, int COLS, int PHASE, int K>
-__global__ void __launch_bounds__(256) k_tiles32(Args a)
+__device__ __forceinline__ void tiles32_wave(const Args &a, const Tile &tl)
 {
-    const Tile tl = tile_of(a);
-    if (!tl.valid)
-        return;
     const int lane = threadIdx.x & 63;
     const int s = tl.s;
     const int64_t tid = (int64_t)s * a.tiles + tl.tile;
@@ -688,6 +695,19 @@ __global__ void __launch_bounds__(256) k_tiles32(Args a)
         if (lane == 0)
             a.best[tid] = Best{best.r, best.l, best.c, 0};
     }
+}
+
+// The sign of 1 - q is uniform over a tile's wavefront.
+template <int COLS, int PHASE, int K>
+__global__ void __launch_bounds__(256) k_tiles32(Args a)
+{
+    const Tile tl = tile_of(a);
+    if (!tl.valid)
+        return;
+    if (a.qc[tl.s / a.nseg].sgn > 0)
+        tiles32_wave<1, COLS, PHASE, K>(a, tl);
+    else
+        tiles32_wave<-1, COLS, PHASE, K>(a, tl);
 }
 
 // k = 3, one workgroup per (problem, row t2, chunk of 1024 columns).  The A
@@ -752,9 +772,8 @@ __device__ __forceinline__ void rows3_loop(const TileCtx &x, const float *Arow, 
 // whose max reaches the threshold.  Rows are visited from the middle
 // outwards so the heaviest rows (t2 (L - t2) tuples) start first.
 template <int SGN, int PHASE>
-__global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
+__device__ __forceinline__ void rows3_body(const Args &a, float *Arow, float *wm)
 {
-    __shared__ float Arow[FUSED_MAX_L + 16];
     const int L = a.L;
     const int nrow = L - 3, nch = a.NC; // NC = column chunks per row
     const int ng = a.T1;                // row groups per wavefront tile
@@ -802,7 +821,7 @@ __global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
     }
     const float4 h2 = x.hl[t2];
     for (int t1 = threadIdx.x; t1 < n1; t1 += K3_THREADS)
-        Arow[t1] = t1 < t2 ? x.hd[t1] + cls32<SGN>(h2, x.hl[t1], x.nq, x.gmax) : -INFINITY;
+        Arow[t1] = t1 < t2 ? x.hd[t1] + cls32<SGN>(h2, x.hl[t1], x.mq, x.gmax) : -INFINITY;
     float r[K3_COLS];
     int t3v[K3_COLS];
     int nv = 0; // column blocks of this wavefront holding a valid column
@@ -812,7 +831,7 @@ __global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
         const int c = cb + lane;
         const int t3 = t2 + 1 + c;
         t3v[v] = t3;
-        r[v] = c < ncols ? cls32<SGN>(x.hl[t3], h2, x.nq, x.gmax) + x.tr[t3] : -INFINITY;
+        r[v] = c < ncols ? cls32<SGN>(x.hl[t3], h2, x.mq, x.gmax) + x.tr[t3] : -INFINITY;
         nv += cb < ncols ? 1 : 0;
     }
     __syncthreads();
@@ -840,7 +859,6 @@ __global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
         for (int g = ngr + lane; g < ng; g += 64)
             gmax_w[g] = -INFINITY;
         // one atomic per workgroup for the problem max
-        __shared__ float wm[K3_THREADS / 64];
         if (lane == 0)
             wm[w] = wmax;
         __syncthreads();
@@ -858,15 +876,32 @@ __global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
     }
 }
 
-// Write one problem's result from its best candidate.
-__device__ __forceinline__ void write_result(const Cand &b, int s, const double *P, int L, int k, double q, double sgn,
-                                             int32_t *thr, double *obj, int32_t *status)
+template <int PHASE>
+__global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
 {
+    extern __shared__ float4 arow_dyn[]; // Lp floats: the A row up to t2 (rounded up to 8)
+    float *Arow = reinterpret_cast<float *>(arow_dyn);
+    __shared__ float wm[K3_THREADS / 64];
+    const int s = (int)((int64_t)blockIdx.x / ((int64_t)(a.L - 3) * a.NC));
+    if (a.qc[s / a.nseg].sgn > 0)
+        rows3_body<1, PHASE>(a, Arow, wm);
+    else
+        rows3_body<-1, PHASE>(a, Arow, wm);
+}
+
+// Write one problem's result from its best candidate.
+// Write problem s's result from its best candidate.
+__device__ __forceinline__ void write_result(const Cand &b, const Args &a, int s, int32_t *thr, double *obj,
+                                             int32_t *status)
+{
+    const int k = a.k, L = a.L;
+    const QConst &qc = a.qc[s / a.nseg];
+    const double q = qc.q, sgn = qc.sgn;
     if (b.r == -INFINITY) {
         for (int j = 0; j < k; ++j)
             thr[(int64_t)s * k + j] = -1;
         obj[s] = NAN;
-        status[s] = P[(int64_t)s * L + L - 1] > 0.0 ? TS_PROBLEM_DEGENERATE : TS_PROBLEM_EMPTY;
+        status[s] = a.P[(int64_t)(s % a.nseg) * L + L - 1] > 0.0 ? TS_PROBLEM_DEGENERATE : TS_PROBLEM_EMPTY;
     } else {
         long long c = b.c;
         for (int j = k - 1; j >= 0; --j) {
@@ -881,24 +916,38 @@ __device__ __forceinline__ void write_result(const Cand &b, int s, const double 
 // Single-launch path: one workgroup per problem does the setup, phase 1,
 // phase 2 and the final reduction; head/tail rows and tile maxima stay in LDS.
 
-template <int SGN, int COLS, int K>
-__global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__restrict__ thr_out,
-                                                         double *__restrict__ obj, int32_t *__restrict__ status)
+// LDS of the one-workgroup path: the rows hd, tr [Lp], the split prefixes
+// hls [Lp] (k = 2) and the tile maxima tmax [tiles] are carved from dynamic
+// LDS sized for the launch (fused_lds_bytes); the rest is static.
+struct FusedLds {
+    float *hd, *tr, *tmax;
+    float4 *hls;
+    double red[2 * (FUSED_THREADS / 64)];
+    float wmax[FUSED_THREADS / 64];
+    double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
+    long long wc[FUSED_THREADS / 64];
+    float sdelta;
+};
+
+static size_t fused_lds_bytes(int Lp, int k, int tiles)
 {
-    __shared__ float hd[FUSED_MAX_L], tr[FUSED_MAX_L];
-    __shared__ float4 hls[FUSED_MAX_L2];
-    __shared__ float tmax[FUSED_MAX_TILES];
-    __shared__ double red[2 * (FUSED_THREADS / 64)];
-    __shared__ float wmax[FUSED_THREADS / 64];
-    __shared__ double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
-    __shared__ long long wc[FUSED_THREADS / 64];
-    __shared__ float sdelta;
+    return (size_t)Lp * (2 * sizeof(float) + (k == 2 ? sizeof(float4) : 0)) + (size_t)tiles * sizeof(float);
+}
+
+template <int SGN, int COLS, int K>
+__device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t *__restrict__ thr_out,
+                                           double *__restrict__ obj, int32_t *__restrict__ status)
+{
+    float *hd = sh.hd, *tr = sh.tr, *tmax = sh.tmax, *wmax = sh.wmax;
+    float4 *hls = sh.hls;
     const int s = blockIdx.x;
-    const double *P = a.P + (int64_t)s * a.L;
+    const QConst &qc = a.qc[s / a.nseg];
+    const double *P = a.P + (int64_t)(s % a.nseg) * a.L;
     const double *Q = a.Q + (int64_t)s * a.L;
-    const Steps stp = head_tail32<SGN>(a, P, Q, hd, tr, K == 2 ? hls : nullptr, red); // k = 2: split prefixes in LDS
+    // k = 2: split prefixes in LDS
+    const Steps stp = head_tail32<SGN>(a, qc, P, Q, hd, tr, K == 2 ? hls : nullptr, sh.red);
     if (threadIdx.x == 0)
-        sdelta = problem_delta(a, stp, Q[a.L - 1]);
+        sh.sdelta = problem_delta(a, qc, stp, Q[a.L - 1]);
     __syncthreads();
     const TileCtx x = make_ctx(a, s, hd, tr, hls);
     const int lane = threadIdx.x & 63;
@@ -921,7 +970,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__rest
     for (int i = 0; i < nw; ++i)
         M = fmaxf(M, wmax[i]);
     if (M > -INFINITY) {
-        const float thr = phase2_threshold(M, sdelta);
+        const float thr = phase2_threshold(M, sh.sdelta);
         for (int tile = w; tile < a.tiles; tile += nw) {
             if (tmax[tile] >= thr) {
                 float acc = -INFINITY;
@@ -931,20 +980,36 @@ __global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__rest
     }
     wave_best(best.r, best.l, best.c);
     if (lane == 0) {
-        wr[w] = best.r;
-        wl[w] = best.l;
-        wc[w] = best.c;
+        sh.wr[w] = best.r;
+        sh.wl[w] = best.l;
+        sh.wc[w] = best.c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 0; i < nw; ++i)
-            if (better(wr[i], wc[i], best.r, best.c)) {
-                best.r = wr[i];
-                best.l = wl[i];
-                best.c = wc[i];
+            if (better(sh.wr[i], sh.wc[i], best.r, best.c)) {
+                best.r = sh.wr[i];
+                best.l = sh.wl[i];
+                best.c = sh.wc[i];
             }
-        write_result(best, s, a.P, a.L, K, a.q, a.sgn, thr_out, obj, status);
+        write_result(best, a, s, thr_out, obj, status);
     }
+}
+
+template <int COLS, int K>
+__global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__restrict__ thr_out,
+                                                         double *__restrict__ obj, int32_t *__restrict__ status)
+{
+    __shared__ FusedLds sh;
+    extern __shared__ float4 dyn[]; // fused_lds_bytes(Lp, K, tiles)
+    sh.hls = dyn;                   // 16-byte aligned: Lp is a multiple of 256
+    sh.hd = reinterpret_cast<float *>(dyn + (K == 2 ? a.Lp : 0));
+    sh.tr = sh.hd + a.Lp;
+    sh.tmax = sh.tr + a.Lp;
+    if (a.qc[blockIdx.x / a.nseg].sgn > 0)
+        fused_body<1, COLS, K>(a, sh, thr_out, obj, status);
+    else
+        fused_body<-1, COLS, K>(a, sh, thr_out, obj, status);
 }
 
 // FP64 mode: exhaustive FP64 keys with the lexicographic tie rule.
@@ -958,7 +1023,8 @@ __global__ void __launch_bounds__(256) k_tiles64(Args a)
     const int L = a.L, Lp = a.Lp, k = a.k;
     const int s = tl.s;
     const int64_t tid = (int64_t)s * a.tiles + tl.tile;
-    const double *P = a.P + (int64_t)s * L;
+    const QConst &c = a.qc[s / a.nseg];
+    const double *P = a.P + (int64_t)(s % a.nseg) * L;
     const double *Q = a.Q + (int64_t)s * L;
     const double *hd = (const double *)a.head + (int64_t)s * Lp;
     const double *tr = (const double *)a.tail + (int64_t)s * Lp;
@@ -985,7 +1051,7 @@ __global__ void __launch_bounds__(256) k_tiles64(Args a)
                 const int t2 = cbase + v * 64 + lane;
                 if (t1 < t2) {
                     const int ti = min(t2, L - 1);
-                    const double key = (hr + cls64(P[ti] - pr, Q[ti] - qr, a.q, a.sgn, a.hmax)) + tr[t2];
+                    const double key = (hr + cls64(P[ti] - pr, Q[ti] - qr, c.q, c.sgn, c.hmax)) + tr[t2];
                     offer(key, ((long long)t1 << 12) | t2);
                 }
             }
@@ -1020,9 +1086,9 @@ __global__ void __launch_bounds__(256) k_tiles64(Args a)
 
 // ---------------------------------------------------------------- final
 
-__global__ void __launch_bounds__(1024) k_final(const Best *__restrict__ best, int per, const double *__restrict__ P,
-                                                int L, int k, double q, double sgn, int32_t *__restrict__ thr,
-                                                double *__restrict__ obj, int32_t *__restrict__ status, int s_base)
+__global__ void __launch_bounds__(1024) k_final(Args a, const Best *__restrict__ best, int per,
+                                                int32_t *__restrict__ thr, double *__restrict__ obj,
+                                                int32_t *__restrict__ status, int s_base)
 {
     const int s = s_base + blockIdx.x;
     const Best *b = best + (int64_t)blockIdx.x * per;
@@ -1068,7 +1134,7 @@ __global__ void __launch_bounds__(1024) k_final(const Best *__restrict__ best, i
                 bl = sl[j];
                 bc = sc[j];
             }
-        write_result(Cand{br, bl, bc}, s, P, L, k, q, sgn, thr, obj, status);
+        write_result(Cand{br, bl, bc}, a, s, thr, obj, status);
     }
 }
 
@@ -1148,68 +1214,73 @@ __global__ void __launch_bounds__(256) k_plain(const double *__restrict__ P, con
 
 // ---------------------------------------------------------------- dispatch
 
-template <int SGN, int COLS, int K>
-static void launch_phases(dim3 g, hipStream_t st, const Args &a)
-{
-    hipLaunchKernelGGL((k_tiles32<SGN, COLS, 1, K>), g, dim3(256), 0, st, a);
-    hipLaunchKernelGGL((k_tiles32<SGN, COLS, 2, K>), g, dim3(256), 0, st, a);
-}
-
-template <int SGN, int COLS>
-static void launch_fp32(int fused_block, int k, dim3 g, int nseg, hipStream_t st, const Args &a, int32_t *thr,
-                        double *obj, int32_t *status)
+template <int COLS>
+static void launch_fp32(int fused_block, int k, dim3 g, hipStream_t st, const Args &a, int32_t *thr, double *obj,
+                        int32_t *status)
 {
     if (fused_block) {
+        const dim3 gf((unsigned)a.nprob), bf((unsigned)fused_block);
+        const size_t lds = fused_lds_bytes(a.Lp, k, a.tiles);
         if (k == 1)
-            hipLaunchKernelGGL((k_fused<SGN, COLS, 1>), dim3(nseg), dim3(fused_block), 0, st, a, thr, obj, status);
+            hipLaunchKernelGGL((k_fused<COLS, 1>), gf, bf, lds, st, a, thr, obj, status);
         else
-            hipLaunchKernelGGL((k_fused<SGN, COLS, 2>), dim3(nseg), dim3(fused_block), 0, st, a, thr, obj, status);
+            hipLaunchKernelGGL((k_fused<COLS, 2>), gf, bf, lds, st, a, thr, obj, status);
         return;
     }
-    if (k == 1)
-        launch_phases<SGN, COLS, 1>(g, st, a);
-    else
-        launch_phases<SGN, COLS, 2>(g, st, a); // k = 3 uses k_rows3
+    if (k == 1) {
+        hipLaunchKernelGGL((k_tiles32<COLS, 1, 1>), g, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_tiles32<COLS, 2, 1>), g, dim3(256), 0, st, a);
+    } else { // k = 3 uses k_rows3
+        hipLaunchKernelGGL((k_tiles32<COLS, 1, 2>), g, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_tiles32<COLS, 2, 2>), g, dim3(256), 0, st, a);
+    }
 }
 
-template <int SGN>
-static void launch_fp32_cols(int cols, int fused, int k, dim3 g, int nseg, hipStream_t st, const Args &a,
-                             int32_t *thr, double *obj, int32_t *status)
+static void launch_fp32_cols(int cols, int fused, int k, dim3 g, hipStream_t st, const Args &a, int32_t *thr,
+                             double *obj, int32_t *status)
 {
     if (cols == 1)
-        launch_fp32<SGN, 1>(fused, k, g, nseg, st, a, thr, obj, status);
+        launch_fp32<1>(fused, k, g, st, a, thr, obj, status);
     else if (cols == 2)
-        launch_fp32<SGN, 2>(fused, k, g, nseg, st, a, thr, obj, status);
+        launch_fp32<2>(fused, k, g, st, a, thr, obj, status);
     else
-        launch_fp32<SGN, 4>(fused, k, g, nseg, st, a, thr, obj, status);
+        launch_fp32<4>(fused, k, g, st, a, thr, obj, status);
 }
 
-ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, double q, int mode, void *ws,
-                        size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t, hipStream_t st)
+QConst make_qconst(double q, int L)
+{
+    QConst c;
+    c.q = q;
+    c.sgn = q < 1.0 ? 1.0 : -1.0;
+    c.hmax = fabs(1.0 - q) * log((double)L);
+    c.mq = (float)(-c.sgn) * (float)q;
+    const double gm = fabs(1.0 - q) * log2((double)L);
+    float g = (float)gm;
+    if ((double)g < gm)
+        g = nextafterf(g, INFINITY);
+    c.gmax = g;
+    return c;
+}
+
+ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, int nq, const double *q, int mode,
+                        void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t,
+                        hipStream_t st)
 {
     (void)ws_bytes;
-    const Plan p = make_plan(nseg, L, k, mode, t.search_cols, t.search_rows);
+    const int nprob = nq * nseg;
+    const Plan p = make_plan(nprob, L, k, mode, t.search_cols, t.search_rows);
     char *base = (char *)ws;
     Args a;
     a.P = P;
     a.Q = Q;
     a.nseg = nseg;
+    a.nprob = nprob;
     a.L = L;
     a.Lp = p.Lp;
     a.k = k;
     a.mode = mode;
-    a.q = q;
-    a.sgn = q < 1.0 ? 1.0 : -1.0;
-    a.hmax = fabs(1.0 - q) * log((double)L);
-    const float q32 = (float)q;
-    a.nq = (float)(-a.sgn) * q32;
-    {
-        double gm = fabs(1.0 - q) * log2((double)L);
-        float g = (float)gm;
-        if ((double)g < gm)
-            g = nextafterf(g, INFINITY);
-        a.gmax = g;
-    }
+    for (int j = 0; j < TS_MAX_Q; ++j)
+        a.qc[j] = make_qconst(q[j < nq ? j : 0], L);
     a.CW = p.CW;
     a.NB = p.NB;
     a.NC = p.NC;
@@ -1229,11 +1300,11 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
         const int64_t ntup = k == 1 ? n : (k == 2 ? n * (n - 1) / 2 : n * (n - 1) * (n - 2) / 6);
         const int blocks = (int)std::min<int64_t>(PLAIN_BLOCKS, std::max<int64_t>(1, (ntup + 255) / 256));
         Best *pb = (Best *)(base + p.off_plain);
-        for (int s = 0; s < nseg; ++s) {
-            hipLaunchKernelGGL(k_plain, dim3(blocks), dim3(256), 0, st, P + (int64_t)s * L, Q + (int64_t)s * L, L,
-                               k, ntup, q, a.sgn, a.hmax, pb);
-            hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, pb, blocks, P, L, k, q, a.sgn, thr, obj, status,
-                               s);
+        for (int s = 0; s < nprob; ++s) {
+            const QConst &c = a.qc[s / nseg];
+            hipLaunchKernelGGL(k_plain, dim3(blocks), dim3(256), 0, st, P + (int64_t)(s % nseg) * L,
+                               Q + (int64_t)s * L, L, k, ntup, c.q, c.sgn, c.hmax, pb);
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, a, pb, blocks, thr, obj, status, s);
         }
         return check_launch("ts_threshold_search (plain)");
     }
@@ -1242,32 +1313,24 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
     // one workgroup per problem when that fills the chip or the problem is small
     const bool can_fuse = fp32 && p.tiles <= FUSED_MAX_TILES && p.Lp <= FUSED_MAX_L &&
                           (k == 1 || (k == 2 && L <= FUSED_MAX_L2));
-    const bool fused = can_fuse && (t.search_path == 1 || (t.search_path == 0 && (k == 1 || nseg >= 128)));
-    const int64_t waves = (int64_t)nseg * p.tiles;
+    const bool fused = can_fuse && (t.search_path == 1 || (t.search_path == 0 && (k == 1 || nprob >= 128)));
+    const int64_t waves = (int64_t)nprob * p.tiles;
     dim3 g((unsigned)((waves + 3) / 4));
     if (fused) {
-        if (a.sgn > 0)
-            launch_fp32_cols<1>(t.search_cols, t.search_block, k, g, nseg, st, a, thr, obj, status);
-        else
-            launch_fp32_cols<-1>(t.search_cols, t.search_block, k, g, nseg, st, a, thr, obj, status);
+        launch_fp32_cols(t.search_cols, t.search_block, k, g, st, a, thr, obj, status);
         return check_launch("ts_threshold_search");
     }
-    hipLaunchKernelGGL(k_setup, dim3(nseg), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_setup, dim3(nprob), dim3(256), 0, st, a);
     if (k == 3 && mode == TS_SEARCH_FP64) {
-        dim3 gp((unsigned)((int64_t)(L - 3) * nseg));
+        dim3 gp((unsigned)((int64_t)(L - 3) * nprob));
         hipLaunchKernelGGL(k_pairs64, gp, dim3(256), 0, st, a);
     }
     if (k == 3 && fp32) {
-        dim3 gr((unsigned)((int64_t)(L - 3) * p.NC * nseg));
-        if (a.sgn > 0) {
-            hipLaunchKernelGGL((k_rows3<1, 1>), gr, dim3(K3_THREADS), 0, st, a);
-            hipLaunchKernelGGL((k_rows3<1, 2>), gr, dim3(K3_THREADS), 0, st, a);
-        } else {
-            hipLaunchKernelGGL((k_rows3<-1, 1>), gr, dim3(K3_THREADS), 0, st, a);
-            hipLaunchKernelGGL((k_rows3<-1, 2>), gr, dim3(K3_THREADS), 0, st, a);
-        }
-        hipLaunchKernelGGL(k_final, dim3(nseg), dim3(1024), 0, st, a.best, p.tiles, P, L, k, q, a.sgn, thr, obj, status,
-                           0);
+        dim3 gr((unsigned)((int64_t)(L - 3) * p.NC * nprob));
+        const size_t lds = (size_t)p.Lp * sizeof(float);
+        hipLaunchKernelGGL(k_rows3<1>, gr, dim3(K3_THREADS), lds, st, a);
+        hipLaunchKernelGGL(k_rows3<2>, gr, dim3(K3_THREADS), lds, st, a);
+        hipLaunchKernelGGL(k_final, dim3(nprob), dim3(1024), 0, st, a, a.best, p.tiles, thr, obj, status, 0);
         return check_launch("ts_threshold_search");
     }
     if (mode == TS_SEARCH_FP64) {
@@ -1277,12 +1340,10 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
             hipLaunchKernelGGL(k_tiles64<2>, g, dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL(k_tiles64<4>, g, dim3(256), 0, st, a);
-    } else if (a.sgn > 0) {
-        launch_fp32_cols<1>(t.search_cols, 0, k, g, nseg, st, a, thr, obj, status);
     } else {
-        launch_fp32_cols<-1>(t.search_cols, 0, k, g, nseg, st, a, thr, obj, status);
+        launch_fp32_cols(t.search_cols, 0, k, g, st, a, thr, obj, status);
     }
-    hipLaunchKernelGGL(k_final, dim3(nseg), dim3(1024), 0, st, a.best, p.tiles, P, L, k, q, a.sgn, thr, obj, status, 0);
+    hipLaunchKernelGGL(k_final, dim3(nprob), dim3(1024), 0, st, a, a.best, p.tiles, thr, obj, status, 0);
     return check_launch("ts_threshold_search");
 }
 

@@ -28,7 +28,8 @@ def lib():
 
 def test_header_declares_the_path():
     names = declared_functions()
-    for n in ("ts_histogram", "ts_prefix", "ts_threshold_search", "ts_label", "ts_search_workspace_bytes",
+    for n in ("ts_histogram", "ts_prefix", "ts_threshold_search", "ts_label", "ts_label_sets",
+              "ts_search_workspace_bytes",
               "ts_last_error", "ts_abi_version"):
         assert n in names, names
 
@@ -53,11 +54,12 @@ class Batch(ctypes.Structure):
 def _bind(lib):
     P, i32, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
     lib.ts_histogram.argtypes = [Batch, Binning, P, P, P]
-    lib.ts_prefix.argtypes = [P, i32, i32, f64, P, P, P]
-    lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.ts_prefix.argtypes = [P, i32, i32, i32, P, P, P, P]
+    lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
     lib.ts_search_workspace_bytes.restype = sz
-    lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, f64, i32, P, sz, P, P, P, P, P]
+    lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, sz, P, P, P, P, P]
     lib.ts_label.argtypes = [Batch, Binning, P, i32, P, P, P]
+    lib.ts_label_sets.argtypes = [Batch, Binning, i32, P, i32, P, P, P]
     lib.ts_last_error.restype = ctypes.c_char_p
     return lib
 
@@ -65,29 +67,38 @@ def _bind(lib):
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
 
 
+def qs(*v):
+    """[host] array of q values."""
+    return ctypes.cast((ctypes.c_double * len(v))(*v), ctypes.c_void_p)
+
+
 def test_abi_version(lib):
     lib.ts_abi_version.restype = ctypes.c_int32
-    assert lib.ts_abi_version() == 1
+    assert lib.ts_abi_version() == 2
 
 
 def test_workspace_sizes(lib):
     _bind(lib)
     ws = lib.ts_search_workspace_bytes
-    assert ws(1, 4096, 1, 0) > 0
-    assert ws(300, 256, 2, 0) >= 300 * 256 * 8  # head + tail rows
-    assert 0 < ws(1, 1024, 3, 0) < ws(1, 1024, 3, 2)  # FP32 k = 3 builds its rows in LDS
-    assert ws(1, 1024, 3, 2) >= 2 * 1024 * 1024 * 8  # FP64 rows
-    assert ws(10, 256, 2, 0) > ws(5, 256, 2, 0)
-    for bad in [(-1, 256, 1, 0), (1, 1, 1, 0), (1, 4097, 1, 0), (1, 256, 0, 0), (1, 256, 4, 0), (1, 256, 1, 7)]:
+    assert ws(1, 4096, 1, 1, 0) > 0
+    assert ws(300, 256, 2, 1, 0) >= 300 * 256 * 8  # head + tail rows
+    assert 0 < ws(1, 1024, 3, 1, 0) < ws(1, 1024, 3, 1, 2)  # FP32 k = 3 builds its rows in LDS
+    assert ws(1, 1024, 3, 1, 2) >= 2 * 1024 * 1024 * 8  # FP64 rows
+    assert ws(10, 256, 2, 1, 0) > ws(5, 256, 2, 1, 0)
+    assert ws(100, 256, 2, 3, 0) == ws(300, 256, 2, 1, 0)  # nq x nseg problems
+    for bad in [(-1, 256, 1, 1, 0), (1, 1, 1, 1, 0), (1, 4097, 1, 1, 0), (1, 256, 0, 1, 0), (1, 256, 4, 1, 0),
+                (1, 256, 1, 1, 7), (1, 256, 1, 0, 0), (1, 256, 1, 9, 0)]:
         assert ws(*bad) == 0, bad
 
 
 @pytest.mark.parametrize("case,expect", [
     ("hist_neg_nseg", 1), ("hist_bad_bins", 1), ("hist_lo_gt_hi", 1), ("hist_null", 1), ("hist_bad_tune", 1),
-    ("prefix_q0", 1), ("prefix_qnan", 1), ("prefix_bins", 1), ("prefix_null", 1),
+    ("prefix_q0", 1), ("prefix_qnan", 1), ("prefix_bins", 1), ("prefix_null", 1), ("prefix_nq0", 1),
+    ("prefix_nq9", 1), ("prefix_qarr_null", 1), ("prefix_second_q_bad", 1),
     ("search_k0", 1), ("search_k4", 1), ("search_q1", 2), ("search_mode", 1), ("search_ws", 3),
-    ("search_bins_lt_k1", 1), ("search_null", 1),
+    ("search_bins_lt_k1", 1), ("search_null", 1), ("search_nq0", 1), ("search_nq9", 1), ("search_q1_in_batch", 2),
     ("label_k", 1), ("label_null", 1), ("label_total_without_seg", 1),
+    ("sets_zero", 1), ("sets_five", 1), ("sets_null_array", 1), ("sets_null_entry", 1), ("sets_k", 1),
 ])
 def test_argument_errors(lib, case, expect):
     _bind(lib)
@@ -107,28 +118,46 @@ def test_argument_errors(lib, case, expect):
         tune = (ctypes.c_int32 * 10)(100, 0, 0, 0, 0, 0, 0, 0, 0, 0)  # block not a multiple of 64
         st = lib.ts_histogram(b1, ok_bin, FAKE, ctypes.cast(tune, T), sx)
     elif case == "prefix_q0":
-        st = lib.ts_prefix(FAKE, 1, 256, 0.0, FAKE, FAKE, sx)
+        st = lib.ts_prefix(FAKE, 1, 256, 1, qs(0.0), FAKE, FAKE, sx)
     elif case == "prefix_qnan":
-        st = lib.ts_prefix(FAKE, 1, 256, float("nan"), FAKE, FAKE, sx)
+        st = lib.ts_prefix(FAKE, 1, 256, 1, qs(float("nan")), FAKE, FAKE, sx)
     elif case == "prefix_bins":
-        st = lib.ts_prefix(FAKE, 1, 1, 0.8, FAKE, FAKE, sx)
+        st = lib.ts_prefix(FAKE, 1, 1, 1, qs(0.8), FAKE, FAKE, sx)
     elif case == "prefix_null":
-        st = lib.ts_prefix(None, 1, 256, 0.8, FAKE, FAKE, sx)
-    elif case in ("search_k0", "search_k4", "search_q1", "search_mode", "search_ws", "search_bins_lt_k1",
-                  "search_null"):
+        st = lib.ts_prefix(None, 1, 256, 1, qs(0.8), FAKE, FAKE, sx)
+    elif case == "prefix_nq0":
+        st = lib.ts_prefix(FAKE, 1, 256, 0, qs(0.8), FAKE, FAKE, sx)
+    elif case == "prefix_nq9":
+        st = lib.ts_prefix(FAKE, 1, 256, 9, qs(*([0.8] * 9)), FAKE, FAKE, sx)
+    elif case == "prefix_qarr_null":
+        st = lib.ts_prefix(FAKE, 1, 256, 1, None, FAKE, FAKE, sx)
+    elif case == "prefix_second_q_bad":
+        st = lib.ts_prefix(FAKE, 1, 256, 2, qs(0.8, -1.0), FAKE, FAKE, sx)
+    elif case.startswith("search_"):
         k = {"search_k0": 0, "search_k4": 4}.get(case, 2)
-        q = 1.0 if case == "search_q1" else 0.8
+        q = {"search_q1": (1.0,), "search_q1_in_batch": (0.5, 1.0, 1.5)}.get(case, (0.8,))
+        nq = {"search_nq0": 0, "search_nq9": 9}.get(case, len(q))
+        if case == "search_nq9":
+            q = (0.8,) * 9
         mode = 9 if case == "search_mode" else 0
         L = 2 if case == "search_bins_lt_k1" else 256
         ws_bytes = 16 if case == "search_ws" else 1 << 40
         P = None if case == "search_null" else FAKE
-        st = lib.ts_threshold_search(P, FAKE, 1, L, k, q, mode, FAKE, ws_bytes, FAKE, FAKE, FAKE, None, sx)
+        st = lib.ts_threshold_search(P, FAKE, 1, L, k, nq, qs(*q), mode, FAKE, ws_bytes, FAKE, FAKE, FAKE, None, sx)
     elif case == "label_k":
         st = lib.ts_label(b1, ok_bin, FAKE, 0, FAKE, None, sx)
     elif case == "label_null":
         st = lib.ts_label(b1, ok_bin, None, 1, FAKE, None, sx)
     elif case == "label_total_without_seg":
         st = lib.ts_label(Batch(None, None, 0, 5), ok_bin, FAKE, 1, FAKE, None, sx)
+    elif case.startswith("sets_"):
+        n = {"sets_zero": 0, "sets_five": 5}.get(case, 2)
+        thr = (T * 5)(*([FAKE.value] * 5))
+        outp = (T * 5)(*([FAKE.value] * 5))
+        if case == "sets_null_entry":
+            outp[1] = None
+        arr = None if case == "sets_null_array" else ctypes.cast(thr, T)
+        st = lib.ts_label_sets(b1, ok_bin, n, arr, 4 if case == "sets_k" else 2, ctypes.cast(outp, T), None, sx)
     assert st == expect, (case, st, lib.ts_last_error())
     assert lib.ts_last_error(), "an error text must be set"
 
@@ -138,5 +167,7 @@ def test_empty_batch_is_a_no_op(lib):
     ok_bin = Binning(-1024, 3071, 256)
     assert lib.ts_histogram(Batch(None, None, 0, 0), ok_bin, None, None, None) == 0
     assert lib.ts_label(Batch(None, None, 0, 0), ok_bin, None, 1, None, None, None) == 0
-    assert lib.ts_prefix(None, 0, 256, 0.8, None, None, None) == 0
-    assert lib.ts_threshold_search(None, None, 0, 256, 2, 0.8, 0, None, 0, None, None, None, None, None) == 0
+    assert lib.ts_label_sets(Batch(None, None, 0, 0), ok_bin, 3, None, 2, None, None, None) == 0
+    assert lib.ts_prefix(None, 0, 256, 1, qs(0.8), None, None, None) == 0
+    assert lib.ts_threshold_search(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, 0, None, None, None, None,
+                                   None) == 0

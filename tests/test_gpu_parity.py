@@ -219,6 +219,43 @@ def test_label_misaligned_output():
     assert np.array_equal(out.cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("nsets", [1, 2, 3, 4])
+def test_label_sets_ragged(ragged, nsets):
+    """One pass over the voxels, one label map per threshold set, each equal
+    to the oracle's labels for that set (ragged, unaligned problems)."""
+    host, base, segs = ragged
+    rng = np.random.default_rng(40 + nsets)
+    b = api.Batch(segs)
+    for lo, hi, L in WINDOWS[:4] + WINDOWS[6:7]:
+        for k in (1, 2, 3):
+            thrs = []
+            for u in range(nsets):
+                thr = np.stack([np.sort(rng.choice(L - 1, k, replace=False)) for _ in segs]).astype(np.int32)
+                thr[(u + 1) % len(segs)] = -1  # a degenerate row in a different problem per set
+                thrs.append(thr)
+            outs = api.label_sets(b, api.binning(lo, hi, L), [to_dev(t) for t in thrs], k)
+            torch.cuda.synchronize()
+            for u in range(nsets):
+                for i, s in enumerate(segs):
+                    want = oracle.label(s.cpu().numpy(), lo, hi, L, thrs[u][i])
+                    assert np.array_equal(outs[u][i].cpu().numpy(), want), (lo, hi, L, k, u, i)
+
+
+def test_label_sets_mixed_output_phases():
+    """Sets whose outputs have different alignment phases take the element
+    path for the whole problem; labels stay exact."""
+    v = to_dev(synth.workload_slice(4).reshape(-1))
+    n = v.numel()
+    bufs = [torch.empty(n + 16, dtype=torch.uint8, device=v.device) for _ in range(3)]
+    outs = [[bufs[0][:n]], [bufs[1][5:5 + n]], [bufs[2][8:8 + n]]]
+    thrs = [np.array([[900, 1500]], np.int32), np.array([[100, 2000]], np.int32), np.array([[1, 4000]], np.int32)]
+    api.label_sets(api.Batch([v]), api.binning(-1024, 3071, 4096), [to_dev(t) for t in thrs], 2, outs=outs)
+    torch.cuda.synchronize()
+    for u in range(3):
+        want = oracle.label(v.cpu().numpy(), -1024, 3071, 4096, thrs[u][0])
+        assert np.array_equal(outs[u][0].cpu().numpy(), want), u
+
+
 def test_determinism_and_batch_invariance():
     vol = synth.make_volume(synth.rng_for(9, 2), 24, 256)
     dv = to_dev(vol)
@@ -273,3 +310,54 @@ def test_search_k3_column_chunks(q):
     thr, obj, st = _search_all(H, 3, q, api.SEARCH_FP32_TIECHECK)
     for i in range(2):
         check_choice(H[i], 3, q, thr[i], obj[i], st[i])
+
+
+QBATCH = (0.5, 1.5, 0.8, 2.0, 0.3, 1.2, 0.95, 3.0)  # both signs of 1 - q, interleaved; TS_MAX_Q values
+
+
+def test_prefix_batched_q_equals_single_calls():
+    rng = np.random.default_rng(71)
+    H = _random_hists(rng, 9, 777, zero_frac=0.5, hi=2000)
+    H[3] = 0  # empty problem
+    hd = to_dev(H.view(np.int32))
+    P, Q = api.prefix(hd, QBATCH)
+    assert tuple(Q.shape) == (len(QBATCH), 9, 777)
+    for j, q in enumerate(QBATCH):
+        P1, Q1 = api.prefix(hd, q)
+        assert torch.equal(P, P1)
+        assert torch.equal(Q[j], Q1), q
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["fp32tie", "fp64", "plain"])
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("path", [0, 1, 2], ids=["auto", "fused", "tiled"])
+def test_search_batched_q_equals_single_calls(mode, k, path):
+    """One launch over nq x nseg problems gives, bit for bit, what nq calls
+    with one q give; the results also match the oracle."""
+    if path and mode != api.SEARCH_FP32_TIECHECK:
+        pytest.skip("paths only differ in the FP32 mode")
+    rng = np.random.default_rng(500 + 10 * k + mode + path)
+    L = {1: 300, 2: 130, 3: 40}[k] if mode == api.SEARCH_PLAIN else {1: 1000, 2: 257, 3: 70}[k]
+    n = 3 if mode == api.SEARCH_PLAIN else 7
+    H = _random_hists(rng, n, L, zero_frac=0.4)
+    H[1] = 0
+    H[1, 5] = 3  # one occupied bin: degenerate
+    qs = QBATCH[:3] if mode == api.SEARCH_PLAIN else QBATCH
+    tune = {"search_path": path} if path else None
+    hd = to_dev(H.view(np.int32))
+    P, Q = api.prefix(hd, qs)
+    thr, obj, st = api.threshold_search(P, Q, k, qs, mode, tune=tune)
+    torch.cuda.synchronize()
+    assert tuple(thr.shape) == (len(qs), n, k)
+    for j, q in enumerate(qs):
+        P1, Q1 = api.prefix(hd, q)
+        t1, o1, s1 = api.threshold_search(P1, Q1, k, q, mode, tune=tune)
+        torch.cuda.synchronize()
+        assert torch.equal(thr[j], t1), (q, thr[j], t1)
+        assert torch.equal(st[j], s1), q
+        o = obj[j].cpu().numpy()
+        assert np.array_equal(o, o1.cpu().numpy(), equal_nan=True), q
+        if mode == api.SEARCH_FP32_TIECHECK:
+            sj = st[j].cpu().numpy()
+            for i in range(n):
+                check_choice(H[i], k, q, thr[j, i].cpu().numpy(), o[i], int(sj[i]))
