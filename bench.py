@@ -39,7 +39,17 @@ WORKLOADS = {
                   "search (177,910,271 tuples), q=0.8, labels", False, -1024, 3071, 1024, 3, (0.8,)),
     "slice": ("one 512x512 int16 slice, 4096-bin histogram over [-1024,3071], k=1, q=0.8, labels",
               False, -1024, 3071, 4096, 1, (0.8,)),
+    "batch64": ("64 volumes 512x512xU{120..600} (23,000+ slices) in one batch, per-slice 256-bin histograms over "
+                "[-1024,-200], per-slice k=2 search, q=0.8, labels", True, -1024, -200, 256, 2, (0.8,)),
+    "serving": ("Poisson trace, 20 volumes/s, half 256x256xU{60..300} and half 512x512xU{120..600}; per volume "
+                "512-bin histogram over [-1024,3071], k=3, q=0.8, labels back in host memory",
+                False, -1024, 3071, 512, 3, (0.8,)),
 }
+
+# distinct volumes generated for the batched and serving workloads; every
+# request takes the first Z slices of one of them (generation costs ~13 s
+# per 512x512x600 volume on one core)
+POOL = 4
 
 
 def parse():
@@ -51,6 +61,9 @@ def parse():
     ap.add_argument("--workload", default="volume300", choices=sorted(WORKLOADS),
                     help="volume300 is the benchmark's workload; the others report the same fields")
     ap.add_argument("--cpu-slices", type=int, default=300, help="slices in the oracle's timed sample")
+    ap.add_argument("--requests", type=int, default=120, help="serving: requests replayed from the trace")
+    ap.add_argument("--per-slice-sample", type=int, default=2000,
+                    help="batch64: slices timed with one launch per slice and stage")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run device-to-device copies of 256 MiB (reference kernel for the PMC byte counters)")
     return ap.parse_args()
@@ -102,6 +115,55 @@ def cpu_baseline(vol, nslices: int, wl):
             "sample": f"{what}, {dt:.2f} s single-threaded"}
 
 
+def _gen(job):
+    from paper_2012_10684_amd import synth
+    kind, i, z, size = job
+    if kind == "batch":
+        return synth.workload_batch_volume(i, z, size)
+    return synth.serving_volume(i, z, size)
+
+
+def make_pool(jobs):
+    """Generate volumes in parallel worker processes (numpy only)."""
+    import multiprocessing as mp
+    n = min(len(jobs), max(1, min(16, len(os.sched_getaffinity(0)))))
+    with mp.get_context("spawn").Pool(n) as pool:
+        return pool.map(_gen, jobs)
+
+
+def bench_serving(args, wl, trace, jobs, vols):
+    import torch
+
+    from paper_2012_10684_amd import api
+    from paper_2012_10684_amd.serve import Engine, Request, latency_stats
+
+    desc, _, LO, HI, L, K, QS = wl
+    torch.cuda.set_device(torch.device("cuda:0"))
+    pinned = {}
+    for (kind, i, z, s), v in zip(jobs, vols):
+        pinned.setdefault(s, []).append(torch.from_numpy(v).pin_memory())
+    reqs = [Request(i, pinned[s][i % len(pinned[s])][:z], t) for i, (t, z, s) in enumerate(trace)]
+    eng = Engine(api.binning(LO, HI, L), K, QS)
+    eng.run([Request(-1 - i, pinned[512][0][:64], 0.0) for i in range(4)], realtime=False)  # warm-up
+    torch.cuda.synchronize()
+    res = eng.run(reqs, realtime=True)
+    wall = max(r.done for r in res)
+    st = latency_stats(res, wall)
+    nvox = sum(r.nvox for r in res)
+    ok = all(int(r.status.max()) == 0 for r in res)
+    line = {
+        "metric": "voxels/s served (arrival to labels in host memory; p50/p99 latency)",
+        "value": nvox / wall, "unit": "voxels/s", "n_gpus": 1, "steps": len(res), "warmup": 4,
+        "ms_per_step": wall / len(res) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "requests": len(res), "voxels": nvox, "bins": L, "k": K, "q": list(QS),
+                   "distinct_volumes": len(jobs)},
+        "latency_p50_ms": st["p50_s"] * 1e3, "latency_p99_ms": st["p99_s"] * 1e3, "latency_max_ms": st["max_s"] * 1e3,
+        "trace_span_s": trace[-1][0], "wall_s": wall, "all_problems_ok": bool(ok),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,6 +175,17 @@ def main():
 
     from paper_2012_10684_amd import api, synth
 
+    wl = WORKLOADS[args.workload]
+    # workers that generate the volume pools start before this process
+    # touches the GPU
+    if args.workload == "serving":
+        trace = synth.serving_trace(args.requests, 20.0)
+        zmax = {sz: max([z for _, z, s_ in trace if s_ == sz] or [1]) for sz in (256, 512)}
+        jobs = [("serve", i, zmax[sz], sz) for sz in (256, 512) for i in range(POOL // 2)]
+        return bench_serving(args, wl, trace, jobs, make_pool(jobs))
+    if args.workload == "batch64":
+        depths = synth.batch_depths(64)
+        pool = make_pool([("batch", i, max(depths), 512) for i in range(POOL)])
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate:
@@ -124,12 +197,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": a.numel(), "bytes_written": b.numel(), "launches": 5}))
         return
-    wl = WORKLOADS[args.workload]
     desc, per_slice, LO, HI, L, K, QS = wl
-    vol = {"volume300": lambda: synth.workload_volume300(0), "volume600": lambda: synth.workload_volume600(0),
-           "slice": lambda: synth.workload_slice(0)[None]}[args.workload]()
-    dv = torch.from_numpy(vol).to(dev)
-    batch = api.Batch.slices(dv) if per_slice else api.Batch([dv.reshape(-1)])
+    if args.workload == "batch64":
+        dpool = [torch.from_numpy(v).to(dev) for v in pool]
+        dvols = [dpool[i % POOL][:z].clone() for i, z in enumerate(depths)]  # one buffer per volume
+        del dpool
+        vol = pool[0][:30]  # the oracle's sample
+        nvox_all = sum(int(v.numel()) for v in dvols)
+        batch = api.Batch([v[z].reshape(-1) for v in dvols for z in range(v.shape[0])])
+    else:
+        vol = {"volume300": lambda: synth.workload_volume300(0), "volume600": lambda: synth.workload_volume600(0),
+               "slice": lambda: synth.workload_slice(0)[None]}[args.workload]()
+        dv = torch.from_numpy(vol).to(dev)
+        nvox_all = int(vol.size)
+        batch = api.Batch.slices(dv) if per_slice else api.Batch([dv.reshape(-1)])
     binn = api.binning(LO, HI, L)
     nseg = batch.nseg
     hist = torch.empty((nseg, L), dtype=torch.int32, device=dev)
@@ -175,7 +256,7 @@ def main():
     per = {n: sum(events[s][i].elapsed_time(events[s][i + 1]) for s in range(args.steps)) * 1e-3 / args.steps
            for i, n in enumerate(names)}
 
-    nvox = int(vol.size)
+    nvox = nvox_all
     n = L - 1
     per_problem = {1: n, 2: n * (n - 1) // 2, 3: n * (n - 1) * (n - 2) // 6}[K]
     tuples = len(QS) * nseg * per_problem
@@ -219,6 +300,51 @@ def main():
         "label_gbs": label_bytes / label_t / 1e9,
         "all_problems_ok": bool(st_ok),
     }
+    steps_us = sorted(events[s][0].elapsed_time(events[s][-1]) * 1e3 for s in range(args.steps))
+    line["step_us_p50"] = float(np.percentile(steps_us, 50))
+    line["step_us_p99"] = float(np.percentile(steps_us, 99))
+    if args.workload == "volume600":
+        # the plain GPU form (one thread per tuple, FP64, one launch per
+        # problem) and the FP64 exhaustive mode, for the speed-up of the search
+        for name, mode in (("plain_fp64", api.SEARCH_PLAIN), ("fp64", api.SEARCH_FP64)):
+            ws2 = torch.empty(api.workspace_bytes(nseg, L, K, mode, nq), dtype=torch.uint8, device=dev)
+            out2 = tuple(torch.empty_like(r) for r in res)
+            api.threshold_search(P, Q, K, QS, mode, ws=ws2, out=out2, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                api.threshold_search(P, Q, K, QS, mode, ws=ws2, out=out2, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 3
+            line[f"search_{name}_us"] = us
+            line[f"search_speedup_vs_{name}"] = us / (per["search"] * 1e6)
+            line[f"search_{name}_same_result"] = bool(torch.equal(out2[0], res[0]))
+            del ws2
+    if args.workload == "batch64":
+        # the same work with one launch per slice and stage, on a sample of slices
+        m = min(args.per_slice_sample, nseg)
+        singles = [api.Batch([batch.segments[i]]) for i in range(m)]
+        h1 = torch.empty((1, L), dtype=torch.int32, device=dev)
+        P1 = torch.empty((1, L), dtype=torch.float64, device=dev)
+        Q1 = torch.empty((1, L), dtype=torch.float64, device=dev)
+        ws1 = torch.empty(api.workspace_bytes(1, L, K), dtype=torch.uint8, device=dev)
+        r1 = (torch.empty((1, K), dtype=torch.int32, device=dev), torch.empty(1, dtype=torch.float64, device=dev),
+              torch.empty(1, dtype=torch.int32, device=dev))
+        o1 = [[outs[0][i]] for i in range(m)]
+        p1 = [api.device_table([outs[0][i].data_ptr()], dev) for i in range(m)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(m):
+            api.histogram(singles[i], binn, out=h1, tune="auto", stream=stream)
+            api.prefix(h1, QS[0], P=P1, Q=Q1, stream=stream)
+            api.threshold_search(P1, Q1, K, QS[0], ws=ws1, out=r1, tune="auto", stream=stream)
+            api.label(singles[i], binn, r1[0], K, outs=o1[i], out_ptrs=p1[i], tune="auto", stream=stream)
+        torch.cuda.synchronize()
+        per_slice_s = (time.perf_counter() - t0) / m
+        line["per_slice_launches_ms_per_step"] = per_slice_s * nseg * 1e3
+        line["batched_speedup_vs_per_slice_launches"] = per_slice_s * nseg / (dt / args.steps)
+        line["per_slice_sample"] = m
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(vol, args.cpu_slices, wl)
     print(json.dumps(line), flush=True)

@@ -108,10 +108,10 @@ typedef struct {
     int32_t hist_replicas;   /* LDS copies of every bin: 1, 2, 4, 8, 16 or 32 */
     int32_t hist_wg_per_cu;  /* persistent histogram workgroups per compute unit: 1..16 */
     int32_t label_block;     /* threads per label workgroup: 64..1024, multiple of 64 */
-    int32_t label_wg_per_cu; /* persistent label workgroups per compute unit: 1..32 */
+    int32_t label_vecs;      /* 16-byte vectors (8 voxels) per label thread: 1, 2 or 4 */
     int32_t search_cols;     /* threshold columns held per lane in a search tile: 1, 2 or 4 */
     int32_t search_rows;     /* rows (first-threshold values) per k=2 search tile: 16..4096, multiple of 4 */
-    int32_t min_chunk;       /* minimum voxels per streaming workgroup: >= 512 */
+    int32_t min_chunk;       /* minimum voxels per histogram workgroup: >= 512 */
     int32_t search_path;     /* 1: one workgroup per problem (k <= 2, nbins <= 1024, or k = 1),
                                 2: one launch per search phase; 0: chosen from the sizes */
     int32_t search_block;    /* threads per workgroup on the one-workgroup path: 256, 512 or 1024 */

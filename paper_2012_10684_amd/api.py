@@ -47,7 +47,7 @@ class _Batch(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "hist_block", "hist_replicas", "hist_wg_per_cu", "label_block", "label_wg_per_cu",
+        "hist_block", "hist_replicas", "hist_wg_per_cu", "label_block", "label_vecs",
         "search_cols", "search_rows", "min_chunk", "search_path", "search_block")]
 
     @classmethod
@@ -123,14 +123,24 @@ def _tune(tune, key_fn=None):
     return ctypes.byref(tune)
 
 
+def device_table(values: Sequence[int], device, stream=None) -> torch.Tensor:
+    """int64 device array of `values`, copied from pinned host memory without
+    blocking the host, ordered on `stream` (default: the current stream)."""
+    h = torch.tensor(list(values) or [0], dtype=torch.int64).pin_memory()
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream(device)):
+        return h.to(device, non_blocking=True)
+
+
 class Batch:
     """Device segment table for a batch of problems.
 
     ``segments`` is a list of 1-D views (int16, CUDA) -- e.g. the slices of a
     volume or whole volumes.  The table holds device pointers and the voxel
-    offsets; the tensors are kept alive by this object."""
+    offsets; the tensors are kept alive by this object.  The table is copied
+    on `stream` (default: the current stream): use the batch on that stream,
+    or synchronise first."""
 
-    def __init__(self, segments: Sequence[torch.Tensor], device=None):
+    def __init__(self, segments: Sequence[torch.Tensor], device=None, stream=None):
         segs = list(segments)
         dev = device or (segs[0].device if segs else torch.device("cuda"))
         for s in segs:
@@ -143,8 +153,8 @@ class Batch:
             offs.append(offs[-1] + n)
         self.total = offs[-1]
         self.nseg = len(segs)
-        self.ptrs = torch.tensor([s.data_ptr() for s in segs] or [0], dtype=torch.int64).to(dev)
-        self.offs = torch.tensor(offs, dtype=torch.int64).to(dev)
+        self.ptrs = device_table([s.data_ptr() for s in segs], dev, stream)
+        self.offs = device_table(offs, dev, stream)
         self._c = _Batch(self.ptrs.data_ptr(), self.offs.data_ptr(), self.nseg, self.total)
 
     @classmethod
@@ -229,7 +239,7 @@ def label(batch: Batch, bin: Binning, thr: torch.Tensor, k: int, outs: Optional[
     if outs is None:
         outs = [torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes]
     if out_ptrs is None:
-        out_ptrs = torch.tensor([o.data_ptr() for o in outs] or [0], dtype=torch.int64).to(dev)
+        out_ptrs = device_table([o.data_ptr() for o in outs], dev, stream)
     t = _tune(tune, lambda a: a.key_label(batch.nseg, batch.total, k))
     _check(_lib.ts_label(batch._c, bin, _ptr(thr), int(k), _ptr(out_ptrs), t, _stream(stream)))
     return outs
@@ -247,7 +257,7 @@ def label_sets(batch: Batch, bin: Binning, thrs: Sequence[torch.Tensor], k: int,
     if outs is None:
         outs = [[torch.empty(m, dtype=torch.uint8, device=dev) for m in batch.sizes] for _ in range(n)]
     if out_ptrs is None:
-        out_ptrs = [torch.tensor([o.data_ptr() for o in oq] or [0], dtype=torch.int64).to(dev) for oq in outs]
+        out_ptrs = [device_table([o.data_ptr() for o in oq], dev, stream) for oq in outs]
     thr_arr = (ctypes.c_void_p * max(n, 1))(*[t.data_ptr() for t in thrs])
     out_arr = (ctypes.c_void_p * max(n, 1))(*[p.data_ptr() for p in out_ptrs])
     t = _tune(tune, lambda a: a.key_label(batch.nseg, batch.total, k, n))

@@ -2,7 +2,7 @@
 
 Every kernel of the path has launch-shape knobs (``ts_tuning``): histogram
 workgroup size, LDS replicas and persistent workgroups per CU; label workgroup
-size and workgroups per CU; search columns per lane, rows per tile, path (one
+size and vectors per thread; search columns per lane, rows per tile, path (one
 workgroup per problem or one launch per phase) and workgroup size.  No knob
 changes any output bit, so the tuner may pick any of them on speed alone.
 
@@ -71,9 +71,8 @@ def histogram_space(L: int) -> Iterable[dict]:
 
 
 def label_space() -> Iterable[dict]:
-    for b, w in itertools.product((256, 512, 1024), (1, 2, 4, 8, 16)):
-        if b * w <= 2048:
-            yield dict(label_block=b, label_wg_per_cu=w)
+    for b, u in itertools.product((64, 128, 256, 512, 1024), (1, 2, 4)):
+        yield dict(label_block=b, label_vecs=u)
 
 
 def search_space(L: int, k: int) -> Iterable[dict]:

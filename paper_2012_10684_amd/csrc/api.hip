@@ -65,7 +65,7 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
     o->hist_replicas = t->hist_replicas ? t->hist_replicas : rep_default;
     o->hist_wg_per_cu = t->hist_wg_per_cu ? t->hist_wg_per_cu : 1;
     o->label_block = t->label_block ? t->label_block : 256;
-    o->label_wg_per_cu = t->label_wg_per_cu ? t->label_wg_per_cu : 8;
+    o->label_vecs = t->label_vecs ? t->label_vecs : 1;
     o->search_cols = t->search_cols ? t->search_cols : 2;
     o->search_rows = t->search_rows ? t->search_rows : 16;
     o->min_chunk = t->min_chunk ? t->min_chunk : 8192;
@@ -81,8 +81,8 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
         return fail(TS_ERR_INVALID_ARG, "tuning: hist_wg_per_cu must be in [1, 16]");
     if (o->label_block < 64 || o->label_block > 1024 || o->label_block % 64)
         return fail(TS_ERR_INVALID_ARG, "tuning: label_block must be a multiple of 64 in [64, 1024]");
-    if (o->label_wg_per_cu < 1 || o->label_wg_per_cu > 32)
-        return fail(TS_ERR_INVALID_ARG, "tuning: label_wg_per_cu must be in [1, 32]");
+    if (o->label_vecs != 1 && o->label_vecs != 2 && o->label_vecs != 4)
+        return fail(TS_ERR_INVALID_ARG, "tuning: label_vecs must be 1, 2 or 4");
     if (o->search_cols != 1 && o->search_cols != 2 && o->search_cols != 4)
         return fail(TS_ERR_INVALID_ARG, "tuning: search_cols must be 1, 2 or 4");
     if (o->search_rows < 16 || o->search_rows > 4096 || o->search_rows % 4)

@@ -22,7 +22,7 @@ int device_cu_count();
 // ---------------------------------------------------------------- tuning
 struct Tune {
     int hist_block, hist_replicas, hist_wg_per_cu;
-    int label_block, label_wg_per_cu;
+    int label_block, label_vecs;
     int search_cols, search_rows;
     int min_chunk;
     int search_path, search_block;

@@ -5,10 +5,9 @@
 // b(v) > t  <=>  v >= cut(t) = lo + ceil((t + 1) * W / L)   (W = hi - lo + 1),
 // which also covers values outside the window (below lo: bin 0, never above a
 // threshold; above hi: bin L-1, above every threshold since cut(t) <= hi + 1).
-// So each voxel costs k integer compares.  Streaming layout as in the
-// histogram: a persistent grid splits the flattened batch into equal ranges;
-// 16-byte loads of 8 voxels and 8-byte stores of 8 labels where the input and
-// output phases agree, element-wise code elsewhere.
+// So each voxel costs k integer compares.  One-shot grid over tiles of the
+// flattened batch; 16-byte loads of 8 voxels and 8-byte stores of 8 labels
+// where the input and output phases agree, element-wise code elsewhere.
 #include <algorithm>
 
 #include "common.h"
@@ -69,114 +68,110 @@ __device__ __forceinline__ v2u lab8(const v4i &w, const Cuts &c)
     return r;
 }
 
-// Up to TS_MAX_LABEL_SETS threshold sets labelled in one pass: each 16-byte
-// load of 8 voxels feeds one 8-byte store per set.
-template <int NS>
-__device__ __forceinline__ void label_vec(const TS_GLOBAL v4i *vp, TS_GLOBAL v2u *const (&op)[NS],
-                                          const Cuts (&cuts)[NS], int64_t nvec)
+// Segment holding flattened position pos: the guess for equal-size segments
+// is checked with the two offsets around it (loaded together with whatever
+// the caller loads for that segment); a binary search settles a wrong guess.
+__device__ __forceinline__ int guess_segment(const int64_t *offs, int nseg, int64_t total, int64_t pos)
 {
-    const int64_t st = blockDim.x;
-    int64_t j = threadIdx.x;
-    // pairs of vectors per thread; the next pair is in flight while the
-    // current one is labelled and stored
-    bool have = j + st < nvec;
-    v4i a0 = {0, 0, 0, 0}, a1 = a0;
-    if (have) {
-        a0 = __builtin_nontemporal_load(vp + j);
-        a1 = __builtin_nontemporal_load(vp + j + st);
-    }
-    while (have) {
-        const int64_t jn = j + 2 * st;
-        const bool nxt = jn + st < nvec;
-        v4i b0 = a0, b1 = a1;
-        if (nxt) {
-            b0 = __builtin_nontemporal_load(vp + jn);
-            b1 = __builtin_nontemporal_load(vp + jn + st);
-        }
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            __builtin_nontemporal_store(lab8(a0, cuts[u]), op[u] + j);
-            __builtin_nontemporal_store(lab8(a1, cuts[u]), op[u] + j + st);
-        }
-        a0 = b0;
-        a1 = b1;
-        j = jn;
-        have = nxt;
-    }
-    for (; j < nvec; j += st) {
-        const v4i a = __builtin_nontemporal_load(vp + j);
-#pragma unroll
-        for (int u = 0; u < NS; ++u)
-            __builtin_nontemporal_store(lab8(a, cuts[u]), op[u] + j);
-    }
+    const double f = (double)pos / (double)total * (double)nseg; // a guess: rounding is harmless
+    return (int)min((double)(nseg - 1), f);
 }
 
-template <int NS>
+// One workgroup per tile of blockDim * 8 * U voxels of the flattened batch,
+// one pass over the voxels for NS threshold sets (up to TS_MAX_LABEL_SETS):
+// each 16-byte load of 8 voxels feeds one 8-byte store per set.  A tile inside
+// one segment whose input and outputs share the 16/8-byte alignment phase is
+// labelled with vector accesses; any other tile voxel by voxel.  A one-shot
+// grid keeps the voxels in flight at any time in one window of HBM, which
+// streams faster on MI355X than long per-workgroup ranges.
+template <int NS, int U>
 __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict__ vox,
-                                                const int64_t *__restrict__ offs, int nseg, int64_t total,
-                                                int64_t chunk, BinMap bm, LabelSets sets, int k)
+                                                const int64_t *__restrict__ offs, int nseg, int64_t total, BinMap bm,
+                                                LabelSets sets, int k)
 {
-    const int64_t beg = (int64_t)blockIdx.x * chunk;
-    const int64_t end = min(total, beg + chunk);
-    if (beg >= end)
-        return;
-    int s = find_segment(offs, nseg, beg);
-    int64_t pos = beg;
-    while (pos < end) {
-        while (s + 1 < nseg && offs[s + 1] <= pos)
+    const int64_t T = (int64_t)blockDim.x * 8 * U;
+    const int64_t t0 = (int64_t)blockIdx.x * T;
+    const int64_t t1 = min(total, t0 + T);
+    int s = guess_segment(offs, nseg, total, t0);
+    int64_t o0 = offs[s], o1 = offs[s + 1];
+    if (!(o0 <= t0 && t0 < o1)) {
+        s = find_segment(offs, nseg, t0);
+        while (s + 1 < nseg && offs[s + 1] <= t0) // skip empty segments
             ++s;
-        const int64_t s0 = offs[s];
-        const int64_t s1 = min(offs[s + 1], end);
-        const TS_GLOBAL int16_t *src = gp(vox[s]);
+        o0 = offs[s];
+        o1 = offs[s + 1];
+    }
+    if (t1 <= o1) { // the whole tile lies in segment s
+        const TS_GLOBAL int16_t *src = gp(vox[s]) + (t0 - o0);
         TS_GLOBAL uint8_t *dst[NS];
         Cuts cuts[NS];
+        bool vec = ((uintptr_t)src & 15u) == 0;
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
-            dst[u] = gpw(sets.out[u][s]);
+            dst[u] = gpw(sets.out[u][s]) + (t0 - o0);
             cuts[u] = make_cuts(sets.thr[u] + (int64_t)s * k, k, bm);
+            vec = vec && ((uintptr_t)dst[u] & 7u) == 0;
         }
-        const int64_t i0 = pos - s0, i1 = s1 - s0;
-        const uintptr_t ain = (uintptr_t)(src + i0);
-        // element phase of 16-byte input alignment; every output must have
-        // the same phase for 8-byte alignment
-        const int64_t hin = (int64_t)(((16u - (ain & 15u)) & 15u) >> 1);
-        bool vec = (ain & 1u) == 0;
-#pragma unroll
-        for (int u = 0; u < NS; ++u)
-            vec = vec && (int64_t)((8u - ((uintptr_t)(dst[u] + i0) & 7u)) & 7u) == hin;
+        const int n = (int)(t1 - t0);
         if (vec) {
-            const int64_t head = min(hin, i1 - i0);
-            if (threadIdx.x < head) {
-                const int v = src[i0 + threadIdx.x];
+            const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(src);
+            const int nvec = n >> 3;
+            v4i w[U];
 #pragma unroll
-                for (int u = 0; u < NS; ++u)
-                    dst[u][i0 + threadIdx.x] = (uint8_t)lab1(v, cuts[u]);
+            for (int j = 0; j < U; ++j) {
+                const int i = threadIdx.x + j * blockDim.x;
+                w[j] = i < nvec ? __builtin_nontemporal_load(vp + i) : v4i{0, 0, 0, 0};
             }
-            const int64_t vb = i0 + head;
-            const int64_t nvec = (i1 - vb) >> 3;
-            TS_GLOBAL v2u *op[NS];
 #pragma unroll
-            for (int u = 0; u < NS; ++u)
-                op[u] = reinterpret_cast<TS_GLOBAL v2u *>(dst[u] + vb);
-            label_vec<NS>(reinterpret_cast<const TS_GLOBAL v4i *>(src + vb), op, cuts, nvec);
-            const int64_t tb = vb + (nvec << 3);
-            if (threadIdx.x < i1 - tb) {
+            for (int j = 0; j < U; ++j) {
+                const int i = threadIdx.x + j * blockDim.x;
+                if (i < nvec) {
+#pragma unroll
+                    for (int u = 0; u < NS; ++u)
+                        __builtin_nontemporal_store(lab8(w[j], cuts[u]),
+                                                    reinterpret_cast<TS_GLOBAL v2u *>(dst[u]) + i);
+                }
+            }
+            const int tb = nvec << 3; // ragged end of the segment
+            if ((int)threadIdx.x < n - tb) {
                 const int v = src[tb + threadIdx.x];
 #pragma unroll
                 for (int u = 0; u < NS; ++u)
                     dst[u][tb + threadIdx.x] = (uint8_t)lab1(v, cuts[u]);
             }
         } else {
-            for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const int v = src[i];
 #pragma unroll
                 for (int u = 0; u < NS; ++u)
                     dst[u][i] = (uint8_t)lab1(v, cuts[u]);
             }
         }
-        pos = s0 + i1;
-        ++s;
+        return;
     }
+    // the tile crosses segment ends: voxel by voxel, segments walked forward
+    for (int64_t pos = t0 + threadIdx.x; pos < t1; pos += blockDim.x) {
+        int sv = s;
+        while (offs[sv + 1] <= pos)
+            ++sv;
+        const int64_t i = pos - offs[sv];
+        const int v = gp(vox[sv])[i];
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            gpw(sets.out[u][sv])[i] = (uint8_t)lab1(v, make_cuts(sets.thr[u] + (int64_t)sv * k, k, bm));
+    }
+}
+
+template <int NS>
+static void launch_label_ns(int U, dim3 g, dim3 blk, hipStream_t st, const ts_batch &b, const BinMap &bm,
+                            const LabelSets &sets, int k)
+{
+    if (U == 1)
+        hipLaunchKernelGGL((k_label<NS, 1>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
+    else if (U == 2)
+        hipLaunchKernelGGL((k_label<NS, 2>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
+    else
+        hipLaunchKernelGGL((k_label<NS, 4>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
 }
 
 ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &sets, int nsets, int k, const Tune &t,
@@ -184,19 +179,16 @@ ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &set
 {
     if (b.total == 0)
         return TS_OK;
-    const int64_t max_wg = (int64_t)device_cu_count() * t.label_wg_per_cu;
-    int64_t grid = std::min<int64_t>(max_wg, (b.total + t.min_chunk - 1) / t.min_chunk);
-    if (grid < 1)
-        grid = 1;
-    int64_t chunk = (b.total + grid - 1) / grid;
-    chunk = (chunk + 63) & ~(int64_t)63;
-    grid = (b.total + chunk - 1) / chunk;
+    const int64_t T = (int64_t)t.label_block * 8 * t.label_vecs;
+    const int64_t grid = (b.total + T - 1) / T;
+    if (grid > 0x7fffffff)
+        return fail(TS_ERR_INVALID_ARG, "ts_label: batch too large for one launch");
     const dim3 g((unsigned)grid), blk(t.label_block);
     switch (nsets) {
-    case 1: hipLaunchKernelGGL(k_label<1>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
-    case 2: hipLaunchKernelGGL(k_label<2>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
-    case 3: hipLaunchKernelGGL(k_label<3>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
-    default: hipLaunchKernelGGL(k_label<4>, g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, chunk, bm, sets, k); break;
+    case 1: launch_label_ns<1>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
+    case 2: launch_label_ns<2>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
+    case 3: launch_label_ns<3>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
+    default: launch_label_ns<4>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
     }
     return check_launch("ts_label");
 }

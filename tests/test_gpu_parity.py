@@ -256,6 +256,38 @@ def test_label_sets_mixed_output_phases():
         assert np.array_equal(outs[u][0].cpu().numpy(), want), u
 
 
+LABEL_TUNES = [dict(label_block=64, label_vecs=1), dict(label_block=256, label_vecs=4),
+               dict(label_block=1024, label_vecs=2), dict(label_block=1024, label_vecs=4)]
+
+
+@pytest.mark.parametrize("tune", LABEL_TUNES, ids=lambda t: f"b{t['label_block']}u{t['label_vecs']}")
+def test_label_tuning_invariant(ragged, tune):
+    """Every tile shape gives the oracle's labels: ragged unaligned problems,
+    slices whose size is not a multiple of the tile (tiles straddle slices),
+    and one long problem with a ragged end."""
+    host, base, segs = ragged
+    rng = np.random.default_rng(77)
+    vol = synth.make_volume(synth.rng_for(9, 5), 9, 64)[:, :37, :29].copy()  # 1073-voxel slices
+    dv = to_dev(vol)
+    long = to_dev(synth.make_volume(synth.rng_for(9, 6), 3, 512).reshape(-1)[:700001].copy())
+    cases = [(api.Batch(segs), [s.cpu().numpy() for s in segs]),
+             (api.Batch.slices(dv), [vol[z].reshape(-1) for z in range(vol.shape[0])]),
+             (api.Batch([long]), [long.cpu().numpy()])]
+    lo, hi, L = -1024, 3071, 1024
+    for b, hosts in cases:
+        for k in (1, 3):
+            thrs = [np.stack([np.sort(rng.choice(L - 1, k, replace=False)) for _ in hosts]).astype(np.int32)
+                    for _ in range(2)]
+            outs = api.label_sets(b, api.binning(lo, hi, L), [to_dev(t) for t in thrs], k, tune=tune)
+            one = api.label(b, api.binning(lo, hi, L), to_dev(thrs[0]), k, tune=tune)
+            torch.cuda.synchronize()
+            for i, h in enumerate(hosts):
+                for u in range(2):
+                    want = oracle.label(h, lo, hi, L, thrs[u][i])
+                    assert np.array_equal(outs[u][i].cpu().numpy(), want), (tune, k, u, i)
+                assert np.array_equal(one[i].cpu().numpy(), outs[0][i].cpu().numpy()), (tune, k, i)
+
+
 def test_determinism_and_batch_invariance():
     vol = synth.make_volume(synth.rng_for(9, 2), 24, 256)
     dv = to_dev(vol)
