@@ -65,9 +65,14 @@ def key_search(nseg: int, L: int, k: int, mode: int) -> str:
 
 
 def histogram_space(L: int) -> Iterable[dict]:
-    for r, b, w in itertools.product((4, 8, 16, 32), (256, 512, 1024), (1, 2, 4, 8)):
-        if L * r * 4 <= 160 * 1024 and w * L * r * 4 <= 160 * 1024:
-            yield dict(hist_replicas=r, hist_block=b, hist_wg_per_cu=w)
+    # min_chunk bounds the workgroup count from below in voxels per workgroup:
+    # large chunks pay off when each workgroup flushes many bins
+    for r, b, w, m in itertools.product((1, 2, 4, 8, 16, 32), (256, 512, 1024), (1, 2, 4, 8), (0, 32768, 131072)):
+        if L * r * 4 <= 160 * 1024 and w * L * r * 4 <= 160 * 1024 and L * r >= 1024:
+            d = dict(hist_replicas=r, hist_block=b, hist_wg_per_cu=w)
+            if m:
+                d["min_chunk"] = m
+            yield d
 
 
 def label_space() -> Iterable[dict]:

@@ -65,7 +65,7 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
     o->hist_replicas = t->hist_replicas ? t->hist_replicas : rep_default;
     o->hist_wg_per_cu = t->hist_wg_per_cu ? t->hist_wg_per_cu : 1;
     o->label_block = t->label_block ? t->label_block : 256;
-    o->label_vecs = t->label_vecs ? t->label_vecs : 1;
+    o->label_vecs = t->label_vecs ? t->label_vecs : 2;
     o->search_cols = t->search_cols ? t->search_cols : 2;
     o->search_rows = t->search_rows ? t->search_rows : 16;
     o->min_chunk = t->min_chunk ? t->min_chunk : 8192;

@@ -35,10 +35,11 @@ __device__ __forceinline__ Cuts make_cuts(const int32_t *thr, int k, const BinMa
     }
     if (!ok)
         return c;
-    const int64_t W = (int64_t)bm.hi - bm.lo + 1;
+    // (t+1) W + L - 1 <= 4095 * 65536 + 4095 < 2^32: exact in uint32
+    const uint32_t W = (uint32_t)((int64_t)bm.hi - bm.lo + 1);
     int cc[3] = {NEVER, NEVER, NEVER};
     for (int j = 0; j < k; ++j)
-        cc[j] = bm.lo + (int)(((int64_t)(t[j] + 1) * W + bm.L - 1) / bm.L);
+        cc[j] = bm.lo + (int)(((uint32_t)(t[j] + 1) * W + (uint32_t)bm.L - 1) / (uint32_t)bm.L);
     c.c0 = cc[0];
     c.c1 = cc[1];
     c.c2 = cc[2];
@@ -77,6 +78,33 @@ __device__ __forceinline__ int guess_segment(const int64_t *offs, int nseg, int6
     return (int)min((double)(nseg - 1), f);
 }
 
+// Cut values of problem s for every set, computed by one lane per (set,
+// threshold) and broadcast through readlane (wavefront-uniform results).
+// (t+1) W <= 4095 * 65536 < 2^32, so the ceiling division is exact in uint32.
+template <int NS>
+__device__ __forceinline__ void wave_cuts(const LabelSets &sets, int s, int k, const BinMap &bm, Cuts (&cuts)[NS])
+{
+    const int lane = threadIdx.x & 63;
+    const int u = lane / 3, j = lane % 3;
+    int c = 0x7fffffff;
+    if (u < NS && j < k) {
+        const int32_t *t = sets.thr[u] + (int64_t)s * k;
+        bool ok = true;
+        for (int i = 0; i < k; ++i) // the whole row must be a strictly ascending tuple in [0, L-2]
+            ok = ok && t[i] >= 0 && t[i] <= bm.L - 2 && (i == 0 || t[i] > t[i - 1]);
+        if (ok) {
+            const uint32_t W = (uint32_t)((int64_t)bm.hi - bm.lo + 1);
+            c = bm.lo + (int)(((uint32_t)(t[j] + 1) * W + (uint32_t)bm.L - 1) / (uint32_t)bm.L);
+        }
+    }
+#pragma unroll
+    for (int u2 = 0; u2 < NS; ++u2) {
+        cuts[u2].c0 = __builtin_amdgcn_readlane(c, 3 * u2);
+        cuts[u2].c1 = __builtin_amdgcn_readlane(c, 3 * u2 + 1);
+        cuts[u2].c2 = __builtin_amdgcn_readlane(c, 3 * u2 + 2);
+    }
+}
+
 // One workgroup per tile of blockDim * 8 * U voxels of the flattened batch,
 // one pass over the voxels for NS threshold sets (up to TS_MAX_LABEL_SETS):
 // each 16-byte load of 8 voxels feeds one 8-byte store per set.  A tile inside
@@ -92,24 +120,36 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
     const int64_t T = (int64_t)blockDim.x * 8 * U;
     const int64_t t0 = (int64_t)blockIdx.x * T;
     const int64_t t1 = min(total, t0 + T);
+    // everything the tile needs from the guessed segment is loaded in one
+    // round trip; a wrong guess (uneven segments) is corrected afterwards
     int s = guess_segment(offs, nseg, total, t0);
     int64_t o0 = offs[s], o1 = offs[s + 1];
+    const int16_t *vs = vox[s];
+    uint8_t *os[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+        os[u] = sets.out[u][s];
+    Cuts cuts[NS];
+    wave_cuts<NS>(sets, s, k, bm, cuts);
     if (!(o0 <= t0 && t0 < o1)) {
         s = find_segment(offs, nseg, t0);
         while (s + 1 < nseg && offs[s + 1] <= t0) // skip empty segments
             ++s;
         o0 = offs[s];
         o1 = offs[s + 1];
+        vs = vox[s];
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            os[u] = sets.out[u][s];
+        wave_cuts<NS>(sets, s, k, bm, cuts);
     }
     if (t1 <= o1) { // the whole tile lies in segment s
-        const TS_GLOBAL int16_t *src = gp(vox[s]) + (t0 - o0);
+        const TS_GLOBAL int16_t *src = gp(vs) + (t0 - o0);
         TS_GLOBAL uint8_t *dst[NS];
-        Cuts cuts[NS];
         bool vec = ((uintptr_t)src & 15u) == 0;
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
-            dst[u] = gpw(sets.out[u][s]) + (t0 - o0);
-            cuts[u] = make_cuts(sets.thr[u] + (int64_t)s * k, k, bm);
+            dst[u] = gpw(os[u]) + (t0 - o0);
             vec = vec && ((uintptr_t)dst[u] & 7u) == 0;
         }
         const int n = (int)(t1 - t0);

@@ -20,7 +20,7 @@
 
 namespace ts {
 
-constexpr int PREFIX_THREADS = 256;
+constexpr int PREFIX_THREADS = 1024; // upper bound: 256 threads below 1024 bins, 1024 from there
 
 __device__ __forceinline__ double readlane_f64(double v, int lane)
 {
@@ -50,6 +50,7 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
     double *Ps = P + (int64_t)s * L;
     double *Qs = Q + (int64_t)blockIdx.x * L;
     const int lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
 
     uint64_t c = 0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
@@ -64,7 +65,7 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
         wsum[threadIdx.x >> 6] = c;
     __syncthreads();
     uint64_t N = 0;
-    for (int w = 0; w < PREFIX_THREADS / 64; ++w)
+    for (int w = 0; w < nw; ++w)
         N += wsum[w];
     if (N == 0) {
         for (int i = threadIdx.x; i < L; i += blockDim.x) {
@@ -131,7 +132,9 @@ ts_status launch_prefix(const uint32_t *hist, int nseg, int L, int nq, const dou
     const size_t lds = (size_t)L * (2 * sizeof(double) + sizeof(uint32_t));
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void *)k_prefix, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_prefix, dim3((unsigned)(nseg * nq)), dim3(PREFIX_THREADS), lds, st, hist, nseg, L, ql, P, Q);
+    // the p^q evaluations (FP64 pow) dominate for large L: more threads there
+    const int threads = L >= 1024 ? 1024 : 256;
+    hipLaunchKernelGGL(k_prefix, dim3((unsigned)(nseg * nq)), dim3(threads), lds, st, hist, nseg, L, ql, P, Q);
     return check_launch("ts_prefix");
 }
 

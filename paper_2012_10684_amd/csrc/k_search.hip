@@ -559,6 +559,42 @@ __device__ __forceinline__ void take(const TileCtx &x, float key, float thr, flo
     }
 }
 
+// Phase 2, one row: FP64 evaluation of the columns whose FP32 key reaches
+// thr (bits of `valid` mark the columns that hold a tuple).  Candidates are
+// rare, so the FP64 objective appears once, in a loop over the set bits,
+// rather than once per unrolled tuple: the phase-2 code stays small and its
+// first execution in each workgroup fetches little from the L2.
+template <int K, int COLS>
+__device__ __forceinline__ void take_cols(const TileCtx &x, const float (&key)[COLS], const int (&tv)[COLS],
+                                          unsigned valid, float thr, Cand &b, int t1, int t2)
+{
+    unsigned m = 0;
+#pragma unroll
+    for (int v = 0; v < COLS; ++v)
+        m |= (((valid >> v) & 1u) && key[v] >= thr) ? (1u << v) : 0u;
+    while (m) {
+        const int v = __builtin_ctz(m);
+        m &= m - 1;
+        int tl = tv[0];
+        float kv = key[0];
+#pragma unroll
+        for (int w = 1; w < COLS; ++w)
+            if (v == w) {
+                tl = tv[w];
+                kv = key[w];
+            }
+        const int t[3] = {t1, K == 2 ? tl : t2, tl};
+        const double lam = lambda64_k<K>(x.P, x.Q, x.L, t, x.q, x.sgn, x.hmax);
+        const double rank = x.mode == TS_SEARCH_FP32_ONLY ? (double)kv : lam;
+        const long long code = make_code(K, t);
+        if (better(rank, code, b.r, b.c)) {
+            b.r = rank;
+            b.l = lam;
+            b.c = code;
+        }
+    }
+}
+
 template <int COLS, int PHASE>
 __device__ __forceinline__ void tile_k1(const TileCtx &x, int b, float thr, float &acc, Cand &best)
 {
@@ -576,7 +612,8 @@ __device__ __forceinline__ void tile_k1(const TileCtx &x, int b, float thr, floa
 // Rows [t1b, t1e) of a k = 2 tile; MASK keeps only t1 < t2.  Rows go in
 // groups of R: the group's row operands are all loaded before any of its
 // tuples is evaluated, so one load latency covers R x COLS class terms.
-template <int SGN, int COLS, int PHASE, bool MASK, int R>
+// Columns [V0, COLS) only: column blocks below V0 hold no t2 > t1 for these rows.
+template <int SGN, int COLS, int PHASE, bool MASK, int R, int V0 = 0>
 __device__ __forceinline__ void rows_k2_group(const TileCtx &x, int t1, const float4 (&hc)[COLS],
                                               const float (&tc)[COLS], const int (&t2v)[COLS], float thr, float &acc,
                                               Cand &best)
@@ -591,7 +628,7 @@ __device__ __forceinline__ void rows_k2_group(const TileCtx &x, int t1, const fl
 #pragma unroll
     for (int u = 0; u < R; ++u) {
 #pragma unroll
-        for (int v = 0; v < COLS; ++v) {
+        for (int v = V0; v < COLS; ++v) {
             const float key = (hdr[u] + cls32<SGN>(hc[v], hr[u], x.mq, x.gmax)) + tc[v];
             if (!MASK || t1 + u < t2v[v])
                 take<PHASE, 2>(x, key, thr, acc, best, t1 + u, t2v[v], 0);
@@ -599,30 +636,49 @@ __device__ __forceinline__ void rows_k2_group(const TileCtx &x, int t1, const fl
     }
 }
 
-template <int SGN, int COLS, int PHASE, bool MASK>
+template <int SGN, int COLS, int PHASE, bool MASK, int V0 = 0>
 __device__ __forceinline__ void rows_k2(const TileCtx &x, int t1b, int t1e, const float4 (&hc)[COLS],
                                         const float (&tc)[COLS], const int (&t2v)[COLS], float thr, float &acc,
                                         Cand &best)
 {
     int t1 = t1b;
     for (; t1 + 8 <= t1e; t1 += 8)
-        rows_k2_group<SGN, COLS, PHASE, MASK, 8>(x, t1, hc, tc, t2v, thr, acc, best);
+        rows_k2_group<SGN, COLS, PHASE, MASK, 8, V0>(x, t1, hc, tc, t2v, thr, acc, best);
     if (t1 + 4 <= t1e) {
-        rows_k2_group<SGN, COLS, PHASE, MASK, 4>(x, t1, hc, tc, t2v, thr, acc, best);
+        rows_k2_group<SGN, COLS, PHASE, MASK, 4, V0>(x, t1, hc, tc, t2v, thr, acc, best);
         t1 += 4;
     }
     for (; t1 < t1e; ++t1)
-        rows_k2_group<SGN, COLS, PHASE, MASK, 1>(x, t1, hc, tc, t2v, thr, acc, best);
+        rows_k2_group<SGN, COLS, PHASE, MASK, 1, V0>(x, t1, hc, tc, t2v, thr, acc, best);
 }
 
+// Rows [rb, re) on the diagonal of a tile whose columns start at cbase: rows
+// in [cbase + 64 V, cbase + 64 (V + 1)) evaluate column blocks V..COLS-1 only
+// (block v < V has every t2 <= t1).
+template <int SGN, int COLS, int PHASE, int V = 0>
+__device__ __forceinline__ void rows_k2_diag(const TileCtx &x, int rb, int re, int cbase, const float4 (&hc)[COLS],
+                                             const float (&tc)[COLS], const int (&t2v)[COLS], float thr,
+                                             float &acc, Cand &best)
+{
+    if constexpr (V < COLS) {
+        const int lo = max(rb, cbase + 64 * V), hi = min(re, cbase + 64 * (V + 1));
+        if (lo < hi)
+            rows_k2<SGN, COLS, PHASE, true, V>(x, lo, hi, hc, tc, t2v, thr, acc, best);
+        rows_k2_diag<SGN, COLS, PHASE, V + 1>(x, rb, re, cbase, hc, tc, t2v, thr, acc, best);
+    }
+}
+
+// Rows of part `part` of `nparts` of the tile (every row when nparts = 1).
 template <int SGN, int COLS, int PHASE>
-__device__ __forceinline__ void tile_k2(const TileCtx &x, int b, int c, float thr, float &acc, Cand &best)
+__device__ __forceinline__ void tile_k2(const TileCtx &x, int b, int c, float thr, float &acc, Cand &best,
+                                        int part = 0, int nparts = 1)
 {
     const int lane = threadIdx.x & 63;
     const int L = x.L;
     const int cbase = b * x.CW;
-    const int r0 = c * x.T1;
-    const int r1 = min(r0 + x.T1, min(L - 2, cbase + x.CW - 1));
+    const int rs = (x.T1 + nparts - 1) / nparts;
+    const int r0 = c * x.T1 + part * rs;
+    const int r1 = min(min(c * x.T1 + x.T1, r0 + rs), min(L - 2, cbase + x.CW - 1));
     if (r0 >= r1)
         return;
     float4 hc[COLS];
@@ -635,9 +691,25 @@ __device__ __forceinline__ void tile_k2(const TileCtx &x, int b, int c, float th
         hc[v] = x.hl[min(t2, L - 1)];
         tc[v] = x.tr[t2]; // -inf past L-2
     }
+    if (PHASE == 2) { // rows one at a time, keys as in phase 1
+#pragma unroll 1
+        for (int t1 = r0; t1 < r1; ++t1) {
+            const float4 hr = x.hl[t1];
+            const float hdr = x.hd[t1];
+            float key[COLS];
+            unsigned valid = 0;
+#pragma unroll
+            for (int v = 0; v < COLS; ++v) {
+                key[v] = (hdr + cls32<SGN>(hc[v], hr, x.mq, x.gmax)) + tc[v];
+                valid |= t1 < t2v[v] ? (1u << v) : 0u;
+            }
+            take_cols<2, COLS>(x, key, t2v, valid, thr, best, t1, 0);
+        }
+        return;
+    }
     const int ra = min(r1, cbase);
     rows_k2<SGN, COLS, PHASE, false>(x, r0, ra, hc, tc, t2v, thr, acc, best); // every t2 > t1
-    rows_k2<SGN, COLS, PHASE, true>(x, max(r0, cbase), r1, hc, tc, t2v, thr, acc, best);
+    rows_k2_diag<SGN, COLS, PHASE>(x, max(r0, cbase), r1, cbase, hc, tc, t2v, thr, acc, best);
 }
 
 template <int SGN, int COLS, int PHASE, int K>
@@ -750,13 +822,18 @@ __device__ __forceinline__ void rows3_loop(const TileCtx &x, const float *Arow, 
                 }
             }
         } else {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
+#pragma unroll 1
+            for (int u = 0; u < 8; ++u) {
+                const float a = Arow[t1 + u];
+                float key[COLS];
+                int tv[COLS];
 #pragma unroll
                 for (int v = 0; v < COLS; ++v) {
-                    float unused = 0.0f;
-                    take<2, 3>(x, av[u] + r[v], thr, unused, best, t1 + u, t2, t3v[v]);
+                    key[v] = a + r[v]; // -inf for columns past the row end
+                    tv[v] = t3v[v];
                 }
+                take_cols<3, COLS>(x, key, tv, (1u << COLS) - 1u, thr, best, t1 + u, t2);
+            }
         }
     }
     acc = fmaxf(acc, fmaxf(acc0, acc1));
@@ -971,10 +1048,21 @@ __device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t 
         M = fmaxf(M, wmax[i]);
     if (M > -INFINITY) {
         const float thr = phase2_threshold(M, sh.sdelta);
-        for (int tile = w; tile < a.tiles; tile += nw) {
-            if (tmax[tile] >= thr) {
-                float acc = -INFINITY;
-                tile_body<SGN, COLS, 2, K>(x, tile % a.NB, tile / a.NB, thr, acc, best);
+        if (K == 1) {
+            for (int tile = w; tile < a.tiles; tile += nw) {
+                if (tmax[tile] >= thr) {
+                    float acc = -INFINITY;
+                    tile_body<SGN, COLS, 2, K>(x, tile % a.NB, tile / a.NB, thr, acc, best);
+                }
+            }
+        } else {
+            // few tiles qualify (typically one): every wavefront takes a share
+            // of the rows of each of them
+            for (int tile = 0; tile < a.tiles; ++tile) {
+                if (tmax[tile] >= thr) {
+                    float acc = -INFINITY;
+                    tile_k2<SGN, COLS, 2>(x, tile % a.NB, tile / a.NB, thr, acc, best, w, nw);
+                }
             }
         }
     }
