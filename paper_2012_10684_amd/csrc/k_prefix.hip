@@ -5,15 +5,15 @@
 //
 //  * C(t) is the exact integer count prefix and P(t) = C(t) / N is one IEEE
 //    division, so P is exact to half an ulp and P(L-1) = 1;
-//  * p_i^q is computed by all threads into LDS; wave 0 then splits the bins
-//    into 64 contiguous chunks, one per lane: each lane sums its chunk left
-//    to right, the chunk bases are chained left to right in registers
-//    (readlane), and Q(t) = base_chunk + local(t).  An empty bin adds +0.0
-//    and a chunk base is the same addition as the last Q of the previous
-//    chunk, so Q(t) == Q(t-1) bit for bit whenever bin t is empty: tuples
-//    that differ only inside a run of empty bins see identical class sums
-//    and tie exactly, as in exact arithmetic;
-//  * results are staged in LDS and written with coalesced stores;
+//  * Q is a block-wide scan in a fixed order: each thread sums E consecutive
+//    bins left to right, the thread totals go through a wavefront
+//    Hillis-Steele scan and a sequential scan of the wavefront totals, and
+//    Q(t) = exclusive base + local prefix;
+//  * an empty bin then takes Q of the last occupied bin at or before it (0
+//    if none): Q(t) == Q(t-1) bit for bit whenever bin t is empty, as in
+//    exact arithmetic, so tuples that differ only inside a run of empty bins
+//    see identical class sums and tie exactly.  The last-occupied index is
+//    an exact integer max-scan;
 //  * one workgroup per (q index, histogram): all q of a call in one launch.
 //    P does not depend on q and is written by the workgroups of q_0.
 #include "common.h"
@@ -21,27 +21,56 @@
 namespace ts {
 
 constexpr int PREFIX_THREADS = 1024; // upper bound: 256 threads below 1024 bins, 1024 from there
-
-__device__ __forceinline__ double readlane_f64(double v, int lane)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
+constexpr int PREFIX_MAX_E = 4;      // bins per thread (L <= 4 * threads)
 
 struct QList {
     double q[TS_MAX_Q];
 };
 
+// Exclusive block-wide scans in a fixed order (every thread returns its
+// exclusive prefix; *total receives the block total).  ws holds one entry per
+// wavefront.
+template <typename T, typename Op>
+__device__ __forceinline__ T block_excl_scan(T x, T ident, Op op, T *ws, T *total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    T incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T v = __shfl_up(incl, o, 64);
+        if (lane >= o)
+            incl = op(v, incl);
+    }
+    if (lane == 63)
+        ws[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) { // sequential over the wavefront totals
+        T run = ident;
+        for (int i = 0; i < nw; ++i) {
+            const T t = ws[i];
+            ws[i] = run;
+            run = op(run, t);
+        }
+        ws[nw] = run;
+    }
+    __syncthreads();
+    const T excl_w = ws[w];
+    T excl = __shfl_up(incl, 1, 64);
+    excl = lane == 0 ? excl_w : op(excl_w, excl);
+    *total = ws[nw];
+    __syncthreads(); // ws is reused by the next scan
+    return excl;
+}
+
 __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__restrict__ hist, int nseg, int L,
                                                            QList ql, double *__restrict__ P, double *__restrict__ Q)
 {
-    extern __shared__ double smem[];
-    double *pq = smem;                        // [L]: p^q, then Q
-    double *sp = smem + L;                    // [L]: P
-    uint32_t *cnt = (uint32_t *)(smem + 2 * L); // [L]: counts
-    __shared__ uint64_t wsum[PREFIX_THREADS / 64];
+    extern __shared__ double smem[]; // [L]: Q before the empty-bin fix-up
+    __shared__ uint64_t wu[PREFIX_THREADS / 64 + 1];
+    __shared__ double wd[PREFIX_THREADS / 64 + 1];
+    __shared__ int wi[PREFIX_THREADS / 64 + 1];
+    double *qs = smem;
+    int *lastocc = reinterpret_cast<int *>(smem + L); // [L]: last occupied bin <= t, or -1
 
     const int s = blockIdx.x % nseg, j = blockIdx.x / nseg;
     const double q = ql.q[j];
@@ -49,24 +78,23 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
     const uint32_t *h = hist + (int64_t)s * L;
     double *Ps = P + (int64_t)s * L;
     double *Qs = Q + (int64_t)blockIdx.x * L;
-    const int lane = threadIdx.x & 63;
-    const int nw = blockDim.x >> 6;
 
-    uint64_t c = 0;
-    for (int i = threadIdx.x; i < L; i += blockDim.x) {
-        const uint32_t ci = h[i];
-        cnt[i] = ci;
-        c += ci;
-    }
+    // this thread's bins [b0, b0 + E)
+    const int E = (L + blockDim.x - 1) / blockDim.x;
+    const int b0 = threadIdx.x * E;
+    uint32_t c[PREFIX_MAX_E];
+    uint64_t csum = 0;
+    int occ = -1;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        c += __shfl_xor(c, o, 64);
-    if (lane == 0)
-        wsum[threadIdx.x >> 6] = c;
-    __syncthreads();
-    uint64_t N = 0;
-    for (int w = 0; w < nw; ++w)
-        N += wsum[w];
+    for (int e = 0; e < PREFIX_MAX_E; ++e) {
+        c[e] = (e < E && b0 + e < L) ? h[b0 + e] : 0u;
+        csum += c[e];
+        if (c[e])
+            occ = b0 + e;
+    }
+    uint64_t N;
+    const uint64_t cbase = block_excl_scan<uint64_t>(
+        csum, 0, [](uint64_t a, uint64_t b) { return a + b; }, wu, &N);
     if (N == 0) {
         for (int i = threadIdx.x; i < L; i += blockDim.x) {
             if (wp)
@@ -76,50 +104,40 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
         return;
     }
     const double Nd = (double)N;
-    for (int i = threadIdx.x; i < L; i += blockDim.x) {
-        const uint32_t ci = cnt[i];
-        pq[i] = ci ? pow((double)ci / Nd, q) : 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int m = (L + 63) / 64;
-        const int b0 = min(L, lane * m), b1 = min(L, b0 + m);
-        uint64_t cs = 0;
-        double qs = 0.0;
-        for (int i = b0; i < b1; ++i) {
-            cs += cnt[i];
-            qs += pq[i];
-        }
-        // exclusive scan of the integer chunk counts (exact in any order)
-        uint64_t incl = cs;
+    double pq[PREFIX_MAX_E];
+    double qloc = 0.0;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint64_t v = __shfl_up(incl, o, 64);
-            if (lane >= o)
-                incl += v;
-        }
-        uint64_t C = incl - cs;
-        // chunk bases of Q chained left to right
-        double run = 0.0, qbase = 0.0;
-        for (int j = 0; j < 64; ++j) {
-            const double tj = readlane_f64(qs, j);
-            if (lane == j)
-                qbase = run;
-            run = run + tj;
-        }
-        double loc = 0.0;
-        for (int i = b0; i < b1; ++i) {
-            C += cnt[i];
-            loc += pq[i];
-            sp[i] = (double)C / Nd;
-            pq[i] = qbase + loc;
+    for (int e = 0; e < PREFIX_MAX_E; ++e) {
+        pq[e] = c[e] ? pow((double)c[e] / Nd, q) : 0.0;
+        qloc += pq[e]; // left to right
+    }
+    double qtot;
+    const double qbase = block_excl_scan<double>(
+        qloc, 0.0, [](double a, double b) { return a + b; }, wd, &qtot);
+    int itot;
+    const int obase = block_excl_scan<int>(
+        occ, -1, [](int a, int b) { return a > b ? a : b; }, wi, &itot);
+    uint64_t C = cbase;
+    double loc = 0.0;
+    int last = obase;
+#pragma unroll
+    for (int e = 0; e < PREFIX_MAX_E; ++e) {
+        if (e < E && b0 + e < L) {
+            const int t = b0 + e;
+            C += c[e];
+            loc += pq[e];
+            if (c[e])
+                last = t;
+            if (wp)
+                Ps[t] = (double)C / Nd;
+            qs[t] = qbase + loc;
+            lastocc[t] = last;
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < L; i += blockDim.x) {
-        if (wp)
-            Ps[i] = sp[i];
-        Qs[i] = pq[i];
+    for (int t = threadIdx.x; t < L; t += blockDim.x) { // coalesced stores
+        const int lt = lastocc[t];
+        Qs[t] = lt < 0 ? 0.0 : qs[lt];
     }
 }
 
@@ -129,11 +147,9 @@ ts_status launch_prefix(const uint32_t *hist, int nseg, int L, int nq, const dou
     QList ql;
     for (int j = 0; j < TS_MAX_Q; ++j)
         ql.q[j] = q[j < nq ? j : 0];
-    const size_t lds = (size_t)L * (2 * sizeof(double) + sizeof(uint32_t));
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_prefix, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    // the p^q evaluations (FP64 pow) dominate for large L: more threads there
+    // L <= 4096 = PREFIX_MAX_E * 1024: 256 threads below 1024 bins (E <= 4)
     const int threads = L >= 1024 ? 1024 : 256;
+    const size_t lds = (size_t)L * (sizeof(double) + sizeof(int));
     hipLaunchKernelGGL(k_prefix, dim3((unsigned)(nseg * nq)), dim3(threads), lds, st, hist, nseg, L, ql, P, Q);
     return check_launch("ts_prefix");
 }

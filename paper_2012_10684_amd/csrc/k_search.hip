@@ -364,7 +364,8 @@ __device__ __forceinline__ float problem_delta(const Args &a, const QConst &c, S
 // past L-2 are -inf.
 template <int SGN>
 __device__ __forceinline__ Steps head_tail32(const Args &a, const QConst &c, const double *P, const double *Q,
-                                             float *hd, float *tl, float4 *hl, double *red)
+                                             float *hd, float *tl, float4 *hl, double *red, double *pl = nullptr,
+                                             double *ql = nullptr)
 {
     const int L = a.L;
     const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -391,6 +392,10 @@ __device__ __forceinline__ Steps head_tail32(const Args &a, const QConst &c, con
         tl[t] = g;
         if (hl)
             hl[t] = h4;
+        if (pl) {
+            pl[t] = p;
+            ql[t] = q;
+        }
     }
     pm = wave_min_f64(pm);
     qm = wave_min_f64(qm);
@@ -993,12 +998,14 @@ __device__ __forceinline__ void write_result(const Cand &b, const Args &a, int s
 // Single-launch path: one workgroup per problem does the setup, phase 1,
 // phase 2 and the final reduction; head/tail rows and tile maxima stay in LDS.
 
-// LDS of the one-workgroup path: the rows hd, tr [Lp], the split prefixes
-// hls [Lp] (k = 2) and the tile maxima tmax [tiles] are carved from dynamic
-// LDS sized for the launch (fused_lds_bytes); the rest is static.
+// LDS of the one-workgroup path: the split prefixes hls [Lp] and FP64 copies
+// of P, Q [Lp] (k = 2; phase 2 reads them), the rows hd, tr [Lp] and the tile
+// maxima tmax [tiles] are carved from dynamic LDS sized for the launch
+// (fused_lds_bytes); the rest is static.
 struct FusedLds {
     float *hd, *tr, *tmax;
     float4 *hls;
+    double *pd, *qd;
     double red[2 * (FUSED_THREADS / 64)];
     float wmax[FUSED_THREADS / 64];
     double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
@@ -1008,7 +1015,8 @@ struct FusedLds {
 
 static size_t fused_lds_bytes(int Lp, int k, int tiles)
 {
-    return (size_t)Lp * (2 * sizeof(float) + (k == 2 ? sizeof(float4) : 0)) + (size_t)tiles * sizeof(float);
+    return (size_t)Lp * (2 * sizeof(float) + (k == 2 ? sizeof(float4) + 2 * sizeof(double) : 0)) +
+           (size_t)tiles * sizeof(float);
 }
 
 template <int SGN, int COLS, int K>
@@ -1021,12 +1029,17 @@ __device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t 
     const QConst &qc = a.qc[s / a.nseg];
     const double *P = a.P + (int64_t)(s % a.nseg) * a.L;
     const double *Q = a.Q + (int64_t)s * a.L;
-    // k = 2: split prefixes in LDS
-    const Steps stp = head_tail32<SGN>(a, qc, P, Q, hd, tr, K == 2 ? hls : nullptr, sh.red);
+    // k = 2: split prefixes and FP64 prefixes in LDS
+    const Steps stp = head_tail32<SGN>(a, qc, P, Q, hd, tr, K == 2 ? hls : nullptr, sh.red,
+                                       K == 2 ? sh.pd : nullptr, K == 2 ? sh.qd : nullptr);
     if (threadIdx.x == 0)
         sh.sdelta = problem_delta(a, qc, stp, Q[a.L - 1]);
     __syncthreads();
-    const TileCtx x = make_ctx(a, s, hd, tr, hls);
+    TileCtx x = make_ctx(a, s, hd, tr, hls);
+    if (K == 2) { // phase 2 reads the prefixes from LDS
+        x.P = sh.pd;
+        x.Q = sh.qd;
+    }
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nw = blockDim.x >> 6;
@@ -1091,7 +1104,9 @@ __global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__rest
     __shared__ FusedLds sh;
     extern __shared__ float4 dyn[]; // fused_lds_bytes(Lp, K, tiles)
     sh.hls = dyn;                   // 16-byte aligned: Lp is a multiple of 256
-    sh.hd = reinterpret_cast<float *>(dyn + (K == 2 ? a.Lp : 0));
+    sh.pd = reinterpret_cast<double *>(dyn + (K == 2 ? a.Lp : 0));
+    sh.qd = sh.pd + (K == 2 ? a.Lp : 0);
+    sh.hd = reinterpret_cast<float *>(sh.qd + (K == 2 ? a.Lp : 0));
     sh.tr = sh.hd + a.Lp;
     sh.tmax = sh.tr + a.Lp;
     if (a.qc[blockIdx.x / a.nseg].sgn > 0)
