@@ -192,17 +192,30 @@ __device__ __forceinline__ double cls64(double dP, double dQ, double q, double s
 }
 
 // FP64 signed Lambda of the tuple t[0..k-1] directly from the prefix sums.
+// The classes go through a rolled loop with one call site of log: the tie
+// check runs for a handful of tuples per problem, so small code (few
+// instruction-cache misses on its first run in each workgroup) matters more
+// than instruction-level parallelism.  Same operations and order as cls64.
 template <int K>
 __device__ __forceinline__ double lambda64_k(const double *P, const double *Q, int L, const int *t, double q,
                                              double sgn, double hmax)
 {
+    const int t0 = t[0], t1 = K > 1 ? t[1] : 0, t2 = K > 2 ? t[2] : 0;
     double acc = 0.0;
     double pa = 0.0, qa = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j <= K; ++j) {
-        const int b = j < K ? t[j] : L - 1;
+        const int b = j == K ? L - 1 : (j == 0 ? t0 : (j == 1 ? t1 : t2));
         const double pb = P[b], qb = Q[b];
-        acc += cls64(pb - pa, qb - qa, q, sgn, hmax);
+        const double dP = pb - pa, dQ = qb - qa;
+        if (!(dP > 0.0))
+            return -INFINITY;
+        double lg[2];
+#pragma unroll 1
+        for (int i = 0; i < 2; ++i)
+            lg[i] = log(i == 0 ? dQ : dP);
+        const double h = sgn * (lg[0] - q * lg[1]);
+        acc += fmin(fmax(h, 0.0), hmax);
         pa = pb;
         qa = qb;
     }
@@ -1061,19 +1074,21 @@ __device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t 
         M = fmaxf(M, wmax[i]);
     if (M > -INFINITY) {
         const float thr = phase2_threshold(M, sh.sdelta);
-        if (K == 1) {
-            for (int tile = w; tile < a.tiles; tile += nw) {
-                if (tmax[tile] >= thr) {
-                    float acc = -INFINITY;
-                    tile_body<SGN, COLS, 2, K>(x, tile % a.NB, tile / a.NB, thr, acc, best);
-                }
-            }
-        } else {
-            // few tiles qualify (typically one): every wavefront takes a share
-            // of the rows of each of them
-            for (int tile = 0; tile < a.tiles; ++tile) {
-                if (tmax[tile] >= thr) {
-                    float acc = -INFINITY;
+        // qualifying tiles found 64 at a time with a ballot (few qualify,
+        // typically one); k = 1: the i-th goes to wavefront i mod nw; k = 2:
+        // every wavefront takes a share of the rows of each of them
+        int nth = 0;
+        for (int base = 0; base < a.tiles; base += 64) {
+            const int t = base + lane;
+            unsigned long long m = __ballot(t < a.tiles && tmax[t] >= thr);
+            while (m) {
+                const int tile = base + __builtin_ctzll(m);
+                m &= m - 1;
+                float acc = -INFINITY;
+                if (K == 1) {
+                    if (nth++ % nw == w)
+                        tile_body<SGN, COLS, 2, K>(x, tile % a.NB, tile / a.NB, thr, acc, best);
+                } else {
                     tile_k2<SGN, COLS, 2>(x, tile % a.NB, tile / a.NB, thr, acc, best, w, nw);
                 }
             }
