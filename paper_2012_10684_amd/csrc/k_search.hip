@@ -1024,6 +1024,7 @@ struct FusedLds {
     double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
     long long wc[FUSED_THREADS / 64];
     float sdelta;
+    int next; // next tile to hand out in phase 1
 };
 
 static size_t fused_lds_bytes(int Lp, int k, int tiles)
@@ -1045,8 +1046,10 @@ __device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t 
     // k = 2: split prefixes and FP64 prefixes in LDS
     const Steps stp = head_tail32<SGN>(a, qc, P, Q, hd, tr, K == 2 ? hls : nullptr, sh.red,
                                        K == 2 ? sh.pd : nullptr, K == 2 ? sh.qd : nullptr);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         sh.sdelta = problem_delta(a, qc, stp, Q[a.L - 1]);
+        sh.next = 0;
+    }
     __syncthreads();
     TileCtx x = make_ctx(a, s, hd, tr, hls);
     if (K == 2) { // phase 2 reads the prefixes from LDS
@@ -1058,9 +1061,20 @@ __device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t 
     const int nw = blockDim.x >> 6;
     Cand best = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL};
     float wm = -INFINITY;
-    for (int tile = w; tile < a.tiles; tile += nw) {
+    // tiles are handed out one at a time from an LDS counter, heaviest first
+    // (the last column block holds the longest t1 rows), so the wavefronts
+    // finish phase 1 together
+    for (;;) {
+        int t = 0;
+        if (lane == 0)
+            t = atomicAdd(&sh.next, 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= a.tiles)
+            break;
+        const int b = a.NB - 1 - t / a.NC, c = t % a.NC;
+        const int tile = c * a.NB + b;
         float acc = -INFINITY;
-        tile_body<SGN, COLS, 1, K>(x, tile % a.NB, tile / a.NB, 0.0f, acc, best);
+        tile_body<SGN, COLS, 1, K>(x, b, c, 0.0f, acc, best);
         acc = wave_max(acc);
         if (lane == 0)
             tmax[tile] = acc;
