@@ -18,7 +18,8 @@
  *                       composition rule recursively;
  *   ts_label            the thresholding kernel function (Algorithm 1),
  *                       extended to k thresholds.
- *   ts_label_sets       ts_label for several threshold sets in one pass.
+ *   ts_label_sets       ts_label for several threshold sets in one pass;
+ *   ts_log2_f32         diagnostic: the FP32 logarithm of the search keys.
  *
  * Conventions shared by every call
  *  - Pointers are DEVICE pointers unless marked [host].  The caller allocates
@@ -209,6 +210,15 @@ ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k
  * Errors: as ts_label, and TS_ERR_INVALID_ARG for nsets out of range. */
 ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int32_t *const *thr, int32_t k,
                         uint8_t *const *const *out, const ts_tuning *tune, ts_stream_t stream);
+
+/* ts_log2_f32 -- diagnostic: y[i] = the FP32 base-2 logarithm that the
+ * FP32 search keys use (the hardware v_log_f32).  The bound on the FP32 key
+ * error that decides which tuples the FP64 tie check revisits takes this
+ * logarithm to be within 4 units of 2^-24 * max(1, |log2 x|) of log2(x) for
+ * normal x; this call lets that be measured against an exact log2.
+ *   x, y   device float [n]; n >= 0.
+ * Errors: TS_ERR_INVALID_ARG for n < 0 or null pointers when n > 0. */
+ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream);
 
 /* [host] Text describing the last non-OK status returned on this thread
  * ("" if none).  The pointer stays valid until the next call on this thread. */

@@ -79,7 +79,9 @@ def _load():
     lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, sz, P, P, P, P, P]
     lib.ts_label.argtypes = [_Batch, Binning, P, i32, P, P, P]
     lib.ts_label_sets.argtypes = [_Batch, Binning, i32, P, i32, P, P, P]
-    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets):
+    lib.ts_log2_f32.argtypes = [P, P, i64, P]
+    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets,
+              lib.ts_log2_f32):
         f.restype = ctypes.c_int
     lib.ts_last_error.argtypes = []
     lib.ts_last_error.restype = ctypes.c_char_p
@@ -274,6 +276,15 @@ def segment(batch: Batch, bin: Binning, k: int, q: float, mode: int = SEARCH_FP3
     thr, obj, status = threshold_search(P, Q, k, q, mode, tune=tune, stream=stream)
     labels = label(batch, bin, thr, k, tune=tune, stream=stream)
     return h, (P, Q), (thr, obj, status), labels
+
+
+def log2_f32(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """The FP32 base-2 logarithm the search keys use (diagnostic)."""
+    if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 CUDA tensor")
+    y = torch.empty_like(x)
+    _check(_lib.ts_log2_f32(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
+    return y
 
 
 def last_error() -> str:

@@ -335,4 +335,15 @@ ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int
     return label_common("ts_label_sets", batch, bin, nsets, thr, k, out, tune, stream);
 }
 
+ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream)
+{
+    if (n < 0)
+        return fail(TS_ERR_INVALID_ARG, "ts_log2_f32: n must be >= 0");
+    if (n > 0 && (!x || !y))
+        return fail(TS_ERR_INVALID_ARG, "ts_log2_f32: null pointer");
+    if (n == 0)
+        return TS_OK;
+    return launch_log2_f32(x, y, n, (hipStream_t)stream);
+}
+
 } // extern "C"

@@ -168,6 +168,7 @@ struct LabelSets {
     const int32_t *thr[TS_MAX_LABEL_SETS];
     uint8_t *const *out[TS_MAX_LABEL_SETS];
 };
+ts_status launch_log2_f32(const float *x, float *y, int64_t n, hipStream_t st);
 ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &sets, int nsets, int k, const Tune &t,
                        hipStream_t st);
 

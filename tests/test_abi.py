@@ -60,6 +60,7 @@ def _bind(lib):
     lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, sz, P, P, P, P, P]
     lib.ts_label.argtypes = [Batch, Binning, P, i32, P, P, P]
     lib.ts_label_sets.argtypes = [Batch, Binning, i32, P, i32, P, P, P]
+    lib.ts_log2_f32.argtypes = [P, P, ctypes.c_int64, P]
     lib.ts_last_error.restype = ctypes.c_char_p
     return lib
 
@@ -99,6 +100,7 @@ def test_workspace_sizes(lib):
     ("search_bins_lt_k1", 1), ("search_null", 1), ("search_nq0", 1), ("search_nq9", 1), ("search_q1_in_batch", 2),
     ("label_k", 1), ("label_null", 1), ("label_total_without_seg", 1),
     ("sets_zero", 1), ("sets_five", 1), ("sets_null_array", 1), ("sets_null_entry", 1), ("sets_k", 1),
+    ("log2_neg", 1), ("log2_null", 1),
 ])
 def test_argument_errors(lib, case, expect):
     _bind(lib)
@@ -150,6 +152,10 @@ def test_argument_errors(lib, case, expect):
         st = lib.ts_label(b1, ok_bin, None, 1, FAKE, None, sx)
     elif case == "label_total_without_seg":
         st = lib.ts_label(Batch(None, None, 0, 5), ok_bin, FAKE, 1, FAKE, None, sx)
+    elif case == "log2_neg":
+        st = lib.ts_log2_f32(FAKE, FAKE, -1, sx)
+    elif case == "log2_null":
+        st = lib.ts_log2_f32(None, FAKE, 10, sx)
     elif case.startswith("sets_"):
         n = {"sets_zero": 0, "sets_five": 5}.get(case, 2)
         thr = (T * 5)(*([FAKE.value] * 5))
@@ -168,6 +174,7 @@ def test_empty_batch_is_a_no_op(lib):
     assert lib.ts_histogram(Batch(None, None, 0, 0), ok_bin, None, None, None) == 0
     assert lib.ts_label(Batch(None, None, 0, 0), ok_bin, None, 1, None, None, None) == 0
     assert lib.ts_label_sets(Batch(None, None, 0, 0), ok_bin, 3, None, 2, None, None, None) == 0
+    assert lib.ts_log2_f32(None, None, 0, None) == 0
     assert lib.ts_prefix(None, 0, 256, 1, qs(0.8), None, None, None) == 0
     assert lib.ts_threshold_search(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, 0, None, None, None, None,
                                    None) == 0

@@ -393,3 +393,23 @@ def test_search_batched_q_equals_single_calls(mode, k, path):
             sj = st[j].cpu().numpy()
             for i in range(n):
                 check_choice(H[i], k, q, thr[j, i].cpu().numpy(), o[i], int(sj[i]))
+
+
+def test_v_log_f32_error_within_the_search_bound():
+    """The FP32 logarithm of the search keys is within LOG2_ERR_UNITS = 4
+    units of 2^-24 * max(1, |log2 x|) of log2(x) (FP64) over normal inputs
+    from 2^-126 to 2^64 (class sums of the search live in this range; the
+    error bound falls back to a full FP64 check below 1e-36)."""
+    rng = np.random.default_rng(2024)
+    e = rng.integers(-126, 64, 4_000_000)
+    m = rng.random(4_000_000)
+    x = np.ldexp(1.0 + m, e).astype(np.float32)
+    x = np.concatenate([x, np.float32([1.0, 2.0, 0.5, 1.0000001, 0.99999994]),
+                        np.nextafter(np.float32(1.0), np.float32(0.0), dtype=np.float32)[None],
+                        np.float32(np.linspace(0.5, 2.0, 200001))])
+    y = api.log2_f32(to_dev(x)).cpu().numpy().astype(np.float64)
+    exact = np.log2(x.astype(np.float64))
+    units = np.abs(y - exact) / (2.0 ** -24 * np.maximum(1.0, np.abs(exact)))
+    worst = float(units.max())
+    say(f"v_log_f32: worst error {worst:.3f} units of 2^-24*max(1,|log2 x|)")
+    assert worst <= 4.0, (worst, x[int(units.argmax())])
