@@ -57,7 +57,7 @@ typedef void *ts_stream_t; /* a hipStream_t; NULL = the default stream */
 typedef enum {
     TS_OK = 0,
     TS_ERR_INVALID_ARG = 1, /* bad sizes, null pointers, bad q/k/window */
-    TS_ERR_UNSUPPORTED = 2, /* valid request the library does not implement (q == 1) */
+    TS_ERR_UNSUPPORTED = 2, /* valid request the library does not implement (none at present) */
     TS_ERR_WORKSPACE = 3,   /* workspace smaller than ts_search_workspace_bytes() */
     TS_ERR_HIP = 4          /* a HIP runtime call or kernel launch failed */
 } ts_status;
@@ -137,13 +137,16 @@ ts_status ts_histogram(ts_batch batch, ts_binning bin, uint32_t *hist, const ts_
  * section compares several q on the same image).
  *   hist   uint32 [nseg][nbins] from ts_histogram;
  *   nq, q  [host] nq (1..TS_MAX_Q) entropic indices (the paper's alpha),
- *          each finite and > 0;
+ *          each finite and > 0; q = 1 selects the Shannon limit (below);
  *   P      out: double [nseg][nbins], P(t) = C(t)/N with C(t) the exact
  *          integer count prefix (one rounding); P(nbins-1) = 1 exactly.
  *          P does not depend on q;
- *   Q      out: double [nq][nseg][nbins], row (j, s) for q[j].  Q is summed
- *          so that an empty bin repeats the previous value bit for bit.
- *          A problem with N = 0 gets P = Q = 0.
+ *   Q      out: double [nq][nseg][nbins], row (j, s) for q[j]: Q(t) =
+ *          sum_{i<=t} p_i^q, or sum_{i<=t} p_i ln p_i for q = 1 (the limit
+ *          q -> 1 of the Tsallis class entropy is the Shannon entropy, whose
+ *          class sums need p ln p).  Q is summed so that an empty bin repeats
+ *          the previous value bit for bit.  A problem with N = 0 gets
+ *          P = Q = 0.
  * Errors: TS_ERR_INVALID_ARG for nseg < 0, nbins outside [2, 4096], nq out
  * of range, null pointers when nseg > 0, a q not finite or <= 0. */
 ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q, double *P,
@@ -165,17 +168,19 @@ size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t
  *   P, Q    double [nseg][nbins] and [nq][nseg][nbins] from ts_prefix with
  *           the same q array;
  *   k       1, 2 or 3;
- *   nq, q   [host] nq (1..TS_MAX_Q) entropic indices, each finite, > 0 and
- *           != 1 (q == 1 is TS_ERR_UNSUPPORTED);
+ *   nq, q   [host] nq (1..TS_MAX_Q) entropic indices, each finite and > 0.
+ *           q = 1 is the Shannon limit (Kapur's objective): class entropies
+ *           S_j = -sum (p_i/w_j) ln(p_i/w_j) composed by addition, S = sum S_j;
  *   mode    TS_SEARCH_*;
  *   ws      device workspace of ws_bytes >= ts_search_workspace_bytes(...);
  *           its contents on entry are ignored;
  *   thr     out: int32 [nq][nseg][k], ascending, or all -1 if no valid tuple;
- *   obj     out: double [nq][nseg], the objective S at thr in FP64 (NaN if none);
+ *   obj     out: double [nq][nseg], the objective S at thr in FP64 (NaN if
+ *           none): expm1(Lambda)/(1-q), or sum S_j for q = 1;
  *   status  out: int32 [nq][nseg], TS_PROBLEM_*.
  * A degenerate or empty problem does not affect the others in the batch.
  * Errors: TS_ERR_INVALID_ARG (sizes, pointers, k, nq, q, mode),
- * TS_ERR_UNSUPPORTED (q == 1), TS_ERR_WORKSPACE. */
+ * TS_ERR_WORKSPACE. */
 ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
                               int32_t nq, const double *q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr,
                               double *obj, int32_t *status, const ts_tuning *tune, ts_stream_t stream);

@@ -225,10 +225,7 @@ static ts_status check_q(const char *fn, int32_t nq, const double *q, bool searc
         if (!(q[j] > 0.0) || !isfinite(q[j]))
             return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": q must be finite and > 0");
     }
-    if (search)
-        for (int j = 0; j < nq; ++j)
-            if (q[j] == 1.0)
-                return fail(TS_ERR_UNSUPPORTED, std::string(fn) + ": q == 1 (Shannon/Kapur limit) is not implemented");
+    (void)search; // every q > 0 is supported, q = 1 being the Shannon limit
     return TS_OK;
 }
 

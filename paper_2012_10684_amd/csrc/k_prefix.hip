@@ -1,7 +1,8 @@
 // k_prefix.hip -- probabilities and prefix sums of one histogram per
 // workgroup (Tsallis-entropy section: p_i = c_i / N, class masses
 // P(t) = sum_{i<=t} p_i, and Q(t) = sum_{i<=t} p_i^q, whose differences give
-// the class sums of p_i^q inside H1 and H2).
+// the class sums of p_i^q inside H1 and H2; for q = 1, the Shannon limit,
+// Q(t) = sum_{i<=t} p_i ln p_i).
 //
 //  * C(t) is the exact integer count prefix and P(t) = C(t) / N is one IEEE
 //    division, so P is exact to half an ulp and P(L-1) = 1;
@@ -108,7 +109,8 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_prefix(const uint32_t *__res
     double qloc = 0.0;
 #pragma unroll
     for (int e = 0; e < PREFIX_MAX_E; ++e) {
-        pq[e] = c[e] ? pow((double)c[e] / Nd, q) : 0.0;
+        const double pe = (double)c[e] / Nd;
+        pq[e] = c[e] ? (q == 1.0 ? pe * log(pe) : pow(pe, q)) : 0.0; // q = 1: the Shannon limit
         qloc += pq[e]; // left to right
     }
     double qtot;

@@ -35,6 +35,12 @@
 //   final   one workgroup per problem reduces the tile bests, writes the tuple,
 //           S = expm1(Lambda)/(1-q) and the status.
 // FP64 mode evaluates every key in FP64 directly (A/R rows in FP64 for k=3).
+//
+// q = 1 is the Shannon limit (Kapur's objective): class entropies
+// S_j = ln w_j - E_j / w_j with E_j the class sum of p ln p (the prefix Q then
+// holds sum p ln p), composed by plain addition; S_j lies in [0, ln m] for a
+// class of m bins.  It runs through the same kernels with sgn = 0 (SGN = 0 in
+// the FP32 templates): one log and one reciprocal per class term.
 // Plain mode is the simple form: one thread per tuple (rank decoded into the
 // tuple), every class evaluated from P and Q in global memory in FP64, a block
 // reduction and a second reduction pass, one problem per launch.
@@ -176,9 +182,16 @@ __device__ __forceinline__ float cls32(const float4 &hb, const float4 &ha, float
 {
     const float dp = (hb.x - ha.x) + (hb.y - ha.y);
     const float dq = (hb.z - ha.z) + (hb.w - ha.w);
-    const float lx = __builtin_amdgcn_logf(dq);
-    const float ly = __builtin_amdgcn_logf(dp);
-    float g = fmaf(mq, ly, SGN > 0 ? lx : -lx); // mq = -sgn * q
+    float g;
+    if (SGN == 0) { // Shannon: log2 w - (E / w) log2(e)
+        const float ly = __builtin_amdgcn_logf(dp);
+        const float r = dq * __builtin_amdgcn_rcpf(dp);
+        g = fmaf(r, -1.44269504f, ly);
+    } else {
+        const float lx = __builtin_amdgcn_logf(dq);
+        const float ly = __builtin_amdgcn_logf(dp);
+        g = fmaf(mq, ly, SGN > 0 ? lx : -lx); // mq = -sgn * q
+    }
     g = __builtin_amdgcn_fmed3f(g, 0.0f, gmax);
     return dp > 0.0f ? g : -INFINITY;
 }
@@ -188,7 +201,7 @@ __device__ __forceinline__ double cls64(double dP, double dQ, double q, double s
 {
     if (!(dP > 0.0))
         return -INFINITY;
-    double h = sgn * (log(dQ) - q * log(dP));
+    const double h = sgn == 0.0 ? log(dP) - dQ / dP : sgn * (log(dQ) - q * log(dP));
     return fmin(fmax(h, 0.0), hmax);
 }
 
@@ -212,10 +225,15 @@ __device__ __forceinline__ double lambda64_k(const double *P, const double *Q, i
         if (!(dP > 0.0))
             return -INFINITY;
         double lg[2];
+        if (sgn == 0.0) { // Shannon
+            lg[1] = log(dP);
+            lg[0] = dQ / dP;
+        } else {
 #pragma unroll 1
-        for (int i = 0; i < 2; ++i)
-            lg[i] = log(i == 0 ? dQ : dP);
-        const double h = sgn * (lg[0] - q * lg[1]);
+            for (int i = 0; i < 2; ++i)
+                lg[i] = log(i == 0 ? dQ : dP);
+        }
+        const double h = sgn == 0.0 ? lg[1] - lg[0] : sgn * (lg[0] - q * lg[1]);
         acc += fmin(fmax(h, 0.0), hmax);
         pa = pb;
         qa = qb;
@@ -315,7 +333,7 @@ __device__ __forceinline__ Steps block_steps(const double *P, const double *Q, i
     double pm = 1.0, qm = INFINITY;
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const double dp = P[t] - (t ? P[t - 1] : 0.0);
-        const double dq = Q[t] - (t ? Q[t - 1] : 0.0);
+        const double dq = fabs(Q[t] - (t ? Q[t - 1] : 0.0)); // Shannon: Q falls
         if (dp > 0.0)
             pm = fmin(pm, dp);
         if (dq > 0.0)
@@ -352,6 +370,7 @@ __device__ __forceinline__ float problem_delta(const Args &a, const QConst &c, S
 {
     if (a.mode == TS_SEARCH_FP32_ONLY)
         return 0.0f;
+    qtot = fabs(qtot); // Shannon: Q(L-1) = sum p ln p <= 0
     if (!(qtot > 0.0) || !(st.dqmin > 1e-36) || !(st.pmin > 1e-36) || qtot > 1e36)
         return INFINITY;
     const float u = 0x1p-24f;
@@ -365,10 +384,22 @@ __device__ __forceinline__ float problem_delta(const Args &a, const QConst &c, S
     const float rq = 2.0f * u + 4.0f * u * u * (float)(qtot / st.dqmin);
     if (!(rp < 1e-3f) || !(rq < 1e-3f))
         return INFINITY;
-    const float ec = (rq + q * rp) * 1.5f                                    // FP32 class sums
-                     + (float)LOG2_ERR_UNITS * u * (Ux + q * Vy)            // v_log_f32
-                     + (float)fabs((double)(-c.sgn * c.mq) - c.q) * Vy      // q rounded to FP32
-                     + u * (gm + 1.0f);                                     // fma + clamp
+    float ec;
+    if (c.sgn == 0.0) {
+        // Shannon term log2 w - (E/w) log2 e: |E/w| <= max |ln p_i| <= ln(1/pmin)
+        // = Vy ln 2 nats; the ratio carries the relative errors of both class
+        // sums, of the reciprocal (2u) and of the product (u), the constant
+        // log2 e its rounding (u); then the fma
+        ec = rp * 1.5f                                      // w cast into the log
+             + (float)LOG2_ERR_UNITS * u * Vy               // v_log_f32
+             + Vy * (rq + rp + 4.1f * u)                    // E / w
+             + u * (2.0f * Vy + gm + 1.0f);                 // fma + clamp
+    } else {
+        ec = (rq + q * rp) * 1.5f                                     // FP32 class sums
+             + (float)LOG2_ERR_UNITS * u * (Ux + q * Vy)              // v_log_f32
+             + (float)fabs((double)(-c.sgn * c.mq) - c.q) * Vy        // q rounded to FP32
+             + u * (gm + 1.0f);                                       // fma + clamp
+    }
     const float kk = (float)a.k;
     const float d = 2.0f * ((kk + 1.0f) * ec + kk * (kk + 1.0f) * u * (gm + 1.0f)) + 1e-9f * (kk + 1.0f) * (gm + 1.0f);
     return d * 1.0001f;
@@ -393,8 +424,9 @@ __device__ __forceinline__ Steps head_tail32(const Args &a, const QConst &c, con
         if (t < L) {
             if (p - p0 > 0.0)
                 pm = fmin(pm, p - p0);
-            if (q - q0 > 0.0)
-                qm = fmin(qm, q - q0);
+            const double dqs = fabs(q - q0); // Shannon: Q falls
+            if (dqs > 0.0)
+                qm = fmin(qm, dqs);
         }
         const float4 h4 = split_hl(p, q);
         float h = -INFINITY, g = -INFINITY;
@@ -441,9 +473,12 @@ __global__ void __launch_bounds__(256) k_setup(Args a)
     else if (c.sgn > 0)
         stp = head_tail32<1>(a, c, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
                              a.hl + (int64_t)s * Lp, red);
-    else
+    else if (c.sgn < 0)
         stp = head_tail32<-1>(a, c, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
                               a.hl + (int64_t)s * Lp, red);
+    else
+        stp = head_tail32<0>(a, c, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
+                             a.hl + (int64_t)s * Lp, red);
     if (threadIdx.x == 0) {
         Meta m;
         m.menc = float_to_ordered(-INFINITY);
@@ -795,10 +830,13 @@ __global__ void __launch_bounds__(256) k_tiles32(Args a)
     const Tile tl = tile_of(a);
     if (!tl.valid)
         return;
-    if (a.qc[tl.s / a.nseg].sgn > 0)
+    const double sgn = a.qc[tl.s / a.nseg].sgn;
+    if (sgn > 0)
         tiles32_wave<1, COLS, PHASE, K>(a, tl);
-    else
+    else if (sgn < 0)
         tiles32_wave<-1, COLS, PHASE, K>(a, tl);
+    else
+        tiles32_wave<0, COLS, PHASE, K>(a, tl);
 }
 
 // k = 3, one workgroup per (problem, row t2, chunk of 1024 columns).  The A
@@ -979,10 +1017,13 @@ __global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
     float *Arow = reinterpret_cast<float *>(arow_dyn);
     __shared__ float wm[K3_THREADS / 64];
     const int s = (int)((int64_t)blockIdx.x / ((int64_t)(a.L - 3) * a.NC));
-    if (a.qc[s / a.nseg].sgn > 0)
+    const double sgn = a.qc[s / a.nseg].sgn;
+    if (sgn > 0)
         rows3_body<1, PHASE>(a, Arow, wm);
-    else
+    else if (sgn < 0)
         rows3_body<-1, PHASE>(a, Arow, wm);
+    else
+        rows3_body<0, PHASE>(a, Arow, wm);
 }
 
 // Write one problem's result from its best candidate.
@@ -1004,7 +1045,7 @@ __device__ __forceinline__ void write_result(const Cand &b, const Args &a, int s
             thr[(int64_t)s * k + j] = (int32_t)(c & 4095);
             c >>= 12;
         }
-        obj[s] = expm1(sgn * b.l) / (1.0 - q);
+        obj[s] = sgn == 0.0 ? b.l : expm1(sgn * b.l) / (1.0 - q); // Shannon: S = sum of S_j
         status[s] = TS_PROBLEM_OK;
     }
 }
@@ -1139,10 +1180,13 @@ __global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__rest
     sh.hd = reinterpret_cast<float *>(sh.qd + (K == 2 ? a.Lp : 0));
     sh.tr = sh.hd + a.Lp;
     sh.tmax = sh.tr + a.Lp;
-    if (a.qc[blockIdx.x / a.nseg].sgn > 0)
+    const double sgn = a.qc[blockIdx.x / a.nseg].sgn;
+    if (sgn > 0)
         fused_body<1, COLS, K>(a, sh, thr_out, obj, status);
-    else
+    else if (sgn < 0)
         fused_body<-1, COLS, K>(a, sh, thr_out, obj, status);
+    else
+        fused_body<0, COLS, K>(a, sh, thr_out, obj, status);
 }
 
 // FP64 mode: exhaustive FP64 keys with the lexicographic tie rule.
@@ -1384,10 +1428,11 @@ QConst make_qconst(double q, int L)
 {
     QConst c;
     c.q = q;
-    c.sgn = q < 1.0 ? 1.0 : -1.0;
-    c.hmax = fabs(1.0 - q) * log((double)L);
+    const bool shannon = q == 1.0; // class entropies at most ln L in either case
+    c.sgn = shannon ? 0.0 : (q < 1.0 ? 1.0 : -1.0);
+    c.hmax = (shannon ? 1.0 : fabs(1.0 - q)) * log((double)L);
     c.mq = (float)(-c.sgn) * (float)q;
-    const double gm = fabs(1.0 - q) * log2((double)L);
+    const double gm = (shannon ? 1.0 : fabs(1.0 - q)) * log2((double)L);
     float g = (float)gm;
     if ((double)g < gm)
         g = nextafterf(g, INFINITY);

@@ -96,8 +96,8 @@ def test_workspace_sizes(lib):
     ("hist_neg_nseg", 1), ("hist_bad_bins", 1), ("hist_lo_gt_hi", 1), ("hist_null", 1), ("hist_bad_tune", 1),
     ("prefix_q0", 1), ("prefix_qnan", 1), ("prefix_bins", 1), ("prefix_null", 1), ("prefix_nq0", 1),
     ("prefix_nq9", 1), ("prefix_qarr_null", 1), ("prefix_second_q_bad", 1),
-    ("search_k0", 1), ("search_k4", 1), ("search_q1", 2), ("search_mode", 1), ("search_ws", 3),
-    ("search_bins_lt_k1", 1), ("search_null", 1), ("search_nq0", 1), ("search_nq9", 1), ("search_q1_in_batch", 2),
+    ("search_k0", 1), ("search_k4", 1), ("search_qneg", 1), ("search_mode", 1), ("search_ws", 3),
+    ("search_bins_lt_k1", 1), ("search_null", 1), ("search_nq0", 1), ("search_nq9", 1), ("search_qnan_in_batch", 1),
     ("label_k", 1), ("label_null", 1), ("label_total_without_seg", 1),
     ("sets_zero", 1), ("sets_five", 1), ("sets_null_array", 1), ("sets_null_entry", 1), ("sets_k", 1),
     ("log2_neg", 1), ("log2_null", 1),
@@ -137,7 +137,7 @@ def test_argument_errors(lib, case, expect):
         st = lib.ts_prefix(FAKE, 1, 256, 2, qs(0.8, -1.0), FAKE, FAKE, sx)
     elif case.startswith("search_"):
         k = {"search_k0": 0, "search_k4": 4}.get(case, 2)
-        q = {"search_q1": (1.0,), "search_q1_in_batch": (0.5, 1.0, 1.5)}.get(case, (0.8,))
+        q = {"search_qneg": (-0.5,), "search_qnan_in_batch": (0.5, 1.0, float("nan"))}.get(case, (0.8,))
         nq = {"search_nq0": 0, "search_nq9": 9}.get(case, len(q))
         if case == "search_nq9":
             q = (0.8,) * 9

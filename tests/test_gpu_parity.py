@@ -132,6 +132,58 @@ def test_search_small_random(mode, k, q):
 
 
 @pytest.mark.parametrize("mode", MODES, ids=["fp32tie", "fp64", "plain"])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_search_shannon_limit_small_random(mode, k):
+    """q = 1: Kapur's objective (sum of class Shannon entropies) against the
+    oracle's literal-sum Kapur mode."""
+    rng = np.random.default_rng(7000 + 10 * k + mode)
+    for L in (k + 1, k + 2, 13, 64, 130):
+        H = _random_hists(rng, 6, L)
+        thr, obj, st = _search_all(H, k, 1.0, mode)
+        for i in range(len(H)):
+            check_choice(H[i], k, 1.0, thr[i], obj[i], st[i], mode=oracle.MODE_KAPUR)
+
+
+def test_prefix_shannon_limit():
+    """q = 1: Q(t) = sum_{i<=t} p_i ln p_i, empty bins repeating Q exactly."""
+    rng = np.random.default_rng(17)
+    hs = [_prefix_case(rng, 1024) for _ in range(4)] + [np.zeros(1024, np.uint32)]
+    one = np.zeros(1024, np.uint32)
+    one[300] = 5  # p = 1: p ln p = 0
+    hs.append(one)
+    H = np.stack(hs)
+    P, Q = api.prefix(to_dev(H.view(np.int32)), 1.0)
+    Q = Q.cpu().numpy()
+    for i, h in enumerate(hs):
+        N = h.sum()
+        if N == 0:
+            assert not Q[i].any()
+            continue
+        p = h.astype(np.float64) / N
+        want = np.cumsum(np.where(p > 0, p * np.log(np.where(p > 0, p, 1.0)), 0.0))
+        tol = 1024 * 2.0 ** -52 * np.maximum(np.abs(want), 1e-300) + 1e-300
+        assert np.all(np.abs(Q[i] - want) <= tol * 4), i
+        z = np.nonzero(h == 0)[0]
+        z = z[z > 0]
+        assert np.array_equal(Q[i][z], Q[i][z - 1])
+
+
+def test_search_shannon_limit_workload_slices():
+    """q = 1 on slices of the 300-slice workload (256 bins, k = 2): the
+    thresholds agree with the oracle's Kapur mode."""
+    vol = synth.workload_volume300(0)[::50]
+    dv = to_dev(vol)
+    b = api.Batch.slices(dv)
+    binn = api.binning(-1024, -200, 256)
+    P, Q = api.prefix(api.histogram(b, binn), 1.0)
+    thr, obj, st = api.threshold_search(P, Q, 2, 1.0)
+    thr, obj, st = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+    for z in range(vol.shape[0]):
+        h = oracle.histogram(vol[z], -1024, -200, 256)
+        check_choice(h, 2, 1.0, thr[z], obj[z], st[z], mode=oracle.MODE_KAPUR)
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["fp32tie", "fp64", "plain"])
 def test_search_edge_cases(mode):
     L = 40
     cases = []
@@ -344,7 +396,7 @@ def test_search_k3_column_chunks(q):
         check_choice(H[i], 3, q, thr[i], obj[i], st[i])
 
 
-QBATCH = (0.5, 1.5, 0.8, 2.0, 0.3, 1.2, 0.95, 3.0)  # both signs of 1 - q, interleaved; TS_MAX_Q values
+QBATCH = (0.5, 1.5, 0.8, 2.0, 1.0, 1.2, 0.3, 3.0)  # both signs of 1 - q and the Shannon limit; TS_MAX_Q values
 
 
 def test_prefix_batched_q_equals_single_calls():
@@ -391,8 +443,9 @@ def test_search_batched_q_equals_single_calls(mode, k, path):
         assert np.array_equal(o, o1.cpu().numpy(), equal_nan=True), q
         if mode == api.SEARCH_FP32_TIECHECK:
             sj = st[j].cpu().numpy()
+            om = oracle.MODE_KAPUR if q == 1.0 else oracle.MODE_PREFIX
             for i in range(n):
-                check_choice(H[i], k, q, thr[j, i].cpu().numpy(), o[i], int(sj[i]))
+                check_choice(H[i], k, q, thr[j, i].cpu().numpy(), o[i], int(sj[i]), mode=om)
 
 
 def test_v_log_f32_error_within_the_search_bound():
