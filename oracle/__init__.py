@@ -20,6 +20,11 @@ Functions and the passages they follow:
                          recursively.
   label               -- Algorithm 1 (thresholding kernel function),
                          generalised to k thresholds.
+  mean3x3 / histogram2d / search2d / objective2d (``oracle2d.c``)
+                      -- Tsallis-entropy section, two-dimensional form: the
+                         3x3 average image, the 2D histogram of (gray level,
+                         average gray level), the class entropies over
+                         quadrants 1 and 3 and the arg max over (t, s).
 """
 from __future__ import annotations
 
@@ -31,6 +36,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC2 = os.path.join(_HERE, "oracle2d.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODE_DIRECT = 0
@@ -43,14 +49,15 @@ EMPTY = 2
 BADARG = 3
 
 
-def compile_source(src: str, out: str) -> str:
-    """Compile one C source into a shared library with gcc (-O2, IEEE
-    semantics, no contraction).  Used for oracle.c itself and, by the tests,
-    for deliberately mutated copies of it."""
+def compile_source(src, out: str) -> str:
+    """Compile C source(s) into a shared library with gcc (-O2, IEEE
+    semantics, no contraction).  Used for the oracle itself and, by the
+    tests, for deliberately mutated copies of oracle.c."""
     tmp = out + ".tmp"
+    srcs = [src] if isinstance(src, str) else list(src)
     subprocess.run(
         ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-         "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, src, "-lm"],
+         "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp] + srcs + ["-lm"],
         check=True)
     os.replace(tmp, out)
     return out
@@ -58,9 +65,14 @@ def compile_source(src: str, out: str) -> str:
 
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        compile_source(_SRC, _LIB)
+    if force or _stale():
+        compile_source([_SRC, _SRC2], _LIB)
     return _LIB
+
+
+def _stale() -> bool:
+    return not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                      os.path.getmtime(_SRC2))
 
 
 def load_library(path: str):
@@ -85,6 +97,15 @@ def _bind(lib):
     lib.or_objective.restype = f64
     lib.or_label.argtypes = [P, i64, i32, i32, i32, P, i32, P]
     lib.or_label.restype = None
+    if hasattr(lib, "or2_search"):  # mutated copies of oracle.c alone lack the 2-D part
+        lib.or2_mean3x3.argtypes = [P, i32, i32, P]
+        lib.or2_mean3x3.restype = None
+        lib.or2_histogram.argtypes = [P, i32, i32, i32, i32, i32, P]
+        lib.or2_histogram.restype = None
+        lib.or2_objective.argtypes = [P, i32, f64, i32, i32, i32]
+        lib.or2_objective.restype = f64
+        lib.or2_search.argtypes = [P, i32, f64, i32, P, P, P, P]
+        lib.or2_search.restype = i32
     return lib
 
 
@@ -94,7 +115,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
@@ -186,3 +207,40 @@ def segment(vox: np.ndarray, lo: int, hi: int, L: int, k: int, q: float, mode: i
     r = search(h, k, q, mode, lib=lib)
     lab = label(vox, lo, hi, L, r.thr, lib=lib)
     return h, r, lab
+
+
+# ------------------------------------------------------------------ 2-D form
+
+def mean3x3(f: np.ndarray, lib=None) -> np.ndarray:
+    """Floor of the 3x3 mean of an integer image (edge pixels repeated)."""
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    H, W = f.shape
+    g = np.empty_like(f)
+    (lib or _load()).or2_mean3x3(_ptr(f), H, W, _ptr(g))
+    return g
+
+
+def histogram2d(img: np.ndarray, lo: int, hi: int, L: int, lib=None) -> np.ndarray:
+    """2D histogram [L, L] (row = gray level, column = 3x3 average gray level)
+    of one int16 image."""
+    img = np.ascontiguousarray(img, dtype=np.int16)
+    H, W = img.shape
+    h = np.empty((L, L), dtype=np.uint32)
+    (lib or _load()).or2_histogram(_ptr(img), H, W, int(lo), int(hi), int(L), _ptr(h))
+    return h
+
+
+def objective2d(h2: np.ndarray, t: int, s: int, q: float, mode: int = MODE_PREFIX, lib=None) -> float:
+    h2 = np.ascontiguousarray(h2, dtype=np.uint32)
+    return float((lib or _load()).or2_objective(_ptr(h2), h2.shape[0], float(q), int(mode), int(t), int(s)))
+
+
+def search2d(h2: np.ndarray, q: float, mode: int = MODE_PREFIX, lib=None) -> SearchResult:
+    """Arg max of the two-dimensional objective over (t, s); thr = [t, s]."""
+    h2 = np.ascontiguousarray(h2, dtype=np.uint32)
+    L = h2.shape[0]
+    t, s_ = ctypes.c_int32(), ctypes.c_int32()
+    obj, sec = ctypes.c_double(), ctypes.c_double()
+    st = (lib or _load()).or2_search(_ptr(h2), L, float(q), int(mode), ctypes.byref(t), ctypes.byref(s_),
+                                      ctypes.byref(obj), ctypes.byref(sec))
+    return SearchResult(np.array([t.value, s_.value], dtype=np.int32), obj.value, sec.value, int(st))
