@@ -19,7 +19,10 @@
  *   ts_label            the thresholding kernel function (Algorithm 1),
  *                       extended to k thresholds.
  *   ts_label_sets       ts_label for several threshold sets in one pass;
- *   ts_log2_f32         diagnostic: the FP32 logarithm of the search keys.
+ *   ts_log2_f32         diagnostic: the FP32 logarithm of the search keys;
+ *   ts_histogram2d,     the paper's two-dimensional form: 2D histogram of
+ *   ts_threshold_search2d  (gray level, 3x3 average gray level) and the
+ *                       arg max over threshold pairs (t, s).
  *
  * Conventions shared by every call
  *  - Pointers are DEVICE pointers unless marked [host].  The caller allocates
@@ -198,6 +201,46 @@ ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, in
  * Errors: TS_ERR_INVALID_ARG for bad sizes, k, binning or null pointers. */
 ts_status ts_label(ts_batch batch, ts_binning bin, const int32_t *thr, int32_t k, uint8_t *const *out,
                    const ts_tuning *tune, ts_stream_t stream);
+
+/* ts_histogram2d -- 2D histograms of the two-dimensional method
+ * (Tsallis-entropy section, 2D form): for every pixel of every image, the
+ * gray level f (ts_binning rule) and the average gray level
+ * g = floor(sum of f over the 3x3 neighbourhood / 9), the neighbourhood
+ * repeating the nearest edge pixel at the image border; h(i, j) counts the
+ * pixels with f = i and g = j.
+ *   batch   nseg images, each height x width int16 pixels in row-major order
+ *           (offs[s+1] - offs[s] = height * width for every s; the host
+ *           checks total = nseg * height * width);
+ *   height, width  image size; 1 <= width <= 4096;
+ *   bin     [host] the binning; nbins <= 256;
+ *   hist    out: uint32 [nseg][nbins][nbins] (row = gray level, column =
+ *           average gray level), overwritten.
+ * Errors: TS_ERR_INVALID_ARG for bad sizes, binning or null pointers. */
+ts_status ts_histogram2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, uint32_t *hist,
+                         ts_stream_t stream);
+
+/* [host] Bytes of workspace ts_threshold_search2d needs (0 if invalid). */
+size_t ts_search2d_workspace_bytes(int32_t nseg, int32_t nbins, int32_t nq);
+
+/* ts_threshold_search2d -- arg max over threshold pairs (t, s), t, s in
+ * [0, nbins-2], of H1 + H2 + (1-q) H1 H2 for the classes {i <= t, j <= s}
+ * and {i > t, j > s} of the 2D histogram (Tsallis-entropy section, 2D
+ * form; the other two quadrants are ignored).  A pair with an empty class is
+ * invalid; ties go to the first pair with t outermost; q = 1 is the Shannon
+ * limit (sum of the two class Shannon entropies).  The class sums come
+ * from 2-D prefix sums formed inside the call (the tables would take
+ * nbins^2 doubles per problem and q); evaluated in FP64.
+ *   hist    uint32 [nseg][nbins][nbins] from ts_histogram2d;
+ *   nq, q   [host] 1..TS_MAX_Q entropic indices, finite, > 0;
+ *   ws      device workspace of ws_bytes >= ts_search2d_workspace_bytes();
+ *   thr     out: int32 [nq][nseg][2] = (t, s), or (-1, -1) if no valid pair;
+ *           only t thresholds the image (ts_label with k = 1);
+ *   obj     out: double [nq][nseg], the objective at (t, s) (NaN if none);
+ *   status  out: int32 [nq][nseg], TS_PROBLEM_*.
+ * Errors: TS_ERR_INVALID_ARG, TS_ERR_WORKSPACE. */
+ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q,
+                                void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status,
+                                ts_stream_t stream);
 
 /* Largest number of threshold sets ts_label_sets takes in one call. */
 #define TS_MAX_LABEL_SETS 4

@@ -80,8 +80,12 @@ def _load():
     lib.ts_label.argtypes = [_Batch, Binning, P, i32, P, P, P]
     lib.ts_label_sets.argtypes = [_Batch, Binning, i32, P, i32, P, P, P]
     lib.ts_log2_f32.argtypes = [P, P, i64, P]
+    lib.ts_histogram2d.argtypes = [_Batch, i32, i32, Binning, P, P]
+    lib.ts_search2d_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.ts_search2d_workspace_bytes.restype = sz
+    lib.ts_threshold_search2d.argtypes = [P, i32, i32, i32, P, P, sz, P, P, P, P]
     for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets,
-              lib.ts_log2_f32):
+              lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d):
         f.restype = ctypes.c_int
     lib.ts_last_error.argtypes = []
     lib.ts_last_error.restype = ctypes.c_char_p
@@ -285,6 +289,41 @@ def log2_f32(x: torch.Tensor, stream=None) -> torch.Tensor:
     y = torch.empty_like(x)
     _check(_lib.ts_log2_f32(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
     return y
+
+
+def histogram2d(batch: Batch, height: int, width: int, bin: Binning, out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """2D histograms uint32 [nseg, L, L] (int32 storage) of height x width images."""
+    L = bin.nbins
+    if out is None:
+        out = torch.empty((batch.nseg, L, L), dtype=torch.int32, device=batch.ptrs.device)
+    _check(_lib.ts_histogram2d(batch._c, int(height), int(width), bin, _ptr(out), _stream(stream)))
+    return out
+
+
+def workspace2d_bytes(nseg: int, nbins: int, nq: int = 1) -> int:
+    return int(_lib.ts_search2d_workspace_bytes(nseg, nbins, nq))
+
+
+def threshold_search2d(hist2d: torch.Tensor, q, ws: Optional[torch.Tensor] = None, out=None, stream=None):
+    """(t, s) pairs int32 [.., nseg, 2], objectives and statuses [.., nseg]; the
+    leading [nq] dimension is present when q is a sequence."""
+    nseg, L, _ = hist2d.shape
+    qs, batched = _qs(q)
+    nq = len(qs)
+    lead = (nq,) if batched else ()
+    need = workspace2d_bytes(nseg, L, nq)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=hist2d.device)
+    if out is None:
+        thr = torch.empty(lead + (nseg, 2), dtype=torch.int32, device=hist2d.device)
+        obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=hist2d.device)
+        status = torch.empty(lead + (nseg,), dtype=torch.int32, device=hist2d.device)
+    else:
+        thr, obj, status = out
+    _check(_lib.ts_threshold_search2d(_ptr(hist2d), nseg, L, nq, _qarr(qs), _ptr(ws), ws.numel(), _ptr(thr),
+                                      _ptr(obj), _ptr(status), _stream(stream)))
+    return thr, obj, status
 
 
 def last_error() -> str:

@@ -332,6 +332,57 @@ ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int
     return label_common("ts_label_sets", batch, bin, nsets, thr, k, out, tune, stream);
 }
 
+ts_status ts_histogram2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, uint32_t *hist,
+                         ts_stream_t stream)
+{
+    ts_status st = check_batch(batch);
+    if (st != TS_OK)
+        return st;
+    BinMap bm;
+    if ((st = make_binmap(bin, &bm)) != TS_OK)
+        return st;
+    if (bin.nbins > 256)
+        return fail(TS_ERR_INVALID_ARG, "ts_histogram2d: nbins must be <= 256");
+    if (height < 1 || width < 1 || width > 4096)
+        return fail(TS_ERR_INVALID_ARG, "ts_histogram2d: need height >= 1 and 1 <= width <= 4096");
+    if (batch.total != (int64_t)batch.nseg * height * width)
+        return fail(TS_ERR_INVALID_ARG, "ts_histogram2d: total must be nseg * height * width");
+    if (batch.nseg > 0 && !hist)
+        return fail(TS_ERR_INVALID_ARG, "ts_histogram2d: hist must not be null");
+    if (batch.nseg == 0)
+        return TS_OK;
+    return launch_hist2d(batch, height, width, bm, hist, (hipStream_t)stream);
+}
+
+size_t ts_search2d_workspace_bytes(int32_t nseg, int32_t nbins, int32_t nq)
+{
+    if (nseg < 0 || nbins < 2 || nbins > 256 || nq < 1 || nq > TS_MAX_Q)
+        return 0;
+    return search2d_workspace_bytes(nseg * nq, nbins);
+}
+
+ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q,
+                                void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status,
+                                ts_stream_t stream)
+{
+    if (nseg < 0)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search2d: nseg must be >= 0");
+    if (nbins < 2 || nbins > 256)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search2d: nbins must be in [2, 256]");
+    ts_status st;
+    if ((st = check_q("ts_threshold_search2d", nq, q, true)) != TS_OK)
+        return st;
+    if (nseg > 0 && (!hist || !thr || !obj || !status))
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search2d: null pointer");
+    const size_t need = search2d_workspace_bytes(nseg * nq, nbins);
+    if (nseg > 0 && (ws_bytes < need || !ws))
+        return fail(TS_ERR_WORKSPACE, "ts_threshold_search2d: workspace too small (need " + std::to_string(need) +
+                                          " bytes, got " + std::to_string(ws_bytes) + ")");
+    if (nseg == 0)
+        return TS_OK;
+    return launch_search2d(hist, nseg, nbins, nq, q, ws, thr, obj, status, (hipStream_t)stream);
+}
+
 ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream)
 {
     if (n < 0)

@@ -61,6 +61,10 @@ def _bind(lib):
     lib.ts_label.argtypes = [Batch, Binning, P, i32, P, P, P]
     lib.ts_label_sets.argtypes = [Batch, Binning, i32, P, i32, P, P, P]
     lib.ts_log2_f32.argtypes = [P, P, ctypes.c_int64, P]
+    lib.ts_histogram2d.argtypes = [Batch, i32, i32, Binning, P, P]
+    lib.ts_search2d_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.ts_search2d_workspace_bytes.restype = sz
+    lib.ts_threshold_search2d.argtypes = [P, i32, i32, i32, P, P, sz, P, P, P, P]
     lib.ts_last_error.restype = ctypes.c_char_p
     return lib
 
@@ -101,6 +105,8 @@ def test_workspace_sizes(lib):
     ("label_k", 1), ("label_null", 1), ("label_total_without_seg", 1),
     ("sets_zero", 1), ("sets_five", 1), ("sets_null_array", 1), ("sets_null_entry", 1), ("sets_k", 1),
     ("log2_neg", 1), ("log2_null", 1),
+    ("h2d_bins", 1), ("h2d_width", 1), ("h2d_total", 1), ("h2d_null", 1),
+    ("s2d_bins", 1), ("s2d_q", 1), ("s2d_ws", 3), ("s2d_null", 1),
 ])
 def test_argument_errors(lib, case, expect):
     _bind(lib)
@@ -152,6 +158,19 @@ def test_argument_errors(lib, case, expect):
         st = lib.ts_label(b1, ok_bin, None, 1, FAKE, None, sx)
     elif case == "label_total_without_seg":
         st = lib.ts_label(Batch(None, None, 0, 5), ok_bin, FAKE, 1, FAKE, None, sx)
+    elif case.startswith("h2d_"):
+        b = Batch(FAKE, FAKE, 2, 2 * 4 * 5)
+        binning = Binning(-1024, 3071, 512 if case == "h2d_bins" else 256)
+        W = 5000 if case == "h2d_width" else 5
+        if case == "h2d_total":
+            b = Batch(FAKE, FAKE, 2, 39)
+        st = lib.ts_histogram2d(b, 4, W, binning, None if case == "h2d_null" else FAKE, sx)
+    elif case.startswith("s2d_"):
+        L = 257 if case == "s2d_bins" else 64
+        q = qs(-1.0) if case == "s2d_q" else qs(0.8)
+        ws_bytes = 8 if case == "s2d_ws" else 1 << 40
+        st = lib.ts_threshold_search2d(None if case == "s2d_null" else FAKE, 3, L, 1, q, FAKE, ws_bytes, FAKE,
+                                       FAKE, FAKE, sx)
     elif case == "log2_neg":
         st = lib.ts_log2_f32(FAKE, FAKE, -1, sx)
     elif case == "log2_null":
@@ -175,6 +194,8 @@ def test_empty_batch_is_a_no_op(lib):
     assert lib.ts_label(Batch(None, None, 0, 0), ok_bin, None, 1, None, None, None) == 0
     assert lib.ts_label_sets(Batch(None, None, 0, 0), ok_bin, 3, None, 2, None, None, None) == 0
     assert lib.ts_log2_f32(None, None, 0, None) == 0
+    assert lib.ts_histogram2d(Batch(None, None, 0, 0), 4, 4, ok_bin, None, None) == 0
+    assert lib.ts_threshold_search2d(None, 0, 64, 1, qs(0.8), None, 0, None, None, None, None) == 0
     assert lib.ts_prefix(None, 0, 256, 1, qs(0.8), None, None, None) == 0
     assert lib.ts_threshold_search(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, 0, None, None, None, None,
                                    None) == 0
