@@ -44,6 +44,10 @@ WORKLOADS = {
               False, -1024, 3071, 4096, 1, (0.8,)),
     "batch64": ("64 volumes 512x512xU{120..600} (23,000+ slices) in one batch, per-slice 256-bin histograms over "
                 "[-1024,-200], per-slice k=2 search, q=0.8, labels", True, -1024, -200, 256, 2, (0.8,)),
+    "volume300_2d": ("volume 512x512x300 int16, the paper's two-dimensional form per slice: 256x256 2D histograms "
+                     "of (gray level, 3x3 average gray level) over [-1024,-200], FP64 arg max over threshold pairs "
+                     "(t, s) for q in {0.5,0.8,1.5}, labels from t for each q", True, -1024, -200, 256, 1,
+                     (0.5, 0.8, 1.5)),
     "serving": ("Poisson trace, 20 volumes/s, half 256x256xU{60..300} and half 512x512xU{120..600}; per volume "
                 "512-bin histogram over [-1024,3071], k=3, q=0.8, labels back in host memory",
                 False, -1024, 3071, 512, 3, (0.8,)),
@@ -167,6 +171,86 @@ def bench_serving(args, wl, trace, jobs, vols):
     print(json.dumps(line), flush=True)
 
 
+def bench_2d(args, wl, dev):
+    import numpy as np
+    import torch
+
+    from paper_2012_10684_amd import api, synth
+
+    desc, _, LO, HI, L, _, QS = wl
+    vol = synth.workload_volume300(0)
+    Z, H, W = vol.shape
+    dv = torch.from_numpy(vol).to(dev)
+    batch = api.Batch.slices(dv)
+    binn = api.binning(LO, HI, L)
+    nq = len(QS)
+    h2 = torch.empty((Z, L, L), dtype=torch.int32, device=dev)
+    ws = torch.empty(api.workspace2d_bytes(Z, L, nq), dtype=torch.uint8, device=dev)
+    res = (torch.empty((nq, 2, Z), dtype=torch.int32, device=dev), torch.empty((nq, Z), dtype=torch.float64, device=dev),
+           torch.empty((nq, Z), dtype=torch.int32, device=dev))
+    thrs = [res[0][j][0] for j in range(nq)]  # t of each q: the k = 1 threshold arrays
+    outs = [[torch.empty(H * W, dtype=torch.uint8, device=dev) for _ in range(Z)] for _ in QS]
+    optrs = [api.device_table([o.data_ptr() for o in oq], dev) for oq in outs]
+    stream = torch.cuda.current_stream()
+    names = ["histogram2d", "search2d", "label"]
+
+    def step(ev=None):
+        ev = ev or {}
+
+        def mark(name, i):
+            if name in ev:
+                ev[name][i].record(stream)
+
+        mark("histogram2d", 0)
+        api.histogram2d(batch, H, W, binn, out=h2, stream=stream)
+        mark("histogram2d", 1)
+        mark("search2d", 0)
+        api.threshold_search2d(h2, QS, ws=ws, out=res, stream=stream)
+        mark("search2d", 1)
+        mark("label", 0)
+        api.label_sets(batch, binn, thrs, 1, outs=outs, out_ptrs=optrs, tune="auto", stream=stream)
+        mark("label", 1)
+
+    def pairs(n, keys):
+        return [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in keys}
+                for _ in range(n)]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    roof = pairs(args.steps, ["label"])
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(roof[i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kev = pairs(min(args.steps, 10), names)
+    for e in kev:
+        step(e)
+    torch.cuda.synchronize()
+    per = {n: sum(e[n][0].elapsed_time(e[n][1]) for e in kev) * 1e-3 / len(kev) for n in names}
+    label_t = sum(e["label"][0].elapsed_time(e["label"][1]) for e in roof) * 1e-3 / len(roof)
+    nvox = int(vol.size)
+    alg = (2 + nq) * nvox
+    st_ok = int((res[2] != 0).sum()) == 0
+    line = {
+        "metric": "voxels/s end-to-end (two-dimensional form; + threshold pairs/s)",
+        "value": nvox * args.steps / dt, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "problems": Z, "voxels": nvox, "bins": L, "q": list(QS)},
+        "pairs_per_s": nq * Z * (L - 1) ** 2 * args.steps / dt,
+        "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
+        "kernel_us_note": "from an untimed pass with events around every kernel (each event adds a gap)",
+        "roofline": {"bound": "hbm", "kernel": "k_label", "achieved": alg / label_t / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg / label_t / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_us": label_t * 1e6},
+        "histogram2d_gbs": 2 * nvox / per["histogram2d"] / 1e9,
+        "all_problems_ok": bool(st_ok),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -191,6 +275,8 @@ def main():
         pool = make_pool([("batch", i, max(depths), 512) for i in range(POOL)])
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "volume300_2d":
+        return bench_2d(args, WORKLOADS[args.workload], dev)
     if args.calibrate:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)

@@ -233,8 +233,9 @@ size_t ts_search2d_workspace_bytes(int32_t nseg, int32_t nbins, int32_t nq);
  *   hist    uint32 [nseg][nbins][nbins] from ts_histogram2d;
  *   nq, q   [host] 1..TS_MAX_Q entropic indices, finite, > 0;
  *   ws      device workspace of ws_bytes >= ts_search2d_workspace_bytes();
- *   thr     out: int32 [nq][nseg][2] = (t, s), or (-1, -1) if no valid pair;
- *           only t thresholds the image (ts_label with k = 1);
+ *   thr     out: int32 [nq][2][nseg]: t in row 0, s in row 1 of each q
+ *           (-1 if no valid pair); only t thresholds the image, and row 0
+ *           is the [nseg][1] threshold array of ts_label with k = 1;
  *   obj     out: double [nq][nseg], the objective at (t, s) (NaN if none);
  *   status  out: int32 [nq][nseg], TS_PROBLEM_*.
  * Errors: TS_ERR_INVALID_ARG, TS_ERR_WORKSPACE. */

@@ -306,8 +306,9 @@ def workspace2d_bytes(nseg: int, nbins: int, nq: int = 1) -> int:
 
 
 def threshold_search2d(hist2d: torch.Tensor, q, ws: Optional[torch.Tensor] = None, out=None, stream=None):
-    """(t, s) pairs int32 [.., nseg, 2], objectives and statuses [.., nseg]; the
-    leading [nq] dimension is present when q is a sequence."""
+    """thresholds int32 [.., 2, nseg] (row 0: t, row 1: s), objectives and
+    statuses [.., nseg]; the leading [nq] dimension is present when q is a
+    sequence.  Row 0 is the k = 1 threshold array of `label`."""
     nseg, L, _ = hist2d.shape
     qs, batched = _qs(q)
     nq = len(qs)
@@ -316,7 +317,7 @@ def threshold_search2d(hist2d: torch.Tensor, q, ws: Optional[torch.Tensor] = Non
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=hist2d.device)
     if out is None:
-        thr = torch.empty(lead + (nseg, 2), dtype=torch.int32, device=hist2d.device)
+        thr = torch.empty(lead + (2, nseg), dtype=torch.int32, device=hist2d.device)
         obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=hist2d.device)
         status = torch.empty(lead + (nseg,), dtype=torch.int32, device=hist2d.device)
     else:

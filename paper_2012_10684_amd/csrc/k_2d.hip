@@ -293,9 +293,11 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
         N += wu[i];
     __syncthreads();
+    // thr is [nq][2][nseg]: t at row 0, s at row 1 of this q
+    int32_t *thr_t = thr + (int64_t)(2 * j) * nseg + s0, *thr_s = thr_t + nseg;
     if (N == 0) {
         if (threadIdx.x == 0) {
-            thr[2 * prob] = thr[2 * prob + 1] = -1;
+            *thr_t = *thr_s = -1;
             obj[prob] = NAN;
             status[prob] = TS_PROBLEM_EMPTY;
         }
@@ -355,12 +357,12 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
                 code = bc[i];
             }
         if (!(best > -INFINITY)) {
-            thr[2 * prob] = thr[2 * prob + 1] = -1;
+            *thr_t = *thr_s = -1;
             obj[prob] = NAN;
             status[prob] = TS_PROBLEM_DEGENERATE;
         } else {
-            thr[2 * prob] = (int32_t)(code >> 12);
-            thr[2 * prob + 1] = (int32_t)(code & 4095);
+            *thr_t = (int32_t)(code >> 12);
+            *thr_s = (int32_t)(code & 4095);
             obj[prob] = sgn == 0.0 ? best : expm1(sgn * best) / (1.0 - q);
             status[prob] = TS_PROBLEM_OK;
         }

@@ -82,7 +82,7 @@ def test_search2d_small_random(q):
         thr, obj, st = api.threshold_search2d(to_dev(H2.view(np.int32)), q)
         thr, obj, st = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
         for i in range(len(H2)):
-            check_pair(H2[i], q, thr[i], obj[i], st[i])
+            check_pair(H2[i], q, thr[:, i], obj[i], st[i])
 
 
 def test_search2d_edge_cases():
@@ -93,7 +93,7 @@ def test_search2d_edge_cases():
     H2[2, 6, 6] = 4  # all valid pairs tie at S = 0: the first, (3, 4)
     H2[3] = 5  # uniform: (L/2 - 1, L/2 - 1)
     thr, obj, st = api.threshold_search2d(to_dev(H2.view(np.int32)), 0.8)
-    thr, st = thr.cpu().numpy(), st.cpu().numpy()
+    thr, st = thr.cpu().numpy().T, st.cpu().numpy()
     assert st.tolist() == [api.PROBLEM_EMPTY, api.PROBLEM_DEGENERATE, 0, 0]
     assert thr[0].tolist() == [-1, -1] and thr[1].tolist() == [-1, -1]
     assert thr[2].tolist() == [3, 4] and obj[2].item() == 0.0
@@ -122,9 +122,9 @@ def test_search2d_workload_slices(q):
     binn = api.binning(-1024, -200, 256)
     h2 = api.histogram2d(b, 512, 512, binn)
     thr, obj, st = api.threshold_search2d(h2, q)
-    labels = api.label(b, binn, thr[:, :1].contiguous(), 1)
+    labels = api.label(b, binn, thr[0], 1)  # row 0 (t) is the k = 1 threshold array
     torch.cuda.synchronize()
-    H2, thr_h, obj_h, st_h = u32(h2), thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+    H2, thr_h, obj_h, st_h = u32(h2), thr.cpu().numpy().T, obj.cpu().numpy(), st.cpu().numpy()
     for z in range(vol.shape[0]):
         want = oracle.histogram2d(vol[z], -1024, -200, 256)
         assert np.array_equal(H2[z], want), z
