@@ -5,16 +5,15 @@
 // {i > t, j > s} (quadrants 1 and 3) and the arg max over (t, s) of the
 // pseudo-additive objective.  Only t thresholds the image (ts_label, k = 1).
 //
-// k_hist2d: one workgroup per band of rows of one image.  The gray levels of
-// three consecutive rows sit in an LDS ring, so each pixel's 3x3 sum is a
-// column sum of the ring plus its two neighbours.  CT neighbourhoods are
-// smooth, so (f, g) stays near the diagonal: cells with |f - g| <= BAND go to
-// an LDS histogram of the band, the two clamp corners (0, 0) and (L-1, L-1)
-// to per-lane LDS counters (under a narrow window they take a large share of
-// the pixels), and the rest straight to the global 2D histogram with
-// atomics.  The LDS atomic is issued for every pixel (cells outside the
-// LDS band land on a per-lane dummy), so its address, not a branch, selects
-// the target.
+// k_hist2d: one workgroup per band of at most 65535 pixels of one image, in
+// chunks of about 4096 pixels: the 8-bit gray levels of a chunk's rows and
+// its two halo rows are staged in LDS in one pass, so each pixel's 3x3 sum
+// reads LDS only.  The whole L x L plane is counted in LDS as 16-bit cells
+// (two per word; 128 KiB at L = 256), which cannot overflow within the
+// band; the two clamp corners (0, 0) and (L-1, L-1), which take a large share
+// of the pixels under a narrow window, count in per-lane LDS words instead of
+// one hot address.  At the end the non-zero cells are added to the global 2D
+// histogram.
 //
 // k_search2d: one workgroup per (q index, problem), one thread per column s.
 // Class 2 sums are accumulated bottom-up over rows and its log term
@@ -34,8 +33,7 @@
 
 namespace ts {
 
-constexpr int H2_THREADS = 256;
-constexpr int H2_BAND = 31;       // |f - g| <= BAND counted in LDS
+constexpr int H2_THREADS = 1024;
 constexpr int H2_MAX_W = 4096;    // row length held in the LDS ring
 constexpr int H2_MAX_L = 256;     // 2D histograms up to 256 x 256
 constexpr int S2_THREADS = 256;   // one thread per column s (L <= 256)
@@ -44,15 +42,15 @@ constexpr int S2_THREADS = 256;   // one thread per column s (L <= 256)
 
 template <int MAP>
 __global__ void __launch_bounds__(H2_THREADS) k_hist2d(const int16_t *const *__restrict__ vox, int nseg, int H,
-                                                       int W, int rows_per_wg, BinMap bm, uint32_t *__restrict__ hist)
+                                                       int W, int rows_per_wg, int chunk_rows, BinMap bm,
+                                                       uint32_t *__restrict__ hist)
 {
     extern __shared__ uint32_t sm[];
     const int L = bm.L;
-    const int BW = 2 * H2_BAND + 1;
-    uint32_t *band = sm;                                  // [L * BW]
-    uint32_t *hot = band + L * BW;                        // [2 * 64]: (0,0), (L-1,L-1) per lane
-    uint32_t *dummy = hot + 128;                          // [64]
-    int *ring = reinterpret_cast<int *>(dummy + 64);      // [3 * W] gray levels of rows r-1, r, r+1
+    const int nw2 = (L * L + 1) / 2;                       // packed 16-bit cells
+    uint32_t *plane = sm;                                  // [nw2]: cell c in half (c & 1) of word c >> 1
+    uint32_t *hot = plane + nw2;                           // [2 * 64]: (0,0), (L-1,L-1) per lane
+    uint8_t *rows = reinterpret_cast<uint8_t *>(hot + 128); // [(chunk_rows + 2) * W] gray levels (L <= 256)
     const int lane = threadIdx.x & 63;
     const int bands = (H + rows_per_wg - 1) / rows_per_wg;
     const int s = blockIdx.x / bands;
@@ -60,58 +58,61 @@ __global__ void __launch_bounds__(H2_THREADS) k_hist2d(const int16_t *const *__r
     const int r1 = min(H, r0 + rows_per_wg);
     const TS_GLOBAL int16_t *img = gp(vox[s]);
     uint32_t *hs = hist + (int64_t)s * L * L;
-    for (int i = threadIdx.x; i < L * BW + 192; i += blockDim.x)
+    for (int i = threadIdx.x; i < nw2 + 128; i += blockDim.x)
         sm[i] = 0u;
-    // ring slot of image row y: y mod 3 (rows r0-1 .. r1 are loaded in order)
-    auto load_row = [&](int y) {
-        const int yc = min(max(y, 0), H - 1);
-        int *dst = ring + ((y + 3) % 3) * W;
-        for (int x = threadIdx.x; x < W; x += blockDim.x)
-            dst[x] = bin_of_t<MAP>(img[(int64_t)yc * W + x], bm);
-    };
-    load_row(r0 - 1);
-    load_row(r0);
-    for (int r = r0; r < r1; ++r) {
-        load_row(r + 1);
+    // chunks of chunk_rows image rows: the gray levels of rows r-1 .. r+n
+    // (edge rows repeated) are staged in LDS in one pass, then every pixel of
+    // rows r .. r+n-1 is counted
+    for (int r = r0; r < r1; r += chunk_rows) {
+        const int n = min(chunk_rows, r1 - r);
+        __syncthreads(); // previous chunk fully counted
+        for (int i = threadIdx.x; i < (n + 2) * W; i += blockDim.x) {
+            const int k = i / W, x = i - k * W;
+            const int y = min(max(r - 1 + k, 0), H - 1);
+            rows[i] = (uint8_t)bin_of_t<MAP>(img[(int64_t)y * W + x], bm);
+        }
         __syncthreads();
-        const int *up = ring + ((r + 2) % 3) * W, *cu = ring + ((r + 3) % 3) * W, *dn = ring + ((r + 4) % 3) * W;
-        for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
+            const int k = i / W + 1, x = i - (k - 1) * W;
             const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
-            const int sum = up[xl] + up[x] + up[xr] + cu[xl] + cu[x] + cu[xr] + dn[xl] + dn[x] + dn[xr];
+            const uint8_t *up = rows + (k - 1) * W, *cu = rows + k * W, *dn = rows + (k + 1) * W;
+            const int sum = (int)up[xl] + up[x] + up[xr] + cu[xl] + cu[x] + cu[xr] + dn[xl] + dn[x] + dn[xr];
             const int f = cu[x];
             const int g = (int)((uint32_t)sum / 9u);
-            const int d = g - f;
-            const bool inb = d >= -H2_BAND && d <= H2_BAND;
-            uint32_t *a = inb ? band + f * BW + (d + H2_BAND) : dummy + lane;
-            if (f == g && (f == 0 || f == L - 1))
-                a = hot + (f == 0 ? 0 : 64) + lane;
-            atomicAdd(a, 1u);
-            if (!inb) // rare: far from the diagonal
-                atomicAdd(&hs[(int64_t)f * L + g], 1u);
+            const int c = f * L + g;
+            const bool corner = f == g && (f == 0 || f == L - 1);
+            uint32_t *a = corner ? hot + (f == 0 ? 0 : 64) + lane : plane + (c >> 1);
+            atomicAdd(a, corner ? 1u : (1u << ((c & 1) << 4)));
         }
-        __syncthreads(); // the ring slot of row r-1 is reloaded next
-    }
-    // fold the clamp-corner counters into the band, then add the band
-    if (threadIdx.x < 2) {
-        uint32_t c = 0;
-        for (int i = 0; i < 64; ++i)
-            c += hot[threadIdx.x * 64 + i];
-        const int f = threadIdx.x == 0 ? 0 : L - 1;
-        atomicAdd(&band[f * BW + H2_BAND], c);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < L * BW; i += blockDim.x) {
-        const uint32_t c = band[i];
-        if (c) {
-            const int f = i / BW, g = f + i % BW - H2_BAND;
-            atomicAdd(&hs[(int64_t)f * L + g], c);
+    // every cell count is at most the workgroup's pixel count (<= 65535): no
+    // half-word overflows.  Add the non-zero cells to the global histogram.
+    for (int i = threadIdx.x; i < nw2; i += blockDim.x) {
+        uint32_t w2 = plane[i];
+        if (i == 0 || i == (L * L - 1) >> 1) { // the clamp corners' per-lane counters
+            for (int j = 0; j < 2; ++j) {
+                const int cell = j == 0 ? 0 : L * L - 1;
+                if ((cell >> 1) != i)
+                    continue;
+                uint32_t cc = 0;
+                for (int l = 0; l < 64; ++l)
+                    cc += hot[j * 64 + l];
+                atomicAdd(&hs[cell], cc); // global directly: the sum may exceed 16 bits
+            }
         }
+        if (w2 & 0xffffu)
+            atomicAdd(&hs[2 * i], w2 & 0xffffu);
+        if ((w2 >> 16) && 2 * i + 1 < L * L)
+            atomicAdd(&hs[2 * i + 1], w2 >> 16);
     }
 }
 
+static int hist2d_chunk_rows(int W) { return std::max(1, 4096 / W); }
+
 size_t hist2d_lds_bytes(int L, int W)
 {
-    return ((size_t)L * (2 * H2_BAND + 1) + 192) * sizeof(uint32_t) + (size_t)3 * W * sizeof(int);
+    return ((size_t)(L * L + 1) / 2 + 128) * sizeof(uint32_t) + (size_t)(hist2d_chunk_rows(W) + 2) * W;
 }
 
 ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint32_t *hist, hipStream_t st)
@@ -121,28 +122,22 @@ ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint3
     const int64_t n = (int64_t)b.nseg * bm.L * bm.L;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, st, hist,
                        n);
-    const int rows = std::max(1, std::min(H, (int)((int64_t)65536 / std::max(W, 1)))); // ~64k pixels per workgroup
+    // at most 65535 pixels per workgroup (16-bit cell counters in LDS)
+    const int rows = std::max(1, std::min(H, 65535 / std::max(W, 1)));
     const int bands = (H + rows - 1) / rows;
+    const int chunk = hist2d_chunk_rows(W);
     const size_t lds = hist2d_lds_bytes(bm.L, W);
     const dim3 g((unsigned)((int64_t)b.nseg * bands)), blk(H2_THREADS);
+#define TS_H2(M)                                                                                                    \
+    (void)hipFuncSetAttribute((const void *)k_hist2d<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+    hipLaunchKernelGGL(k_hist2d<M>, g, blk, lds, st, b.vox, b.nseg, H, W, rows, chunk, bm, hist)
     switch (map_kind(bm)) {
-    case 0:
-        (void)hipFuncSetAttribute((const void *)k_hist2d<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_hist2d<0>, g, blk, lds, st, b.vox, b.nseg, H, W, rows, bm, hist);
-        break;
-    case 1:
-        (void)hipFuncSetAttribute((const void *)k_hist2d<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_hist2d<1>, g, blk, lds, st, b.vox, b.nseg, H, W, rows, bm, hist);
-        break;
-    case 2:
-        (void)hipFuncSetAttribute((const void *)k_hist2d<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_hist2d<2>, g, blk, lds, st, b.vox, b.nseg, H, W, rows, bm, hist);
-        break;
-    default:
-        (void)hipFuncSetAttribute((const void *)k_hist2d<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_hist2d<3>, g, blk, lds, st, b.vox, b.nseg, H, W, rows, bm, hist);
-        break;
+    case 0: TS_H2(0); break;
+    case 1: TS_H2(1); break;
+    case 2: TS_H2(2); break;
+    default: TS_H2(3); break;
     }
+#undef TS_H2
     return check_launch("ts_histogram2d");
 }
 
@@ -152,11 +147,12 @@ struct Q2List {
     double q[TS_MAX_Q];
 };
 
-// Row prefix (dir = +1) or suffix (dir = -1) along s of one 2D histogram row
-// for the thread's column s = threadIdx.x, in a fixed order: the exact
-// integer count c and the FP64 sum of p^q (or p ln p), where an empty cell
-// repeats the value of the nearest occupied cell on the side it is summed
-// from.  ws* hold one entry per wavefront (+1).
+// Row prefix (DIR = +1) or suffix (DIR = -1) along s of one 2D histogram
+// row, in a fixed order: scan position p = threadIdx.x is column p (prefix)
+// or column L-1-p (suffix); c is that column's count, loaded by the caller.
+// Returns the exact integer count sum and the FP64 sum of p^q (or p ln p) up
+// to the position, where an empty cell repeats the value of the nearest
+// occupied cell before it in scan order.  ws* hold one entry per wavefront.
 struct RowSums {
     uint64_t c;
     double q;
@@ -170,32 +166,21 @@ __device__ __forceinline__ double pterm(uint32_t c, double N, double q)
     return q == 1.0 ? p * log(p) : pow(p, q);
 }
 
-template <int DIR>
-__device__ __forceinline__ RowSums row_scan(const uint32_t *__restrict__ hrow, int L, double N, double q,
-                                            uint64_t *wu, double *wd, int *wi, double *rq)
+// Per-wavefront totals of one row scan: count, FP64 sum, last occupied scan
+// position of the wavefront (or -1) and the inclusive sum there.
+struct WaveTot {
+    uint64_t c;
+    double v;
+    int occ;
+    double occv;
+};
+
+__device__ __forceinline__ RowSums row_scan(uint32_t c, double pv, WaveTot *wt)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    // position along the scan direction
-    const int s = threadIdx.x;
-    const bool in = s < L;
-    const uint32_t c = in ? hrow[s] : 0u;
-    const double v = in ? pterm(c, N, q) : 0.0;
-    // the scan index: ascending s for prefixes, descending for suffixes
-    // (lanes are reversed for suffixes so that every scan runs over lanes in
-    // ascending order)
-    const int pos = DIR > 0 ? s : (blockDim.x - 1 - s);
-    // exchange through LDS so that lane order is scan order
-    __shared__ uint32_t xc[S2_THREADS];
-    __shared__ double xv[S2_THREADS];
-    xc[pos] = c;
-    xv[pos] = v;
-    __syncthreads();
-    const uint32_t mc = xc[threadIdx.x];
-    const double mv = xv[threadIdx.x];
-    __syncthreads();
-    uint64_t ic = mc;
-    double iv = mv;
-    int occ = mc ? (int)threadIdx.x : -1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t ic = c;
+    double iv = pv; // p^q (or p ln p) of this cell
+    int occ = c ? (int)threadIdx.x : -1;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint64_t tc = __shfl_up(ic, o, 64);
@@ -207,47 +192,32 @@ __device__ __forceinline__ RowSums row_scan(const uint32_t *__restrict__ hrow, i
             occ = max(occ, to);
         }
     }
-    if (lane == 63) {
-        wu[w] = ic;
-        wd[w] = iv;
-        wi[w] = occ;
-    }
+    // inclusive sum at this wavefront's last occupied position so far
+    const double ivocc = __shfl(iv, occ < 0 ? 0 : (occ & 63), 64);
+    if (lane == 63) // ivocc of lane 63: the sum at the wavefront's last occupied position
+        wt[w] = WaveTot{ic, iv, occ, ivocc};
     __syncthreads();
-    if (threadIdx.x == 0) { // sequential over the wavefront totals
-        uint64_t rc = 0;
-        double rv = 0.0;
-        int ro = -1;
-        for (int i = 0; i < nw; ++i) {
-            const uint64_t a = wu[i];
-            const double b = wd[i];
-            const int o2 = wi[i];
-            wu[i] = rc;
-            wd[i] = rv;
-            wi[i] = ro;
-            rc += a;
-            rv = rv + b;
-            ro = max(ro, o2);
+    // totals of the earlier wavefronts, combined in order
+    uint64_t bc = 0;
+    double bv = 0.0;
+    int bo = -1;
+    double bov = 0.0;
+    for (int i = 0; i < w; ++i) {
+        const WaveTot t = wt[i];
+        bc += t.c;
+        if (t.occ >= 0) {
+            bo = t.occ;
+            bov = bv + t.occv; // the sum at that position, as its own wavefront formed it after the base
         }
+        bv = bv + t.v;
     }
-    __syncthreads();
-    ic += wu[w];
-    iv = wd[w] + iv;
-    occ = max(occ, wi[w]);
-    // empty cells take the sum at the last occupied scan position
-    rq[threadIdx.x] = iv;
-    __syncthreads();
-    const double fixed = occ < 0 ? 0.0 : rq[occ];
-    __syncthreads();
-    // back to column order
-    __shared__ uint64_t yc[S2_THREADS];
-    __shared__ double yv[S2_THREADS];
-    yc[threadIdx.x] = ic;
-    yv[threadIdx.x] = fixed;
-    __syncthreads();
     RowSums r;
-    r.c = yc[pos];
-    r.q = yv[pos];
-    __syncthreads();
+    r.c = bc + ic;
+    // empty cells take the sum at the last occupied position in scan order
+    if (occ >= 0)
+        r.q = bv + ivocc;
+    else
+        r.q = bo >= 0 ? bov : 0.0;
     return r;
 }
 
@@ -267,9 +237,7 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
                                                          double *__restrict__ obj, int32_t *__restrict__ status)
 {
     __shared__ uint64_t wu[S2_THREADS / 64 + 1];
-    __shared__ double wd[S2_THREADS / 64 + 1];
-    __shared__ int wi[S2_THREADS / 64 + 1];
-    __shared__ double rq[S2_THREADS];
+    __shared__ WaveTot wt[2][S2_THREADS / 64]; // alternate rows: one barrier per row scan
     __shared__ double br[S2_THREADS / 64];
     __shared__ long long bc[S2_THREADS / 64];
     const int prob = blockIdx.x, s0 = prob % nseg, j = prob / nseg;
@@ -304,29 +272,41 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
         return;
     }
     const double Nd = (double)N;
-    // class 2, bottom-up: B(t, s) = sums over {i >= t, j >= s}
+    // class 2, bottom-up: B(t, s) = sums over {i >= t, j >= s}; thread p
+    // holds column L-1-p (suffix order); each row's counts are loaded one
+    // row ahead
+    const int cb = L - 1 - s; // this thread's column in the suffix pass
     uint64_t bcnt = 0;
     double bq = 0.0;
+    uint32_t cn = (s < L) ? h[(int64_t)(L - 1) * L + cb] : 0u;
     for (int t = L - 1; t >= 1; --t) {
-        const RowSums r = row_scan<-1>(h + (int64_t)t * L, L, Nd, q, wu, wd, wi, rq);
+        const uint32_t c = cn;
+        if (t > 1)
+            cn = (s < L) ? h[(int64_t)(t - 1) * L + cb] : 0u;
+        const RowSums r = row_scan(c, pterm(c, Nd, q), wt[t & 1]);
         bcnt += r.c;
         bq = bq + r.q;
         if (s < L)
-            lbp[(int64_t)t * L + s] = class_term2(bcnt, bq, Nd, q, sgn, hmax);
+            lbp[(int64_t)t * L + cb] = class_term2(bcnt, bq, Nd, q, sgn, hmax);
     }
-    // class 1, top-down: A(t, s) = sums over {i <= t, j <= s}; pair (t, s)
-    // adds class 2 at (t+1, s+1)
+    // class 1, top-down: A(t, s) = sums over {i <= t, j <= s}, thread s holds
+    // column s; the pair (t, s) adds class 2 at (t+1, s+1), written above by
+    // another thread of the workgroup
+    __syncthreads();
     uint64_t acnt = 0;
     double aq = 0.0;
     double best = -INFINITY;
     long long code = 0x7fffffffffffffffLL;
+    cn = (s < L) ? h[s] : 0u;
     for (int t = 0; t <= L - 2; ++t) {
-        const RowSums r = row_scan<1>(h + (int64_t)t * L, L, Nd, q, wu, wd, wi, rq);
+        const uint32_t c = cn;
+        cn = (s < L) ? h[(int64_t)(t + 1) * L + s] : 0u;
+        const double lbv = s <= L - 2 ? lbp[(int64_t)(t + 1) * L + s + 1] : -INFINITY;
+        const RowSums r = row_scan(c, pterm(c, Nd, q), wt[t & 1]);
         acnt += r.c;
         aq = aq + r.q;
         if (s <= L - 2) {
             const double la = class_term2(acnt, aq, Nd, q, sgn, hmax);
-            const double lbv = lbp[(int64_t)(t + 1) * L + s + 1];
             const double lam = la + lbv;
             const long long cd = ((long long)t << 12) | s;
             if (lam > -INFINITY && (lam > best || (lam == best && cd < code))) {
