@@ -228,17 +228,21 @@ size_t ts_search2d_workspace_bytes(int32_t nseg, int32_t nbins, int32_t nq);
  * form; the other two quadrants are ignored).  A pair with an empty class is
  * invalid; ties go to the first pair with t outermost; q = 1 is the Shannon
  * limit (sum of the two class Shannon entropies).  The class sums come
- * from 2-D prefix sums formed inside the call (the tables would take
- * nbins^2 doubles per problem and q); evaluated in FP64.
+ * from 2-D prefix sums formed inside the call, pairs are ranked by FP32
+ * keys, and every pair whose key lies within twice the keys' proven error
+ * bound of the best key is evaluated in FP64: the result is the FP64 arg
+ * max.
  *   hist    uint32 [nseg][nbins][nbins] from ts_histogram2d;
  *   nq, q   [host] 1..TS_MAX_Q entropic indices, finite, > 0;
- *   ws      device workspace of ws_bytes >= ts_search2d_workspace_bytes();
+ *   ws      device workspace of ws_bytes >= ts_search2d_workspace_bytes(),
+ *           8-byte aligned; overwritten;
  *   thr     out: int32 [nq][2][nseg]: t in row 0, s in row 1 of each q
  *           (-1 if no valid pair); only t thresholds the image, and row 0
  *           is the [nseg][1] threshold array of ts_label with k = 1;
  *   obj     out: double [nq][nseg], the objective at (t, s) (NaN if none);
  *   status  out: int32 [nq][nseg], TS_PROBLEM_*.
- * Errors: TS_ERR_INVALID_ARG, TS_ERR_WORKSPACE. */
+ * Errors: TS_ERR_INVALID_ARG (also for a workspace that is not 8-byte
+ * aligned), TS_ERR_WORKSPACE. */
 ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q,
                                 void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status,
                                 ts_stream_t stream);

@@ -358,7 +358,7 @@ size_t ts_search2d_workspace_bytes(int32_t nseg, int32_t nbins, int32_t nq)
 {
     if (nseg < 0 || nbins < 2 || nbins > 256 || nq < 1 || nq > TS_MAX_Q)
         return 0;
-    return search2d_workspace_bytes(nseg * nq, nbins);
+    return search2d_workspace_bytes(nseg, nq, nbins);
 }
 
 ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q,
@@ -374,12 +374,14 @@ ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbin
         return st;
     if (nseg > 0 && (!hist || !thr || !obj || !status))
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search2d: null pointer");
-    const size_t need = search2d_workspace_bytes(nseg * nq, nbins);
+    const size_t need = search2d_workspace_bytes(nseg, nq, nbins);
     if (nseg > 0 && (ws_bytes < need || !ws))
         return fail(TS_ERR_WORKSPACE, "ts_threshold_search2d: workspace too small (need " + std::to_string(need) +
                                           " bytes, got " + std::to_string(ws_bytes) + ")");
     if (nseg == 0)
         return TS_OK;
+    if ((uintptr_t)ws & 7)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search2d: workspace must be 8-byte aligned");
     return launch_search2d(hist, nseg, nbins, nq, q, ws, thr, obj, status, (hipStream_t)stream);
 }
 

@@ -11,6 +11,10 @@
 namespace ts {
 
 constexpr int WAVE = 64;
+// v_log_f32 error bound used by the FP32 search keys' error bounds, in units
+// of 2^-24 * max(1, |log2 x|); ts_log2_f32 applies the same instruction so
+// that the bound can be checked against an FP64 log2.
+constexpr double LOG2_ERR_UNITS = 4.0;
 constexpr int MAX_BINS = 4096;
 
 // ---------------------------------------------------------------- errors
@@ -171,7 +175,7 @@ struct LabelSets {
 __global__ void k_fill_u32(uint32_t *p, int64_t n); // k_histogram.hip
 size_t hist2d_lds_bytes(int L, int W);
 ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint32_t *hist, hipStream_t st);
-size_t search2d_workspace_bytes(int nprob, int L);
+size_t search2d_workspace_bytes(int nseg, int nq, int L);
 ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const double *q, void *ws, int32_t *thr,
                           double *obj, int32_t *status, hipStream_t st);
 ts_status launch_log2_f32(const float *x, float *y, int64_t n, hipStream_t st);

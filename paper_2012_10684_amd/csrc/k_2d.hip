@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -36,7 +37,10 @@ namespace ts {
 constexpr int H2_THREADS = 1024;
 constexpr int H2_MAX_W = 4096;    // row length held in the LDS ring
 constexpr int H2_MAX_L = 256;     // 2D histograms up to 256 x 256
-constexpr int S2_THREADS = 256;   // one thread per column s (L <= 256)
+constexpr int S2_THREADS = 64;    // one wavefront per (q, image)
+constexpr int S2_CPL = 4;         // columns per lane (L <= 256)
+constexpr int S2_TAB = 2048;      // p^q (or p ln p) of counts below this from an LDS table
+constexpr int S2_RING = 4;        // rows of counts in flight ahead of the row being summed
 
 // ------------------------------------------------------------------ histogram
 
@@ -147,175 +151,419 @@ struct Q2List {
     double q[TS_MAX_Q];
 };
 
-// Row prefix (DIR = +1) or suffix (DIR = -1) along s of one 2D histogram
-// row, in a fixed order: scan position p = threadIdx.x is column p (prefix)
-// or column L-1-p (suffix); c is that column's count, loaded by the caller.
-// Returns the exact integer count sum and the FP64 sum of p^q (or p ln p) up
-// to the position, where an empty cell repeats the value of the nearest
-// occupied cell before it in scan order.  ws* hold one entry per wavefront.
-struct RowSums {
-    uint64_t c;
-    double q;
-};
-
-__device__ __forceinline__ double pterm(uint32_t c, double N, double q)
+// With p_ij = c_ij / N the class term sgn(1-q) (ln Q - q ln w) equals
+// sgn(1-q) (ln sum c^q - q ln C) for a class of C pixels, and the Shannon
+// term ln w - E / w equals ln C - (sum c ln c) / C: N cancels, so the search
+// works on raw counts.  cterm(c) is c^q (c ln c for q = 1), 0 for c = 0.
+__device__ __forceinline__ double cterm(uint32_t c, double q)
 {
     if (!c)
         return 0.0;
-    const double p = (double)c / N;
-    return q == 1.0 ? p * log(p) : pow(p, q);
+    const double x = (double)c;
+    return q == 1.0 ? x * log(x) : pow(x, q);
 }
 
-// Per-wavefront totals of one row scan: count, FP64 sum, last occupied scan
-// position of the wavefront (or -1) and the inclusive sum there.
-struct WaveTot {
-    uint64_t c;
-    double v;
-    int occ;
-    double occv;
-};
-
-__device__ __forceinline__ RowSums row_scan(uint32_t c, double pv, WaveTot *wt)
+// the same value, from the table tab[c] = cterm(c) for small counts (the
+// table holds the identical expression, so both give the same bits)
+__device__ __forceinline__ double cterm_tab(uint32_t c, const double *tab, double q)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t ic = c;
-    double iv = pv; // p^q (or p ln p) of this cell
-    int occ = c ? (int)threadIdx.x : -1;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t tc = __shfl_up(ic, o, 64);
-        const double tv = __shfl_up(iv, o, 64);
-        const int to = __shfl_up(occ, o, 64);
-        if (lane >= o) {
-            ic += tc;
-            iv = tv + iv;
-            occ = max(occ, to);
-        }
-    }
-    // inclusive sum at this wavefront's last occupied position so far
-    const double ivocc = __shfl(iv, occ < 0 ? 0 : (occ & 63), 64);
-    if (lane == 63) // ivocc of lane 63: the sum at the wavefront's last occupied position
-        wt[w] = WaveTot{ic, iv, occ, ivocc};
-    __syncthreads();
-    // totals of the earlier wavefronts, combined in order
-    uint64_t bc = 0;
-    double bv = 0.0;
-    int bo = -1;
-    double bov = 0.0;
-    for (int i = 0; i < w; ++i) {
-        const WaveTot t = wt[i];
-        bc += t.c;
-        if (t.occ >= 0) {
-            bo = t.occ;
-            bov = bv + t.occv; // the sum at that position, as its own wavefront formed it after the base
-        }
-        bv = bv + t.v;
-    }
-    RowSums r;
-    r.c = bc + ic;
-    // empty cells take the sum at the last occupied position in scan order
-    if (occ >= 0)
-        r.q = bv + ivocc;
-    else
-        r.q = bo >= 0 ? bov : 0.0;
-    return r;
+    return c < (uint32_t)S2_TAB ? tab[c] : cterm(c, q);
 }
 
-// sgn(1-q) (ln Q - q ln w) for Tsallis, ln w - E / w for q = 1; -inf when
-// the class is empty; clamped to [0, hmax]
-__device__ __forceinline__ double class_term2(uint64_t c, double sumq, double N, double q, double sgn, double hmax)
+// Cross-lane moves within the wavefront (DPP): lanes without a source, or in
+// rows masked off, receive 0, the identity of the sums below.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v)
+{
+    const uint32_t lo = dpp32<CTRL, ROWS>((uint32_t)v), hi = dpp32<CTRL, ROWS>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dppv(T v)
+{
+    if constexpr (std::is_same<T, double>::value)
+        return __longlong_as_double((long long)dpp64<CTRL, ROWS>((uint64_t)__double_as_longlong(v)));
+    else if constexpr (sizeof(T) == 4)
+        return (T)dpp32<CTRL, ROWS>((uint32_t)v);
+    else
+        return (T)dpp64<CTRL, ROWS>((uint64_t)v);
+}
+
+// Exclusive sum over the lanes of the wavefront in a fixed order: a
+// Hillis-Steele scan within each row of 16 lanes, then the rows carried by
+// broadcasts of lanes 15 and 31, then a shift by one lane.
+template <typename T>
+__device__ __forceinline__ T wave_excl_sum(T v)
+{
+    v = v + dppv<0x111, 0xf>(v); // row_shr:1
+    v = v + dppv<0x112, 0xf>(v); // row_shr:2
+    v = v + dppv<0x114, 0xf>(v); // row_shr:4
+    v = v + dppv<0x118, 0xf>(v); // row_shr:8
+    v = v + dppv<0x142, 0xa>(v); // row_bcast:15 into rows 1 and 3
+    v = v + dppv<0x143, 0xc>(v); // row_bcast:31 into rows 2 and 3
+    return dppv<0x138, 0xf>(v);  // wave_shr:1: lane 0 gets 0
+}
+
+// Sums along s of one 2D histogram row, S2_CPL cells per lane: scan position
+// p = S2_CPL * lane + u (u = 0 .. S2_CPL-1) is column p (prefix order) or
+// column L-1-p (suffix order).  For every position the exact count sum and
+// the FP64 sum of cterm up to it: within the lane sequentially, after the
+// lane's exclusive base.  An empty position takes the value at the nearest
+// occupied position before it in scan order, so an all-empty column never
+// changes a class sum (bit for bit) and the pairs it separates tie.
+template <typename CT>
+__device__ __forceinline__ void row_sums(const uint32_t (&c)[S2_CPL], const double *tab, double q,
+                                         CT (&rc)[S2_CPL], double (&rq)[S2_CPL])
+{
+    const int lane = threadIdx.x & 63;
+    CT lc = 0;
+    double lq = 0.0;
+    int first = S2_CPL; // first occupied position of this lane
+    CT pc[S2_CPL];
+    double pq[S2_CPL];
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        lc += (CT)c[u];
+        lq = lq + cterm_tab(c[u], tab, q); // an empty cell adds +0.0: bits unchanged
+        pc[u] = lc;
+        pq[u] = lq;
+        if (c[u] && first == S2_CPL)
+            first = u;
+    }
+    const uint64_t occ = __ballot(lc != 0);
+    const CT bc = wave_excl_sum<CT>(lc);
+    const double bq = wave_excl_sum<double>(lq);
+    const double last = bq + lq; // the value at this lane's last occupied position
+    const uint64_t before = occ & ((1ull << lane) - 1ull);
+    const int src = before ? 63 - __clzll((long long)before) : lane;
+    const double prev_raw = __shfl(last, src, 64);
+    const double prev = before ? prev_raw : 0.0;
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        rc[u] = bc + pc[u];
+        rq[u] = u >= first ? bq + pq[u] : prev;
+    }
+}
+
+// FP64 class term from the class sums: sgn(1-q) (ln S - q ln C) for Tsallis,
+// ln C - S / C for q = 1 (S = sum of cterm, C = pixels); -inf for an empty
+// class; clamped to [0, hmax].  Called only for the few rows the FP64
+// re-check visits: kept out of line so that its registers do not burden the
+// FP32 passes.
+__device__ __noinline__ double class_term2(uint64_t c, double sumq, double q, double sgn, double hmax)
 {
     if (c == 0)
         return -INFINITY;
-    const double w = (double)c / N;
-    const double h = sgn == 0.0 ? log(w) - sumq / w : sgn * (log(sumq) - q * log(w));
+    const double C = (double)c;
+    const double h = sgn == 0.0 ? log(C) - sumq / C : sgn * (log(sumq) - q * log(C));
     return fmin(fmax(h, 0.0), hmax);
 }
 
-__global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restrict__ hist, int nseg, int L, Q2List ql,
-                                                         double *__restrict__ lb, int32_t *__restrict__ thr,
-                                                         double *__restrict__ obj, int32_t *__restrict__ status)
+// Per-problem constants of the search.
+struct S2 {
+    const uint32_t *h; // the L x L histogram
+    int L;
+    bool vec;          // rows load as 16-byte vectors (L % 4 == 0, aligned)
+    double q, sgn, hmax;
+    const double *tab; // cterm of counts below S2_TAB
+    float mq;          // -sgn * q rounded to FP32 (Tsallis)
+    float gmax;        // hmax / ln 2 rounded up
+};
+
+// The same class term in log2 units in FP32, from the FP64 class sums: the
+// key of the search.  Its error against class_term2 / ln 2 is bounded in
+// s2_delta.
+__device__ __forceinline__ float class_key32(uint64_t c, double sumq, const S2 &p)
 {
-    __shared__ uint64_t wu[S2_THREADS / 64 + 1];
-    __shared__ WaveTot wt[2][S2_THREADS / 64]; // alternate rows: one barrier per row scan
-    __shared__ double br[S2_THREADS / 64];
-    __shared__ long long bc[S2_THREADS / 64];
-    const int prob = blockIdx.x, s0 = prob % nseg, j = prob / nseg;
-    const double q = ql.q[j];
-    const double sgn = q == 1.0 ? 0.0 : (q < 1.0 ? 1.0 : -1.0);
-    const double hmax = (q == 1.0 ? 1.0 : fabs(1.0 - q)) * 2.0 * log((double)L); // a class holds at most L^2 cells
-    const uint32_t *h = hist + (int64_t)s0 * L * L;
-    double *lbp = lb + (int64_t)prob * L * L;
-    const int s = threadIdx.x;
-    // N
-    uint64_t n = 0;
-    for (int i = threadIdx.x; i < L * L; i += blockDim.x)
-        n += h[i];
+    if (c == 0)
+        return -INFINITY;
+    const float lc = __builtin_amdgcn_logf((float)c);
+    float g;
+    if (p.sgn == 0.0) { // Shannon: log2 C - (S / C) log2 e
+        const float r = (float)(sumq / (double)c);
+        g = fmaf(r, -1.44269504f, lc);
+    } else {
+        const float lx = __builtin_amdgcn_logf((float)sumq);
+        g = fmaf(p.mq, lc, p.sgn > 0.0 ? lx : -lx);
+    }
+    return __builtin_amdgcn_fmed3f(g, 0.0f, p.gmax);
+}
+
+// Bound on |key32 - key64 / ln 2| for every pair of one problem (key32 the
+// sum of the two FP32 class keys, key64 the FP64 sum of class_term2 from the
+// same class sums) for an image of N pixels.  Per class: the casts of C and
+// S (or S / C) to FP32 (2^-24 relative each, 1.5 * 2^-24 after the log2),
+// v_log_f32 (LOG2_ERR_UNITS * 2^-24 * max(1, |log2 x|)), q or log2 e rounded
+// to FP32, the fma; then the FP32 sum of the two clamped terms, and the
+// clamp at gmax instead of hmax / ln 2.  Magnitudes: 1 <= C <= N; a class of
+// m <= L^2 occupied cells has 1 <= S <= max(C^q, m^(1-q) C^q), so
+// 0 <= log2 S <= q log2 N + 2 |1-q| log2 L; 0 <= S / C <= ln N for q = 1.
+// Infinity when S could leave the FP32 range: every pair is then re-checked
+// in FP64.
+__device__ __forceinline__ double s2_delta(const S2 &p, double N)
+{
+    const double u = 0x1p-24;
+    const double lN = log2(N) * 1.0001 + 1e-6;
+    const double q = p.q;
+    double e1;
+    if (p.sgn == 0.0) {
+        const double r = lN * 0.6931471805599453 * 1.0001; // S / C <= ln N
+        e1 = 1.5 * u + LOG2_ERR_UNITS * u * fmax(1.0, lN) + 2.0 * u * 1.4426950408889634 * r +
+             u * (lN + 1.4426950408889634 * r);
+    } else {
+        const double Ux = q * lN + 2.0 * fabs(1.0 - q) * log2((double)p.L) * 1.0001 + 1e-6, Vy = lN;
+        if (Ux > 120.0)
+            return INFINITY;
+        e1 = 1.5 * u * (1.0 + q) + LOG2_ERR_UNITS * u * (fmax(1.0, Ux) + q * fmax(1.0, Vy)) + u * q * Vy +
+             u * (Ux + q * Vy);
+    }
+    return (2.0 * e1 + 2.0 * u * (double)p.gmax + 2.0 * 0x1p-20 * (double)p.gmax) * 1.01 + 1e-12;
+}
+
+// Counts of row t in the lane's scan positions (DIR = +1: column
+// S2_CPL * lane + u; DIR = -1: column L-1-(S2_CPL * lane + u)); t < 0 gives
+// zeros.
+template <int DIR>
+__device__ __forceinline__ void load_row(const uint32_t *h, int L, bool vec, int t, uint32_t (&c)[S2_CPL])
+{
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        n += __shfl_xor(n, o, 64);
-    if ((threadIdx.x & 63) == 0)
-        wu[threadIdx.x >> 6] = n;
-    __syncthreads();
-    uint64_t N = 0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
-        N += wu[i];
-    __syncthreads();
-    // thr is [nq][2][nseg]: t at row 0, s at row 1 of this q
-    int32_t *thr_t = thr + (int64_t)(2 * j) * nseg + s0, *thr_s = thr_t + nseg;
-    if (N == 0) {
-        if (threadIdx.x == 0) {
-            *thr_t = *thr_s = -1;
-            obj[prob] = NAN;
-            status[prob] = TS_PROBLEM_EMPTY;
-        }
+    for (int u = 0; u < S2_CPL; ++u)
+        c[u] = 0u;
+    if (t < 0)
         return;
+    const uint32_t *row = h + (int64_t)t * L;
+    if (vec) {
+        if (S2_CPL * lane < L) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(row + (DIR > 0 ? S2_CPL * lane : L - S2_CPL - S2_CPL * lane));
+            if (DIR > 0) {
+                c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+            } else {
+                c[0] = v.w; c[1] = v.z; c[2] = v.y; c[3] = v.x;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u) {
+            const int col = DIR > 0 ? S2_CPL * lane + u : L - 1 - (S2_CPL * lane + u);
+            if (col >= 0 && col < L)
+                c[u] = row[col];
+        }
     }
-    const double Nd = (double)N;
-    // class 2, bottom-up: B(t, s) = sums over {i >= t, j >= s}; thread p
-    // holds column L-1-p (suffix order); each row's counts are loaded one
-    // row ahead
-    const int cb = L - 1 - s; // this thread's column in the suffix pass
-    uint64_t bcnt = 0;
-    double bq = 0.0;
-    uint32_t cn = (s < L) ? h[(int64_t)(L - 1) * L + cb] : 0u;
-    for (int t = L - 1; t >= 1; --t) {
-        const uint32_t c = cn;
-        if (t > 1)
-            cn = (s < L) ? h[(int64_t)(t - 1) * L + cb] : 0u;
-        const RowSums r = row_scan(c, pterm(c, Nd, q), wt[t & 1]);
-        bcnt += r.c;
-        bq = bq + r.q;
-        if (s < L)
-            lbp[(int64_t)t * L + cb] = class_term2(bcnt, bq, Nd, q, sgn, hmax);
+}
+
+// Visits n rows of the compacted list of rows holding counts, rows[k0],
+// rows[k0 + DIR], ..., with each row's sums along s (row_sums, in DIR's scan
+// order) and S2_CPL auxiliary values aux(k, .) per lane (stored keys the row
+// needs); the counts and auxiliary values of the next S2_RING rows are in
+// flight meanwhile.
+template <int DIR, typename CT, typename A, typename F>
+__device__ __forceinline__ void for_rows(const S2 &p, const int *rows, int k0, int n, A &&aux, F &&f)
+{
+    uint32_t ring[S2_RING][S2_CPL];
+    float xr[S2_RING][S2_CPL];
+#pragma unroll
+    for (int d = 0; d < S2_RING; ++d) {
+        load_row<DIR>(p.h, p.L, p.vec, d < n ? rows[k0 + DIR * d] : -1, ring[d]);
+        aux(d < n ? k0 + DIR * d : -1, xr[d]);
     }
-    // class 1, top-down: A(t, s) = sums over {i <= t, j <= s}, thread s holds
-    // column s; the pair (t, s) adds class 2 at (t+1, s+1), written above by
-    // another thread of the workgroup
-    __syncthreads();
-    uint64_t acnt = 0;
-    double aq = 0.0;
-    double best = -INFINITY;
-    long long code = 0x7fffffffffffffffLL;
-    cn = (s < L) ? h[s] : 0u;
-    for (int t = 0; t <= L - 2; ++t) {
-        const uint32_t c = cn;
-        cn = (s < L) ? h[(int64_t)(t + 1) * L + s] : 0u;
-        const double lbv = s <= L - 2 ? lbp[(int64_t)(t + 1) * L + s + 1] : -INFINITY;
-        const RowSums r = row_scan(c, pterm(c, Nd, q), wt[t & 1]);
-        acnt += r.c;
-        aq = aq + r.q;
-        if (s <= L - 2) {
-            const double la = class_term2(acnt, aq, Nd, q, sgn, hmax);
-            const double lam = la + lbv;
-            const long long cd = ((long long)t << 12) | s;
-            if (lam > -INFINITY && (lam > best || (lam == best && cd < code))) {
-                best = lam;
-                code = cd;
+    for (int i0 = 0; i0 < n; i0 += S2_RING) {
+#pragma unroll
+        for (int d = 0; d < S2_RING; ++d) {
+            const int i = i0 + d;
+            if (i < n) {
+                uint32_t c[S2_CPL];
+                float x[S2_CPL];
+#pragma unroll
+                for (int u = 0; u < S2_CPL; ++u) {
+                    c[u] = ring[d][u];
+                    x[u] = xr[d][u];
+                }
+                const int inext = i + S2_RING;
+                load_row<DIR>(p.h, p.L, p.vec, inext < n ? rows[k0 + DIR * inext] : -1, ring[d]);
+                aux(inext < n ? k0 + DIR * inext : -1, xr[d]);
+                CT rc[S2_CPL];
+                double rq[S2_CPL];
+                row_sums<CT>(c, p.tab, p.q, rc, rq);
+                f(k0 + DIR * i, rc, rq, x);
             }
         }
     }
-    // first best pair of the workgroup
+}
+
+__device__ __forceinline__ float wave_max_f32(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One (q index, problem) per wavefront; CT is the type of in-row count sums
+// (uint32_t when the image holds fewer than 2^32 pixels).  R >= 1 rows hold
+// counts, listed in rows[] in increasing order.  A row without counts
+// (t >= 1) leaves the class 1 sums unchanged and B(t+1, .) = B(t, .): its
+// pairs tie exactly with those of row t-1, which come first, so only listed
+// rows are visited, and the class 2 partner of the listed row rows[k] is
+// rows[k+1].
+//  1. class 2 keys, bottom-up: B(t, s) = sums over {i >= t, j >= s} (scan
+//     position p is column L-1-p); FP32 key of every listed row t >= 1 into
+//     k2 (workspace, [L][L] floats);
+//  2. class 1, top-down: A(t, s) = sums over {i <= t, j <= s}; the pair key
+//     is the FP32 class 1 key plus k2 at (rows[k+1], s+1); row maxima rmax[k]
+//     and the maximum M;
+//  3. rows with rmax >= M - 2 delta (the FP64 arg max is among them): the
+//     FP64 class 2 terms of their partner rows into t2 (workspace, doubles),
+//     by the bottom-up sums again;
+//  4. top-down again: the FP64 value of every pair of those rows whose key
+//     is >= M - 2 delta; the first best pair (t outermost).
+template <typename CT>
+__device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, const int *rows, float *rmax, float *k2,
+                                              double *t2, int32_t *thr_t, int32_t *thr_s, double *obj_p,
+                                              int32_t *status_p)
+{
+    const int lane = threadIdx.x & 63, L = p.L;
+    int colB[S2_CPL], colA[S2_CPL];
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        colB[u] = L - 1 - (S2_CPL * lane + u);
+        colA[u] = S2_CPL * lane + u;
+    }
+    const int kB = rows[0] == 0 ? 1 : 0; // class 2 starts at row 1 at the earliest
+    // pairs exist for listed rows k with k + 1 < R (rows[k] <= L - 2 follows)
+    const int npair = R - 1;
+    auto none = [](int, float(&)[S2_CPL]) {};
+    // the stored class 2 keys at (rows[k + 1], s + 1) for the lane's columns s
+    auto partner = [&](int k, float(&x)[S2_CPL]) {
+        const float *row2 = k < 0 ? nullptr : k2 + (int64_t)rows[k + 1] * L;
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u)
+            x[u] = (row2 && colA[u] <= L - 2) ? row2[colA[u] + 1] : -INFINITY;
+    };
+
+    // 1. class 2 keys
+    {
+        uint64_t bc[S2_CPL] = {};
+        double bq[S2_CPL] = {};
+        for_rows<-1, CT>(p, rows, R - 1, R - kB, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
+                                                           const float(&)[S2_CPL]) {
+            float *row = k2 + (int64_t)rows[k] * L;
+#pragma unroll
+            for (int u = 0; u < S2_CPL; ++u) {
+                bc[u] += rc[u];
+                bq[u] = bq[u] + rq[u];
+                if (colB[u] >= 0)
+                    row[colB[u]] = class_key32(bc[u], bq[u], p);
+            }
+        });
+    }
+    __syncthreads();
+    // 2. pair keys, row maxima
+    float M = -INFINITY;
+    {
+        uint64_t ac[S2_CPL] = {};
+        double aq[S2_CPL] = {};
+        for_rows<1, CT>(p, rows, 0, npair, partner, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
+                                                        const float(&x)[S2_CPL]) {
+            float m = -INFINITY;
+#pragma unroll
+            for (int u = 0; u < S2_CPL; ++u) {
+                ac[u] += rc[u];
+                aq[u] = aq[u] + rq[u];
+                if (colA[u] <= L - 2)
+                    m = fmaxf(m, class_key32(ac[u], aq[u], p) + x[u]);
+            }
+            m = wave_max_f32(m);
+            if (lane == 0)
+                rmax[k] = m;
+            M = fmaxf(M, m);
+        });
+    }
+    const double delta = s2_delta(p, N);
+    const bool all = !(delta < INFINITY);
+    if (!all && !(M > -INFINITY)) { // every key finite for a valid pair: none is valid
+        if (lane == 0) {
+            *thr_t = *thr_s = -1;
+            *obj_p = NAN;
+            *status_p = TS_PROBLEM_DEGENERATE;
+        }
+        return;
+    }
+    const double T = all ? -INFINITY : (double)M - 2.0 * delta;
+    __syncthreads();
+    // candidate rows: kc0 .. kc1 (listed-row indices)
+    int kc0 = npair, kc1 = -1;
+    for (int k = lane; k < npair; k += 64)
+        if (all || (double)rmax[k] >= T) {
+            kc0 = min(kc0, k);
+            kc1 = max(kc1, k);
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        kc0 = min(kc0, __shfl_xor(kc0, o, 64));
+        kc1 = max(kc1, __shfl_xor(kc1, o, 64));
+    }
+    // 3. FP64 class 2 terms of the partner rows rows[k + 1], k a candidate
+    if (kc1 >= 0) {
+        uint64_t bc[S2_CPL] = {};
+        double bq[S2_CPL] = {};
+        for_rows<-1, CT>(p, rows, R - 1, R - 1 - kc0, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
+                                                                 const float(&)[S2_CPL]) {
+#pragma unroll
+            for (int u = 0; u < S2_CPL; ++u) {
+                bc[u] += rc[u];
+                bq[u] = bq[u] + rq[u];
+            }
+            if (all || (double)rmax[k - 1] >= T) {
+                double *row = t2 + (int64_t)rows[k] * L;
+#pragma unroll
+                for (int u = 0; u < S2_CPL; ++u)
+                    if (colB[u] >= 0)
+                        row[colB[u]] = class_term2(bc[u], bq[u], p.q, p.sgn, p.hmax);
+            }
+        });
+    }
+    __syncthreads();
+    // 4. FP64 values of the candidate pairs
+    double best = -INFINITY;
+    long long code = 0x7fffffffffffffffLL;
+    if (kc1 >= 0) {
+        uint64_t ac[S2_CPL] = {};
+        double aq[S2_CPL] = {};
+        for_rows<1, CT>(p, rows, 0, kc1 + 1, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
+                                                       const float(&)[S2_CPL]) {
+#pragma unroll
+            for (int u = 0; u < S2_CPL; ++u) {
+                ac[u] += rc[u];
+                aq[u] = aq[u] + rq[u];
+            }
+            if (!(all || (double)rmax[k] >= T))
+                return;
+            const int t = rows[k], r2 = rows[k + 1];
+            const float *row2 = k2 + (int64_t)r2 * L;
+            const double *row2d = t2 + (int64_t)r2 * L;
+#pragma unroll
+            for (int u = 0; u < S2_CPL; ++u) {
+                if (colA[u] <= L - 2) {
+                    const float key = class_key32(ac[u], aq[u], p) + row2[colA[u] + 1];
+                    if (all || (double)key >= T) {
+                        const double lam = class_term2(ac[u], aq[u], p.q, p.sgn, p.hmax) + row2d[colA[u] + 1];
+                        const long long cd = ((long long)t << 12) | colA[u];
+                        if (lam > -INFINITY && (lam > best || (lam == best && cd < code))) {
+                            best = lam;
+                            code = cd;
+                        }
+                    }
+                }
+            }
+        });
+    }
+    // first best pair of the wavefront
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         const double b2 = __shfl_xor(best, o, 64);
@@ -325,31 +573,126 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
             code = c2;
         }
     }
-    if ((threadIdx.x & 63) == 0) {
-        br[threadIdx.x >> 6] = best;
-        bc[threadIdx.x >> 6] = code;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
-            if (br[i] > best || (br[i] == best && bc[i] < code)) {
-                best = br[i];
-                code = bc[i];
-            }
+    if (lane == 0) {
         if (!(best > -INFINITY)) {
             *thr_t = *thr_s = -1;
-            obj[prob] = NAN;
-            status[prob] = TS_PROBLEM_DEGENERATE;
+            *obj_p = NAN;
+            *status_p = TS_PROBLEM_DEGENERATE;
         } else {
             *thr_t = (int32_t)(code >> 12);
             *thr_s = (int32_t)(code & 4095);
-            obj[prob] = sgn == 0.0 ? best : expm1(sgn * best) / (1.0 - q);
-            status[prob] = TS_PROBLEM_OK;
+            *obj_p = p.sgn == 0.0 ? best : expm1(p.sgn * best) / (1.0 - p.q);
+            *status_p = TS_PROBLEM_OK;
         }
     }
 }
 
-size_t search2d_workspace_bytes(int nprob, int L) { return (size_t)nprob * L * L * sizeof(double); }
+// Which rows of each image hold counts, and the image's pixel count: one
+// wavefront per group of 16 rows, all 16 rows' loads in flight together.
+// mask[s][g] bit d: row 16 g + d holds counts; cnt[s][g]: its pixels.
+__global__ void __launch_bounds__(64) k_rows2d(const uint32_t *__restrict__ hist, int L, int groups,
+                                               uint16_t *__restrict__ mask, uint64_t *__restrict__ cnt)
+{
+    const int s0 = blockIdx.x / groups, g = blockIdx.x % groups;
+    const uint32_t *h = hist + (int64_t)s0 * L * L;
+    const bool vec = (L % S2_CPL) == 0 && ((uintptr_t)h & 15) == 0;
+    uint32_t c[16][S2_CPL];
+#pragma unroll
+    for (int d = 0; d < 16; ++d)
+        load_row<1>(h, L, vec, 16 * g + d < L ? 16 * g + d : -1, c[d]);
+    uint32_t bits = 0;
+    uint64_t n = 0;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        uint64_t r = 0;
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u)
+            r += c[d][u];
+        n += r;
+        if (__ballot(r != 0))
+            bits |= 1u << d;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        n += __shfl_xor(n, o, 64);
+    if (threadIdx.x == 0) {
+        mask[(int64_t)s0 * 16 + g] = (uint16_t)bits;
+        cnt[(int64_t)s0 * 16 + g] = n;
+    }
+}
+
+__global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restrict__ hist, int nseg, int L, Q2List ql,
+                                                         float *__restrict__ k2all, double *__restrict__ t2all,
+                                                         const uint16_t *__restrict__ mask,
+                                                         const uint64_t *__restrict__ cnt, int32_t *__restrict__ thr,
+                                                         double *__restrict__ obj, int32_t *__restrict__ status)
+{
+    __shared__ double tab[S2_TAB];
+    __shared__ int rows[H2_MAX_L];
+    __shared__ float rmax[H2_MAX_L];
+    const int lane = threadIdx.x & 63;
+    const int prob = blockIdx.x, s0 = prob % nseg, j = prob / nseg;
+    S2 p;
+    p.h = hist + (int64_t)s0 * L * L;
+    p.L = L;
+    p.vec = (L % S2_CPL) == 0 && ((uintptr_t)p.h & 15) == 0;
+    p.q = ql.q[j];
+    p.sgn = p.q == 1.0 ? 0.0 : (p.q < 1.0 ? 1.0 : -1.0);
+    p.hmax = (p.q == 1.0 ? 1.0 : fabs(1.0 - p.q)) * 2.0 * log((double)L); // a class holds at most L^2 cells
+    p.mq = (float)(-p.sgn * p.q);
+    p.gmax = (float)(p.hmax * 1.4426950408889634 * (1.0 + 0x1p-20));
+    p.tab = tab;
+    // the image's pixel count and its rows holding counts, in increasing
+    // order: lane l looks at rows 4l .. 4l+3 (groups past the last hold no
+    // rows below L)
+    const int groups = (L + 15) / 16;
+    uint64_t n = lane < groups ? cnt[(int64_t)s0 * 16 + lane] : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        n += __shfl_xor(n, o, 64);
+    const uint32_t g16 = (4 * lane) / 16 < groups ? mask[(int64_t)s0 * 16 + (4 * lane) / 16] : 0u;
+    uint32_t nib = (g16 >> ((4 * lane) % 16)) & 0xfu;
+    if (4 * lane + 4 > L)
+        nib &= (4 * lane < L) ? (1u << (L - 4 * lane)) - 1u : 0u;
+    const uint32_t pos = wave_excl_sum<uint32_t>((uint32_t)__popc(nib));
+    uint32_t w = pos;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        if (nib & (1u << d))
+            rows[w++] = 4 * lane + d;
+    const int R = __shfl(w, 63, 64);
+    // thr is [nq][2][nseg]: t at row 0, s at row 1 of this q
+    int32_t *thr_t = thr + (int64_t)(2 * j) * nseg + s0, *thr_s = thr_t + nseg;
+    if (n == 0) {
+        if (lane == 0) {
+            *thr_t = *thr_s = -1;
+            obj[prob] = NAN;
+            status[prob] = TS_PROBLEM_EMPTY;
+        }
+        return;
+    }
+    for (int i = lane; i < S2_TAB; i += 64)
+        tab[i] = cterm((uint32_t)i, p.q);
+    __syncthreads();
+    float *k2 = k2all + (int64_t)prob * L * L;
+    double *t2 = t2all + (int64_t)prob * L * L;
+    if (n >> 32)
+        search2d_body<uint64_t>(p, (double)n, R, rows, rmax, k2, t2, thr_t, thr_s, obj + prob, status + prob);
+    else
+        search2d_body<uint32_t>(p, (double)n, R, rows, rmax, k2, t2, thr_t, thr_s, obj + prob, status + prob);
+}
+
+// Workspace: FP64 terms [nprob][L][L], FP32 keys [nprob][L][L], row masks
+// uint16 [nseg][16] and pixel counts uint64 [nseg][16], each part starting
+// 256-byte aligned (the workspace itself must be 8-byte aligned).
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t search2d_workspace_bytes(int nseg, int nq, int L)
+{
+    const size_t cells = (size_t)nseg * nq * L * L;
+    return up256(cells * sizeof(double)) + up256(cells * sizeof(float)) + up256((size_t)nseg * 16 * 2) +
+           (size_t)nseg * 16 * 8;
+}
 
 ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const double *q, void *ws, int32_t *thr,
                           double *obj, int32_t *status, hipStream_t st)
@@ -357,8 +700,16 @@ ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const d
     Q2List ql;
     for (int i = 0; i < TS_MAX_Q; ++i)
         ql.q[i] = q[i < nq ? i : 0];
-    hipLaunchKernelGGL(k_search2d, dim3((unsigned)(nseg * nq)), dim3(S2_THREADS), 0, st, hist, nseg, L, ql,
-                       (double *)ws, thr, obj, status);
+    const size_t cells = (size_t)nseg * nq * L * L;
+    char *w = (char *)ws;
+    double *t2 = (double *)w;
+    float *k2 = (float *)(w + up256(cells * sizeof(double)));
+    uint16_t *mask = (uint16_t *)(w + up256(cells * sizeof(double)) + up256(cells * sizeof(float)));
+    uint64_t *cnt = (uint64_t *)((char *)mask + up256((size_t)nseg * 16 * 2));
+    const int groups = (L + 15) / 16;
+    hipLaunchKernelGGL(k_rows2d, dim3((unsigned)(nseg * groups)), dim3(64), 0, st, hist, L, groups, mask, cnt);
+    hipLaunchKernelGGL(k_search2d, dim3((unsigned)(nseg * nq)), dim3(S2_THREADS), 0, st, hist, nseg, L, ql, k2, t2, mask,
+                       cnt, thr, obj, status);
     return check_launch("ts_threshold_search2d");
 }
 

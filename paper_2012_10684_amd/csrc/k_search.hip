@@ -52,10 +52,6 @@
 
 namespace ts {
 
-// v_log_f32 error bound used in delta, in units of 2^-24 * max(1, |log2 x|);
-// ts_log2_f32 applies the same instruction so that the bound can be checked
-// against an FP64 log2.
-constexpr double LOG2_ERR_UNITS = 4.0;
 constexpr int PLAIN_BLOCKS = 65536;
 constexpr int K3_THREADS = 256;                // k = 3 rows kernel
 constexpr int K3_COLS = 4;                     // columns per lane

@@ -132,3 +132,61 @@ def test_search2d_workload_slices(q):
         lab = oracle.label(vol[z].reshape(-1), -1024, -200, 256, thr_h[z][:1])
         assert np.array_equal(labels[z].cpu().numpy(), lab), z
     say(f"2-D pairs at q={q}: {thr_h.tolist()}")
+
+
+@pytest.mark.parametrize("L", [129, 254, 255, 256])
+def test_search2d_wide_histograms(L):
+    """Widths up to the 256-level maximum, including ones that leave a lane
+    with fewer than four columns."""
+    rng = np.random.default_rng(L)
+    H2 = np.stack([_rand_h2(rng, L, zero_frac=0.7, hi=200) for _ in range(2)])
+    for q in (0.6, 1.4):
+        thr, obj, st = api.threshold_search2d(to_dev(H2.view(np.int32)), q)
+        thr, obj, st = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+        for i in range(len(H2)):
+            check_pair(H2[i], q, thr[:, i], obj[i], st[i])
+
+
+def test_search2d_empty_rows_and_columns():
+    """Runs of empty gray levels (rows) and empty average levels (columns)
+    make whole blocks of pairs tie exactly; the first pair must win, as in
+    the oracle."""
+    rng = np.random.default_rng(21)
+    L = 64
+    cases = []
+    for k in range(6):
+        h = _rand_h2(rng, L, zero_frac=0.4)
+        rows = rng.choice(L, size=L // 2, replace=False)
+        cols = rng.choice(L, size=L // 3, replace=False)
+        h[rows, :] = 0
+        h[:, cols] = 0
+        cases.append(h)
+    banded = np.zeros((L, L), np.uint32)  # two blobs separated by empty rows and columns
+    banded[2:10, 3:12] = rng.integers(1, 50, (8, 9))
+    banded[40:50, 45:60] = rng.integers(1, 50, (10, 15))
+    cases.append(banded)
+    H2 = np.stack(cases)
+    for q in (0.5, 1.0, 2.0):
+        thr, obj, st = api.threshold_search2d(to_dev(H2.view(np.int32)), q)
+        thr, obj, st = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+        for i in range(len(H2)):
+            check_pair(H2[i], q, thr[:, i], obj[i], st[i])
+        r = oracle.search2d(banded, q, oracle.MODE_KAPUR if q == 1.0 else oracle.MODE_PREFIX)
+        assert thr[:, -1].tolist() == r.thr.tolist(), (q, thr[:, -1], r)
+
+
+def test_search2d_counts_beyond_32_bits():
+    """Histograms whose total exceeds 2^32 (and one row that does alone)."""
+    rng = np.random.default_rng(7)
+    L = 20
+    a = rng.integers(0, 1 << 28, (L, L)).astype(np.uint32)
+    a[rng.random((L, L)) < 0.3] = 0
+    b = _rand_h2(rng, L, zero_frac=0.3)
+    b[5, :] = 0xF0000000  # this row alone sums to 20 * 0xF0000000
+    H2 = np.stack([a, b])
+    assert int(a.astype(np.int64).sum()) > 1 << 32
+    for q in (0.7, 1.0, 1.6):
+        thr, obj, st = api.threshold_search2d(to_dev(H2.view(np.int32)), q)
+        thr, obj, st = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+        for i in range(len(H2)):
+            check_pair(H2[i], q, thr[:, i], obj[i], st[i])
