@@ -163,12 +163,8 @@ __device__ __forceinline__ double cterm(uint32_t c, double q)
     return q == 1.0 ? x * log(x) : pow(x, q);
 }
 
-// the same value, from the table tab[c] = cterm(c) for small counts (the
-// table holds the identical expression, so both give the same bits)
-__device__ __forceinline__ double cterm_tab(uint32_t c, const double *tab, double q)
-{
-    return c < (uint32_t)S2_TAB ? tab[c] : cterm(c, q);
-}
+// out of line for the rare counts past the table (small code in the row loops)
+__device__ __noinline__ double cterm_big(uint32_t c, double q) { return cterm(c, q); }
 
 // Cross-lane moves within the wavefront (DPP): lanes without a source, or in
 // rows masked off, receive 0, the identity of the sums below.
@@ -226,10 +222,26 @@ __device__ __forceinline__ void row_sums(const uint32_t (&c)[S2_CPL], const doub
     int first = S2_CPL; // first occupied position of this lane
     CT pc[S2_CPL];
     double pq[S2_CPL];
+    // cterm from the table tab[c] for small counts (the table holds the
+    // identical expression, so both give the same bits); a count past the
+    // table anywhere in the row takes the out-of-line path
+    double t[S2_CPL];
+    bool big = false;
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        t[u] = tab[min(c[u], (uint32_t)S2_TAB - 1u)];
+        big |= c[u] >= (uint32_t)S2_TAB;
+    }
+    if (__ballot(big)) {
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u)
+            if (c[u] >= (uint32_t)S2_TAB)
+                t[u] = cterm_big(c[u], q);
+    }
 #pragma unroll
     for (int u = 0; u < S2_CPL; ++u) {
         lc += (CT)c[u];
-        lq = lq + cterm_tab(c[u], tab, q); // an empty cell adds +0.0: bits unchanged
+        lq = lq + t[u]; // an empty cell adds +0.0: bits unchanged
         pc[u] = lc;
         pq[u] = lq;
         if (c[u] && first == S2_CPL)
@@ -271,27 +283,28 @@ struct S2 {
     bool vec;          // rows load as 16-byte vectors (L % 4 == 0, aligned)
     double q, sgn, hmax;
     const double *tab; // cterm of counts below S2_TAB
-    float mq;          // -sgn * q rounded to FP32 (Tsallis)
+    float mq;          // -q rounded to FP32 (Tsallis)
+    float sg;          // sgn(1-q) as +-1 (Tsallis)
     float gmax;        // hmax / ln 2 rounded up
 };
 
 // The same class term in log2 units in FP32, from the FP64 class sums: the
 // key of the search.  Its error against class_term2 / ln 2 is bounded in
-// s2_delta.
-__device__ __forceinline__ float class_key32(uint64_t c, double sumq, const S2 &p)
+// s2_delta.  sgn(1-q) (log2 S - q log2 C) is formed as the fma
+// log2 S - q log2 C times +-1 (exact).
+template <typename CT>
+__device__ __forceinline__ float class_key32(CT c, double sumq, const S2 &p)
 {
-    if (c == 0)
-        return -INFINITY;
     const float lc = __builtin_amdgcn_logf((float)c);
     float g;
     if (p.sgn == 0.0) { // Shannon: log2 C - (S / C) log2 e
         const float r = (float)(sumq / (double)c);
         g = fmaf(r, -1.44269504f, lc);
     } else {
-        const float lx = __builtin_amdgcn_logf((float)sumq);
-        g = fmaf(p.mq, lc, p.sgn > 0.0 ? lx : -lx);
+        g = fmaf(p.mq, lc, __builtin_amdgcn_logf((float)sumq)) * p.sg;
     }
-    return __builtin_amdgcn_fmed3f(g, 0.0f, p.gmax);
+    g = __builtin_amdgcn_fmed3f(g, 0.0f, p.gmax);
+    return c ? g : -INFINITY;
 }
 
 // Bound on |key32 - key64 / ln 2| for every pair of one problem (key32 the
@@ -326,72 +339,76 @@ __device__ __forceinline__ double s2_delta(const S2 &p, double N)
 }
 
 // Counts of row t in the lane's scan positions (DIR = +1: column
-// S2_CPL * lane + u; DIR = -1: column L-1-(S2_CPL * lane + u)); t < 0 gives
-// zeros.
+// S2_CPL * lane + u; DIR = -1: column L-1-(S2_CPL * lane + u)); zero past
+// the row's ends.  t must be a valid row.  The loads are unconditional
+// (clamped addresses, masked values) so that several rows' loads can be in
+// flight at once.
 template <int DIR>
 __device__ __forceinline__ void load_row(const uint32_t *h, int L, bool vec, int t, uint32_t (&c)[S2_CPL])
 {
     const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int u = 0; u < S2_CPL; ++u)
-        c[u] = 0u;
-    if (t < 0)
-        return;
     const uint32_t *row = h + (int64_t)t * L;
     if (vec) {
-        if (S2_CPL * lane < L) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(row + (DIR > 0 ? S2_CPL * lane : L - S2_CPL - S2_CPL * lane));
-            if (DIR > 0) {
-                c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
-            } else {
-                c[0] = v.w; c[1] = v.z; c[2] = v.y; c[3] = v.x;
-            }
+        const bool ok = S2_CPL * lane < L;
+        const int off = ok ? (DIR > 0 ? S2_CPL * lane : L - S2_CPL - S2_CPL * lane) : 0;
+        const uint4 v = *reinterpret_cast<const uint4 *>(row + off);
+        if (DIR > 0) {
+            c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        } else {
+            c[0] = v.w; c[1] = v.z; c[2] = v.y; c[3] = v.x;
         }
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u)
+            c[u] = ok ? c[u] : 0u;
     } else {
 #pragma unroll
         for (int u = 0; u < S2_CPL; ++u) {
             const int col = DIR > 0 ? S2_CPL * lane + u : L - 1 - (S2_CPL * lane + u);
-            if (col >= 0 && col < L)
-                c[u] = row[col];
+            const bool ok = col >= 0 && col < L;
+            const uint32_t v = row[ok ? col : 0];
+            c[u] = ok ? v : 0u;
         }
     }
 }
 
-// Visits n rows of the compacted list of rows holding counts, rows[k0],
+// Visits n >= 0 rows of the compacted list of rows holding counts, rows[k0],
 // rows[k0 + DIR], ..., with each row's sums along s (row_sums, in DIR's scan
 // order) and S2_CPL auxiliary values aux(k, .) per lane (stored keys the row
 // needs); the counts and auxiliary values of the next S2_RING rows are in
-// flight meanwhile.
+// flight meanwhile.  Past the last row the ring reloads the last row and its
+// sums are discarded.
 template <int DIR, typename CT, typename A, typename F>
 __device__ __forceinline__ void for_rows(const S2 &p, const int *rows, int k0, int n, A &&aux, F &&f)
 {
+    if (n <= 0)
+        return;
     uint32_t ring[S2_RING][S2_CPL];
     float xr[S2_RING][S2_CPL];
 #pragma unroll
     for (int d = 0; d < S2_RING; ++d) {
-        load_row<DIR>(p.h, p.L, p.vec, d < n ? rows[k0 + DIR * d] : -1, ring[d]);
-        aux(d < n ? k0 + DIR * d : -1, xr[d]);
+        const int kk = k0 + DIR * min(d, n - 1);
+        load_row<DIR>(p.h, p.L, p.vec, rows[kk], ring[d]);
+        aux(kk, xr[d]);
     }
     for (int i0 = 0; i0 < n; i0 += S2_RING) {
 #pragma unroll
         for (int d = 0; d < S2_RING; ++d) {
             const int i = i0 + d;
-            if (i < n) {
-                uint32_t c[S2_CPL];
-                float x[S2_CPL];
+            uint32_t c[S2_CPL];
+            float x[S2_CPL];
 #pragma unroll
-                for (int u = 0; u < S2_CPL; ++u) {
-                    c[u] = ring[d][u];
-                    x[u] = xr[d][u];
-                }
-                const int inext = i + S2_RING;
-                load_row<DIR>(p.h, p.L, p.vec, inext < n ? rows[k0 + DIR * inext] : -1, ring[d]);
-                aux(inext < n ? k0 + DIR * inext : -1, xr[d]);
-                CT rc[S2_CPL];
-                double rq[S2_CPL];
-                row_sums<CT>(c, p.tab, p.q, rc, rq);
-                f(k0 + DIR * i, rc, rq, x);
+            for (int u = 0; u < S2_CPL; ++u) {
+                c[u] = ring[d][u];
+                x[u] = xr[d][u];
             }
+            const int kk = k0 + DIR * min(i + S2_RING, n - 1);
+            load_row<DIR>(p.h, p.L, p.vec, rows[kk], ring[d]);
+            aux(kk, xr[d]);
+            CT rc[S2_CPL];
+            double rq[S2_CPL];
+            row_sums<CT>(c, p.tab, p.q, rc, rq);
+            if (i < n)
+                f(k0 + DIR * i, rc, rq, x);
         }
     }
 }
@@ -440,15 +457,17 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
     auto none = [](int, float(&)[S2_CPL]) {};
     // the stored class 2 keys at (rows[k + 1], s + 1) for the lane's columns s
     auto partner = [&](int k, float(&x)[S2_CPL]) {
-        const float *row2 = k < 0 ? nullptr : k2 + (int64_t)rows[k + 1] * L;
+        const float *row2 = k2 + (int64_t)rows[k + 1] * L; // k <= R - 2 in the pass that uses it
 #pragma unroll
-        for (int u = 0; u < S2_CPL; ++u)
-            x[u] = (row2 && colA[u] <= L - 2) ? row2[colA[u] + 1] : -INFINITY;
+        for (int u = 0; u < S2_CPL; ++u) {
+            const float v = row2[min(colA[u] + 1, L - 1)]; // unconditional load, masked below
+            x[u] = colA[u] <= L - 2 ? v : -INFINITY;
+        }
     };
 
     // 1. class 2 keys
     {
-        uint64_t bc[S2_CPL] = {};
+        CT bc[S2_CPL] = {};
         double bq[S2_CPL] = {};
         for_rows<-1, CT>(p, rows, R - 1, R - kB, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
                                                            const float(&)[S2_CPL]) {
@@ -466,7 +485,7 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
     // 2. pair keys, row maxima
     float M = -INFINITY;
     {
-        uint64_t ac[S2_CPL] = {};
+        CT ac[S2_CPL] = {};
         double aq[S2_CPL] = {};
         for_rows<1, CT>(p, rows, 0, npair, partner, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
                                                         const float(&x)[S2_CPL]) {
@@ -510,7 +529,7 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
     }
     // 3. FP64 class 2 terms of the partner rows rows[k + 1], k a candidate
     if (kc1 >= 0) {
-        uint64_t bc[S2_CPL] = {};
+        CT bc[S2_CPL] = {};
         double bq[S2_CPL] = {};
         for_rows<-1, CT>(p, rows, R - 1, R - 1 - kc0, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
                                                                  const float(&)[S2_CPL]) {
@@ -533,7 +552,7 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
     double best = -INFINITY;
     long long code = 0x7fffffffffffffffLL;
     if (kc1 >= 0) {
-        uint64_t ac[S2_CPL] = {};
+        CT ac[S2_CPL] = {};
         double aq[S2_CPL] = {};
         for_rows<1, CT>(p, rows, 0, kc1 + 1, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
                                                        const float(&)[S2_CPL]) {
@@ -598,8 +617,8 @@ __global__ void __launch_bounds__(64) k_rows2d(const uint32_t *__restrict__ hist
     const bool vec = (L % S2_CPL) == 0 && ((uintptr_t)h & 15) == 0;
     uint32_t c[16][S2_CPL];
 #pragma unroll
-    for (int d = 0; d < 16; ++d)
-        load_row<1>(h, L, vec, 16 * g + d < L ? 16 * g + d : -1, c[d]);
+    for (int d = 0; d < 16; ++d) // rows past L reload row L-1 and count as empty
+        load_row<1>(h, L, vec, min(16 * g + d, L - 1), c[d]);
     uint32_t bits = 0;
     uint64_t n = 0;
 #pragma unroll
@@ -608,6 +627,8 @@ __global__ void __launch_bounds__(64) k_rows2d(const uint32_t *__restrict__ hist
 #pragma unroll
         for (int u = 0; u < S2_CPL; ++u)
             r += c[d][u];
+        if (16 * g + d >= L)
+            r = 0;
         n += r;
         if (__ballot(r != 0))
             bits |= 1u << d;
@@ -639,7 +660,8 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
     p.q = ql.q[j];
     p.sgn = p.q == 1.0 ? 0.0 : (p.q < 1.0 ? 1.0 : -1.0);
     p.hmax = (p.q == 1.0 ? 1.0 : fabs(1.0 - p.q)) * 2.0 * log((double)L); // a class holds at most L^2 cells
-    p.mq = (float)(-p.sgn * p.q);
+    p.mq = (float)(-p.q);
+    p.sg = p.q < 1.0 ? 1.0f : -1.0f;
     p.gmax = (float)(p.hmax * 1.4426950408889634 * (1.0 + 0x1p-20));
     p.tab = tab;
     // the image's pixel count and its rows holding counts, in increasing
