@@ -173,7 +173,7 @@ struct LabelSets {
     uint8_t *const *out[TS_MAX_LABEL_SETS];
 };
 __global__ void k_fill_u32(uint32_t *p, int64_t n); // k_histogram.hip
-size_t hist2d_lds_bytes(int L, int W);
+size_t hist2d_lds_bytes(int L, int H, int W);
 ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint32_t *hist, hipStream_t st);
 size_t search2d_workspace_bytes(int nseg, int nq, int L);
 ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const double *q, void *ws, int32_t *thr,

@@ -34,15 +34,22 @@
 
 namespace ts {
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 constexpr int H2_THREADS = 1024;
 constexpr int H2_MAX_W = 4096;    // row length held in the LDS ring
 constexpr int H2_MAX_L = 256;     // 2D histograms up to 256 x 256
+constexpr int H2_LDS = 160 * 1024; // LDS of one workgroup: the plane (128 KiB at L = 256) and staged rows
 constexpr int S2_THREADS = 64;    // one wavefront per (q, image)
 constexpr int S2_CPL = 4;         // columns per lane (L <= 256)
 constexpr int S2_TAB = 2048;      // p^q (or p ln p) of counts below this from an LDS table
 constexpr int S2_RING = 4;        // rows of counts in flight ahead of the row being summed
 
 // ------------------------------------------------------------------ histogram
+
+// LDS layout of k_hist2d: the packed plane, the per-lane corner counters,
+// then the staged gray levels (16-byte aligned).
+__host__ __device__ inline int hist2d_rows_offset(int L) { return (((L * L + 1) / 2 + 128) * 4 + 15) & ~15; }
 
 template <int MAP>
 __global__ void __launch_bounds__(H2_THREADS) k_hist2d(const int16_t *const *__restrict__ vox, int nseg, int H,
@@ -54,7 +61,7 @@ __global__ void __launch_bounds__(H2_THREADS) k_hist2d(const int16_t *const *__r
     const int nw2 = (L * L + 1) / 2;                       // packed 16-bit cells
     uint32_t *plane = sm;                                  // [nw2]: cell c in half (c & 1) of word c >> 1
     uint32_t *hot = plane + nw2;                           // [2 * 64]: (0,0), (L-1,L-1) per lane
-    uint8_t *rows = reinterpret_cast<uint8_t *>(hot + 128); // [(chunk_rows + 2) * W] gray levels (L <= 256)
+    uint8_t *rows = reinterpret_cast<uint8_t *>(sm) + hist2d_rows_offset(L); // [(chunk_rows + 2) * W]
     const int lane = threadIdx.x & 63;
     const int bands = (H + rows_per_wg - 1) / rows_per_wg;
     const int s = blockIdx.x / bands;
@@ -62,31 +69,83 @@ __global__ void __launch_bounds__(H2_THREADS) k_hist2d(const int16_t *const *__r
     const int r1 = min(H, r0 + rows_per_wg);
     const TS_GLOBAL int16_t *img = gp(vox[s]);
     uint32_t *hs = hist + (int64_t)s * L * L;
+    const bool vec = (W % 8) == 0 && ((uintptr_t)img & 15) == 0;
     for (int i = threadIdx.x; i < nw2 + 128; i += blockDim.x)
         sm[i] = 0u;
+    // one count: (f, g) = (gray level, floor of the 3x3 mean); the clamp
+    // corners count in per-lane words, every other cell in its half-word
+    auto count = [&](int f, int sum) {
+        const int g = (int)((uint32_t)sum / 9u);
+        const int c = f * L + g;
+        const bool corner = f == g && (f == 0 || f == L - 1);
+        uint32_t *a = corner ? hot + (f == 0 ? 0 : 64) + lane : plane + (c >> 1);
+        atomicAdd(a, corner ? 1u : (1u << ((c & 1) << 4)));
+    };
     // chunks of chunk_rows image rows: the gray levels of rows r-1 .. r+n
     // (edge rows repeated) are staged in LDS in one pass, then every pixel of
     // rows r .. r+n-1 is counted
     for (int r = r0; r < r1; r += chunk_rows) {
         const int n = min(chunk_rows, r1 - r);
         __syncthreads(); // previous chunk fully counted
-        for (int i = threadIdx.x; i < (n + 2) * W; i += blockDim.x) {
-            const int k = i / W, x = i - k * W;
-            const int y = min(max(r - 1 + k, 0), H - 1);
-            rows[i] = (uint8_t)bin_of_t<MAP>(img[(int64_t)y * W + x], bm);
+        if (vec) { // 8 pixels per 16-byte load, 8 gray levels per 8-byte LDS store
+            const int nv = (n + 2) * W / 8;
+            for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+                const int e = i * 8, k = e / W, x = e - k * W;
+                const int y = min(max(r - 1 + k, 0), H - 1);
+                const v4i v = *reinterpret_cast<const TS_GLOBAL v4i *>(img + (int64_t)y * W + x);
+                const uint32_t w4[4] = {(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};
+                uint32_t b[2] = {0u, 0u};
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int16_t h16 = (int16_t)(w4[j >> 1] >> ((j & 1) * 16));
+                    b[j >> 2] |= (uint32_t)bin_of_t<MAP>(h16, bm) << ((j & 3) * 8);
+                }
+                *reinterpret_cast<uint2 *>(rows + e) = make_uint2(b[0], b[1]);
+            }
+        } else {
+            for (int i = threadIdx.x; i < (n + 2) * W; i += blockDim.x) {
+                const int k = i / W, x = i - k * W;
+                const int y = min(max(r - 1 + k, 0), H - 1);
+                rows[i] = (uint8_t)bin_of_t<MAP>(img[(int64_t)y * W + x], bm);
+            }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
-            const int k = i / W + 1, x = i - (k - 1) * W;
-            const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
-            const uint8_t *up = rows + (k - 1) * W, *cu = rows + k * W, *dn = rows + (k + 1) * W;
-            const int sum = (int)up[xl] + up[x] + up[xr] + cu[xl] + cu[x] + cu[xr] + dn[xl] + dn[x] + dn[xr];
-            const int f = cu[x];
-            const int g = (int)((uint32_t)sum / 9u);
-            const int c = f * L + g;
-            const bool corner = f == g && (f == 0 || f == L - 1);
-            uint32_t *a = corner ? hot + (f == 0 ? 0 : 64) + lane : plane + (c >> 1);
-            atomicAdd(a, corner ? 1u : (1u << ((c & 1) << 4)));
+        if ((W & 3) == 0) { // 4 pixels per thread: one aligned word and its two neighbours per row
+            const int n4 = n * W / 4;
+            for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+                const int e = i * 4, k = e / W + 1, x = e - (k - 1) * W;
+                int hsum[3][4];
+                int fcen[4];
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const uint8_t *row = rows + (k - 1 + dy) * W;
+                    const uint32_t wd = *reinterpret_cast<const uint32_t *>(row + x);
+                    int b[6];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        b[j + 1] = (wd >> (8 * j)) & 0xff;
+                    b[0] = x > 0 ? row[x - 1] : b[1];          // edge pixel repeated
+                    b[5] = x + 4 < W ? row[x + 4] : b[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        hsum[dy][j] = b[j] + b[j + 1] + b[j + 2];
+                    if (dy == 1) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            fcen[j] = b[j + 1];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    count(fcen[j], hsum[0][j] + hsum[1][j] + hsum[2][j]);
+            }
+        } else {
+            for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
+                const int k = i / W + 1, x = i - (k - 1) * W;
+                const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
+                const uint8_t *up = rows + (k - 1) * W, *cu = rows + k * W, *dn = rows + (k + 1) * W;
+                count(cu[x], (int)up[xl] + up[x] + up[xr] + cu[xl] + cu[x] + cu[xr] + dn[xl] + dn[x] + dn[xr]);
+            }
         }
     }
     __syncthreads();
@@ -112,12 +171,31 @@ __global__ void __launch_bounds__(H2_THREADS) k_hist2d(const int16_t *const *__r
     }
 }
 
-static int hist2d_chunk_rows(int W) { return std::max(1, 4096 / W); }
+// Band and chunk sizes: bands of at most 65535 pixels (16-bit cells),
+// balanced over the image's rows; chunks as large as the LDS left beside the
+// plane allows, balanced over the band.
+struct Hist2dShape {
+    int rows_per_wg, chunk_rows;
+    size_t lds;
+};
 
-size_t hist2d_lds_bytes(int L, int W)
+static Hist2dShape hist2d_shape(int L, int H, int W)
 {
-    return ((size_t)(L * L + 1) / 2 + 128) * sizeof(uint32_t) + (size_t)(hist2d_chunk_rows(W) + 2) * W;
+    Hist2dShape sh;
+    const int max_rows = std::max(1, std::min(H, 65535 / std::max(W, 1)));
+    const int bands = (H + max_rows - 1) / max_rows;
+    sh.rows_per_wg = (H + bands - 1) / bands;
+    const int base = hist2d_rows_offset(L);
+    const int fit = std::max(3, (H2_LDS - base) / std::max(W, 1)); // staged rows that fit (>= 3 by the launch check)
+    int chunk = std::max(1, std::min(fit - 2, sh.rows_per_wg));
+    const int nch = (sh.rows_per_wg + chunk - 1) / chunk;
+    chunk = (sh.rows_per_wg + nch - 1) / nch;
+    sh.chunk_rows = chunk;
+    sh.lds = (size_t)base + (size_t)(chunk + 2) * W;
+    return sh;
 }
+
+size_t hist2d_lds_bytes(int L, int H, int W) { return hist2d_shape(L, H, W).lds; }
 
 ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint32_t *hist, hipStream_t st)
 {
@@ -126,11 +204,10 @@ ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint3
     const int64_t n = (int64_t)b.nseg * bm.L * bm.L;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, st, hist,
                        n);
-    // at most 65535 pixels per workgroup (16-bit cell counters in LDS)
-    const int rows = std::max(1, std::min(H, 65535 / std::max(W, 1)));
+    const Hist2dShape sh = hist2d_shape(bm.L, H, W);
+    const int rows = sh.rows_per_wg, chunk = sh.chunk_rows;
+    const size_t lds = sh.lds;
     const int bands = (H + rows - 1) / rows;
-    const int chunk = hist2d_chunk_rows(W);
-    const size_t lds = hist2d_lds_bytes(bm.L, W);
     const dim3 g((unsigned)((int64_t)b.nseg * bands)), blk(H2_THREADS);
 #define TS_H2(M)                                                                                                    \
     (void)hipFuncSetAttribute((const void *)k_hist2d<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
