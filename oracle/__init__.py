@@ -42,6 +42,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 MODE_DIRECT = 0
 MODE_PREFIX = 1
 MODE_KAPUR = 2
+COMP_RECURSIVE = 0  # T <- T + S_j + (1-q) T S_j
+COMP_SUMPROD = 1    # sum_j S_j + (1-q) prod_j S_j
 
 OK = 0
 DEGENERATE = 1
@@ -95,6 +97,10 @@ def _bind(lib):
     lib.or_search.restype = i32
     lib.or_objective.argtypes = [P, i32, i32, f64, i32, P]
     lib.or_objective.restype = f64
+    lib.or_search_c.argtypes = [P, i32, i32, f64, i32, i32, P, P, P]
+    lib.or_search_c.restype = i32
+    lib.or_objective_c.argtypes = [P, i32, i32, f64, i32, i32, P]
+    lib.or_objective_c.restype = f64
     lib.or_label.argtypes = [P, i64, i32, i32, i32, P, i32, P]
     lib.or_label.restype = None
     if hasattr(lib, "or2_search"):  # mutated copies of oracle.c alone lack the 2-D part
@@ -175,22 +181,27 @@ class SearchResult:
         return f"SearchResult(thr={self.thr.tolist()}, obj={self.obj!r}, second={self.second!r}, status={self.status})"
 
 
-def search(hist: np.ndarray, k: int, q: float, mode: int = MODE_PREFIX, lib=None) -> SearchResult:
+def search(hist: np.ndarray, k: int, q: float, mode: int = MODE_PREFIX, lib=None,
+           comp: int = COMP_RECURSIVE) -> SearchResult:
+    """Exhaustive first arg max; comp selects the composition of the class
+    entropies (COMP_RECURSIVE: the pseudo-additive rule applied recursively;
+    COMP_SUMPROD: sum of S_j + (1-q) product of S_j)."""
     h = np.ascontiguousarray(hist, dtype=np.uint32)
     thr = np.empty(k, dtype=np.int32)
     best = ctypes.c_double()
     second = ctypes.c_double()
-    st = (lib or _load()).or_search(_ptr(h), h.size, int(k), float(q), int(mode), _ptr(thr),
-                           ctypes.byref(best), ctypes.byref(second))
+    st = (lib or _load()).or_search_c(_ptr(h), h.size, int(k), float(q), int(mode), int(comp), _ptr(thr),
+                                      ctypes.byref(best), ctypes.byref(second))
     if st == BADARG:
         raise ValueError(f"oracle.search: bad arguments L={h.size} k={k} q={q} mode={mode}")
     return SearchResult(thr, best.value, second.value, st)
 
 
-def objective(hist: np.ndarray, thr, q: float, mode: int = MODE_PREFIX, lib=None) -> float:
+def objective(hist: np.ndarray, thr, q: float, mode: int = MODE_PREFIX, lib=None,
+              comp: int = COMP_RECURSIVE) -> float:
     h = np.ascontiguousarray(hist, dtype=np.uint32)
     t = np.ascontiguousarray(np.asarray(thr, dtype=np.int32).reshape(-1))
-    return float((lib or _load()).or_objective(_ptr(h), h.size, t.size, float(q), int(mode), _ptr(t)))
+    return float((lib or _load()).or_objective_c(_ptr(h), h.size, t.size, float(q), int(mode), int(comp), _ptr(t)))
 
 
 def label(vox: np.ndarray, lo: int, hi: int, L: int, thr, lib=None) -> np.ndarray:

@@ -19,6 +19,10 @@
  *    define H1, H2, P1, P2).
  *  - more than two classes: the pseudo-additive composition rule of the
  *    objective phi is applied recursively, T <- T + S_j + (1-q) T S_j.
+ *    A second composition, the multilevel form used elsewhere in the
+ *    literature, sum_j S_j + (1-q) prod_j S_j, is offered beside it
+ *    (or_search_c / or_objective_c with OR_COMP_SUMPROD); both equal the
+ *    paper's H1 + H2 + (1-q) H1 H2 for one threshold.
  *  - a class with zero probability mass makes the tuple invalid.
  *  - bins with p_i = 0 contribute nothing to the sum of (p_i/w)^q.
  *  - ties: the first tuple in lexicographic order (t1 outermost) wins.
@@ -38,6 +42,9 @@
 #define OR_MODE_DIRECT 0 /* class sums evaluated literally, O(L) per class */
 #define OR_MODE_PREFIX 1 /* class sums from sequential prefix sums, O(1) */
 #define OR_MODE_KAPUR 2  /* Shannon (q -> 1) limit, literal sums */
+
+#define OR_COMP_RECURSIVE 0 /* T <- T + S_j + (1-q) T S_j */
+#define OR_COMP_SUMPROD 1   /* sum_j S_j + (1-q) prod_j S_j */
 
 /* ------------------------------------------------------------------ */
 /* Pre-processing section: linear map of intensity levels to L gray levels. */
@@ -154,6 +161,18 @@ static double compose(const double *S, int32_t ncls, double q, int kapur)
     return T;
 }
 
+/* The multilevel variant: the plain sum of the class entropies plus (1 - q)
+   times their product (for the Kapur limit, the plain sum). */
+static double compose_sumprod(const double *S, int32_t ncls, double q, int kapur)
+{
+    double sum = 0.0, prod = 1.0;
+    for (int32_t j = 0; j < ncls; ++j) {
+        sum += S[j];
+        prod *= S[j];
+    }
+    return kapur ? sum : sum + (1.0 - q) * prod;
+}
+
 typedef struct {
     int32_t L;
     double q;
@@ -163,6 +182,7 @@ typedef struct {
     int64_t *C;     /* [L] count prefix (prefix mode) */
     double *Q;      /* [L] prefix of p^q (prefix mode) */
     double *table;  /* [L*L] class entropies memoised by (a,b) (prefix mode, k >= 2) */
+    int32_t comp;   /* OR_COMP_* */
 } ctx_t;
 
 static double class_entropy(const ctx_t *cx, int32_t a, int32_t b)
@@ -189,6 +209,8 @@ static double tuple_objective(const ctx_t *cx, const int32_t *t, int32_t k)
             return NAN;
         a = b + 1;
     }
+    if (cx->comp == OR_COMP_SUMPROD)
+        return compose_sumprod(S, k + 1, cx->q, cx->mode == OR_MODE_KAPUR);
     return compose(S, k + 1, cx->q, cx->mode == OR_MODE_KAPUR);
 }
 
@@ -255,8 +277,8 @@ static int args_ok(int32_t L, int32_t k, double q, int32_t mode)
    Outputs: thr[k] (all -1 when no tuple is valid), *best, and *second = the
    largest objective over all valid tuples other than the winner (NAN if
    there is none).  Returns OR_OK, OR_DEGENERATE, OR_EMPTY or OR_BADARG. */
-int32_t or_search(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t mode,
-                  int32_t *thr, double *best, double *second)
+int32_t or_search_c(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t mode, int32_t comp,
+                    int32_t *thr, double *best, double *second)
 {
     for (int32_t j = 0; j < k && j < 16; ++j)
         thr[j] = -1;
@@ -266,8 +288,11 @@ int32_t or_search(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t 
         return OR_BADARG;
     if (k > L - 1)
         return OR_DEGENERATE;
+    if (comp != OR_COMP_RECURSIVE && comp != OR_COMP_SUMPROD)
+        return OR_BADARG;
     ctx_t cx;
     int st = ctx_init(&cx, hist, L, k, q, mode);
+    cx.comp = comp;
     if (st != OR_OK) {
         ctx_free(&cx);
         return st;
@@ -313,10 +338,17 @@ int32_t or_search(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t 
     return OR_OK;
 }
 
-/* Objective of one given tuple (NAN if invalid or out of range). */
-double or_objective(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t mode, const int32_t *thr)
+int32_t or_search(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t mode,
+                  int32_t *thr, double *best, double *second)
 {
-    if (!args_ok(L, k, q, mode))
+    return or_search_c(hist, L, k, q, mode, OR_COMP_RECURSIVE, thr, best, second);
+}
+
+/* Objective of one given tuple (NAN if invalid or out of range). */
+double or_objective_c(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t mode, int32_t comp,
+                      const int32_t *thr)
+{
+    if (!args_ok(L, k, q, mode) || (comp != OR_COMP_RECURSIVE && comp != OR_COMP_SUMPROD))
         return NAN;
     for (int32_t j = 0; j < k; ++j) {
         if (thr[j] < 0 || thr[j] > L - 2)
@@ -326,11 +358,17 @@ double or_objective(const uint32_t *hist, int32_t L, int32_t k, double q, int32_
     }
     ctx_t cx;
     int st = ctx_init(&cx, hist, L, 1, q, mode); /* no table: one tuple only */
+    cx.comp = comp;
     double S = NAN;
     if (st == OR_OK)
         S = tuple_objective(&cx, thr, k);
     ctx_free(&cx);
     return S;
+}
+
+double or_objective(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t mode, const int32_t *thr)
+{
+    return or_objective_c(hist, L, k, q, mode, OR_COMP_RECURSIVE, thr);
 }
 
 /* Thresholding kernel function (Algorithm 1) generalised to k thresholds:

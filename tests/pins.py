@@ -322,10 +322,102 @@ def pin_labels(lib=None):
     assert not oracle.label(v, -1024, 3071, 4096, [-1], lib=lib).any(), "no valid tuple labels everything 0"
 
 
+# ---- the multilevel variant: sum_j S_j + (1-q) prod_j S_j ----------------
+
+SP = oracle.COMP_SUMPROD
+
+
+def _sumprod_closed(sizes, q):
+    S = [ln_q(m, q) for m in sizes]
+    return sum(S) + (1.0 - q) * float(np.prod(S))
+
+
+def pin_sumprod_uniform_closed_form(lib=None, mode=oracle.MODE_PREFIX):
+    """Uniform histogram: each class entropy is ln_q(m_j) (m_j bins), so the
+    variant is sum ln_q(m_j) + (1-q) prod ln_q(m_j); the arg max is the first
+    tuple whose class sizes maximise that closed form."""
+    for L, k, q in [(10, 2, 0.5), (9, 3, 1.5), (12, 2, 2.0), (16, 3, 0.8), (8, 1, 0.7), (11, 2, 3.0)]:
+        h = np.full(L, 3, dtype=np.uint32)
+        best, best_t = -np.inf, None
+        for t in _tuples(L, k):
+            want = _sumprod_closed(_class_sizes(L, t), q)
+            S = oracle.objective(h, t, q, mode, lib=lib, comp=SP)
+            assert abs(S - want) <= 1e-12 * max(1.0, abs(want)), f"sumprod uniform L={L} k={k} q={q} t={t}"
+            if want > best + 1e-12 * max(1.0, abs(want)):
+                best, best_t = want, t
+        r = oracle.search(h, k, q, mode, lib=lib, comp=SP)
+        assert abs(r.obj - best) <= 1e-12 * max(1.0, abs(best)), (L, k, q, r, best)
+        got = _sumprod_closed(_class_sizes(L, r.thr.tolist()), q)
+        assert abs(got - best) <= 1e-12 * max(1.0, abs(best)), (L, k, q, r, best_t)
+
+
+def pin_sumprod_k1_is_paper(lib=None, mode=oracle.MODE_PREFIX):
+    """One threshold: both compositions are the paper's H1 + H2 + (1-q) H1 H2."""
+    rng = np.random.default_rng(23)
+    for q in (0.4, 0.9, 1.6, 2.5):
+        h = rng.integers(0, 40, 19).astype(np.uint32)
+        for t in range(18):
+            a = oracle.objective(h, [t], q, mode, lib=lib)
+            b = oracle.objective(h, [t], q, mode, lib=lib, comp=SP)
+            assert (np.isnan(a) and np.isnan(b)) or abs(a - b) <= 1e-13 * max(1.0, abs(a)), (q, t, a, b)
+        ra, rb = oracle.search(h, 1, q, mode, lib=lib), oracle.search(h, 1, q, mode, lib=lib, comp=SP)
+        assert ra.thr.tolist() == rb.thr.tolist(), (q, ra, rb)
+
+
+def _gini_classes(h, t):
+    p = h / h.sum()
+    edges = [-1] + list(t) + [len(h) - 1]
+    out = []
+    for j in range(len(t) + 1):
+        c = p[edges[j] + 1: edges[j + 1] + 1]
+        out.append(1.0 - float(np.sum((c / c.sum()) ** 2)))
+    return out
+
+
+def pin_sumprod_q2(lib=None, mode=oracle.MODE_PREFIX):
+    """q = 2: class entropies are Gini-Simpson indices 1 - sum (p/w)^2, so
+    the variant is sum G_j - prod G_j."""
+    rng = np.random.default_rng(29)
+    for L, k in [(9, 2), (8, 3)]:
+        h = rng.integers(1, 50, L).astype(np.uint32)
+        for t in _tuples(L, k):
+            G = _gini_classes(h, t)
+            want = sum(G) - float(np.prod(G))
+            S = oracle.objective(h, t, 2.0, mode, lib=lib, comp=SP)
+            assert abs(S - want) <= 1e-12, (L, k, t, S, want)
+
+
+def pin_sumprod_kapur_limit(lib=None, mode=oracle.MODE_PREFIX):
+    """q -> 1: the product term vanishes and the variant tends to the sum of
+    the class Shannon entropies."""
+    rng = np.random.default_rng(31)
+    for L, k in [(10, 2), (9, 3)]:
+        h = rng.integers(1, 200, L).astype(np.uint32)
+        for t in _tuples(L, k):
+            K = _kapur(h, t)
+            for q in (1.0 - 1e-6, 1.0 + 1e-6):
+                S = oracle.objective(h, t, q, mode, lib=lib, comp=SP)
+                assert abs(S - K) <= 1e-5 * (1.0 + K) ** 3, (L, k, t, q, S, K)
+
+
+def pin_sumprod_symmetry(lib=None, mode=oracle.MODE_PREFIX):
+    rng = np.random.default_rng(37)
+    for L, k, q in [(14, 2, 0.5), (12, 3, 1.5)]:
+        half = rng.integers(0, 30, L // 2).astype(np.uint32)
+        h = np.concatenate([half, half[::-1]])
+        for t in _tuples(L, k):
+            mt = tuple(sorted(L - 2 - x for x in t))
+            a = oracle.objective(h, t, q, mode, lib=lib, comp=SP)
+            b = oracle.objective(h, mt, q, mode, lib=lib, comp=SP)
+            assert (np.isnan(a) and np.isnan(b)) or abs(a - b) <= 1e-12 * max(1, abs(a)), (t, mt, a, b)
+
+
 ALL_PINS = [
     pin_binmap_identity, pin_binmap_edges, pin_histogram, pin_uniform_closed_form, pin_uniform_argmax,
     pin_separated_bins, pin_q2_gini_simpson, pin_kapur_limit, pin_dp, pin_symmetry, pin_invariances,
-    pin_direct_vs_prefix, pin_prefix, pin_labels,
+    pin_direct_vs_prefix, pin_prefix, pin_labels, pin_sumprod_uniform_closed_form, pin_sumprod_k1_is_paper,
+    pin_sumprod_q2, pin_sumprod_kapur_limit, pin_sumprod_symmetry,
 ]
 MODE_PINS = [pin_uniform_closed_form, pin_uniform_argmax, pin_separated_bins, pin_q2_gini_simpson,
-             pin_kapur_limit, pin_dp, pin_symmetry, pin_invariances]
+             pin_kapur_limit, pin_dp, pin_symmetry, pin_invariances, pin_sumprod_uniform_closed_form,
+             pin_sumprod_k1_is_paper, pin_sumprod_q2, pin_sumprod_kapur_limit, pin_sumprod_symmetry]

@@ -25,7 +25,7 @@ MUTANTS = {
     "no_normalisation": ("s += pow(p[i] / w, q);", "s += pow(p[i], q);"),
     "prefix_no_normalisation": ("return (1.0 - dq / pow(w, q)) / (q - 1.0);", "return (1.0 - dq / w) / (q - 1.0);"),
     "transposed_pow": ("s += pow(p[i] / w, q);", "s += pow(q, p[i] / w);"),
-    "class_overlap": ("        a = b + 1;\n    }\n    return compose", "        a = b;\n    }\n    return compose"),
+    "class_overlap": ("        a = b + 1;\n    }\n    if (cx->comp", "        a = b;\n    }\n    if (cx->comp"),
     "threshold_range": ("        t[j] = j;\n    int found = 0;", "        t[j] = j + 1;\n    int found = 0;"),
     "tie_rule_last": ("if (!found || S > b1) {", "if (!found || S >= b1) {"),
     "argmin": ("if (!found || S > b1) {", "if (!found || S < b1) {"),
@@ -35,6 +35,10 @@ MUTANTS = {
     "prefix_mass_from_q": ("P[i] = (double)C / (double)N;", "P[i] = acc;"),
     "prefix_reset": ("acc += pow((double)hist[i] / (double)N, q);", "acc = pow((double)hist[i] / (double)N, q);"),
     "prefix_class_start": ("double dq = Q[b] - (a > 0 ? Q[a - 1] : 0.0);", "double dq = Q[b] - Q[a];"),
+    "sumprod_drop_product": ("return kapur ? sum : sum + (1.0 - q) * prod;", "return sum;"),
+    "sumprod_product_sign": ("return kapur ? sum : sum + (1.0 - q) * prod;", "return kapur ? sum : sum + (q - 1.0) * prod;"),
+    "sumprod_product_skips_first": ("        prod *= S[j];\n", "        prod *= (j ? S[j] : 1.0);\n"),
+    "sumprod_composes_recursively": ("    if (cx->comp == OR_COMP_SUMPROD)\n", "    if (0)\n"),
     "empty_class_allowed": ("    if (!(w > 0.0))\n        return NAN;\n    double s = 0.0;\n    for (int32_t i = a; i <= b; ++i)\n        if (p[i] > 0.0)\n            s += pow",
                             "    if (!(w > 0.0))\n        return 0.0;\n    double s = 0.0;\n    for (int32_t i = a; i <= b; ++i)\n        if (p[i] > 0.0)\n            s += pow"),
 }
