@@ -94,8 +94,12 @@ enum {
                                     tuple within the FP32 error bound (default; exact) */
     TS_SEARCH_FP32_ONLY = 1,     /* FP32 keys only: first tuple with the largest FP32 key */
     TS_SEARCH_FP64 = 2,          /* FP64 exhaustive keys */
-    TS_SEARCH_PLAIN = 3          /* one thread per tuple, all classes evaluated directly in
+    TS_SEARCH_PLAIN = 3,         /* one thread per tuple, all classes evaluated directly in
                                     FP64, one launch per problem: the simple GPU form */
+    TS_SEARCH_SUMPROD = 4        /* a different objective: the multilevel form
+                                    sum_j S_j + (1-q) prod_j S_j of the class entropies
+                                    (equal to the paper's for k = 1), FP64 exhaustive, all
+                                    problems in one launch; obj is that value */
 };
 
 /* Per-problem outcome written by ts_threshold_search. */

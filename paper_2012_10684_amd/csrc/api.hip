@@ -249,7 +249,7 @@ ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t n
 size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq, int32_t mode)
 {
     if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || k < 1 || k > 3 || nq < 1 || nq > TS_MAX_Q || mode < 0 ||
-        mode > 3)
+        mode > TS_SEARCH_SUMPROD)
         return 0;
     return search_workspace_bytes(nseg * nq, nbins, k, mode, 4);
 }
@@ -266,7 +266,7 @@ ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, in
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: k must be 1, 2 or 3");
     if (nbins < k + 1)
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nbins must be >= k + 1");
-    if (mode < 0 || mode > 3)
+    if (mode < 0 || mode > TS_SEARCH_SUMPROD)
         return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: unknown mode");
     ts_status st;
     if ((st = check_q("ts_threshold_search", nq, q, true)) != TS_OK)

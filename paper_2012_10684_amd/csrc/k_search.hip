@@ -91,6 +91,18 @@ struct Plan {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static int64_t tuples_of(int L, int k)
+{
+    const int64_t n = L - 1;
+    return k == 1 ? n : (k == 2 ? n * (n - 1) / 2 : n * (n - 1) * (n - 2) / 6);
+}
+
+// Workgroups per problem of the sum-product search: about 8 tuples per thread.
+static int sumprod_blocks(int L, int k)
+{
+    return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (tuples_of(L, k) + 2047) / 2048));
+}
+
 static Plan make_plan(int nseg, int L, int k, int mode, int cols, int T1)
 {
     Plan p;
@@ -141,11 +153,13 @@ static Plan make_plan(int nseg, int L, int k, int mode, int cols, int T1)
     if (mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY)
         o = align256(o + (size_t)nseg * p.tiles * (k == 3 ? p.T1 : 1) * sizeof(float));
     p.off_best = o;
-    if (mode != TS_SEARCH_PLAIN)
+    if (mode != TS_SEARCH_PLAIN && mode != TS_SEARCH_SUMPROD)
         o = align256(o + (size_t)nseg * p.tiles * sizeof(Best));
     p.off_plain = o;
     if (mode == TS_SEARCH_PLAIN)
         o = align256(o + (size_t)PLAIN_BLOCKS * sizeof(Best));
+    if (mode == TS_SEARCH_SUMPROD)
+        o = align256(o + (size_t)nseg * sumprod_blocks(L, k) * sizeof(Best));
     p.bytes = o;
     return p;
 }
@@ -1041,7 +1055,8 @@ __device__ __forceinline__ void write_result(const Cand &b, const Args &a, int s
             thr[(int64_t)s * k + j] = (int32_t)(c & 4095);
             c >>= 12;
         }
-        obj[s] = sgn == 0.0 ? b.l : expm1(sgn * b.l) / (1.0 - q); // Shannon: S = sum of S_j
+        // Shannon: S = sum of S_j; the sum-product variant ranks by S itself
+        obj[s] = (sgn == 0.0 || a.mode == TS_SEARCH_SUMPROD) ? b.l : expm1(sgn * b.l) / (1.0 - q);
         status[s] = TS_PROBLEM_OK;
     }
 }
@@ -1385,6 +1400,82 @@ __global__ void __launch_bounds__(256) k_plain(const double *__restrict__ P, con
     }
 }
 
+// ---------------------------------------------------------------- sum-product variant
+
+// The multilevel variant sum_j S_j + (1-q) prod_j S_j of one tuple in FP64
+// from the prefix sums, each class entropy S_j = (1 - Q_j / w_j^q) / (q - 1)
+// = -expm1(ln Q_j - q ln w_j) / (q - 1) (for q = 1 the Shannon entropy
+// ln w_j - E_j / w_j, composed by the plain sum); -inf when a class is empty.
+__device__ __forceinline__ double sumprod64(const double *P, const double *Q, int L, int k, const int *t, double q,
+                                            double sgn)
+{
+    double sum = 0.0, prod = 1.0;
+    double pa = 0.0, qa = 0.0;
+#pragma unroll 1
+    for (int j = 0; j <= k; ++j) {
+        const int b = j == k ? L - 1 : t[j];
+        const double pb = P[b], qb = Q[b];
+        const double dP = pb - pa, dQ = qb - qa;
+        if (!(dP > 0.0))
+            return -INFINITY;
+        const double S = sgn == 0.0 ? log(dP) - dQ / dP : -expm1(log(dQ) - q * log(dP)) / (q - 1.0);
+        sum += S;
+        prod *= S;
+        pa = pb;
+        qa = qb;
+    }
+    return sgn == 0.0 ? sum : sum + (1.0 - q) * prod;
+}
+
+// Every tuple of every problem: workgroup blockIdx.x covers one contiguous
+// range of tuple ranks of problem blockIdx.x / per (combinatorial number
+// system), one tuple per thread at a time; the first best of the range goes
+// to out[blockIdx.x] (reduced per problem by k_final).
+__global__ void __launch_bounds__(256) k_sumprod(Args a, int64_t ntup, int per, Best *__restrict__ out)
+{
+    const int s = blockIdx.x / per, part = blockIdx.x % per;
+    const QConst &c = a.qc[s / a.nseg];
+    const double *P = a.P + (int64_t)(s % a.nseg) * a.L;
+    const double *Q = a.Q + (int64_t)s * a.L;
+    const int64_t chunk = (ntup + per - 1) / per;
+    const int64_t r0 = (int64_t)part * chunk, r1 = min(ntup, r0 + chunk);
+    double br = -INFINITY, bl = -INFINITY;
+    long long bc = 0x7fffffffffffffffLL;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        int t[3];
+        int64_t v = r;
+        for (int j = a.k; j >= 1; --j) {
+            const int64_t x = inv_binom(v, j);
+            t[j - 1] = (int)x;
+            v -= binom(x, j);
+        }
+        const double S = sumprod64(P, Q, a.L, a.k, t, c.q, c.sgn);
+        const long long code = make_code(a.k, t);
+        if (better(S, code, br, bc)) {
+            br = S;
+            bl = S;
+            bc = code;
+        }
+    }
+    wave_best(br, bl, bc);
+    __shared__ double sr[4];
+    __shared__ long long sc[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sr[w] = br;
+        sc[w] = bc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+            if (better(sr[i], sc[i], br, bc)) {
+                br = sr[i];
+                bc = sc[i];
+            }
+        out[blockIdx.x] = Best{br, br, bc, 0};
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 
 template <int COLS>
@@ -1469,6 +1560,14 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
     a.tmax = (float *)(base + p.off_tmax);
     a.best = (Best *)(base + p.off_best);
 
+    if (mode == TS_SEARCH_SUMPROD) {
+        const int per = sumprod_blocks(L, k);
+        Best *pb = (Best *)(base + p.off_plain);
+        hipLaunchKernelGGL(k_sumprod, dim3((unsigned)((int64_t)nprob * per)), dim3(256), 0, st, a, tuples_of(L, k), per,
+                           pb);
+        hipLaunchKernelGGL(k_final, dim3((unsigned)nprob), dim3(1024), 0, st, a, pb, per, thr, obj, status, 0);
+        return check_launch("ts_threshold_search (sum-product)");
+    }
     if (mode == TS_SEARCH_PLAIN) {
         const int64_t n = L - 1;
         const int64_t ntup = k == 1 ? n : (k == 2 ? n * (n - 1) / 2 : n * (n - 1) * (n - 2) / 6);

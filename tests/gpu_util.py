@@ -32,9 +32,11 @@ def u32(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy().view(np.uint32)
 
 
-def check_choice(h: np.ndarray, k: int, q: float, thr, obj, status, mode=oracle.MODE_PREFIX, ref=None):
-    """Compare one GPU search result with the oracle.  Returns (exact, ref)."""
-    r = ref if ref is not None else oracle.search(h, k, q, mode)
+def check_choice(h: np.ndarray, k: int, q: float, thr, obj, status, mode=oracle.MODE_PREFIX, ref=None,
+                 comp=oracle.COMP_RECURSIVE):
+    """Compare one GPU search result with the oracle (objective composed as
+    comp).  Returns (exact, ref)."""
+    r = ref if ref is not None else oracle.search(h, k, q, mode, comp=comp)
     thr = [int(x) for x in np.asarray(thr).reshape(-1)]
     if r.status != oracle.OK:
         assert status == r.status, (status, r)
@@ -44,7 +46,7 @@ def check_choice(h: np.ndarray, k: int, q: float, thr, obj, status, mode=oracle.
     assert status == 0, (status, r)
     exact = thr == r.thr.tolist()
     if not exact:
-        s_gpu = oracle.objective(h, thr, q, mode)
+        s_gpu = oracle.objective(h, thr, q, mode, comp=comp)
         assert np.isfinite(s_gpu), (thr, r)
         assert s_gpu >= r.obj - THR_REL_TIE * abs(r.obj), (
             f"thresholds {thr} vs oracle {r.thr.tolist()}: S {s_gpu!r} vs {r.obj!r} (gap {r.rel_gap():.3g})")
