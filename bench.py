@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import math
 import json
 import os
 import sys
@@ -440,6 +441,41 @@ def main():
             line[f"search_speedup_vs_{name}"] = us / (per["search"] * 1e6)
             line[f"search_{name}_same_result"] = bool(torch.equal(out2[0], res[0]))
             del ws2
+    if args.workload in ("volume300", "volume600"):
+        # the multilevel variant objective sum S_j + (1-q) prod S_j (FP64 exhaustive), reported beside the
+        # paper's objective: a different objective, so its thresholds are not compared
+        ws3 = torch.empty(api.workspace_bytes(nseg, L, K, api.SEARCH_SUMPROD, nq), dtype=torch.uint8, device=dev)
+        out3 = tuple(torch.empty_like(r) for r in res)
+        api.threshold_search(P, Q, K, QS, api.SEARCH_SUMPROD, ws=ws3, out=out3, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            api.threshold_search(P, Q, K, QS, api.SEARCH_SUMPROD, ws=ws3, out=out3, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 3
+        line["search_sumprod_fp64_us"] = us
+        line["search_sumprod_tuples_per_s"] = nq * nseg * math.comb(L - 1, K) / (us * 1e-6)
+        line["search_sumprod_all_ok"] = bool(int((out3[2] != 0).sum()) == 0)
+        del ws3
+    if args.workload in ("volume300", "volume600"):
+        # the dynamic-programming search (same objective and tuple as the default search; k (L-1)^2 / 2
+        # FP64 class terms per problem), at the workload's k and with one threshold more
+        for kk in (K, K + 1):
+            wsd = torch.empty(api.workspace_dp_bytes(nseg, L, kk, nq), dtype=torch.uint8, device=dev)
+            outd = (torch.empty((nq, nseg, kk), dtype=torch.int32, device=dev),
+                    torch.empty_like(res[1]), torch.empty_like(res[2]))
+            api.threshold_search_dp(P, Q, kk, QS, ws=wsd, out=outd, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                api.threshold_search_dp(P, Q, kk, QS, ws=wsd, out=outd, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            line[f"search_dp_k{kk}_us"] = e0.elapsed_time(e1) * 1e3 / 3
+            if kk == K:
+                line["search_dp_same_result"] = bool(torch.equal(outd[0], res[0]))
+            del wsd
     if args.workload == "batch64":
         # the same work with one launch per slice and stage, on a sample of slices
         m = min(args.per_slice_sample, nseg)

@@ -251,6 +251,37 @@ ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbin
                                 void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status,
                                 ts_stream_t stream);
 
+/* Largest number of thresholds ts_threshold_search_dp takes. */
+#define TS_DP_MAX_K 16
+
+/* [host] Bytes of workspace ts_threshold_search_dp needs (0 if invalid):
+ * k * nq * nseg * nbins doubles. */
+size_t ts_search_dp_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq);
+
+/* ts_threshold_search_dp -- the arg max of ts_threshold_search (same
+ * objective, classes, validity and first-tuple rule) by dynamic programming
+ * over the class boundaries instead of enumerating tuples, for any k in
+ * 1..TS_DP_MAX_K (Tsallis-entropy section: with 1 + (1-q) S = prod_j
+ * Q_j / w_j^q the arg max of S is the arg max of a sum of class terms, which
+ * is separable over consecutive classes).  k (nbins-1)^2 / 2 FP64 class
+ * terms per problem instead of C(nbins-1, k) tuples.  The maximum is exact
+ * for the per-tuple sums formed right to left in FP64 (the exhaustive
+ * search forms them left to right: the two can differ in the last bits, so
+ * of two tuples within a few ulps either may be reported); among the tuples
+ * reaching it, the first in lexicographic order is returned, and tuples that
+ * differ only inside runs of empty bins tie exactly.
+ *   P, Q, nq, q   as for ts_threshold_search;
+ *   k             1..TS_DP_MAX_K, nbins >= k + 1;
+ *   ws            device workspace of ws_bytes >= ts_search_dp_workspace_bytes(),
+ *                 8-byte aligned; overwritten;
+ *   thr           out: int32 [nq][nseg][k], ascending, or all -1;
+ *   obj           out: double [nq][nseg], the objective S (NaN if none);
+ *   status        out: int32 [nq][nseg], TS_PROBLEM_*.
+ * Errors: TS_ERR_INVALID_ARG, TS_ERR_WORKSPACE. */
+ts_status ts_threshold_search_dp(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
+                                 int32_t nq, const double *q, void *ws, size_t ws_bytes, int32_t *thr, double *obj,
+                                 int32_t *status, ts_stream_t stream);
+
 /* Largest number of threshold sets ts_label_sets takes in one call. */
 #define TS_MAX_LABEL_SETS 4
 

@@ -84,8 +84,11 @@ def _load():
     lib.ts_search2d_workspace_bytes.argtypes = [i32, i32, i32]
     lib.ts_search2d_workspace_bytes.restype = sz
     lib.ts_threshold_search2d.argtypes = [P, i32, i32, i32, P, P, sz, P, P, P, P]
+    lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.ts_search_dp_workspace_bytes.restype = sz
+    lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
     for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets,
-              lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d):
+              lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d, lib.ts_threshold_search_dp):
         f.restype = ctypes.c_int
     lib.ts_last_error.argtypes = []
     lib.ts_last_error.restype = ctypes.c_char_p
@@ -236,6 +239,35 @@ def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q, mode: int = SE
     t = _tune(tune, lambda a: a.key_search(nseg * nq, L, k, mode))
     _check(_lib.ts_threshold_search(_ptr(P), _ptr(Q), nseg, L, int(k), nq, _qarr(qs), int(mode), _ptr(ws),
                                     ws.numel(), _ptr(thr), _ptr(obj), _ptr(status), t, _stream(stream)))
+    return thr, obj, status
+
+
+DP_MAX_K = 16
+
+
+def workspace_dp_bytes(nseg: int, nbins: int, k: int, nq: int = 1) -> int:
+    return int(_lib.ts_search_dp_workspace_bytes(nseg, nbins, k, nq))
+
+
+def threshold_search_dp(P: torch.Tensor, Q: torch.Tensor, k: int, q, ws: Optional[torch.Tensor] = None, out=None,
+                        stream=None):
+    """The arg max of threshold_search by dynamic programming, k in 1..DP_MAX_K;
+    outputs as for threshold_search."""
+    nseg, L = P.shape
+    qs, batched = _qs(q)
+    nq = len(qs)
+    lead = (nq,) if batched else ()
+    need = workspace_dp_bytes(nseg, L, k, nq)
+    if ws is None:
+        ws = torch.empty(max(need, 8), dtype=torch.uint8, device=P.device)
+    if out is None:
+        thr = torch.empty(lead + (nseg, k), dtype=torch.int32, device=P.device)
+        obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=P.device)
+        status = torch.empty(lead + (nseg,), dtype=torch.int32, device=P.device)
+    else:
+        thr, obj, status = out
+    _check(_lib.ts_threshold_search_dp(_ptr(P), _ptr(Q), nseg, L, int(k), nq, _qarr(qs), _ptr(ws), ws.numel(),
+                                       _ptr(thr), _ptr(obj), _ptr(status), _stream(stream)))
     return thr, obj, status
 
 

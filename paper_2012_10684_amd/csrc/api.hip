@@ -385,6 +385,43 @@ ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbin
     return launch_search2d(hist, nseg, nbins, nq, q, ws, thr, obj, status, (hipStream_t)stream);
 }
 
+size_t ts_search_dp_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq)
+{
+    if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || k < 1 || k > TS_DP_MAX_K || nq < 1 || nq > TS_MAX_Q)
+        return 0;
+    return dp_workspace_bytes(nseg * nq, nbins, k);
+}
+
+ts_status ts_threshold_search_dp(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
+                                 int32_t nq, const double *q, void *ws, size_t ws_bytes, int32_t *thr, double *obj,
+                                 int32_t *status, ts_stream_t stream)
+{
+    if (nseg < 0)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search_dp: nseg must be >= 0");
+    if (nbins < 2 || nbins > MAX_BINS)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search_dp: nbins must be in [2, 4096]");
+    if (k < 1 || k > TS_DP_MAX_K)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search_dp: k must be in 1.." + std::to_string(TS_DP_MAX_K));
+    if (nbins < k + 1)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search_dp: nbins must be >= k + 1");
+    ts_status st;
+    if ((st = check_q("ts_threshold_search_dp", nq, q, true)) != TS_OK)
+        return st;
+    if ((int64_t)nseg * nq * (nbins - 1) > 0x7fffffff)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search_dp: too many problems");
+    if (nseg > 0 && (!P || !Q || !thr || !obj || !status))
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search_dp: null pointer");
+    const size_t need = dp_workspace_bytes(nseg * nq, nbins, k);
+    if (nseg > 0 && (ws_bytes < need || !ws))
+        return fail(TS_ERR_WORKSPACE, "ts_threshold_search_dp: workspace too small (need " + std::to_string(need) +
+                                          " bytes, got " + std::to_string(ws_bytes) + ")");
+    if (nseg == 0)
+        return TS_OK;
+    if ((uintptr_t)ws & 7)
+        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search_dp: workspace must be 8-byte aligned");
+    return launch_dp(P, Q, nseg, nbins, k, nq, q, ws, thr, obj, status, (hipStream_t)stream);
+}
+
 ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream)
 {
     if (n < 0)

@@ -65,6 +65,9 @@ def _bind(lib):
     lib.ts_search2d_workspace_bytes.argtypes = [i32, i32, i32]
     lib.ts_search2d_workspace_bytes.restype = sz
     lib.ts_threshold_search2d.argtypes = [P, i32, i32, i32, P, P, sz, P, P, P, P]
+    lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.ts_search_dp_workspace_bytes.restype = sz
+    lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
     lib.ts_last_error.restype = ctypes.c_char_p
     return lib
 
@@ -94,6 +97,10 @@ def test_workspace_sizes(lib):
     for bad in [(-1, 256, 1, 1, 0), (1, 1, 1, 1, 0), (1, 4097, 1, 1, 0), (1, 256, 0, 1, 0), (1, 256, 4, 1, 0),
                 (1, 256, 1, 1, 7), (1, 256, 1, 0, 0), (1, 256, 1, 9, 0)]:
         assert ws(*bad) == 0, bad
+    dpws = lib.ts_search_dp_workspace_bytes
+    assert dpws(1, 1024, 4, 1) == 4 * 1024 * 8 and dpws(300, 256, 2, 3) == 2 * 900 * 256 * 8
+    for bad in [(-1, 256, 2, 1), (1, 1, 1, 1), (1, 4097, 1, 1), (1, 256, 0, 1), (1, 256, 17, 1), (1, 256, 2, 0)]:
+        assert dpws(*bad) == 0, bad
 
 
 @pytest.mark.parametrize("case,expect", [
@@ -107,6 +114,7 @@ def test_workspace_sizes(lib):
     ("log2_neg", 1), ("log2_null", 1),
     ("h2d_bins", 1), ("h2d_width", 1), ("h2d_total", 1), ("h2d_null", 1),
     ("s2d_bins", 1), ("s2d_q", 1), ("s2d_ws", 3), ("s2d_null", 1),
+    ("dp_k0", 1), ("dp_k17", 1), ("dp_bins_lt_k1", 1), ("dp_q", 1), ("dp_ws", 3), ("dp_null", 1), ("dp_misaligned", 1),
 ])
 def test_argument_errors(lib, case, expect):
     _bind(lib)
@@ -171,6 +179,14 @@ def test_argument_errors(lib, case, expect):
         ws_bytes = 8 if case == "s2d_ws" else 1 << 40
         st = lib.ts_threshold_search2d(None if case == "s2d_null" else FAKE, 3, L, 1, q, FAKE, ws_bytes, FAKE,
                                        FAKE, FAKE, sx)
+    elif case.startswith("dp_"):
+        k = {"dp_k0": 0, "dp_k17": 17}.get(case, 5)
+        L = 5 if case == "dp_bins_lt_k1" else 512
+        q = qs(0.0) if case == "dp_q" else qs(0.8)
+        ws_bytes = 8 if case == "dp_ws" else 1 << 40
+        ws = ctypes.c_void_p(0x1004) if case == "dp_misaligned" else FAKE
+        st = lib.ts_threshold_search_dp(None if case == "dp_null" else FAKE, FAKE, 2, L, k, 1, q, ws, ws_bytes, FAKE,
+                                        FAKE, FAKE, sx)
     elif case == "log2_neg":
         st = lib.ts_log2_f32(FAKE, FAKE, -1, sx)
     elif case == "log2_null":
@@ -196,6 +212,7 @@ def test_empty_batch_is_a_no_op(lib):
     assert lib.ts_log2_f32(None, None, 0, None) == 0
     assert lib.ts_histogram2d(Batch(None, None, 0, 0), 4, 4, ok_bin, None, None) == 0
     assert lib.ts_threshold_search2d(None, 0, 64, 1, qs(0.8), None, 0, None, None, None, None) == 0
+    assert lib.ts_threshold_search_dp(None, None, 0, 1024, 4, 1, qs(0.8), None, 0, None, None, None, None) == 0
     assert lib.ts_prefix(None, 0, 256, 1, qs(0.8), None, None, None) == 0
     assert lib.ts_threshold_search(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, 0, None, None, None, None,
                                    None) == 0
