@@ -25,6 +25,10 @@ Functions and the passages they follow:
                          3x3 average image, the 2D histogram of (gray level,
                          average gray level), the class entropies over
                          quadrants 1 and 3 and the arg max over (t, s).
+  morph / opening (``morph.c``)
+                      -- Morphology section: gray-scale erosion and dilation
+                         by a flat disk, the opening and the residue
+                         original - opened.
 """
 from __future__ import annotations
 
@@ -37,6 +41,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRC2 = os.path.join(_HERE, "oracle2d.c")
+_SRC3 = os.path.join(_HERE, "morph.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODE_DIRECT = 0
@@ -68,13 +73,13 @@ def compile_source(src, out: str) -> str:
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so."""
     if force or _stale():
-        compile_source([_SRC, _SRC2], _LIB)
+        compile_source([_SRC, _SRC2, _SRC3], _LIB)
     return _LIB
 
 
 def _stale() -> bool:
-    return not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
-                                                                      os.path.getmtime(_SRC2))
+    return not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+        os.path.getmtime(p) for p in (_SRC, _SRC2, _SRC3))
 
 
 def load_library(path: str):
@@ -112,6 +117,11 @@ def _bind(lib):
         lib.or2_objective.restype = f64
         lib.or2_search.argtypes = [P, i32, f64, i32, P, P, P, P]
         lib.or2_search.restype = i32
+    if hasattr(lib, "or_open"):  # mutated copies of the other sources alone lack it
+        lib.or_morph.argtypes = [P, i32, i32, i32, i32, P]
+        lib.or_morph.restype = None
+        lib.or_open.argtypes = [P, i32, i32, i32, P, P, P]
+        lib.or_open.restype = None
     return lib
 
 
@@ -255,3 +265,28 @@ def search2d(h2: np.ndarray, q: float, mode: int = MODE_PREFIX, lib=None) -> Sea
     st = (lib or _load()).or2_search(_ptr(h2), L, float(q), int(mode), ctypes.byref(t), ctypes.byref(s_),
                                       ctypes.byref(obj), ctypes.byref(sec))
     return SearchResult(np.array([t.value, s_.value], dtype=np.int32), obj.value, sec.value, int(st))
+
+
+def morph(f: np.ndarray, r: int, take_max: bool, lib=None) -> np.ndarray:
+    """Gray-scale erosion (take_max False) or dilation by the disk of radius r
+    (pixels outside the image take no part)."""
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    H, W = f.shape
+    out = np.empty_like(f)
+    (lib or _load()).or_morph(_ptr(f), H, W, int(r), int(bool(take_max)), _ptr(out))
+    return out
+
+
+def opening(f: np.ndarray, r: int, lib=None):
+    """(opened, residue = f - opened) of the gray image f by the disk of radius r."""
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    H, W = f.shape
+    tmp, opened, residue = np.empty_like(f), np.empty_like(f), np.empty_like(f)
+    (lib or _load()).or_open(_ptr(f), H, W, int(r), _ptr(tmp), _ptr(opened), _ptr(residue))
+    return opened, residue
+
+
+def gray(img: np.ndarray, lo: int, hi: int, L: int, lib=None) -> np.ndarray:
+    """Gray levels of an int16 image under the bin map (same shape)."""
+    v = np.ascontiguousarray(img, dtype=np.int16)
+    return bin_map(v.reshape(-1), lo, hi, L, lib=lib).reshape(v.shape)
