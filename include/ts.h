@@ -282,6 +282,31 @@ ts_status ts_threshold_search_dp(const double *P, const double *Q, int32_t nseg,
                                  int32_t nq, const double *q, void *ws, size_t ws_bytes, int32_t *thr, double *obj,
                                  int32_t *status, ts_stream_t stream);
 
+/* Largest disk radius ts_open2d takes. */
+#define TS_MORPH_MAX_RADIUS 32
+
+/* [host] Bytes of workspace ts_open2d needs: one byte per pixel. */
+size_t ts_open2d_workspace_bytes(int32_t nseg, int32_t height, int32_t width);
+
+/* ts_open2d -- the morphology step before thresholding (Morphology section):
+ * gray-scale opening of each image's gray levels (the ts_binning rule) by a
+ * flat disk of the given radius, B = {(dx, dy) : dx^2 + dy^2 <= radius^2}:
+ * erosion (the minimum under B), then dilation (the maximum under B) of the
+ * result; pixels outside the image take no part.  The residue
+ * gray - opened (>= 0) is the image with the structures wider than the disk
+ * (the chest) removed.
+ *   batch   nseg images of height x width int16 pixels, row-major (one
+ *           pointer per image; total = nseg * height * width);
+ *   bin     [host] the binning; nbins <= 256;
+ *   radius  0..TS_MORPH_MAX_RADIUS (the paper's disk: 10);
+ *   ws      device workspace of ws_bytes >= ts_open2d_workspace_bytes()
+ *           (the eroded images); overwritten;
+ *   opened  out: uint8 [nseg][height][width], or NULL;
+ *   residue out: uint8 [nseg][height][width], or NULL (not both NULL).
+ * Errors: TS_ERR_INVALID_ARG, TS_ERR_WORKSPACE. */
+ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, int32_t radius, void *ws,
+                    size_t ws_bytes, uint8_t *opened, uint8_t *residue, ts_stream_t stream);
+
 /* Largest number of threshold sets ts_label_sets takes in one call. */
 #define TS_MAX_LABEL_SETS 4
 

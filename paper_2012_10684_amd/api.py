@@ -84,11 +84,15 @@ def _load():
     lib.ts_search2d_workspace_bytes.argtypes = [i32, i32, i32]
     lib.ts_search2d_workspace_bytes.restype = sz
     lib.ts_threshold_search2d.argtypes = [P, i32, i32, i32, P, P, sz, P, P, P, P]
+    lib.ts_open2d_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.ts_open2d_workspace_bytes.restype = sz
+    lib.ts_open2d.argtypes = [_Batch, i32, i32, Binning, i32, P, sz, P, P, P]
     lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
     lib.ts_search_dp_workspace_bytes.restype = sz
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
     for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets,
-              lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d, lib.ts_threshold_search_dp):
+              lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d, lib.ts_threshold_search_dp,
+              lib.ts_open2d):
         f.restype = ctypes.c_int
     lib.ts_last_error.argtypes = []
     lib.ts_last_error.restype = ctypes.c_char_p
@@ -243,6 +247,28 @@ def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q, mode: int = SE
 
 
 DP_MAX_K = 16
+MORPH_MAX_RADIUS = 32
+
+
+def open2d(batch: Batch, height: int, width: int, bin: Binning, radius: int = 10, ws: Optional[torch.Tensor] = None,
+           opened: Optional[torch.Tensor] = None, residue: Optional[torch.Tensor] = None, want=("opened", "residue"),
+           stream=None):
+    """Gray-scale opening of each image by a flat disk (uint8 [nseg, H, W]) and
+    the residue gray - opened; returns (opened, residue), None for an output
+    not wanted."""
+    dev = batch.ptrs.device
+    shape = (batch.nseg, height, width)
+    if opened is None and "opened" in want:
+        opened = torch.empty(shape, dtype=torch.uint8, device=dev)
+    if residue is None and "residue" in want:
+        residue = torch.empty(shape, dtype=torch.uint8, device=dev)
+    need = int(_lib.ts_open2d_workspace_bytes(batch.nseg, height, width))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(_lib.ts_open2d(batch._c, height, width, bin, int(radius), _ptr(ws), ws.numel(),
+                          _ptr(opened) if opened is not None else None,
+                          _ptr(residue) if residue is not None else None, _stream(stream)))
+    return opened, residue
 
 
 def workspace_dp_bytes(nseg: int, nbins: int, k: int, nq: int = 1) -> int:

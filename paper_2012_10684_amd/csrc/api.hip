@@ -422,6 +422,41 @@ ts_status ts_threshold_search_dp(const double *P, const double *Q, int32_t nseg,
     return launch_dp(P, Q, nseg, nbins, k, nq, q, ws, thr, obj, status, (hipStream_t)stream);
 }
 
+size_t ts_open2d_workspace_bytes(int32_t nseg, int32_t height, int32_t width)
+{
+    if (nseg < 0 || height < 1 || width < 1)
+        return 0;
+    return open2d_workspace_bytes(nseg, height, width);
+}
+
+ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, int32_t radius, void *ws,
+                    size_t ws_bytes, uint8_t *opened, uint8_t *residue, ts_stream_t stream)
+{
+    ts_status st = check_batch(batch);
+    if (st != TS_OK)
+        return st;
+    BinMap bm;
+    if ((st = make_binmap(bin, &bm)) != TS_OK)
+        return st;
+    if (bin.nbins > 256)
+        return fail(TS_ERR_INVALID_ARG, "ts_open2d: nbins must be <= 256 (8-bit gray levels)");
+    if (radius < 0 || radius > TS_MORPH_MAX_RADIUS)
+        return fail(TS_ERR_INVALID_ARG, "ts_open2d: radius must be in 0.." + std::to_string(TS_MORPH_MAX_RADIUS));
+    if (height < 1 || width < 1)
+        return fail(TS_ERR_INVALID_ARG, "ts_open2d: need height >= 1 and width >= 1");
+    if (batch.total != (int64_t)batch.nseg * height * width)
+        return fail(TS_ERR_INVALID_ARG, "ts_open2d: total must be nseg * height * width");
+    if (batch.nseg > 0 && !opened && !residue)
+        return fail(TS_ERR_INVALID_ARG, "ts_open2d: opened and residue are both null");
+    const size_t need = open2d_workspace_bytes(batch.nseg, height, width);
+    if (batch.nseg > 0 && (ws_bytes < need || !ws))
+        return fail(TS_ERR_WORKSPACE, "ts_open2d: workspace too small (need " + std::to_string(need) + " bytes, got " +
+                                          std::to_string(ws_bytes) + ")");
+    if (batch.nseg == 0)
+        return TS_OK;
+    return launch_open2d(batch, height, width, bm, radius, (uint8_t *)ws, opened, residue, (hipStream_t)stream);
+}
+
 ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream)
 {
     if (n < 0)

@@ -1,0 +1,143 @@
+// k_morph.hip -- the paper's morphology step (Morphology section): gray-scale
+// erosion (minimum) and dilation (maximum) of the gray-level image under a
+// flat disk B = {(dx, dy) : dx^2 + dy^2 <= r^2}, the opening (dilation of the
+// erosion) and the residue original - opened that removes the large bright
+// chest structures.  Pixels outside the image take no part.
+//
+// One workgroup per 64 x 64 output tile of one image.  The tile and a halo of
+// r pixels are staged in LDS (gray levels; outside the image the neutral
+// value, 255 for the minimum and 0 for the maximum).  The disk is the union
+// over row offsets dy of horizontal runs of half-width w(dy) =
+// floor(sqrt(r^2 - dy^2)); w grows as |dy| falls, so a row buffer H holds
+// the horizontal minimum (maximum) of half-width w for every staged row and
+// is widened in place, one distinct w at a time, and each output takes the
+// minimum (maximum) of H at rows y - |dy| and y + |dy| when w = w(dy).  Per
+// output pixel: about 2r (1 + 2r / 64) LDS reads to widen H and 2r + 1 to
+// combine, for each of the two passes.
+#include "common.h"
+
+namespace ts {
+
+constexpr int MO_TX = 64, MO_TY = 64, MO_THREADS = 256;
+constexpr int MO_PER = MO_TX * MO_TY / MO_THREADS; // outputs per thread
+constexpr int MO_SW = MO_TX + 2 * TS_MORPH_MAX_RADIUS;  // largest staged row
+constexpr int MO_SH = MO_TY + 2 * TS_MORPH_MAX_RADIUS;  // largest staged column
+
+__device__ __forceinline__ int isqrt_floor(int n)
+{
+    int w = (int)sqrt((double)n);
+    while (w * w > n)
+        --w;
+    while ((w + 1) * (w + 1) <= n)
+        ++w;
+    return w;
+}
+
+// MAXOP = false: erosion of the gray levels of the int16 images (src16,
+// binned) into dst; MAXOP = true: dilation of the uint8 images src8 into dst
+// and/or the residue gray(src16) - dilation into res.
+template <bool MAXOP, int MAP>
+__global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__restrict__ src16,
+                                                      const uint8_t *__restrict__ src8, int H, int W, int r,
+                                                      BinMap bm, uint8_t *__restrict__ dst, uint8_t *__restrict__ res)
+{
+    __shared__ uint8_t in[MO_SH * MO_SW];
+    __shared__ uint8_t hr[MO_SH * MO_TX];
+    const int tiles_x = (W + MO_TX - 1) / MO_TX, tiles_y = (H + MO_TY - 1) / MO_TY;
+    const int s = blockIdx.x / (tiles_x * tiles_y);
+    const int tile = blockIdx.x % (tiles_x * tiles_y);
+    const int x0 = (tile % tiles_x) * MO_TX, y0 = (tile / tiles_x) * MO_TY;
+    const int sw = MO_TX + 2 * r, sh = MO_TY + 2 * r;
+    const uint8_t neutral = MAXOP ? 0 : 255;
+    const int64_t img_off = (int64_t)s * H * W;
+    const TS_GLOBAL int16_t *img16 = gp(src16[s]);
+    // stage the tile and its halo
+    for (int i = threadIdx.x; i < sh * sw; i += blockDim.x) {
+        const int row = i / sw, col = i - row * sw;
+        const int y = y0 - r + row, x = x0 - r + col;
+        uint8_t v = neutral;
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            if (MAXOP)
+                v = src8[img_off + (int64_t)y * W + x];
+            else
+                v = (uint8_t)bin_of_t<MAP>(img16[(int64_t)y * W + x], bm);
+        }
+        in[i] = v;
+    }
+    __syncthreads();
+    // half-width 0: the staged pixel itself
+    for (int i = threadIdx.x; i < sh * MO_TX; i += blockDim.x) {
+        const int row = i / MO_TX, c = i - row * MO_TX;
+        hr[i] = in[row * sw + c + r];
+    }
+    const int c = threadIdx.x % MO_TX, yb = threadIdx.x / MO_TX; // outputs (yb + 4 i, c)
+    uint8_t out[MO_PER];
+#pragma unroll
+    for (int i = 0; i < MO_PER; ++i)
+        out[i] = neutral;
+    int cur = 0;
+    for (int a = r; a >= 0; --a) {
+        const int w = isqrt_floor(r * r - a * a);
+        __syncthreads(); // the previous combine step has read hr
+        if (w > cur) {   // widen every staged row from half-width cur to w
+            for (int i = threadIdx.x; i < sh * MO_TX; i += blockDim.x) {
+                const int row = i / MO_TX, cc = i - row * MO_TX;
+                const uint8_t *rin = in + row * sw + cc + r;
+                int v = hr[i];
+                for (int d = cur + 1; d <= w; ++d) {
+                    const int lft = rin[-d], rgt = rin[d];
+                    v = MAXOP ? max(v, max(lft, rgt)) : min(v, min(lft, rgt));
+                }
+                hr[i] = (uint8_t)v;
+            }
+            cur = w;
+            __syncthreads();
+        }
+        // rows y - a and y + a of every output take half-width w(a)
+#pragma unroll
+        for (int i = 0; i < MO_PER; ++i) {
+            const int yy = yb + 4 * i + r; // staged row of the output
+            const int lo = hr[(yy - a) * MO_TX + c], hi = hr[(yy + a) * MO_TX + c];
+            const int v = MAXOP ? max((int)out[i], max(lo, hi)) : min((int)out[i], min(lo, hi));
+            out[i] = (uint8_t)v;
+        }
+    }
+    const int x = x0 + c;
+    if (x >= W)
+        return;
+#pragma unroll
+    for (int i = 0; i < MO_PER; ++i) {
+        const int y = y0 + yb + 4 * i;
+        if (y >= H)
+            continue;
+        const int64_t o = img_off + (int64_t)y * W + x;
+        if (dst)
+            dst[o] = out[i];
+        if (MAXOP && res) {
+            const int f = bin_of_t<MAP>(img16[(int64_t)y * W + x], bm);
+            res[o] = (uint8_t)(f - (int)out[i]);
+        }
+    }
+}
+
+size_t open2d_workspace_bytes(int nseg, int H, int W) { return (size_t)nseg * H * W; }
+
+ts_status launch_open2d(const ts_batch &b, int H, int W, const BinMap &bm, int r, uint8_t *eroded,
+                        uint8_t *opened, uint8_t *residue, hipStream_t st)
+{
+    const int tiles = ((W + MO_TX - 1) / MO_TX) * ((H + MO_TY - 1) / MO_TY);
+    const dim3 g((unsigned)((int64_t)b.nseg * tiles)), blk(MO_THREADS);
+#define TS_MO(M)                                                                                                     \
+    hipLaunchKernelGGL((k_morph<false, M>), g, blk, 0, st, b.vox, nullptr, H, W, r, bm, eroded, nullptr);           \
+    hipLaunchKernelGGL((k_morph<true, M>), g, blk, 0, st, b.vox, eroded, H, W, r, bm, opened, residue)
+    switch (map_kind(bm)) {
+    case 0: TS_MO(0); break;
+    case 1: TS_MO(1); break;
+    case 2: TS_MO(2); break;
+    default: TS_MO(3); break;
+    }
+#undef TS_MO
+    return check_launch("ts_open2d");
+}
+
+} // namespace ts
