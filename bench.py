@@ -51,6 +51,9 @@ WORKLOADS = {
                      "of (gray level, 3x3 average gray level) over [-1024,-200], FP64 arg max over threshold pairs "
                      "(t, s) for q in {0.5,0.8,1.5}, labels from t for each q", True, -1024, -200, 256, 1,
                      (0.5, 0.8, 1.5)),
+    "volume300_open": ("volume 512x512x300 int16, the paper's morphology step per slice: gray levels over "
+                       "[-1024,-200] (256), opening by a flat disk of radius 10 (erosion, then dilation), opened "
+                       "image and residue gray - opened", True, -1024, -200, 256, 0, ()),
     "serving": ("Poisson trace, 20 volumes/s, half 256x256xU{60..300} and half 512x512xU{120..600}; per volume "
                 "512-bin histogram over [-1024,3071], k=3, q=0.8, labels back in host memory",
                 False, -1024, 3071, 512, 3, (0.8,)),
@@ -174,6 +177,61 @@ def bench_serving(args, wl, trace, jobs, vols):
     print(json.dumps(line), flush=True)
 
 
+def bench_open(args, wl, dev):
+    import numpy as np
+    import torch
+
+    from paper_2012_10684_amd import api, synth
+
+    desc, _, LO, HI, L, _, _ = wl
+    R = 10
+    vol = synth.workload_volume300(0)
+    Z, H, W = vol.shape
+    dv = torch.from_numpy(vol).to(dev)
+    batch = api.Batch.slices(dv)
+    binn = api.binning(LO, HI, L)
+    opened = torch.empty((Z, H, W), dtype=torch.uint8, device=dev)
+    residue = torch.empty_like(opened)
+    ws = torch.empty(Z * H * W, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        api.open2d(batch, H, W, binn, R, ws=ws, opened=opened, residue=residue, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e in ev:
+        e[0].record(stream)
+        step()
+        e[1].record(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    avg = sum(a.elapsed_time(b) for a, b in ev) * 1e-3 / len(ev)
+    nvox = int(vol.size)
+    # algorithmic work: every output is the minimum (then maximum) of the pixels under the disk
+    disk = sum(1 for dy in range(-R, R + 1) for dx in range(-R, R + 1) if dx * dx + dy * dy <= R * R)
+    ops = 2 * nvox * (disk - 1)
+    alg = 8 * nvox  # 2 B in + 1 B eroded out; 1 B eroded in + 2 B in (residue) + 1 B opened + 1 B residue out
+    line = {
+        "metric": "voxels/s (morphology step: opening by a disk of radius 10 + residue)",
+        "value": nvox * args.steps / dt, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": desc, "images": Z, "voxels": nvox, "radius": R, "disk_pixels": disk},
+        "roofline": {"bound": "hbm", "kernel": "k_morph (erosion + dilation)", "achieved": alg / avg / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6,
+                     "note": "the HBM side of the step (8 B per pixel over both passes); the kernels are bound by "
+                             "LDS byte reads, about 2r (1 + 2r / 64) + 2r + 2 per output per pass"},
+        "lds_reads_per_pixel": 2 * (2 * R * (1 + 2 * R / 64) + 2 * R + 2),
+        "min_max_ops_naive": ops,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_2d(args, wl, dev):
     import numpy as np
     import torch
@@ -285,6 +343,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "volume300_2d":
         return bench_2d(args, WORKLOADS[args.workload], dev)
+    if args.workload == "volume300_open":
+        return bench_open(args, WORKLOADS[args.workload], dev)
     if args.calibrate:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
