@@ -101,31 +101,52 @@ def load_traffic(kernel_file: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(vol, nslices: int, wl):
+def cpu_baseline(vol, nslices: int, wl, gpu_thr=None, gpu_obj=None):
+    """The oracle timed on a sample of the workload; with the GPU's thresholds
+    and objectives ([nq][problem][k], [nq][problem]) also their agreement on
+    that sample (the objective error per configuration)."""
     import numpy as np
     import oracle
 
     _, per_slice, LO, HI, L, K, QS = wl
+    refs = []
     t0 = time.perf_counter()
     if per_slice:
         sample = vol[:nslices]
         for z in range(sample.shape[0]):
             h = oracle.histogram(sample[z], LO, HI, L)
-            for q in QS:
+            for j, q in enumerate(QS):
                 r = oracle.search(h, K, q, oracle.MODE_PREFIX)
                 oracle.label(sample[z].reshape(-1), LO, HI, L, r.thr)
+                refs.append((j, z, r))
         what = f"{sample.shape[0]} of the {vol.shape[0]} slices: oracle histogram + {len(QS)} x (prefix-mode k={K} search + labels)"
     else:
         sample = vol
         h = oracle.histogram(sample, LO, HI, L)
-        for q in QS:
+        for j, q in enumerate(QS):
             r = oracle.search(h, K, q, oracle.MODE_PREFIX)
             oracle.label(sample.reshape(-1), LO, HI, L, r.thr)
+            refs.append((j, 0, r))
         what = f"the whole input: oracle histogram + prefix-mode k={K} search + labels"
     dt = time.perf_counter() - t0
     nvox = int(np.prod(sample.shape))
-    return {"value": nvox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+    base = {"value": nvox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
             "sample": f"{what}, {dt:.2f} s single-threaded"}
+    check = None
+    if gpu_thr is not None:
+        same, err, near = 0, 0.0, 0
+        for j, z, r in refs:
+            if r.status != oracle.OK:
+                continue
+            t = [int(x) for x in gpu_thr[j][z]]
+            if t == r.thr.tolist():
+                same += 1
+            elif r.rel_gap() < 1e-6:
+                near += 1
+            err = max(err, abs(float(gpu_obj[j][z]) - r.obj) / abs(r.obj))
+        check = {"problems": len(refs), "thresholds_identical": same, "differing_within_1e-6_gap": near,
+                 "max_rel_objective_error": err}
+    return base, check
 
 
 def _gen(job):
@@ -561,7 +582,8 @@ def main():
         line["batched_speedup_vs_per_slice_launches"] = per_slice_s * nseg / (dt / args.steps)
         line["per_slice_sample"] = m
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(vol, args.cpu_slices, wl)
+        line["cpu_baseline"], line["oracle_check"] = cpu_baseline(vol, args.cpu_slices, wl, res[0].cpu().numpy(),
+                                                                  res[1].cpu().numpy())
     print(json.dumps(line), flush=True)
 
 
