@@ -192,12 +192,17 @@ ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, in
                               int32_t nq, const double *q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr,
                               double *obj, int32_t *status, const ts_tuning *tune, ts_stream_t stream);
 
+/* Largest number of thresholds ts_threshold_search_dp finds and ts_label /
+ * ts_label_sets apply. */
+#define TS_DP_MAX_K 16
+
 /* ts_label -- thresholding kernel function (Algorithm 1) with k thresholds:
  * a voxel whose gray level (ts_binning rule) is b gets the label
  * #{j : b > t_j} (0..k); for k = 1 this is 1 iff b >= T with T = t + 1.
  *   batch  problems to label (same layout as for ts_histogram);
  *   bin    [host] the binning used for the histogram;
- *   thr    int32 [nseg][k] from ts_threshold_search.  A row that is not
+ *   k      1..TS_DP_MAX_K;
+ *   thr    int32 [nseg][k] from ts_threshold_search(_dp).  A row that is not
  *          strictly ascending within [0, nbins-2] (e.g. the all -1 row of a
  *          degenerate problem) labels its whole problem 0;
  *   out    device array [nseg] of device pointers; problem s writes
@@ -250,9 +255,6 @@ size_t ts_search2d_workspace_bytes(int32_t nseg, int32_t nbins, int32_t nq);
 ts_status ts_threshold_search2d(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t nq, const double *q,
                                 void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status,
                                 ts_stream_t stream);
-
-/* Largest number of thresholds ts_threshold_search_dp takes. */
-#define TS_DP_MAX_K 16
 
 /* [host] Bytes of workspace ts_threshold_search_dp needs (0 if invalid):
  * k * nq * nseg * nbins doubles. */

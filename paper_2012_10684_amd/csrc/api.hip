@@ -297,8 +297,8 @@ static ts_status label_common(const char *fn, ts_batch batch, ts_binning bin, in
     BinMap bm;
     if ((st = make_binmap(bin, &bm)) != TS_OK)
         return st;
-    if (k < 1 || k > 3)
-        return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": k must be 1, 2 or 3");
+    if (k < 1 || k > TS_DP_MAX_K)
+        return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": k must be in 1.." + std::to_string(TS_DP_MAX_K));
     if (nsets < 1 || nsets > TS_MAX_LABEL_SETS)
         return fail(TS_ERR_INVALID_ARG, std::string(fn) + ": nsets must be 1.." + std::to_string(TS_MAX_LABEL_SETS));
     LabelSets sets = {};

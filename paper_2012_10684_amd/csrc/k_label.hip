@@ -17,49 +17,66 @@ namespace ts {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
+// Cut values of one threshold set: label = #{j : v >= c[j]}.  KM = 3 holds
+// k <= 3 thresholds, KM = LABEL_MAX_K up to that many; unused cuts are never
+// reached.
+constexpr int LABEL_MAX_K = TS_DP_MAX_K;
+
+template <int KM>
 struct Cuts {
-    int c0, c1, c2; // label = [v >= c0] + [v >= c1] + [v >= c2]
+    int c[KM];
 };
 
 // Cut values of problem s; a row that is not a strictly ascending tuple in
 // [0, L-2] (e.g. the -1 row of a degenerate problem) gives no cuts (all 0).
-__device__ __forceinline__ Cuts make_cuts(const int32_t *thr, int k, const BinMap &bm)
+template <int KM>
+__device__ __forceinline__ Cuts<KM> make_cuts(const int32_t *thr, int k, const BinMap &bm)
 {
     const int NEVER = 0x7fffffff;
-    Cuts c = {NEVER, NEVER, NEVER};
-    int t[3] = {-1, -1, -1};
+    Cuts<KM> c;
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+        c.c[j] = NEVER;
+    int t[KM];
     bool ok = true;
-    for (int j = 0; j < k; ++j) {
-        t[j] = thr[j];
-        ok = ok && t[j] >= 0 && t[j] <= bm.L - 2 && (j == 0 || t[j] > t[j - 1]);
+#pragma unroll
+    for (int j = 0; j < KM; ++j) { // static indices: the arrays stay in registers
+        t[j] = j < k ? thr[j] : 0;
+        if (j < k)
+            ok = ok && t[j] >= 0 && t[j] <= bm.L - 2 && (j == 0 || t[j] > t[j > 0 ? j - 1 : 0]);
     }
     if (!ok)
         return c;
     // (t+1) W + L - 1 <= 4095 * 65536 + 4095 < 2^32: exact in uint32
     const uint32_t W = (uint32_t)((int64_t)bm.hi - bm.lo + 1);
-    int cc[3] = {NEVER, NEVER, NEVER};
-    for (int j = 0; j < k; ++j)
-        cc[j] = bm.lo + (int)(((uint32_t)(t[j] + 1) * W + (uint32_t)bm.L - 1) / (uint32_t)bm.L);
-    c.c0 = cc[0];
-    c.c1 = cc[1];
-    c.c2 = cc[2];
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+        if (j < k)
+            c.c[j] = bm.lo + (int)(((uint32_t)(t[j] + 1) * W + (uint32_t)bm.L - 1) / (uint32_t)bm.L);
     return c;
 }
 
-__device__ __forceinline__ uint32_t lab1(int v, const Cuts &c)
+template <int KM>
+__device__ __forceinline__ uint32_t lab1(int v, const Cuts<KM> &c)
 {
-    return (uint32_t)(v >= c.c0) + (uint32_t)(v >= c.c1) + (uint32_t)(v >= c.c2);
+    uint32_t n = 0; // unused cuts are never reached (0x7fffffff > any int16)
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+        n += (uint32_t)(v >= c.c[j]);
+    return n;
 }
 
 // labels of the two int16 in a dword, packed as bytes 0 and 1 of the result
-__device__ __forceinline__ uint32_t lab2(uint32_t w, const Cuts &c)
+template <int KM>
+__device__ __forceinline__ uint32_t lab2(uint32_t w, const Cuts<KM> &c)
 {
     int v0 = (int)(int16_t)(w & 0xffffu);
     int v1 = (int)(int16_t)(w >> 16);
     return lab1(v0, c) | (lab1(v1, c) << 8);
 }
 
-__device__ __forceinline__ v2u lab8(const v4i &w, const Cuts &c)
+template <int KM>
+__device__ __forceinline__ v2u lab8(const v4i &w, const Cuts<KM> &c)
 {
     uint32_t a = lab2((uint32_t)w.x, c) | (lab2((uint32_t)w.y, c) << 16);
     uint32_t b = lab2((uint32_t)w.z, c) | (lab2((uint32_t)w.w, c) << 16);
@@ -81,11 +98,14 @@ __device__ __forceinline__ int guess_segment(const int64_t *offs, int nseg, int6
 // Cut values of problem s for every set, computed by one lane per (set,
 // threshold) and broadcast through readlane (wavefront-uniform results).
 // (t+1) W <= 4095 * 65536 < 2^32, so the ceiling division is exact in uint32.
-template <int NS>
-__device__ __forceinline__ void wave_cuts(const LabelSets &sets, int s, int k, const BinMap &bm, Cuts (&cuts)[NS])
+// NS * KM <= 64 lanes.
+template <int NS, int KM>
+__device__ __forceinline__ void wave_cuts(const LabelSets &sets, int s, int k, const BinMap &bm,
+                                          Cuts<KM> (&cuts)[NS])
 {
+    static_assert(NS * KM <= 64, "one lane per (set, threshold)");
     const int lane = threadIdx.x & 63;
-    const int u = lane / 3, j = lane % 3;
+    const int u = lane / KM, j = lane % KM;
     int c = 0x7fffffff;
     if (u < NS && j < k) {
         const int32_t *t = sets.thr[u] + (int64_t)s * k;
@@ -99,9 +119,9 @@ __device__ __forceinline__ void wave_cuts(const LabelSets &sets, int s, int k, c
     }
 #pragma unroll
     for (int u2 = 0; u2 < NS; ++u2) {
-        cuts[u2].c0 = __builtin_amdgcn_readlane(c, 3 * u2);
-        cuts[u2].c1 = __builtin_amdgcn_readlane(c, 3 * u2 + 1);
-        cuts[u2].c2 = __builtin_amdgcn_readlane(c, 3 * u2 + 2);
+#pragma unroll
+        for (int j2 = 0; j2 < KM; ++j2) // up to 64 values: vector registers beyond the 3-cut case
+            cuts[u2].c[j2] = KM == 3 ? __builtin_amdgcn_readlane(c, KM * u2 + j2) : __shfl(c, KM * u2 + j2, 64);
     }
 }
 
@@ -112,7 +132,7 @@ __device__ __forceinline__ void wave_cuts(const LabelSets &sets, int s, int k, c
 // labelled with vector accesses; any other tile voxel by voxel.  A one-shot
 // grid keeps the voxels in flight at any time in one window of HBM, which
 // streams faster on MI355X than long per-workgroup ranges.
-template <int NS, int U>
+template <int NS, int U, int KM>
 __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict__ vox,
                                                 const int64_t *__restrict__ offs, int nseg, int64_t total, BinMap bm,
                                                 LabelSets sets, int k)
@@ -129,8 +149,8 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
 #pragma unroll
     for (int u = 0; u < NS; ++u)
         os[u] = sets.out[u][s];
-    Cuts cuts[NS];
-    wave_cuts<NS>(sets, s, k, bm, cuts);
+    Cuts<KM> cuts[NS];
+    wave_cuts<NS, KM>(sets, s, k, bm, cuts);
     if (!(o0 <= t0 && t0 < o1)) {
         s = find_segment(offs, nseg, t0);
         while (s + 1 < nseg && offs[s + 1] <= t0) // skip empty segments
@@ -141,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
 #pragma unroll
         for (int u = 0; u < NS; ++u)
             os[u] = sets.out[u][s];
-        wave_cuts<NS>(sets, s, k, bm, cuts);
+        wave_cuts<NS, KM>(sets, s, k, bm, cuts);
     }
     if (t1 <= o1) { // the whole tile lies in segment s
         const TS_GLOBAL int16_t *src = gp(vs) + (t0 - o0);
@@ -198,20 +218,32 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
         const int v = gp(vox[sv])[i];
 #pragma unroll
         for (int u = 0; u < NS; ++u)
-            gpw(sets.out[u][sv])[i] = (uint8_t)lab1(v, make_cuts(sets.thr[u] + (int64_t)sv * k, k, bm));
+            gpw(sets.out[u][sv])[i] = (uint8_t)lab1(v, make_cuts<KM>(sets.thr[u] + (int64_t)sv * k, k, bm));
     }
 }
 
-template <int NS>
+template <int NS, int KM>
 static void launch_label_ns(int U, dim3 g, dim3 blk, hipStream_t st, const ts_batch &b, const BinMap &bm,
                             const LabelSets &sets, int k)
 {
     if (U == 1)
-        hipLaunchKernelGGL((k_label<NS, 1>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
+        hipLaunchKernelGGL((k_label<NS, 1, KM>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
     else if (U == 2)
-        hipLaunchKernelGGL((k_label<NS, 2>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
+        hipLaunchKernelGGL((k_label<NS, 2, KM>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
     else
-        hipLaunchKernelGGL((k_label<NS, 4>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
+        hipLaunchKernelGGL((k_label<NS, 4, KM>), g, blk, 0, st, b.vox, b.offs, b.nseg, b.total, bm, sets, k);
+}
+
+template <int KM>
+static void launch_label_km(int nsets, int U, dim3 g, dim3 blk, hipStream_t st, const ts_batch &b, const BinMap &bm,
+                            const LabelSets &sets, int k)
+{
+    switch (nsets) {
+    case 1: launch_label_ns<1, KM>(U, g, blk, st, b, bm, sets, k); break;
+    case 2: launch_label_ns<2, KM>(U, g, blk, st, b, bm, sets, k); break;
+    case 3: launch_label_ns<3, KM>(U, g, blk, st, b, bm, sets, k); break;
+    default: launch_label_ns<4, KM>(U, g, blk, st, b, bm, sets, k); break;
+    }
 }
 
 ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &sets, int nsets, int k, const Tune &t,
@@ -224,12 +256,10 @@ ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &set
     if (grid > 0x7fffffff)
         return fail(TS_ERR_INVALID_ARG, "ts_label: batch too large for one launch");
     const dim3 g((unsigned)grid), blk(t.label_block);
-    switch (nsets) {
-    case 1: launch_label_ns<1>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
-    case 2: launch_label_ns<2>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
-    case 3: launch_label_ns<3>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
-    default: launch_label_ns<4>(t.label_vecs, g, blk, st, b, bm, sets, k); break;
-    }
+    if (k <= 3)
+        launch_label_km<3>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k);
+    else
+        launch_label_km<LABEL_MAX_K>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k);
     return check_launch("ts_label");
 }
 

@@ -213,7 +213,7 @@ def test_argument_errors(lib, case, expect):
         if case == "sets_null_entry":
             outp[1] = None
         arr = None if case == "sets_null_array" else ctypes.cast(thr, T)
-        st = lib.ts_label_sets(b1, ok_bin, n, arr, 4 if case == "sets_k" else 2, ctypes.cast(outp, T), None, sx)
+        st = lib.ts_label_sets(b1, ok_bin, n, arr, 17 if case == "sets_k" else 2, ctypes.cast(outp, T), None, sx)
     assert st == expect, (case, st, lib.ts_last_error())
     assert lib.ts_last_error(), "an error text must be set"
 

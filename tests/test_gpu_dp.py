@@ -150,4 +150,9 @@ def test_dp_k4_whole_volume_histogram(q):
     assert abs(obj[0] - want) <= 1e-9 * abs(want), (obj[0], want)
     s_or = oracle.objective(H[0], thr[0], q, oracle.MODE_PREFIX)
     assert abs(s_or - want) <= 1e-9 * abs(want), (thr[0], s_or, want)
+    # the four thresholds label the volume (labels 0..4)
+    dv = to_dev(vol).reshape(-1)
+    lab = api.label(api.Batch([dv]), binn, to_dev(thr), 4)[0]
+    torch.cuda.synchronize()
+    assert np.array_equal(lab.cpu().numpy(), oracle.label(vol.reshape(-1), -1024, 3071, 1024, thr[0]))
     say(f"k=4 q={q}: thresholds {thr[0].tolist()} S={obj[0]!r}")

@@ -261,6 +261,32 @@ def test_label_ragged(ragged):
                 assert np.array_equal(outs[i].cpu().numpy(), want), (lo, hi, L, k, i)
 
 
+@pytest.mark.parametrize("k", [4, 7, 16])
+def test_label_many_thresholds_ragged(ragged, k):
+    """k >= 4 thresholds (the DP search's range): labels 0..k bit-exact on
+    ragged, unaligned problems, alone and as several sets in one pass."""
+    host, base, segs = ragged
+    rng = np.random.default_rng(60 + k)
+    b = api.Batch(segs)
+    for lo, hi, L in [(-1024, 3071, 4096), (-1024, -200, 256), (-5, 7, 13), (3, 1000, 7)]:
+        if L - 1 < k:
+            continue
+        thrs = []
+        for u in range(3):
+            thr = np.stack([np.sort(rng.choice(L - 1, k, replace=False)) for _ in segs]).astype(np.int32)
+            thr[(u + 2) % len(segs)] = -1  # degenerate row
+            thrs.append(thr)
+        one = api.label(b, api.binning(lo, hi, L), to_dev(thrs[0]), k)
+        sets = api.label_sets(b, api.binning(lo, hi, L), [to_dev(t) for t in thrs], k)
+        torch.cuda.synchronize()
+        for i, sg in enumerate(segs):
+            v = sg.cpu().numpy()
+            assert np.array_equal(one[i].cpu().numpy(), oracle.label(v, lo, hi, L, thrs[0][i])), (lo, hi, L, k, i)
+            for u in range(3):
+                want = oracle.label(v, lo, hi, L, thrs[u][i])
+                assert np.array_equal(sets[u][i].cpu().numpy(), want), (lo, hi, L, k, u, i)
+
+
 def test_label_misaligned_output():
     v = to_dev(synth.workload_slice(3).reshape(-1))
     out_buf = torch.empty(v.numel() + 16, dtype=torch.uint8, device=v.device)
