@@ -490,12 +490,26 @@ __device__ __forceinline__ void for_rows(const S2 &p, const int *rows, int k0, i
     }
 }
 
+// Maximum over the wavefront by DPP moves (no LDS round trips): within rows
+// of 16 lanes, then carried by the broadcasts of lanes 15 and 31; lanes
+// without a source read -inf.  The result is read from lane 63.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_max_step(float v)
+{
+    const int ninf = __float_as_int(-INFINITY);
+    const float o = __int_as_float(__builtin_amdgcn_update_dpp(ninf, __float_as_int(v), CTRL, ROWS, 0xf, false));
+    return fmaxf(v, o);
+}
+
 __device__ __forceinline__ float wave_max_f32(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
+    v = dpp_max_step<0x111, 0xf>(v); // row_shr:1
+    v = dpp_max_step<0x112, 0xf>(v); // row_shr:2
+    v = dpp_max_step<0x114, 0xf>(v); // row_shr:4
+    v = dpp_max_step<0x118, 0xf>(v); // row_shr:8
+    v = dpp_max_step<0x142, 0xa>(v); // row_bcast:15
+    v = dpp_max_step<0x143, 0xc>(v); // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // One (q index, problem) per wavefront; CT is the type of in-row count sums
