@@ -51,9 +51,10 @@ WORKLOADS = {
                      "of (gray level, 3x3 average gray level) over [-1024,-200], FP64 arg max over threshold pairs "
                      "(t, s) for q in {0.5,0.8,1.5}, labels from t for each q", True, -1024, -200, 256, 1,
                      (0.5, 0.8, 1.5)),
-    "volume300_open": ("volume 512x512x300 int16, the paper's morphology step per slice: gray levels over "
-                       "[-1024,-200] (256), opening by a flat disk of radius 10 (erosion, then dilation), opened "
-                       "image and residue gray - opened", True, -1024, -200, 256, 0, ()),
+    "volume300_open": ("volume 512x512x300 int16, the paper's segmentation step per slice: gray levels over "
+                       "[-1024,-200] (256), opening by a flat disk of radius 10 (erosion, then dilation), residue "
+                       "gray - opened, Tsallis threshold (k=1) of the residue for q in {0.5,0.8,1.5}, residue labels",
+                       True, -1024, -200, 256, 1, (0.5, 0.8, 1.5)),
     "serving": ("Poisson trace, 20 volumes/s, half 256x256xU{60..300} and half 512x512xU{120..600}; per volume "
                 "512-bin histogram over [-1024,3071], k=3, q=0.8, labels back in host memory",
                 False, -1024, 3071, 512, 3, (0.8,)),
@@ -199,56 +200,101 @@ def bench_serving(args, wl, trace, jobs, vols):
 
 
 def bench_open(args, wl, dev):
+    """The paper's segmentation step per slice: opening by the disk of radius
+    10 (residue = gray - opened), then the Tsallis threshold selected on the
+    residue's gray levels for each q (one threshold) and the residue labelled."""
     import numpy as np
     import torch
 
     from paper_2012_10684_amd import api, synth
 
-    desc, _, LO, HI, L, _, _ = wl
-    R = 10
+    desc, _, LO, HI, L, _, QS = wl
+    R, K = 10, 1
     vol = synth.workload_volume300(0)
     Z, H, W = vol.shape
+    nq = len(QS)
     dv = torch.from_numpy(vol).to(dev)
     batch = api.Batch.slices(dv)
     binn = api.binning(LO, HI, L)
+    ident = api.binning(0, L - 1, L)
     opened = torch.empty((Z, H, W), dtype=torch.uint8, device=dev)
-    residue = torch.empty_like(opened)
+    r16 = torch.empty((Z, H, W), dtype=torch.int16, device=dev)
     ws = torch.empty(Z * H * W, dtype=torch.uint8, device=dev)
+    rb = api.Batch.slices(r16)
+    hist = torch.empty((Z, L), dtype=torch.int32, device=dev)
+    P = torch.empty((Z, L), dtype=torch.float64, device=dev)
+    Q = torch.empty((nq, Z, L), dtype=torch.float64, device=dev)
+    wss = torch.empty(api.workspace_bytes(Z, L, K, api.SEARCH_FP32_TIECHECK, nq), dtype=torch.uint8, device=dev)
+    res = (torch.empty((nq, Z, K), dtype=torch.int32, device=dev), torch.empty((nq, Z), dtype=torch.float64, device=dev),
+           torch.empty((nq, Z), dtype=torch.int32, device=dev))
+    thrs = [res[0][j] for j in range(nq)]
+    outs = [[torch.empty(H * W, dtype=torch.uint8, device=dev) for _ in range(Z)] for _ in QS]
+    optrs = [api.device_table([o.data_ptr() for o in oq], dev) for oq in outs]
     stream = torch.cuda.current_stream()
+    names = ["opening", "histogram", "prefix", "search", "label"]
 
-    def step():
-        api.open2d(batch, H, W, binn, R, ws=ws, opened=opened, residue=residue, stream=stream)
+    def step(ev=None):
+        ev = ev or {}
+
+        def mark(name, i):
+            if name in ev:
+                ev[name][i].record(stream)
+
+        mark("opening", 0)
+        api.open2d(batch, H, W, binn, R, ws=ws, opened=opened, residue16=r16, want=(), stream=stream)
+        mark("opening", 1)
+        mark("histogram", 0)
+        api.histogram(rb, ident, out=hist, tune="auto", stream=stream)
+        mark("histogram", 1)
+        mark("prefix", 0)
+        api.prefix(hist, QS, P=P, Q=Q, stream=stream)
+        mark("prefix", 1)
+        mark("search", 0)
+        api.threshold_search(P, Q, K, QS, ws=wss, out=res, tune="auto", stream=stream)
+        mark("search", 1)
+        mark("label", 0)
+        api.label_sets(rb, ident, thrs, K, outs=outs, out_ptrs=optrs, tune="auto", stream=stream)
+        mark("label", 1)
+
+    def pairs(n, keys):
+        return [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in keys}
+                for _ in range(n)]
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    roof = pairs(args.steps, ["opening"])
     t0 = time.perf_counter()
-    for e in ev:
-        e[0].record(stream)
-        step()
-        e[1].record(stream)
+    for i in range(args.steps):
+        step(roof[i])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    avg = sum(a.elapsed_time(b) for a, b in ev) * 1e-3 / len(ev)
+    kev = pairs(min(args.steps, 10), names)
+    for e in kev:
+        step(e)
+    torch.cuda.synchronize()
+    per = {n: sum(e[n][0].elapsed_time(e[n][1]) for e in kev) * 1e-3 / len(kev) for n in names}
+    avg = sum(e["opening"][0].elapsed_time(e["opening"][1]) for e in roof) * 1e-3 / len(roof)
     nvox = int(vol.size)
-    # algorithmic work: every output is the minimum (then maximum) of the pixels under the disk
-    disk = sum(1 for dy in range(-R, R + 1) for dx in range(-R, R + 1) if dx * dx + dy * dy <= R * R)
-    ops = 2 * nvox * (disk - 1)
-    alg = 8 * nvox  # 2 B in + 1 B eroded out; 1 B eroded in + 2 B in (residue) + 1 B opened + 1 B residue out
+    alg = (2 + 1) * nvox + (1 + 2 + 1 + 2) * nvox  # erosion: int16 in, eroded out; dilation: eroded + int16 in,
+    # opened + int16 residue out
     line = {
-        "metric": "voxels/s (morphology step: opening by a disk of radius 10 + residue)",
+        "metric": "voxels/s (the paper's segmentation step: opening by a disk of radius 10, Tsallis threshold "
+                  "of the residue, labels)",
         "value": nvox * args.steps / dt, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": desc, "images": Z, "voxels": nvox, "radius": R, "disk_pixels": disk},
+        "config": {"workload": desc, "images": Z, "voxels": nvox, "radius": R, "k": K, "q": list(QS)},
+        "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
+        "kernel_us_note": "from an untimed pass with events around every stage (each event adds a gap)",
         "roofline": {"bound": "hbm", "kernel": "k_morph (erosion + dilation)", "achieved": alg / avg / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6,
-                     "note": "the HBM side of the step (8 B per pixel over both passes); the kernels are bound by "
-                             "LDS byte reads, about 2r (1 + 2r / 64) + 2r + 2 per output per pass"},
+                     "note": "the HBM side of the opening (9 B per pixel over both passes: int16 in, eroded out and "
+                             "in, int16 re-read, opened out, int16 residue out); the passes are bound by LDS byte "
+                             "reads, about 2r (1 + 2r / 64) + 2r + 2 per output per pass"},
         "lds_reads_per_pixel": 2 * (2 * R * (1 + 2 * R / 64) + 2 * R + 2),
-        "min_max_ops_naive": ops,
+        "all_problems_ok": bool(int((res[2] != 0).sum()) == 0),
     }
     print(json.dumps(line), flush=True)
 

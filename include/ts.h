@@ -303,11 +303,16 @@ size_t ts_open2d_workspace_bytes(int32_t nseg, int32_t height, int32_t width);
  *   radius  0..TS_MORPH_MAX_RADIUS (the paper's disk: 10);
  *   ws      device workspace of ws_bytes >= ts_open2d_workspace_bytes()
  *           (the eroded images); overwritten;
- *   opened  out: uint8 [nseg][height][width], or NULL;
- *   residue out: uint8 [nseg][height][width], or NULL (not both NULL).
+ *   opened    out: uint8 [nseg][height][width], or NULL;
+ *   residue   out: uint8 [nseg][height][width], or NULL;
+ *   residue16 out: the residue as int16 [nseg][height][width], or NULL: gray
+ *             levels that ts_histogram / ts_label take directly with the
+ *             binning {0, nbins-1, nbins} (each level its own bin), so the
+ *             threshold is selected on the image after the morphology step,
+ *             as the paper's segmentation does (at least one output).
  * Errors: TS_ERR_INVALID_ARG, TS_ERR_WORKSPACE. */
 ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, int32_t radius, void *ws,
-                    size_t ws_bytes, uint8_t *opened, uint8_t *residue, ts_stream_t stream);
+                    size_t ws_bytes, uint8_t *opened, uint8_t *residue, int16_t *residue16, ts_stream_t stream);
 
 /* Largest number of threshold sets ts_label_sets takes in one call. */
 #define TS_MAX_LABEL_SETS 4

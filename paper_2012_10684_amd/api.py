@@ -86,7 +86,7 @@ def _load():
     lib.ts_threshold_search2d.argtypes = [P, i32, i32, i32, P, P, sz, P, P, P, P]
     lib.ts_open2d_workspace_bytes.argtypes = [i32, i32, i32]
     lib.ts_open2d_workspace_bytes.restype = sz
-    lib.ts_open2d.argtypes = [_Batch, i32, i32, Binning, i32, P, sz, P, P, P]
+    lib.ts_open2d.argtypes = [_Batch, i32, i32, Binning, i32, P, sz, P, P, P, P]
     lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
     lib.ts_search_dp_workspace_bytes.restype = sz
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
@@ -251,24 +251,30 @@ MORPH_MAX_RADIUS = 32
 
 
 def open2d(batch: Batch, height: int, width: int, bin: Binning, radius: int = 10, ws: Optional[torch.Tensor] = None,
-           opened: Optional[torch.Tensor] = None, residue: Optional[torch.Tensor] = None, want=("opened", "residue"),
-           stream=None):
+           opened: Optional[torch.Tensor] = None, residue: Optional[torch.Tensor] = None,
+           residue16: Optional[torch.Tensor] = None, want=("opened", "residue"), stream=None):
     """Gray-scale opening of each image by a flat disk (uint8 [nseg, H, W]) and
-    the residue gray - opened; returns (opened, residue), None for an output
-    not wanted."""
+    the residue gray - opened (uint8, and as int16 when "residue16" is
+    wanted); returns (opened, residue, residue16), None for an output not
+    wanted."""
     dev = batch.ptrs.device
     shape = (batch.nseg, height, width)
     if opened is None and "opened" in want:
         opened = torch.empty(shape, dtype=torch.uint8, device=dev)
     if residue is None and "residue" in want:
         residue = torch.empty(shape, dtype=torch.uint8, device=dev)
+    if residue16 is None and "residue16" in want:
+        residue16 = torch.empty(shape, dtype=torch.int16, device=dev)
     need = int(_lib.ts_open2d_workspace_bytes(batch.nseg, height, width))
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    _check(_lib.ts_open2d(batch._c, height, width, bin, int(radius), _ptr(ws), ws.numel(),
-                          _ptr(opened) if opened is not None else None,
-                          _ptr(residue) if residue is not None else None, _stream(stream)))
-    return opened, residue
+
+    def p(t):
+        return _ptr(t) if t is not None else None
+
+    _check(_lib.ts_open2d(batch._c, height, width, bin, int(radius), _ptr(ws), ws.numel(), p(opened), p(residue),
+                          p(residue16), _stream(stream)))
+    return opened, residue, residue16
 
 
 def workspace_dp_bytes(nseg: int, nbins: int, k: int, nq: int = 1) -> int:

@@ -430,7 +430,7 @@ size_t ts_open2d_workspace_bytes(int32_t nseg, int32_t height, int32_t width)
 }
 
 ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, int32_t radius, void *ws,
-                    size_t ws_bytes, uint8_t *opened, uint8_t *residue, ts_stream_t stream)
+                    size_t ws_bytes, uint8_t *opened, uint8_t *residue, int16_t *residue16, ts_stream_t stream)
 {
     ts_status st = check_batch(batch);
     if (st != TS_OK)
@@ -446,15 +446,16 @@ ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bi
         return fail(TS_ERR_INVALID_ARG, "ts_open2d: need height >= 1 and width >= 1");
     if (batch.total != (int64_t)batch.nseg * height * width)
         return fail(TS_ERR_INVALID_ARG, "ts_open2d: total must be nseg * height * width");
-    if (batch.nseg > 0 && !opened && !residue)
-        return fail(TS_ERR_INVALID_ARG, "ts_open2d: opened and residue are both null");
+    if (batch.nseg > 0 && !opened && !residue && !residue16)
+        return fail(TS_ERR_INVALID_ARG, "ts_open2d: every output is null");
     const size_t need = open2d_workspace_bytes(batch.nseg, height, width);
     if (batch.nseg > 0 && (ws_bytes < need || !ws))
         return fail(TS_ERR_WORKSPACE, "ts_open2d: workspace too small (need " + std::to_string(need) + " bytes, got " +
                                           std::to_string(ws_bytes) + ")");
     if (batch.nseg == 0)
         return TS_OK;
-    return launch_open2d(batch, height, width, bm, radius, (uint8_t *)ws, opened, residue, (hipStream_t)stream);
+    return launch_open2d(batch, height, width, bm, radius, (uint8_t *)ws, opened, residue, residue16,
+                         (hipStream_t)stream);
 }
 
 ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream)

@@ -179,7 +179,7 @@ size_t search2d_workspace_bytes(int nseg, int nq, int L);
 size_t dp_workspace_bytes(int nprob, int L, int k);
 size_t open2d_workspace_bytes(int nseg, int H, int W);
 ts_status launch_open2d(const ts_batch &b, int H, int W, const BinMap &bm, int r, uint8_t *eroded,
-                        uint8_t *opened, uint8_t *residue, hipStream_t st);
+                        uint8_t *opened, uint8_t *residue, int16_t *residue16, hipStream_t st);
 ts_status launch_dp(const double *P, const double *Q, int nseg, int L, int k, int nq, const double *q, void *ws,
                     int32_t *thr, double *obj, int32_t *status, hipStream_t st);
 ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const double *q, void *ws, int32_t *thr,

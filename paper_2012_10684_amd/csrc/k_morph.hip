@@ -35,11 +35,13 @@ __device__ __forceinline__ int isqrt_floor(int n)
 
 // MAXOP = false: erosion of the gray levels of the int16 images (src16,
 // binned) into dst; MAXOP = true: dilation of the uint8 images src8 into dst
-// and/or the residue gray(src16) - dilation into res.
+// and/or the residue gray(src16) - dilation into res (uint8) and res16
+// (int16).
 template <bool MAXOP, int MAP>
 __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__restrict__ src16,
                                                       const uint8_t *__restrict__ src8, int H, int W, int r,
-                                                      BinMap bm, uint8_t *__restrict__ dst, uint8_t *__restrict__ res)
+                                                      BinMap bm, uint8_t *__restrict__ dst, uint8_t *__restrict__ res,
+                                                      int16_t *__restrict__ res16)
 {
     __shared__ uint8_t in[MO_SH * MO_SW];
     __shared__ uint8_t hr[MO_SH * MO_TX];
@@ -113,9 +115,12 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
         const int64_t o = img_off + (int64_t)y * W + x;
         if (dst)
             dst[o] = out[i];
-        if (MAXOP && res) {
+        if (MAXOP && (res || res16)) {
             const int f = bin_of_t<MAP>(img16[(int64_t)y * W + x], bm);
-            res[o] = (uint8_t)(f - (int)out[i]);
+            if (res)
+                res[o] = (uint8_t)(f - (int)out[i]);
+            if (res16)
+                res16[o] = (int16_t)(f - (int)out[i]);
         }
     }
 }
@@ -123,13 +128,13 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
 size_t open2d_workspace_bytes(int nseg, int H, int W) { return (size_t)nseg * H * W; }
 
 ts_status launch_open2d(const ts_batch &b, int H, int W, const BinMap &bm, int r, uint8_t *eroded,
-                        uint8_t *opened, uint8_t *residue, hipStream_t st)
+                        uint8_t *opened, uint8_t *residue, int16_t *residue16, hipStream_t st)
 {
     const int tiles = ((W + MO_TX - 1) / MO_TX) * ((H + MO_TY - 1) / MO_TY);
     const dim3 g((unsigned)((int64_t)b.nseg * tiles)), blk(MO_THREADS);
 #define TS_MO(M)                                                                                                     \
-    hipLaunchKernelGGL((k_morph<false, M>), g, blk, 0, st, b.vox, nullptr, H, W, r, bm, eroded, nullptr);           \
-    hipLaunchKernelGGL((k_morph<true, M>), g, blk, 0, st, b.vox, eroded, H, W, r, bm, opened, residue)
+    hipLaunchKernelGGL((k_morph<false, M>), g, blk, 0, st, b.vox, nullptr, H, W, r, bm, eroded, nullptr, nullptr);  \
+    hipLaunchKernelGGL((k_morph<true, M>), g, blk, 0, st, b.vox, eroded, H, W, r, bm, opened, residue, residue16)
     switch (map_kind(bm)) {
     case 0: TS_MO(0); break;
     case 1: TS_MO(1); break;

@@ -67,7 +67,7 @@ def _bind(lib):
     lib.ts_threshold_search2d.argtypes = [P, i32, i32, i32, P, P, sz, P, P, P, P]
     lib.ts_open2d_workspace_bytes.argtypes = [i32, i32, i32]
     lib.ts_open2d_workspace_bytes.restype = sz
-    lib.ts_open2d.argtypes = [Batch, i32, i32, Binning, i32, P, sz, P, P, P]
+    lib.ts_open2d.argtypes = [Batch, i32, i32, Binning, i32, P, sz, P, P, P, P]
     lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
     lib.ts_search_dp_workspace_bytes.restype = sz
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
@@ -193,7 +193,7 @@ def test_argument_errors(lib, case, expect):
         Hh = 0 if case == "open_height" else 6
         ws_bytes = 10 if case == "open_ws" else 1 << 30
         outs = (None, None) if case == "open_no_output" else (FAKE, None)
-        st = lib.ts_open2d(b, Hh, 7, binning, r, FAKE, ws_bytes, outs[0], outs[1], sx)
+        st = lib.ts_open2d(b, Hh, 7, binning, r, FAKE, ws_bytes, outs[0], outs[1], None, sx)
     elif case.startswith("dp_"):
         k = {"dp_k0": 0, "dp_k17": 17}.get(case, 5)
         L = 5 if case == "dp_bins_lt_k1" else 512
@@ -228,7 +228,7 @@ def test_empty_batch_is_a_no_op(lib):
     assert lib.ts_histogram2d(Batch(None, None, 0, 0), 4, 4, ok_bin, None, None) == 0
     assert lib.ts_threshold_search2d(None, 0, 64, 1, qs(0.8), None, 0, None, None, None, None) == 0
     assert lib.ts_threshold_search_dp(None, None, 0, 1024, 4, 1, qs(0.8), None, 0, None, None, None, None) == 0
-    assert lib.ts_open2d(Batch(None, None, 0, 0), 8, 8, ok_bin, 10, None, 0, None, None, None) == 0
+    assert lib.ts_open2d(Batch(None, None, 0, 0), 8, 8, ok_bin, 10, None, 0, None, None, None, None) == 0
     assert lib.ts_open2d_workspace_bytes(3, 512, 512) == 3 * 512 * 512
     assert lib.ts_prefix(None, 0, 256, 1, qs(0.8), None, None, None) == 0
     assert lib.ts_threshold_search(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, 0, None, None, None, None,

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import say, to_dev
+from gpu_util import check_choice, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,7 @@ from paper_2012_10684_amd import api, synth  # noqa: E402
 def _check(imgs, lo, hi, L, r, want=("opened", "residue")):
     n, H, W = imgs.shape
     dv = to_dev(imgs)
-    o, res = api.open2d(api.Batch.slices(dv), H, W, api.binning(lo, hi, L), r, want=want)
+    o, res, r16 = api.open2d(api.Batch.slices(dv), H, W, api.binning(lo, hi, L), r, want=want)
     torch.cuda.synchronize()
     for i in range(n):
         g = oracle.gray(imgs[i], lo, hi, L)
@@ -30,6 +30,8 @@ def _check(imgs, lo, hi, L, r, want=("opened", "residue")):
             assert np.array_equal(o[i].cpu().numpy().astype(np.int32), oo), (H, W, r, i)
         if res is not None:
             assert np.array_equal(res[i].cpu().numpy().astype(np.int32), rr), (H, W, r, i)
+        if r16 is not None:
+            assert np.array_equal(r16[i].cpu().numpy().astype(np.int32), rr), (H, W, r, i)
 
 
 @pytest.mark.parametrize("r", [0, 1, 3, 10, 17, 32])
@@ -60,3 +62,33 @@ def test_open2d_single_outputs():
     imgs = rng.integers(-1024, 500, (3, 40, 77)).astype(np.int16)
     _check(imgs, -1024, 3071, 256, 6, want=("opened",))
     _check(imgs, -1024, 3071, 256, 6, want=("residue",))
+    _check(imgs, -1024, 3071, 256, 6, want=("residue16",))
+
+
+@pytest.mark.parametrize("q", [0.5, 1.5])
+def test_segmentation_after_the_opening(q):
+    """The paper's segmentation step on workload slices: opening by the
+    disk of radius 10, then the Tsallis threshold selected on the residue
+    image and the residue thresholded (histogram of its gray levels, one
+    threshold, labels), all against the oracle."""
+    lo, hi, L, r = -1024, -200, 256, 10
+    vol = synth.workload_volume300(0)[::150]
+    n, H, W = vol.shape
+    _, _, r16 = api.open2d(api.Batch.slices(to_dev(vol)), H, W, api.binning(lo, hi, L), r, want=("residue16",))
+    ident = api.binning(0, L - 1, L)  # each gray level its own bin
+    b = api.Batch.slices(r16)
+    h = api.histogram(b, ident)
+    P, Q = api.prefix(h, q)
+    thr, obj, st = api.threshold_search(P, Q, 1, q)
+    lab = api.label(b, ident, thr, 1)
+    torch.cuda.synchronize()
+    Hg = h.cpu().numpy().view(np.uint32)
+    for i in range(n):
+        _, rr = oracle.opening(oracle.gray(vol[i], lo, hi, L), r)
+        rr16 = rr.astype(np.int16)
+        want_h = oracle.histogram(rr16.reshape(-1), 0, L - 1, L)
+        assert np.array_equal(Hg[i], want_h), i
+        check_choice(want_h, 1, q, thr[i].cpu().numpy(), obj[i].item(), st[i].item())
+        want_l = oracle.label(rr16.reshape(-1), 0, L - 1, L, thr[i].cpu().numpy())
+        assert np.array_equal(lab[i].cpu().numpy(), want_l), i
+    say(f"segmentation after the opening, q={q}: thresholds {thr[:, 0].tolist()}")
