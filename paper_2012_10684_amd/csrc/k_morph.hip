@@ -53,55 +53,58 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
     const uint8_t neutral = MAXOP ? 0 : 255;
     const int64_t img_off = (int64_t)s * H * W;
     const TS_GLOBAL int16_t *img16 = gp(src16[s]);
-    // stage the tile and its halo
-    for (int i = threadIdx.x; i < sh * sw; i += blockDim.x) {
-        const int row = i / sw, col = i - row * sw;
-        const int y = y0 - r + row, x = x0 - r + col;
-        uint8_t v = neutral;
-        if (y >= 0 && y < H && x >= 0 && x < W) {
-            if (MAXOP)
-                v = src8[img_off + (int64_t)y * W + x];
-            else
-                v = (uint8_t)bin_of_t<MAP>(img16[(int64_t)y * W + x], bm);
+    const int c = threadIdx.x % MO_TX, yb = threadIdx.x / MO_TX; // lane column, row phase (0..3)
+    // stage the tile and its halo: rows yb, yb + 4, ..., columns c, c + 64
+    for (int row = yb; row < sh; row += MO_THREADS / MO_TX) {
+        const int y = y0 - r + row;
+        const bool yin = y >= 0 && y < H;
+        for (int col = c; col < sw; col += MO_TX) {
+            const int x = x0 - r + col;
+            int v = neutral;
+            if (yin && x >= 0 && x < W) {
+                if (MAXOP)
+                    v = src8[img_off + (int64_t)y * W + x];
+                else
+                    v = bin_of_t<MAP>(img16[(int64_t)y * W + x], bm);
+            }
+            in[row * sw + col] = (uint8_t)v;
         }
-        in[i] = v;
     }
     __syncthreads();
     // half-width 0: the staged pixel itself
-    for (int i = threadIdx.x; i < sh * MO_TX; i += blockDim.x) {
-        const int row = i / MO_TX, c = i - row * MO_TX;
-        hr[i] = in[row * sw + c + r];
-    }
-    const int c = threadIdx.x % MO_TX, yb = threadIdx.x / MO_TX; // outputs (yb + 4 i, c)
-    uint8_t out[MO_PER];
+    for (int row = yb; row < sh; row += MO_THREADS / MO_TX)
+        hr[row * MO_TX + c] = in[row * sw + c + r];
+    // outputs (yb + 4 i, c), i < MO_PER
+    int out[MO_PER];
 #pragma unroll
     for (int i = 0; i < MO_PER; ++i)
         out[i] = neutral;
     int cur = 0;
+    __syncthreads(); // hr at half-width 0
     for (int a = r; a >= 0; --a) {
         const int w = isqrt_floor(r * r - a * a);
-        __syncthreads(); // the previous combine step has read hr
-        if (w > cur) {   // widen every staged row from half-width cur to w
-            for (int i = threadIdx.x; i < sh * MO_TX; i += blockDim.x) {
-                const int row = i / MO_TX, cc = i - row * MO_TX;
-                const uint8_t *rin = in + row * sw + cc + r;
-                int v = hr[i];
+        if (w > cur) { // widen every staged row from half-width cur to w
+            __syncthreads(); // the combine steps before have read hr
+            for (int row = yb; row < sh; row += MO_THREADS / MO_TX) {
+                const uint8_t *rin = in + row * sw + c + r;
+                int v = hr[row * MO_TX + c];
+#pragma unroll 4
                 for (int d = cur + 1; d <= w; ++d) {
                     const int lft = rin[-d], rgt = rin[d];
                     v = MAXOP ? max(v, max(lft, rgt)) : min(v, min(lft, rgt));
                 }
-                hr[i] = (uint8_t)v;
+                hr[row * MO_TX + c] = (uint8_t)v;
             }
             cur = w;
             __syncthreads();
         }
-        // rows y - a and y + a of every output take half-width w(a)
+        // rows y - a and y + a of every output take half-width w(a); output
+        // i sits 4 i staged rows below output 0 (immediate LDS offsets)
+        const uint8_t *plo = hr + (yb + r - a) * MO_TX + c, *phi = hr + (yb + r + a) * MO_TX + c;
 #pragma unroll
         for (int i = 0; i < MO_PER; ++i) {
-            const int yy = yb + 4 * i + r; // staged row of the output
-            const int lo = hr[(yy - a) * MO_TX + c], hi = hr[(yy + a) * MO_TX + c];
-            const int v = MAXOP ? max((int)out[i], max(lo, hi)) : min((int)out[i], min(lo, hi));
-            out[i] = (uint8_t)v;
+            const int lo = plo[4 * MO_TX * i], hi = phi[4 * MO_TX * i];
+            out[i] = MAXOP ? max(out[i], max(lo, hi)) : min(out[i], min(lo, hi));
         }
     }
     const int x = x0 + c;
