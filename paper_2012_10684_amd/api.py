@@ -171,10 +171,10 @@ class Batch:
         self._c = _Batch(self.ptrs.data_ptr(), self.offs.data_ptr(), self.nseg, self.total)
 
     @classmethod
-    def slices(cls, volume: torch.Tensor) -> "Batch":
+    def slices(cls, volume: torch.Tensor, stream=None) -> "Batch":
         """One problem per slice of a (Z, H, W) volume."""
         v = volume.contiguous()
-        return cls([v[z].reshape(-1) for z in range(v.shape[0])])
+        return cls([v[z].reshape(-1) for z in range(v.shape[0])], stream=stream)
 
     @classmethod
     def whole(cls, volumes: Iterable[torch.Tensor]) -> "Batch":
@@ -344,6 +344,78 @@ def segment(batch: Batch, bin: Binning, k: int, q: float, mode: int = SEARCH_FP3
     thr, obj, status = threshold_search(P, Q, k, q, mode, tune=tune, stream=stream)
     labels = label(batch, bin, thr, k, tune=tune, stream=stream)
     return h, (P, Q), (thr, obj, status), labels
+
+
+class Segmentation:
+    """Result of batch_segment: the problems' histograms, thresholds
+    ([nq, nseg, k]), objectives and statuses ([nq, nseg]) and, per q, the
+    label maps of every input volume in its own shape (uint8)."""
+
+    def __init__(self, hist, thr, obj, status, labels, residues=None):
+        self.hist, self.thr, self.obj, self.status, self.labels = hist, thr, obj, status, labels
+        self.residues = residues  # int16 residue volumes when the opening ran first
+
+
+def batch_segment(volumes: Sequence[torch.Tensor], bin: Binning, k: int, q, per: str = "slice",
+                  mode: int = SEARCH_FP32_TIECHECK, method: str = "auto", open_radius: Optional[int] = None,
+                  tune=None, stream=None) -> Segmentation:
+    """Segment a list of int16 CUDA volumes of any shapes in one launch per
+    stage: one problem per slice (per="slice") or per volume
+    (per="volume"); q a value or a sequence of up to MAX_LABEL_SETS values
+    (all q searched in one launch, labelled in one pass); method "exhaustive"
+    (ts_threshold_search with `mode`), "dp" (ts_threshold_search_dp) or
+    "auto" (exhaustive for k <= 3, dp beyond).  With open_radius (per="slice"
+    only), each slice is first opened by that disk and the threshold is
+    selected and applied on the residue (the paper's segmentation order;
+    gray levels through the identity binning).  Only marshalling: every step
+    runs in libts."""
+    if per not in ("slice", "volume"):
+        raise ValueError("per must be 'slice' or 'volume'")
+    vols = [v.contiguous() for v in volumes]
+    qs, batched = _qs(q)
+    if len(qs) > MAX_LABEL_SETS:
+        raise ValueError(f"at most {MAX_LABEL_SETS} q values")
+    if method == "auto":
+        method = "exhaustive" if k <= 3 else "dp"
+    residues = None
+    if open_radius is not None:
+        if per != "slice":
+            raise ValueError("the opening works on images: use per='slice'")
+        residues = []
+        for v in vols:
+            if v.dim() != 3:
+                raise ValueError("open_radius needs (Z, H, W) volumes")
+            _, _, r16 = open2d(Batch.slices(v, stream=stream), v.shape[1], v.shape[2], bin, open_radius,
+                               want=("residue16",), stream=stream)
+            residues.append(r16)
+        src = residues
+        bin = binning(0, bin.nbins - 1, bin.nbins)
+    else:
+        src = vols
+    if per == "slice":
+        segs = [v[z].reshape(-1) for v in src for z in range(v.shape[0])]
+    else:
+        segs = [v.reshape(-1) for v in src]
+    batch = Batch(segs, stream=stream)
+    h = histogram(batch, bin, tune=tune, stream=stream)
+    P, Q = prefix(h, list(qs), stream=stream)
+    if method == "dp":
+        thr, obj, status = threshold_search_dp(P, Q, k, list(qs), stream=stream)
+    else:
+        thr, obj, status = threshold_search(P, Q, k, list(qs), mode, tune=tune, stream=stream)
+    maps = label_sets(batch, bin, [thr[j] for j in range(len(qs))], k, tune=tune, stream=stream)
+    labels = []
+    for j in range(len(qs)):
+        per_vol, i = [], 0
+        for v in src:
+            if per == "slice":
+                per_vol.append(torch.stack([maps[j][i + z].view(v.shape[1:]) for z in range(v.shape[0])]))
+                i += v.shape[0]
+            else:
+                per_vol.append(maps[j][i].view(v.shape))
+                i += 1
+        labels.append(per_vol)
+    return Segmentation(h, thr, obj, status, labels, residues)
 
 
 def log2_f32(x: torch.Tensor, stream=None) -> torch.Tensor:
