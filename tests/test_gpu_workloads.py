@@ -82,3 +82,44 @@ def test_volume600_whole_k3():
     say(f"gpu {thr.cpu().numpy()[0].tolist()} oracle {r.thr.tolist()} S {float(obj[0])!r} vs {r.obj!r}")
     want = oracle.label(vol.reshape(-1), -1024, 3071, 1024, thr.cpu().numpy()[0])
     assert np.array_equal(labels[0].cpu().numpy(), want)
+
+
+def test_batch64_sampled_slices():
+    """64 volumes 512x512xU{120..600} (about 23,000 slices, 6e9 voxels) in one
+    batch, per-slice 256 bins over [-1024, -200], k = 2, q in {0.5, 0.8,
+    1.5}, labels for every q in one pass: the benchmark's launch
+    configuration.  The volumes are copies of the first Z slices of one
+    generated volume (the benchmark draws from a pool of four; generating
+    more here would need worker processes after the GPU is in use).  Sampled
+    slices are checked against the oracle."""
+    depths = synth.batch_depths(64)
+    say(f"generating a 512x512x{max(depths)} volume")
+    pool = synth.workload_batch_volume(0, max(depths), 512)
+    dpool = to_dev(pool)
+    dvols = [dpool[:z].clone() for z in depths]  # one buffer per volume
+    del dpool
+    segs = [v[z].reshape(-1) for v in dvols for z in range(v.shape[0])]
+    where = [(vi, z) for vi, v in enumerate(dvols) for z in range(v.shape[0])]
+    b = api.Batch(segs)
+    binn = api.binning(-1024, -200, 256)
+    qs = (0.5, 0.8, 1.5)
+    h = api.histogram(b, binn, tune="auto")
+    P, Q = api.prefix(h, qs)
+    thr, obj, st = api.threshold_search(P, Q, 2, qs, tune="auto")
+    labels = api.label_sets(b, binn, [thr[j] for j in range(3)], 2, tune="auto")
+    torch.cuda.synchronize()
+    say(f"{b.nseg} slices segmented; checking a sample")
+    rng = np.random.default_rng(64)
+    idx = sorted(set(rng.integers(0, b.nseg, 36).tolist()) | {0, b.nseg - 1})
+    H = u32(h)
+    thr_h, obj_h, st_h = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+    for i in idx:
+        vi, z = where[i]
+        sl = pool[z].reshape(-1)
+        want_h = oracle.histogram(sl, -1024, -200, 256)
+        assert np.array_equal(H[i], want_h), (i, vi, z)
+        for j, q in enumerate(qs):
+            check_choice(want_h, 2, q, thr_h[j, i], obj_h[j, i], st_h[j, i])
+            want = oracle.label(sl, -1024, -200, 256, thr_h[j, i])
+            assert np.array_equal(labels[j][i].cpu().numpy(), want), (i, q)
+    assert int((st != 0).sum()) == 0
