@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=120, help="serving: requests replayed from the trace")
     ap.add_argument("--per-slice-sample", type=int, default=2000,
                     help="batch64: slices timed with one launch per slice and stage")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the step captured as HIP graphs, checked against an eager step "
+                         "(default: eager launches, measured faster on MI355X)")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run device-to-device copies of 256 MiB (reference kernel for the PMC byte counters)")
     return ap.parse_args()
@@ -88,16 +91,16 @@ def src_hash(name: str) -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(kernel_file: str):
+def load_traffic(kernel_file: str, workload: str):
     """HBM traffic per launch from the committed PMC summary, if it was taken
-    on the current source of that kernel (else None)."""
+    on the current source of that kernel and on this workload (else None)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(p))
     except (OSError, ValueError):
         return None
     e = d.get(kernel_file)
-    if not e or e.get("src_sha") != src_hash(kernel_file):
+    if not e or e.get("src_sha") != src_hash(kernel_file) or e.get("workload") != workload:
         return None
     return e.get("bytes_per_launch")
 
@@ -384,6 +387,54 @@ def bench_2d(args, wl, dev):
     print(json.dumps(line), flush=True)
 
 
+def capture_graphs(step, stream, hist, res, outs, sample_labels: bool):
+    """Capture one step as two HIP graphs (histogram + prefix + search, then
+    labels) on a side stream, and check three replays against an eager step:
+    before each replay the outputs are overwritten with junk, after it the
+    histogram, thresholds, objectives, statuses and label maps must equal the
+    eager step's bit for bit (label maps of every slice, or of every 97th
+    slice for the batched workload).  Between replays an eager step runs.
+    "verified" is False when a replay does not match (the caller then times
+    eager launches)."""
+    import torch
+
+    step()
+    torch.cuda.synchronize()
+    pick = (lambda oq: oq[::97] + oq[-1:]) if sample_labels else (lambda oq: oq)
+
+    def snapshot():
+        return [hist.clone()] + [r.clone() for r in res] + [torch.cat([o.reshape(-1) for o in pick(oq)])
+                                                            for oq in outs]
+
+    ref = snapshot()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(stream)
+    g_pre, g_lab = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_pre, stream=gs):
+        step(st=gs, parts=("pre",))
+    with torch.cuda.graph(g_lab, stream=gs):
+        step(st=gs, parts=("label",))
+    torch.cuda.synchronize()
+    ok = True
+    for _ in range(3):
+        hist.fill_(-1)
+        res[0].fill_(-7)
+        res[1].fill_(float("nan"))
+        res[2].fill_(-9)
+        for oq in outs:
+            for o in pick(oq):
+                o.fill_(0xEE)
+        torch.cuda.synchronize()
+        g_pre.replay()
+        g_lab.replay()
+        torch.cuda.synchronize()
+        bits = lambda t: t.view(torch.int64) if t.dtype == torch.float64 else t  # NaN objectives compare too
+        ok = ok and all(torch.equal(bits(a), bits(b)) for a, b in zip(snapshot(), ref))
+        step()
+        torch.cuda.synchronize()
+    return {"graphs": (g_pre, g_lab), "verified": ok}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -451,28 +502,33 @@ def main():
     stream = torch.cuda.current_stream()
     names = ["histogram", "prefix", "search", "label"]
 
-    def step(ev=None):
-        """One pass of the path; ev maps kernel names (or "step") to a
-        (start, end) pair of events recorded around that kernel."""
+    def step(ev=None, st=None, parts=("pre", "label")):
+        """One pass of the path on stream st (default: the current stream);
+        ev maps kernel names (or "step") to a (start, end) pair of events
+        recorded around that kernel; parts selects histogram + prefix +
+        search ("pre") and labels ("label")."""
         ev = ev or {}
+        st = st or stream
 
         def mark(name, i):
             if name in ev:
-                ev[name][i].record(stream)
+                ev[name][i].record(st)
 
         mark("step", 0)
-        mark("histogram", 0)
-        api.histogram(batch, binn, out=hist, tune="auto", stream=stream)
-        mark("histogram", 1)
-        mark("prefix", 0)
-        api.prefix(hist, QS, P=P, Q=Q, stream=stream)
-        mark("prefix", 1)
-        mark("search", 0)
-        api.threshold_search(P, Q, K, QS, api.SEARCH_FP32_TIECHECK, ws=ws, out=res, tune="auto", stream=stream)
-        mark("search", 1)
-        mark("label", 0)
-        api.label_sets(batch, binn, thrs, K, outs=outs, out_ptrs=optrs, tune="auto", stream=stream)
-        mark("label", 1)
+        if "pre" in parts:
+            mark("histogram", 0)
+            api.histogram(batch, binn, out=hist, tune="auto", stream=st)
+            mark("histogram", 1)
+            mark("prefix", 0)
+            api.prefix(hist, QS, P=P, Q=Q, stream=st)
+            mark("prefix", 1)
+            mark("search", 0)
+            api.threshold_search(P, Q, K, QS, api.SEARCH_FP32_TIECHECK, ws=ws, out=res, tune="auto", stream=st)
+            mark("search", 1)
+        if "label" in parts:
+            mark("label", 0)
+            api.label_sets(batch, binn, thrs, K, outs=outs, out_ptrs=optrs, tune="auto", stream=st)
+            mark("label", 1)
         mark("step", 1)
 
     def pairs(n, keys):
@@ -485,18 +541,38 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    captured = None if not args.graph else capture_graphs(step, stream, hist, res, outs, args.workload == "batch64")
+    graphs = captured if captured and captured["verified"] else None
     # the timed steps record events only around the label pass (the kernel
     # with the most algorithmic bytes: (2 + nq) B/voxel against the
     # histogram's 2): each recorded event adds a few us of gap to the stream
     roof_ev = pairs(args.steps, ["label"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(roof_ev[s])
+    if graphs is not None:
+        # one step = the replay of the histogram/prefix/search graph, then
+        # the replay of the label graph, both on this stream
+        g_pre, g_lab = graphs["graphs"]
+        for s in range(args.steps):
+            g_pre.replay()
+            roof_ev[s]["label"][0].record(stream)
+            g_lab.replay()
+            roof_ev[s]["label"][1].record(stream)
+    else:
+        for s in range(args.steps):
+            step(roof_ev[s])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
     label_t = avg_us(roof_ev, "label") * 1e-6
+    if graphs is not None:
+        # the same steps launched eagerly (untimed for the record)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        for s in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        graphs["eager_ms_per_step"] = (time.perf_counter() - te) / args.steps * 1e3
     # untimed passes after the timed region: events around every kernel (the
     # per-kernel breakdown), then around whole steps (step percentiles)
     nb = min(args.steps, 20)
@@ -519,7 +595,7 @@ def main():
     alg = label_bytes
     src = "k_label.hip"
     achieved = alg / avg / 1e9
-    traffic = load_traffic(src)
+    traffic = load_traffic(src, args.workload)
     # correctness guard: every problem found a valid tuple, every label pass wrote labels in [0, K]
     st_ok = int((res[2] != 0).sum()) == 0
     line = {
@@ -547,6 +623,11 @@ def main():
         "label_gbs": achieved,
         "all_problems_ok": bool(st_ok),
     }
+    line["launch"] = "hip_graph_replay" if graphs is not None else "eager"
+    if captured is not None:
+        line["graph_replays_match_eager"] = captured["verified"]
+    if graphs is not None:
+        line["eager_ms_per_step"] = graphs["eager_ms_per_step"]
     steps_us = sorted(e["step"][0].elapsed_time(e["step"][1]) * 1e3 for e in sev)
     line["step_us_p50"] = float(np.percentile(steps_us, 50))
     line["step_us_p99"] = float(np.percentile(steps_us, 99))
@@ -569,6 +650,18 @@ def main():
             line[f"search_{name}_same_result"] = bool(torch.equal(out2[0], res[0]))
             del ws2
     if args.workload in ("volume300", "volume600"):
+        # FP32 keys alone (no FP64 re-check) against the exact default: how many problems pick another
+        # tuple, and how much lower the FP64 objective of that tuple is
+        ws4 = torch.empty(api.workspace_bytes(nseg, L, K, api.SEARCH_FP32_ONLY, nq), dtype=torch.uint8, device=dev)
+        out4 = tuple(torch.empty_like(r) for r in res)
+        api.threshold_search(P, Q, K, QS, api.SEARCH_FP32_ONLY, ws=ws4, out=out4, stream=stream)
+        torch.cuda.synchronize()
+        ok = res[2] == 0
+        diff = (out4[0] != res[0]).any(dim=-1) & ok
+        rel = ((res[1] - out4[1]).abs() / res[1].abs().clamp_min(1e-300))[ok]
+        line["fp32_only_mismatched_problems"] = int(diff.sum())
+        line["fp32_only_max_rel_objective_loss"] = float(rel.max()) if rel.numel() else 0.0
+        del ws4
         # the multilevel variant objective sum S_j + (1-q) prod S_j (FP64 exhaustive), reported beside the
         # paper's objective: a different objective, so its thresholds are not compared
         ws3 = torch.empty(api.workspace_bytes(nseg, L, K, api.SEARCH_SUMPROD, nq), dtype=torch.uint8, device=dev)

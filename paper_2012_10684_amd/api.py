@@ -119,18 +119,27 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+_TUNED: dict = {}  # size-class key -> Tuning or None, for "auto" (the default cache is read once)
+
+
 def _tune(tune, key_fn=None):
     """None: library defaults; "auto": the autotuner's cached shapes for this
-    size class (defaults if none); a dict or Tuning: those shapes."""
+    size class (defaults if none), resolved once per size class; a dict or
+    Tuning: those shapes."""
     if tune is None:
         return None
     if isinstance(tune, str):
         if tune != "auto":
             raise ValueError(f"unknown tuning {tune!r}")
-        from . import autotune
-        tune = autotune.lookup(key_fn(autotune)) if key_fn else None
-        if not tune:
+        if not key_fn:
             return None
+        from . import autotune
+        key = key_fn(autotune)
+        if key not in _TUNED:
+            d = autotune.lookup(key)
+            _TUNED[key] = Tuning.from_dict(d) if d else None
+        t = _TUNED[key]
+        return ctypes.byref(t) if t is not None else None
     if isinstance(tune, dict):
         tune = Tuning.from_dict(tune)
     return ctypes.byref(tune)

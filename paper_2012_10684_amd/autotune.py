@@ -40,11 +40,23 @@ def cache_path() -> str:
     return os.environ.get("TS_AUTOTUNE_CACHE", DEFAULT_CACHE)
 
 
+_ARCH: Dict[int, str] = {}
+
+
 def _arch() -> str:
+    """Architecture name of the current device (memoised per device)."""
     try:
-        return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+        i = torch.cuda.current_device()
     except Exception:  # no GPU: keys still work for reading the cache
         return "gfx950"
+    a = _ARCH.get(i)
+    if a is None:
+        try:
+            a = torch.cuda.get_device_properties(i).gcnArchName.split(":")[0]
+        except Exception:
+            a = "gfx950"
+        _ARCH[i] = a
+    return a
 
 
 def _p2(n: int) -> int:
