@@ -60,6 +60,10 @@ WORKLOADS = {
                 False, -1024, 3071, 512, 3, (0.8,)),
 }
 
+# the timed steps record HIP events around the roofline kernel in every
+# EV_EVERY-th step only
+EV_EVERY = 4
+
 # distinct volumes generated for the batched and serving workloads; every
 # request takes the first Z slices of one of them (generation costs ~13 s
 # per 512x512x600 volume on one core)
@@ -69,7 +73,7 @@ POOL = 4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="volume300", choices=sorted(WORKLOADS),
@@ -78,6 +82,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=120, help="serving: requests replayed from the trace")
     ap.add_argument("--per-slice-sample", type=int, default=2000,
                     help="batch64: slices timed with one launch per slice and stage")
+    ap.add_argument("--inputs", type=int, default=None,
+                    help="resident copies of the input the steps cycle through (default: 4 for volume300 and "
+                         "volume600, whose volume would otherwise sit in the memory-side cache; else 1)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured as HIP graphs, checked against an eager step "
                          "(default: eager launches, measured faster on MI355X)")
@@ -266,10 +273,11 @@ def bench_open(args, wl, dev):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    roof = pairs(args.steps, ["opening"])
+    roof_d = dict(zip(range(0, args.steps, EV_EVERY), pairs(len(range(0, args.steps, EV_EVERY)), ["opening"])))
+    roof = list(roof_d.values())
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(roof[i])
+        step(roof_d.get(i))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kev = pairs(min(args.steps, 10), names)
@@ -349,10 +357,11 @@ def bench_2d(args, wl, dev):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    roof = pairs(args.steps, ["search2d"])
+    roof_d = dict(zip(range(0, args.steps, EV_EVERY), pairs(len(range(0, args.steps, EV_EVERY)), ["search2d"])))
+    roof = list(roof_d.values())
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(roof[i])
+        step(roof_d.get(i))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kev = pairs(min(args.steps, 10), names)
@@ -486,6 +495,21 @@ def main():
         dv = torch.from_numpy(vol).to(dev)
         nvox_all = int(vol.size)
         batch = api.Batch.slices(dv) if per_slice else api.Batch([dv.reshape(-1)])
+    # the steps cycle through n_in resident copies of the input, so a step
+    # does not find its voxels in the 256 MB memory-side cache from the
+    # previous step (every copy holds the same values, so every step's
+    # results are the same)
+    n_in = args.inputs if args.inputs is not None else (4 if args.workload in ("volume300", "volume600") else 1)
+    if n_in < 1:
+        raise SystemExit("--inputs must be >= 1")
+    batches = [batch]
+    for _ in range(n_in - 1):
+        if args.workload == "batch64":
+            cp = [v.clone() for v in dvols]
+            batches.append(api.Batch([v[z].reshape(-1) for v in cp for z in range(v.shape[0])]))
+        else:
+            cp = dv.clone()
+            batches.append(api.Batch.slices(cp) if per_slice else api.Batch([cp.reshape(-1)]))
     binn = api.binning(LO, HI, L)
     nseg = batch.nseg
     hist = torch.empty((nseg, L), dtype=torch.int32, device=dev)
@@ -502,13 +526,14 @@ def main():
     stream = torch.cuda.current_stream()
     names = ["histogram", "prefix", "search", "label"]
 
-    def step(ev=None, st=None, parts=("pre", "label")):
-        """One pass of the path on stream st (default: the current stream);
-        ev maps kernel names (or "step") to a (start, end) pair of events
-        recorded around that kernel; parts selects histogram + prefix +
-        search ("pre") and labels ("label")."""
+    def step(ev=None, st=None, parts=("pre", "label"), i=0):
+        """One pass of the path over input copy i on stream st (default: the
+        current stream); ev maps kernel names (or "step") to a (start, end)
+        pair of events recorded around that kernel; parts selects histogram +
+        prefix + search ("pre") and labels ("label")."""
         ev = ev or {}
         st = st or stream
+        batch = batches[i % n_in]
 
         def mark(name, i):
             if name in ev:
@@ -538,39 +563,47 @@ def main():
     def avg_us(evs, key):
         return sum(e[key][0].elapsed_time(e[key][1]) for e in evs) * 1e3 / len(evs)
 
-    for _ in range(args.warmup):
-        step()
+    for w in range(args.warmup):
+        step(i=w)
     torch.cuda.synchronize()
-    captured = None if not args.graph else capture_graphs(step, stream, hist, res, outs, args.workload == "batch64")
+    captured = None
+    if args.graph:  # one pair of graphs per input copy
+        caps = [capture_graphs(lambda j=j, **kw: step(i=j, **kw), stream, hist, res, outs,
+                               args.workload == "batch64") for j in range(n_in)]
+        captured = {"graphs": [c["graphs"] for c in caps], "verified": all(c["verified"] for c in caps)}
     graphs = captured if captured and captured["verified"] else None
     # the timed steps record events only around the label pass (the kernel
     # with the most algorithmic bytes: (2 + nq) B/voxel against the
-    # histogram's 2): each recorded event adds a few us of gap to the stream
-    roof_ev = pairs(args.steps, ["label"])
+    # histogram's 2), and only in every EV_EVERY-th step: each recorded event
+    # adds a few us of gap to the stream
+    sampled = list(range(0, args.steps, EV_EVERY))
+    roof_ev = {s: p for s, p in zip(sampled, pairs(len(sampled), ["label"]))}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if graphs is not None:
         # one step = the replay of the histogram/prefix/search graph, then
         # the replay of the label graph, both on this stream
-        g_pre, g_lab = graphs["graphs"]
         for s in range(args.steps):
+            g_pre, g_lab = graphs["graphs"][s % n_in]
             g_pre.replay()
-            roof_ev[s]["label"][0].record(stream)
+            if s in roof_ev:
+                roof_ev[s]["label"][0].record(stream)
             g_lab.replay()
-            roof_ev[s]["label"][1].record(stream)
+            if s in roof_ev:
+                roof_ev[s]["label"][1].record(stream)
     else:
         for s in range(args.steps):
-            step(roof_ev[s])
+            step(roof_ev.get(s), i=s)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
-    label_t = avg_us(roof_ev, "label") * 1e-6
+    label_t = avg_us(list(roof_ev.values()), "label") * 1e-6
     if graphs is not None:
         # the same steps launched eagerly (untimed for the record)
         torch.cuda.synchronize()
         te = time.perf_counter()
         for s in range(args.steps):
-            step()
+            step(i=s)
         torch.cuda.synchronize()
         graphs["eager_ms_per_step"] = (time.perf_counter() - te) / args.steps * 1e3
     # untimed passes after the timed region: events around every kernel (the
@@ -578,10 +611,10 @@ def main():
     nb = min(args.steps, 20)
     kev = pairs(nb, names)
     for s in range(nb):
-        step(kev[s])
+        step(kev[s], i=s)
     sev = pairs(args.steps, ["step"])
     for s in range(args.steps):
-        step(sev[s])
+        step(sev[s], i=s)
     torch.cuda.synchronize()
     per = {n: avg_us(kev, n) * 1e-6 for n in names}
 
@@ -611,7 +644,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "problems": nseg, "voxels": nvox, "bins": L, "k": K, "q": list(QS)},
+        "config": {"workload": desc, "problems": nseg, "voxels": nvox, "bins": L, "k": K, "q": list(QS),
+                   "input_copies": n_in},
         "tuples_per_s": tuples * args.steps / dt,
         "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
         "kernel_us_note": "from an untimed pass with events around every kernel (each event adds a gap)",
