@@ -5,9 +5,11 @@
 // b(v) > t  <=>  v >= cut(t) = lo + ceil((t + 1) * W / L)   (W = hi - lo + 1),
 // which also covers values outside the window (below lo: bin 0, never above a
 // threshold; above hi: bin L-1, above every threshold since cut(t) <= hi + 1).
-// So each voxel costs k integer compares.  One-shot grid over tiles of the
-// flattened batch; 16-byte loads of 8 voxels and 8-byte stores of 8 labels
-// where the input and output phases agree, element-wise code elsewhere.
+// So each voxel costs k integer compares; on the vector path two voxels
+// share each operation (packed 16-bit arithmetic).  One-shot grid over tiles
+// of the flattened batch; 16-byte loads of 8 voxels and 8-byte stores of 8
+// labels where the input and output phases agree, element-wise code
+// elsewhere.
 #include <algorithm>
 
 #include "common.h"
@@ -17,8 +19,8 @@ namespace ts {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
-// Cut values of one threshold set: label = #{j : v >= c[j]}.  KM = 3 holds
-// k <= 3 thresholds, KM = LABEL_MAX_K up to that many; unused cuts are never
+// Cut values of one threshold set: label = #{j : v >= c[j]}.  KM = k for k
+// <= 3; KM = LABEL_MAX_K holds up to that many, unused cuts are never
 // reached.
 constexpr int LABEL_MAX_K = TS_DP_MAX_K;
 
@@ -66,23 +68,75 @@ __device__ __forceinline__ uint32_t lab1(int v, const Cuts<KM> &c)
     return n;
 }
 
-// labels of the two int16 in a dword, packed as bytes 0 and 1 of the result
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+
+// Cut values as int16 for the packed path: label = nk - #{j : v < c[j]},
+// where v < c  <=>  the saturated int16 difference v - c is negative (the
+// true difference lies in [-65535, 65535] and saturation keeps its sign).
+// The cut is clamped to [-32768, 32768] and its low 16 bits kept: a cut
+// above 32767 is never reached and becomes 0x8000 = -32768 (v < c never
+// holds), left out of nk; a cut at or below -32768 is always reached, -32768
+// again, counted in nk.  (No select picks the disabled value: the compiler
+// in use dropped such a select when its result fed the packed subtract.)
+// base = nk in every byte.
 template <int KM>
-__device__ __forceinline__ uint32_t lab2(uint32_t w, const Cuts<KM> &c)
-{
-    int v0 = (int)(int16_t)(w & 0xffffu);
-    int v1 = (int)(int16_t)(w >> 16);
-    return lab1(v0, c) | (lab1(v1, c) << 8);
-}
+struct PCuts {
+    int c[KM]; // int16 values (int elements stay in registers at every KM)
+    uint32_t base;
+};
 
 template <int KM>
-__device__ __forceinline__ v2u lab8(const v4i &w, const Cuts<KM> &c)
+__device__ __forceinline__ PCuts<KM> pack_cuts(const Cuts<KM> &c)
 {
-    uint32_t a = lab2((uint32_t)w.x, c) | (lab2((uint32_t)w.y, c) << 16);
-    uint32_t b = lab2((uint32_t)w.z, c) | (lab2((uint32_t)w.w, c) << 16);
+    PCuts<KM> p;
+    uint32_t nk = 0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        p.c[j] = min(max(c.c[j], -32768), 32768);
+        nk += c.c[j] <= 32767 ? 1u : 0u;
+    }
+    p.base = nk * 0x01010101u;
+    return p;
+}
+
+// Label of one voxel from the packed cuts (the same rule as lab8).
+template <int KM>
+__device__ __forceinline__ uint32_t lab1p(int v, const PCuts<KM> &p)
+{
+    const s2 vv = {(short)v, (short)v};
+    u2 acc = {0, 0};
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const s2 c = {(short)p.c[j], (short)p.c[j]};
+        acc += __builtin_bit_cast(u2, __builtin_elementwise_sub_sat(vv, c)) >> (u2){15, 15};
+    }
+    return (p.base & 0xffu) - (uint32_t)acc.x;
+}
+
+// Labels of 8 int16 voxels (16 bytes) as 8 bytes: two voxels per packed
+// 16-bit operation (saturating subtract, sign bit, add), then the 16-bit
+// counts are gathered into bytes and subtracted from nk (no borrow: every
+// count is <= nk).
+template <int KM>
+__device__ __forceinline__ v2u lab8(const v4i &w, const PCuts<KM> &p)
+{
+    uint32_t n[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const s2 v = __builtin_bit_cast(s2, (uint32_t)w[d]);
+        u2 acc = {0, 0};
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+            const s2 c = {(short)p.c[j], (short)p.c[j]};
+            acc += __builtin_bit_cast(u2, __builtin_elementwise_sub_sat(v, c)) >> (u2){15, 15};
+        }
+        n[d] = __builtin_bit_cast(uint32_t, acc);
+    }
+    // bytes 0 and 2 of n[0] (voxels 0, 1), then of n[1] (voxels 2, 3)
     v2u r;
-    r.x = a;
-    r.y = b;
+    r.x = p.base - __builtin_amdgcn_perm(n[1], n[0], 0x06040200u);
+    r.y = p.base - __builtin_amdgcn_perm(n[3], n[2], 0x06040200u);
     return r;
 }
 
@@ -121,7 +175,7 @@ __device__ __forceinline__ void wave_cuts(const LabelSets &sets, int s, int k, c
     for (int u2 = 0; u2 < NS; ++u2) {
 #pragma unroll
         for (int j2 = 0; j2 < KM; ++j2) // up to 64 values: vector registers beyond the 3-cut case
-            cuts[u2].c[j2] = KM == 3 ? __builtin_amdgcn_readlane(c, KM * u2 + j2) : __shfl(c, KM * u2 + j2, 64);
+            cuts[u2].c[j2] = KM <= 3 ? __builtin_amdgcn_readlane(c, KM * u2 + j2) : __shfl(c, KM * u2 + j2, 64);
     }
 }
 
@@ -174,6 +228,10 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
         }
         const int n = (int)(t1 - t0);
         if (vec) {
+            PCuts<KM> pc[NS];
+#pragma unroll
+            for (int u = 0; u < NS; ++u)
+                pc[u] = pack_cuts(cuts[u]);
             const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(src);
             const int nvec = n >> 3;
             v4i w[U];
@@ -188,7 +246,7 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
                 if (i < nvec) {
 #pragma unroll
                     for (int u = 0; u < NS; ++u)
-                        __builtin_nontemporal_store(lab8(w[j], cuts[u]),
+                        __builtin_nontemporal_store(lab8(w[j], pc[u]),
                                                     reinterpret_cast<TS_GLOBAL v2u *>(dst[u]) + i);
                 }
             }
@@ -197,7 +255,7 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
                 const int v = src[tb + threadIdx.x];
 #pragma unroll
                 for (int u = 0; u < NS; ++u)
-                    dst[u][tb + threadIdx.x] = (uint8_t)lab1(v, cuts[u]);
+                    dst[u][tb + threadIdx.x] = (uint8_t)lab1p(v, pc[u]);
             }
         } else {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -256,10 +314,12 @@ ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &set
     if (grid > 0x7fffffff)
         return fail(TS_ERR_INVALID_ARG, "ts_label: batch too large for one launch");
     const dim3 g((unsigned)grid), blk(t.label_block);
-    if (k <= 3)
-        launch_label_km<3>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k);
-    else
-        launch_label_km<LABEL_MAX_K>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k);
+    switch (k) { // as many cut values as thresholds up to 3, else the 16-cut instance
+    case 1: launch_label_km<1>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k); break;
+    case 2: launch_label_km<2>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k); break;
+    case 3: launch_label_km<3>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k); break;
+    default: launch_label_km<LABEL_MAX_K>(nsets, t.label_vecs, g, blk, st, b, bm, sets, k); break;
+    }
     return check_launch("ts_label");
 }
 

@@ -261,6 +261,41 @@ def test_label_ragged(ragged):
                 assert np.array_equal(outs[i].cpu().numpy(), want), (lo, hi, L, k, i)
 
 
+@pytest.mark.parametrize("win", [(32760, 32767, 16), (-32768, -32760, 16), (-32768, 32767, 4096), (32767, 32767, 4),
+                                 (-32768, -32768, 5), (-1024, -200, 256)], ids=lambda w: f"{w[0]}_{w[1]}_{w[2]}")
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_label_every_int16(win, k):
+    """Every int16 value, shuffled, in problems whose lengths are and are not
+    multiples of 8: windows at both ends of the int16 range (cut values of
+    -32767 and of 32768, the latter reached by no voxel), one and three
+    threshold sets, thresholds including 0 and L - 2."""
+    lo, hi, L = win
+    if L - 1 < k:
+        pytest.skip("fewer than k + 1 bins")
+    rng = np.random.default_rng(k * 1000 + L)
+    allv = rng.permutation(np.arange(-32768, 32768, dtype=np.int64).astype(np.int16))
+    cuts = [0, 8192, 8195, 40000, 65536]  # problems of 8192, 3, 31805 and 25536 voxels
+    segs = [allv[a:b] for a, b in zip(cuts[:-1], cuts[1:])]
+    dsegs = [to_dev(sg) for sg in segs]
+    thrs = []
+    for u in range(3):
+        rows = [np.sort(rng.choice(L - 1, k, replace=False)) for _ in segs]
+        rows[u % len(segs)][0] = 0
+        rows[(u + 1) % len(segs)][-1] = L - 2
+        for r in rows:
+            r.sort()
+        thrs.append(np.stack(rows).astype(np.int32))
+    b = api.Batch(dsegs)
+    binn = api.binning(lo, hi, L)
+    one = api.label(b, binn, to_dev(thrs[0]), k)
+    sets = api.label_sets(b, binn, [to_dev(t) for t in thrs], k)
+    torch.cuda.synchronize()
+    for i, sg in enumerate(segs):
+        assert np.array_equal(one[i].cpu().numpy(), oracle.label(sg, lo, hi, L, thrs[0][i])), (win, k, i)
+        for u in range(3):
+            assert np.array_equal(sets[u][i].cpu().numpy(), oracle.label(sg, lo, hi, L, thrs[u][i])), (win, k, u, i)
+
+
 @pytest.mark.parametrize("k", [4, 7, 16])
 def test_label_many_thresholds_ragged(ragged, k):
     """k >= 4 thresholds (the DP search's range): labels 0..k bit-exact on
