@@ -105,6 +105,16 @@ __device__ __forceinline__ int find_segment(const int64_t *offs, int nseg, int64
     return lo;
 }
 
+// A guess at the segment holding flattened position pos (0 <= pos < total),
+// exact for segments of equal size: callers check it with the two offsets
+// around it (loaded together with whatever they load for that segment) and
+// fall back to find_segment when it is wrong.
+__device__ __forceinline__ int guess_segment(int nseg, int64_t total, int64_t pos)
+{
+    const double f = (double)pos / (double)total * (double)nseg; // rounding only costs the fallback
+    return (int)min((double)(nseg - 1), f);
+}
+
 // ---------------------------------------------------------------- reductions
 // Wavefront reductions with DPP lane moves (full-rate VALU; no LDS round
 // trips): swaps within quads, mirrors within half-rows and rows, then the

@@ -78,7 +78,11 @@ __global__ void __launch_bounds__(1024) k_histogram(const int16_t *const *__rest
     if (beg >= end)
         return;
     const uint32_t rep = threadIdx.x % R;
-    int s = find_segment(offs, nseg, beg);
+    // the segment of the first voxel: an arithmetic guess checked with two
+    // offsets in one round trip (a binary search only when it is wrong)
+    int s = guess_segment(nseg, total, beg);
+    if (!(offs[s] <= beg && beg < offs[s + 1]))
+        s = find_segment(offs, nseg, beg);
     int64_t pos = beg;
     while (pos < end) {
         // skip empty problems that start at pos

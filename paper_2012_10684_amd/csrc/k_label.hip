@@ -140,15 +140,6 @@ __device__ __forceinline__ v2u lab8(const v4i &w, const PCuts<KM> &p)
     return r;
 }
 
-// Segment holding flattened position pos: the guess for equal-size segments
-// is checked with the two offsets around it (loaded together with whatever
-// the caller loads for that segment); a binary search settles a wrong guess.
-__device__ __forceinline__ int guess_segment(const int64_t *offs, int nseg, int64_t total, int64_t pos)
-{
-    const double f = (double)pos / (double)total * (double)nseg; // a guess: rounding is harmless
-    return (int)min((double)(nseg - 1), f);
-}
-
 // Cut values of problem s for every set, computed by one lane per (set,
 // threshold) and broadcast through readlane (wavefront-uniform results).
 // (t+1) W <= 4095 * 65536 < 2^32, so the ceiling division is exact in uint32.
@@ -196,7 +187,7 @@ __global__ void __launch_bounds__(1024) k_label(const int16_t *const *__restrict
     const int64_t t1 = min(total, t0 + T);
     // everything the tile needs from the guessed segment is loaded in one
     // round trip; a wrong guess (uneven segments) is corrected afterwards
-    int s = guess_segment(offs, nseg, total, t0);
+    int s = guess_segment(nseg, total, t0);
     int64_t o0 = offs[s], o1 = offs[s + 1];
     const int16_t *vs = vox[s];
     uint8_t *os[NS];
