@@ -60,6 +60,10 @@ WORKLOADS = {
                 False, -1024, 3071, 512, 3, (0.8,)),
 }
 
+# the oracle's timed sample is repeated until this much CPU time has run
+CPU_MIN_S = 10.0
+CPU_MAX_PASSES = 100000
+
 # the timed steps record HIP events around the roofline kernel in every
 # EV_EVERY-th step only
 EV_EVERY = 4
@@ -120,29 +124,43 @@ def cpu_baseline(vol, nslices: int, wl, gpu_thr=None, gpu_obj=None):
     import oracle
 
     _, per_slice, LO, HI, L, K, QS = wl
-    refs = []
-    t0 = time.perf_counter()
-    if per_slice:
-        sample = vol[:nslices]
-        for z in range(sample.shape[0]):
-            h = oracle.histogram(sample[z], LO, HI, L)
+    sample = vol[:nslices] if per_slice else vol
+
+    def one_pass(refs):
+        if per_slice:
+            for z in range(sample.shape[0]):
+                h = oracle.histogram(sample[z], LO, HI, L)
+                for j, q in enumerate(QS):
+                    r = oracle.search(h, K, q, oracle.MODE_PREFIX)
+                    oracle.label(sample[z].reshape(-1), LO, HI, L, r.thr)
+                    refs.append((j, z, r))
+        else:
+            h = oracle.histogram(sample, LO, HI, L)
             for j, q in enumerate(QS):
                 r = oracle.search(h, K, q, oracle.MODE_PREFIX)
-                oracle.label(sample[z].reshape(-1), LO, HI, L, r.thr)
-                refs.append((j, z, r))
-        what = f"{sample.shape[0]} of the {vol.shape[0]} slices: oracle histogram + {len(QS)} x (prefix-mode k={K} search + labels)"
+                oracle.label(sample.reshape(-1), LO, HI, L, r.thr)
+                refs.append((j, 0, r))
+
+    if per_slice:
+        what = (f"{sample.shape[0]} of the {vol.shape[0]} slices: oracle histogram + {len(QS)} x "
+                f"(prefix-mode k={K} search + labels)")
     else:
-        sample = vol
-        h = oracle.histogram(sample, LO, HI, L)
-        for j, q in enumerate(QS):
-            r = oracle.search(h, K, q, oracle.MODE_PREFIX)
-            oracle.label(sample.reshape(-1), LO, HI, L, r.thr)
-            refs.append((j, 0, r))
         what = f"the whole input: oracle histogram + prefix-mode k={K} search + labels"
-    dt = time.perf_counter() - t0
-    nvox = int(np.prod(sample.shape))
+    # the sample is passed over again until CPU_MIN_S of oracle work has run
+    # (at most CPU_MAX_PASSES passes), so short samples are timed over a
+    # stable interval
+    refs = []
+    passes = 0
+    t0 = time.perf_counter()
+    while True:
+        one_pass(refs if passes == 0 else [])
+        passes += 1
+        dt = time.perf_counter() - t0
+        if dt >= CPU_MIN_S or passes >= CPU_MAX_PASSES:
+            break
+    nvox = int(np.prod(sample.shape)) * passes
     base = {"value": nvox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}, {dt:.2f} s single-threaded"}
+            "sample": f"{what}, {passes} pass(es), {dt:.2f} s single-threaded"}
     check = None
     if gpu_thr is not None:
         same, err, near = 0, 0.0, 0
