@@ -182,7 +182,7 @@ struct LabelSets {
     const int32_t *thr[TS_MAX_LABEL_SETS];
     uint8_t *const *out[TS_MAX_LABEL_SETS];
 };
-__global__ void k_fill_u32(uint32_t *p, int64_t n); // k_histogram.hip
+ts_status launch_fill_u32(uint32_t *p, int64_t n, hipStream_t st); // zero n words (k_histogram.hip)
 size_t hist2d_lds_bytes(int L, int H, int W);
 ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint32_t *hist, hipStream_t st);
 size_t search2d_workspace_bytes(int nseg, int nq, int L);

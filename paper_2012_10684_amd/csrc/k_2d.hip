@@ -202,8 +202,11 @@ ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint3
     if (W > H2_MAX_W || bm.L > H2_MAX_L)
         return fail(TS_ERR_INVALID_ARG, "ts_histogram2d: width or nbins beyond the LDS layout");
     const int64_t n = (int64_t)b.nseg * bm.L * bm.L;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, st, hist,
-                       n);
+    {
+        ts_status e = launch_fill_u32(hist, n, st);
+        if (e != TS_OK)
+            return e;
+    }
     const Hist2dShape sh = hist2d_shape(bm.L, H, W);
     const int rows = sh.rows_per_wg, chunk = sh.chunk_rows;
     const size_t lds = sh.lds;

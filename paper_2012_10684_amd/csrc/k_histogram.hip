@@ -24,12 +24,31 @@ namespace ts {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// Zero n words: the words before the first 16-byte boundary, then 16-byte
+// stores, then the last n mod 4 words (p is 4-byte aligned).
 __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride)
+    const int64_t head = min(n, (int64_t)(((16u - ((uintptr_t)p & 15u)) & 15u) >> 2));
+    const int64_t nv = (n - head) >> 2;
+    uint4 *v = reinterpret_cast<uint4 *>(p + head);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = i; j < nv; j += stride)
+        v[j] = make_uint4(0u, 0u, 0u, 0u);
+    if (i < head)
         p[i] = 0u;
+    const int64_t t0 = head + (nv << 2);
+    if (i < n - t0)
+        p[t0 + i] = 0u;
+}
+
+ts_status launch_fill_u32(uint32_t *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0)
+        return TS_OK;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ((n >> 2) + 255) / 256));
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, p, n);
+    return check_launch("zero fill");
 }
 
 template <int R, int MAP>
@@ -173,9 +192,7 @@ ts_status launch_histogram(const ts_batch &b, const BinMap &bm, uint32_t *hist, 
 {
     const int64_t nh = (int64_t)b.nseg * bm.L;
     {
-        int grid = (int)std::min<int64_t>((nh + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, hist, nh);
-        ts_status e = check_launch("ts_histogram (zero fill)");
+        ts_status e = launch_fill_u32(hist, nh, st);
         if (e != TS_OK)
             return e;
     }

@@ -66,6 +66,25 @@ def test_histogram_every_int16(win):
     assert np.array_equal(h, oracle.histogram(allv, lo, hi, L)), win
 
 
+@pytest.mark.parametrize("off", [0, 1, 2, 3])
+@pytest.mark.parametrize("L", [13, 256])
+def test_histogram_into_offset_view(ragged, off, L):
+    """The output may start at any word: the zero fill's head, 16-byte body
+    and tail all land in the histogram rows and nowhere else, over a buffer
+    holding junk from an earlier use."""
+    host, base, segs = ragged
+    lo, hi = (-5, 7) if L == 13 else (-1024, -200)
+    n = len(segs) * L
+    buf = torch.full((n + 8,), 0x5EED, dtype=torch.int32, device=base.device)
+    out = buf[off:off + n].view(len(segs), L)
+    api.histogram(api.Batch(segs), api.binning(lo, hi, L), out=out)
+    got = buf.cpu().numpy()
+    assert np.all(got[:off] == 0x5EED) and np.all(got[off + n:] == 0x5EED), "words outside the rows changed"
+    h = got[off:off + n].reshape(len(segs), L).view(np.uint32)
+    for i, sg in enumerate(segs):
+        assert np.array_equal(h[i], oracle.histogram(sg.cpu().numpy(), lo, hi, L)), (off, L, i)
+
+
 @pytest.mark.parametrize("tune", [None, dict(hist_replicas=1, hist_block=64), dict(hist_replicas=4, hist_block=1024),
                                   dict(hist_wg_per_cu=1, min_chunk=512)], ids=["default", "r1b64", "r4b1024", "small"])
 def test_histogram_tuning_invariant(ragged, tune):
