@@ -98,8 +98,12 @@ def parse():
 
 
 def src_hash(name: str) -> str:
-    p = os.path.join(ROOT, "paper_2012_10684_amd", "csrc", name)
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of a kernel's source file and the header every kernel includes."""
+    d = os.path.join(ROOT, "paper_2012_10684_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (name, "common.h"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel_file: str, workload: str):
