@@ -469,8 +469,9 @@ def capture_graphs(step, stream, hist, res, outs, sample_labels: bool):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
-              f"(the per-slice problems are independent: see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (independent problems would be "
+              f"sharded across GPUs by voxel count with no exchange; one large volume needs three small "
+              f"collectives per step)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
