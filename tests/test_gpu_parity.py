@@ -407,7 +407,7 @@ def test_label_tuning_invariant(ragged, tune):
              (api.Batch([long]), [long.cpu().numpy()])]
     lo, hi, L = -1024, 3071, 1024
     for b, hosts in cases:
-        for k in (1, 3):
+        for k in (1, 2, 3):
             thrs = [np.stack([np.sort(rng.choice(L - 1, k, replace=False)) for _ in hosts]).astype(np.int32)
                     for _ in range(2)]
             outs = api.label_sets(b, api.binning(lo, hi, L), [to_dev(t) for t in thrs], k, tune=tune)
