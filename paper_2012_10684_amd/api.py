@@ -380,6 +380,13 @@ def batch_segment(volumes: Sequence[torch.Tensor], bin: Binning, k: int, q, per:
     runs in libts."""
     if per not in ("slice", "volume"):
         raise ValueError("per must be 'slice' or 'volume'")
+    # every tensor this call makes (copies, outputs) is allocated on the
+    # stream the kernels run on
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+        return _batch_segment(volumes, bin, k, q, per, mode, method, open_radius, tune, stream)
+
+
+def _batch_segment(volumes, bin, k, q, per, mode, method, open_radius, tune, stream) -> Segmentation:
     vols = [v.contiguous() for v in volumes]
     qs, batched = _qs(q)
     if len(qs) > MAX_LABEL_SETS:
@@ -412,18 +419,14 @@ def batch_segment(volumes: Sequence[torch.Tensor], bin: Binning, k: int, q, per:
         thr, obj, status = threshold_search_dp(P, Q, k, list(qs), stream=stream)
     else:
         thr, obj, status = threshold_search(P, Q, k, list(qs), mode, tune=tune, stream=stream)
-    maps = label_sets(batch, bin, [thr[j] for j in range(len(qs))], k, tune=tune, stream=stream)
-    labels = []
-    for j in range(len(qs)):
-        per_vol, i = [], 0
-        for v in src:
-            if per == "slice":
-                per_vol.append(torch.stack([maps[j][i + z].view(v.shape[1:]) for z in range(v.shape[0])]))
-                i += v.shape[0]
-            else:
-                per_vol.append(maps[j][i].view(v.shape))
-                i += 1
-        labels.append(per_vol)
+    # label maps in each volume's shape; the label pass writes every problem
+    # straight into its slice (or volume) of them
+    labels = [[torch.empty(v.shape, dtype=torch.uint8, device=v.device) for v in src] for _ in qs]
+    if per == "slice":
+        outs = [[lv[z].reshape(-1) for lv in lj for z in range(lv.shape[0])] for lj in labels]
+    else:
+        outs = [[lv.reshape(-1) for lv in lj] for lj in labels]
+    label_sets(batch, bin, [thr[j] for j in range(len(qs))], k, outs=outs, tune=tune, stream=stream)
     return Segmentation(h, thr, obj, status, labels, residues)
 
 

@@ -77,3 +77,23 @@ def test_batch_segment_after_the_opening():
             want = oracle.label(rr16, 0, L - 1, L, thr[0, i]).reshape(v.shape[1:])
             assert np.array_equal(res.labels[0][vi][z].cpu().numpy(), want), (vi, z)
             i += 1
+
+
+def test_batch_segment_on_a_side_stream():
+    """Given a stream, every kernel and every tensor the call makes is on
+    that stream: after synchronising it alone the results equal those of a
+    call on the current stream, bit for bit."""
+    rng = np.random.default_rng(9)
+    vols = [to_dev(v) for v in _vols(rng, [(4, 64, 72), (2, 31, 45)])]
+    binn = api.binning(-1024, -200, 256)
+    ref = api.batch_segment(vols, binn, 2, (0.8, 1.5), per="slice")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    got = api.batch_segment(vols, binn, 2, (0.8, 1.5), per="slice", stream=s)
+    s.synchronize()
+    assert torch.equal(got.hist, ref.hist) and torch.equal(got.thr, ref.thr) and torch.equal(got.status, ref.status)
+    assert torch.equal(got.obj.view(torch.int64), ref.obj.view(torch.int64))
+    for j in range(2):
+        for vi in range(len(vols)):
+            assert torch.equal(got.labels[j][vi], ref.labels[j][vi]), (j, vi)
