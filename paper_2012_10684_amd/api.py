@@ -17,6 +17,7 @@ order).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from typing import Iterable, List, Optional, Sequence
@@ -115,6 +116,13 @@ def _stream(stream) -> Optional[int]:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Context in which the binding allocates the tensors of a call: the
+    stream the call's kernels run on, so the caching allocator reuses that
+    memory only after them (torch's current stream when none is given)."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -197,8 +205,8 @@ def binning(lo: int, hi: int, nbins: int) -> Binning:
 
 def histogram(batch: Batch, bin: Binning, out: Optional[torch.Tensor] = None, tune=None, stream=None):
     if out is None:
-        dev = batch.ptrs.device
-        out = torch.empty((batch.nseg, bin.nbins), dtype=torch.int32, device=dev)
+        with _on(stream):
+            out = torch.empty((batch.nseg, bin.nbins), dtype=torch.int32, device=batch.ptrs.device)
     t = _tune(tune, lambda a: a.key_histogram(batch.nseg, batch.total, bin.nbins))
     _check(_lib.ts_histogram(batch._c, bin, _ptr(out), t, _stream(stream)))
     return out
@@ -220,10 +228,11 @@ def prefix(hist: torch.Tensor, q, P=None, Q=None, stream=None):
     """P [nseg, L] and Q: [nseg, L] for a scalar q, [nq, nseg, L] for a sequence."""
     nseg, L = hist.shape
     qs, batched = _qs(q)
-    if P is None:
-        P = torch.empty((nseg, L), dtype=torch.float64, device=hist.device)
-    if Q is None:
-        Q = torch.empty(((len(qs),) if batched else ()) + (nseg, L), dtype=torch.float64, device=hist.device)
+    with _on(stream):
+        if P is None:
+            P = torch.empty((nseg, L), dtype=torch.float64, device=hist.device)
+        if Q is None:
+            Q = torch.empty(((len(qs),) if batched else ()) + (nseg, L), dtype=torch.float64, device=hist.device)
     _check(_lib.ts_prefix(_ptr(hist), nseg, L, len(qs), _qarr(qs), _ptr(P), _ptr(Q), _stream(stream)))
     return P, Q
 
@@ -241,14 +250,15 @@ def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q, mode: int = SE
     nq = len(qs)
     lead = (nq,) if batched else ()
     need = workspace_bytes(nseg, L, k, mode, nq)
-    if ws is None:
-        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=P.device)
-    if out is None:
-        thr = torch.empty(lead + (nseg, k), dtype=torch.int32, device=P.device)
-        obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=P.device)
-        status = torch.empty(lead + (nseg,), dtype=torch.int32, device=P.device)
-    else:
-        thr, obj, status = out
+    with _on(stream):
+        if ws is None:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=P.device)
+        if out is None:
+            thr = torch.empty(lead + (nseg, k), dtype=torch.int32, device=P.device)
+            obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=P.device)
+            status = torch.empty(lead + (nseg,), dtype=torch.int32, device=P.device)
+        else:
+            thr, obj, status = out
     t = _tune(tune, lambda a: a.key_search(nseg * nq, L, k, mode))
     _check(_lib.ts_threshold_search(_ptr(P), _ptr(Q), nseg, L, int(k), nq, _qarr(qs), int(mode), _ptr(ws),
                                     ws.numel(), _ptr(thr), _ptr(obj), _ptr(status), t, _stream(stream)))
@@ -268,15 +278,16 @@ def open2d(batch: Batch, height: int, width: int, bin: Binning, radius: int = 10
     wanted."""
     dev = batch.ptrs.device
     shape = (batch.nseg, height, width)
-    if opened is None and "opened" in want:
-        opened = torch.empty(shape, dtype=torch.uint8, device=dev)
-    if residue is None and "residue" in want:
-        residue = torch.empty(shape, dtype=torch.uint8, device=dev)
-    if residue16 is None and "residue16" in want:
-        residue16 = torch.empty(shape, dtype=torch.int16, device=dev)
     need = int(_lib.ts_open2d_workspace_bytes(batch.nseg, height, width))
-    if ws is None:
-        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    with _on(stream):
+        if opened is None and "opened" in want:
+            opened = torch.empty(shape, dtype=torch.uint8, device=dev)
+        if residue is None and "residue" in want:
+            residue = torch.empty(shape, dtype=torch.uint8, device=dev)
+        if residue16 is None and "residue16" in want:
+            residue16 = torch.empty(shape, dtype=torch.int16, device=dev)
+        if ws is None:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
 
     def p(t):
         return _ptr(t) if t is not None else None
@@ -299,14 +310,15 @@ def threshold_search_dp(P: torch.Tensor, Q: torch.Tensor, k: int, q, ws: Optiona
     nq = len(qs)
     lead = (nq,) if batched else ()
     need = workspace_dp_bytes(nseg, L, k, nq)
-    if ws is None:
-        ws = torch.empty(max(need, 8), dtype=torch.uint8, device=P.device)
-    if out is None:
-        thr = torch.empty(lead + (nseg, k), dtype=torch.int32, device=P.device)
-        obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=P.device)
-        status = torch.empty(lead + (nseg,), dtype=torch.int32, device=P.device)
-    else:
-        thr, obj, status = out
+    with _on(stream):
+        if ws is None:
+            ws = torch.empty(max(need, 8), dtype=torch.uint8, device=P.device)
+        if out is None:
+            thr = torch.empty(lead + (nseg, k), dtype=torch.int32, device=P.device)
+            obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=P.device)
+            status = torch.empty(lead + (nseg,), dtype=torch.int32, device=P.device)
+        else:
+            thr, obj, status = out
     _check(_lib.ts_threshold_search_dp(_ptr(P), _ptr(Q), nseg, L, int(k), nq, _qarr(qs), _ptr(ws), ws.numel(),
                                        _ptr(thr), _ptr(obj), _ptr(status), _stream(stream)))
     return thr, obj, status
@@ -316,7 +328,8 @@ def label(batch: Batch, bin: Binning, thr: torch.Tensor, k: int, outs: Optional[
           out_ptrs: Optional[torch.Tensor] = None, tune=None, stream=None):
     dev = batch.ptrs.device
     if outs is None:
-        outs = [torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes]
+        with _on(stream):
+            outs = [torch.empty(n, dtype=torch.uint8, device=dev) for n in batch.sizes]
     if out_ptrs is None:
         out_ptrs = device_table([o.data_ptr() for o in outs], dev, stream)
     t = _tune(tune, lambda a: a.key_label(batch.nseg, batch.total, k))
@@ -334,7 +347,8 @@ def label_sets(batch: Batch, bin: Binning, thrs: Sequence[torch.Tensor], k: int,
     dev = batch.ptrs.device
     n = len(thrs)
     if outs is None:
-        outs = [[torch.empty(m, dtype=torch.uint8, device=dev) for m in batch.sizes] for _ in range(n)]
+        with _on(stream):
+            outs = [[torch.empty(m, dtype=torch.uint8, device=dev) for m in batch.sizes] for _ in range(n)]
     if out_ptrs is None:
         out_ptrs = [device_table([o.data_ptr() for o in oq], dev, stream) for oq in outs]
     thr_arr = (ctypes.c_void_p * max(n, 1))(*[t.data_ptr() for t in thrs])
@@ -382,7 +396,7 @@ def batch_segment(volumes: Sequence[torch.Tensor], bin: Binning, k: int, q, per:
         raise ValueError("per must be 'slice' or 'volume'")
     # every tensor this call makes (copies, outputs) is allocated on the
     # stream the kernels run on
-    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+    with _on(stream):
         return _batch_segment(volumes, bin, k, q, per, mode, method, open_radius, tune, stream)
 
 
@@ -434,7 +448,8 @@ def log2_f32(x: torch.Tensor, stream=None) -> torch.Tensor:
     """The FP32 base-2 logarithm the search keys use (diagnostic)."""
     if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous float32 CUDA tensor")
-    y = torch.empty_like(x)
+    with _on(stream):
+        y = torch.empty_like(x)
     _check(_lib.ts_log2_f32(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
     return y
 
@@ -444,7 +459,8 @@ def histogram2d(batch: Batch, height: int, width: int, bin: Binning, out: Option
     """2D histograms uint32 [nseg, L, L] (int32 storage) of height x width images."""
     L = bin.nbins
     if out is None:
-        out = torch.empty((batch.nseg, L, L), dtype=torch.int32, device=batch.ptrs.device)
+        with _on(stream):
+            out = torch.empty((batch.nseg, L, L), dtype=torch.int32, device=batch.ptrs.device)
     _check(_lib.ts_histogram2d(batch._c, int(height), int(width), bin, _ptr(out), _stream(stream)))
     return out
 
@@ -462,14 +478,15 @@ def threshold_search2d(hist2d: torch.Tensor, q, ws: Optional[torch.Tensor] = Non
     nq = len(qs)
     lead = (nq,) if batched else ()
     need = workspace2d_bytes(nseg, L, nq)
-    if ws is None:
-        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=hist2d.device)
-    if out is None:
-        thr = torch.empty(lead + (2, nseg), dtype=torch.int32, device=hist2d.device)
-        obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=hist2d.device)
-        status = torch.empty(lead + (nseg,), dtype=torch.int32, device=hist2d.device)
-    else:
-        thr, obj, status = out
+    with _on(stream):
+        if ws is None:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=hist2d.device)
+        if out is None:
+            thr = torch.empty(lead + (2, nseg), dtype=torch.int32, device=hist2d.device)
+            obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=hist2d.device)
+            status = torch.empty(lead + (nseg,), dtype=torch.int32, device=hist2d.device)
+        else:
+            thr, obj, status = out
     _check(_lib.ts_threshold_search2d(_ptr(hist2d), nseg, L, nq, _qarr(qs), _ptr(ws), ws.numel(), _ptr(thr),
                                       _ptr(obj), _ptr(status), _stream(stream)))
     return thr, obj, status
