@@ -254,27 +254,45 @@ size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t
     return search_workspace_bytes(nseg * nq, nbins, k, mode, 4);
 }
 
+} // extern "C"
+
+namespace ts {
+
+ts_status check_search_args(const char *fn, const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
+                            int32_t nq, const double *q, int32_t mode, int32_t *thr, double *obj, int32_t *status)
+{
+    const std::string f(fn);
+    if (nseg < 0)
+        return fail(TS_ERR_INVALID_ARG, f + ": nseg must be >= 0");
+    if (nbins < 2 || nbins > MAX_BINS)
+        return fail(TS_ERR_INVALID_ARG, f + ": nbins must be in [2, 4096]");
+    if (k < 1 || k > 3)
+        return fail(TS_ERR_INVALID_ARG, f + ": k must be 1, 2 or 3");
+    if (nbins < k + 1)
+        return fail(TS_ERR_INVALID_ARG, f + ": nbins must be >= k + 1");
+    if (mode < 0 || mode > TS_SEARCH_SUMPROD)
+        return fail(TS_ERR_INVALID_ARG, f + ": unknown mode");
+    ts_status st;
+    if ((st = check_q(fn, nq, q, true)) != TS_OK)
+        return st;
+    if ((int64_t)nseg * nq > 0x7fffffff / 2)
+        return fail(TS_ERR_INVALID_ARG, f + ": too many problems");
+    if (nseg > 0 && (!P || !Q || !thr || !obj || !status))
+        return fail(TS_ERR_INVALID_ARG, f + ": null pointer");
+    return TS_OK;
+}
+
+} // namespace ts
+
+extern "C" {
+
 ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k, int32_t nq,
                               const double *q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr, double *obj,
                               int32_t *status, const ts_tuning *tune, ts_stream_t stream)
 {
-    if (nseg < 0)
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nseg must be >= 0");
-    if (nbins < 2 || nbins > MAX_BINS)
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nbins must be in [2, 4096]");
-    if (k < 1 || k > 3)
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: k must be 1, 2 or 3");
-    if (nbins < k + 1)
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: nbins must be >= k + 1");
-    if (mode < 0 || mode > TS_SEARCH_SUMPROD)
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: unknown mode");
     ts_status st;
-    if ((st = check_q("ts_threshold_search", nq, q, true)) != TS_OK)
+    if ((st = check_search_args("ts_threshold_search", P, Q, nseg, nbins, k, nq, q, mode, thr, obj, status)) != TS_OK)
         return st;
-    if ((int64_t)nseg * nq > 0x7fffffff / 2)
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: too many problems");
-    if (nseg > 0 && (!P || !Q || !thr || !obj || !status))
-        return fail(TS_ERR_INVALID_ARG, "ts_threshold_search: null pointer");
     Tune t;
     if ((st = resolve_tuning(tune, nbins, &t)) != TS_OK)
         return st;

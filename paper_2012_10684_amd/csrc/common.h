@@ -200,6 +200,12 @@ ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &set
 
 struct SearchPlan;
 size_t search_workspace_bytes(int nseg, int L, int k, int mode, int cols);
+// workspace bytes the search touches for these sizes and this tuning (0 on
+// the one-workgroup-per-problem path, which keeps everything in LDS)
+size_t search_need_bytes(int nprob, int L, int k, int mode, const Tune &t);
+// argument checks shared by the search entry points
+ts_status check_search_args(const char *fn, const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
+                            int32_t nq, const double *q, int32_t mode, int32_t *thr, double *obj, int32_t *status);
 ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, int nq, const double *q, int mode,
                         void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t,
                         hipStream_t st);

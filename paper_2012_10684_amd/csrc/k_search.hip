@@ -602,15 +602,25 @@ __device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *h
     return x;
 }
 
-// Phase 1 folds every key into acc; phase 2 evaluates every key >= thr in
-// FP64 and keeps the best (rank, then first tuple).
+// Whether phase 2 re-checks a tuple: its indices form a tuple (the padded
+// slots past L - 2 and the masked triangle do not) and its FP32 key is not
+// below thr.  Written as !(key < thr) so that thr = -inf (an infinite error
+// bound) selects every tuple whatever its FP32 key.
+__device__ __forceinline__ bool rechecked(bool is_tuple, float key, float thr)
+{
+    return is_tuple && !(key < thr);
+}
+
+// Phase 1 folds every key into acc; phase 2 evaluates every re-checked tuple
+// in FP64 and keeps the best (rank, then first tuple).  is_tuple: t1 < t2 < t3
+// all within [0, L - 2].
 template <int PHASE, int K>
 __device__ __forceinline__ void take(const TileCtx &x, float key, float thr, float &acc, Cand &b, int t1, int t2,
-                                     int t3)
+                                     int t3, bool is_tuple)
 {
     if (PHASE == 1) {
         acc = fmaxf(acc, key);
-    } else if (key >= thr) {
+    } else if (rechecked(is_tuple, key, thr)) {
         const int t[3] = {t1, t2, t3};
         const double lam = lambda64_k<K>(x.P, x.Q, x.L, t, x.q, x.sgn, x.hmax);
         const double rank = x.mode == TS_SEARCH_FP32_ONLY ? (double)key : lam;
@@ -623,8 +633,9 @@ __device__ __forceinline__ void take(const TileCtx &x, float key, float thr, flo
     }
 }
 
-// Phase 2, one row: FP64 evaluation of the columns whose FP32 key reaches
-// thr (bits of `valid` mark the columns that hold a tuple).  Candidates are
+// Phase 2, one row: FP64 evaluation of the re-checked columns (bits of
+// `valid` mark the columns that hold a tuple: every index within [0, L - 2]
+// and ascending).  Candidates are
 // rare, so the FP64 objective appears once, in a loop over the set bits,
 // rather than once per unrolled tuple: the phase-2 code stays small and its
 // first execution in each workgroup fetches little from the L2.
@@ -635,7 +646,7 @@ __device__ __forceinline__ void take_cols(const TileCtx &x, const float (&key)[C
     unsigned m = 0;
 #pragma unroll
     for (int v = 0; v < COLS; ++v)
-        m |= (((valid >> v) & 1u) && key[v] >= thr) ? (1u << v) : 0u;
+        m |= rechecked((valid >> v) & 1u, key[v], thr) ? (1u << v) : 0u;
     while (m) {
         const int v = __builtin_ctz(m);
         m &= m - 1;
@@ -666,7 +677,7 @@ __device__ __forceinline__ void tile_k1(const TileCtx &x, int b, float thr, floa
 #pragma unroll
     for (int v = 0; v < COLS; ++v) {
         const int t = b * x.CW + v * 64 + lane; // t < Lp: entries past L-2 are -inf
-        take<PHASE, 1>(x, x.hd[t] + x.tr[t], thr, acc, best, t, 0, 0);
+        take<PHASE, 1>(x, x.hd[t] + x.tr[t], thr, acc, best, t, 0, 0, t <= x.L - 2);
     }
 }
 
@@ -695,7 +706,7 @@ __device__ __forceinline__ void rows_k2_group(const TileCtx &x, int t1, const fl
         for (int v = V0; v < COLS; ++v) {
             const float key = (hdr[u] + cls32<SGN>(hc[v], hr[u], x.mq, x.gmax)) + tc[v];
             if (!MASK || t1 + u < t2v[v])
-                take<PHASE, 2>(x, key, thr, acc, best, t1 + u, t2v[v], 0);
+                take<PHASE, 2>(x, key, thr, acc, best, t1 + u, t2v[v], 0, t2v[v] <= x.L - 2);
         }
     }
 }
@@ -765,7 +776,7 @@ __device__ __forceinline__ void tile_k2(const TileCtx &x, int b, int c, float th
 #pragma unroll
             for (int v = 0; v < COLS; ++v) {
                 key[v] = (hdr + cls32<SGN>(hc[v], hr, x.mq, x.gmax)) + tc[v];
-                valid |= t1 < t2v[v] ? (1u << v) : 0u;
+                valid |= (t1 < t2v[v] && t2v[v] <= L - 2) ? (1u << v) : 0u;
             }
             take_cols<2, COLS>(x, key, t2v, valid, thr, best, t1, 0);
         }
@@ -894,12 +905,15 @@ __device__ __forceinline__ void rows3_loop(const TileCtx &x, const float *Arow, 
                 const float a = Arow[t1 + u];
                 float key[COLS];
                 int tv[COLS];
+                unsigned valid = 0;
 #pragma unroll
                 for (int v = 0; v < COLS; ++v) {
                     key[v] = a + r[v]; // -inf for columns past the row end
                     tv[v] = t3v[v];
+                    // rows t1 >= t2 (A is -inf there) and columns past L - 2 hold no tuple
+                    valid |= (t1 + u < t2 && t3v[v] <= x.L - 2) ? (1u << v) : 0u;
                 }
-                take_cols<3, COLS>(x, key, tv, (1u << COLS) - 1u, thr, best, t1 + u, t2);
+                take_cols<3, COLS>(x, key, tv, valid, thr, best, t1 + u, t2);
             }
         }
     }
@@ -1527,6 +1541,22 @@ QConst make_qconst(double q, int L)
     return c;
 }
 
+// One workgroup per problem (k_fused, nothing in the workspace) when that
+// fills the chip or the problem is small, unless the tuning forces a path.
+static bool fused_path(const Plan &p, int nprob, const Tune &t)
+{
+    const bool fp32 = p.mode == TS_SEARCH_FP32_TIECHECK || p.mode == TS_SEARCH_FP32_ONLY;
+    const bool can_fuse = fp32 && p.tiles <= FUSED_MAX_TILES && p.Lp <= FUSED_MAX_L &&
+                          (p.k == 1 || (p.k == 2 && p.L <= FUSED_MAX_L2));
+    return can_fuse && (t.search_path == 1 || (t.search_path == 0 && (p.k == 1 || nprob >= 128)));
+}
+
+size_t search_need_bytes(int nprob, int L, int k, int mode, const Tune &t)
+{
+    const Plan p = make_plan(nprob, L, k, mode, t.search_cols, t.search_rows);
+    return fused_path(p, nprob, t) ? 0 : p.bytes;
+}
+
 ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, int nq, const double *q, int mode,
                         void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t,
                         hipStream_t st)
@@ -1583,10 +1613,7 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
     }
 
     const bool fp32 = mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY;
-    // one workgroup per problem when that fills the chip or the problem is small
-    const bool can_fuse = fp32 && p.tiles <= FUSED_MAX_TILES && p.Lp <= FUSED_MAX_L &&
-                          (k == 1 || (k == 2 && L <= FUSED_MAX_L2));
-    const bool fused = can_fuse && (t.search_path == 1 || (t.search_path == 0 && (k == 1 || nprob >= 128)));
+    const bool fused = fused_path(p, nprob, t);
     const int64_t waves = (int64_t)nprob * p.tiles;
     dim3 g((unsigned)((waves + 3) / 4));
     if (fused) {
