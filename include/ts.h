@@ -140,8 +140,9 @@ ts_status ts_histogram(ts_batch batch, ts_binning bin, uint32_t *hist, const ts_
 /* ts_prefix -- probabilities and prefix sums (Tsallis-entropy section:
  * p_i = c_i / N with N = sum c_i, class masses P(t) = sum_{i<=t} p_i, and
  * Q(t) = sum_{i<=t} p_i^q, the sum whose differences give the class sums of
- * p_i^q in H1 and H2), for nq entropic indices at once (the experiments
- * section compares several q on the same image).
+ * p_i^q in H1 and H2), for nq entropic indices at once (the same section
+ * leaves the index alpha as a parameter to tune, so a caller may search
+ * several values on the same image).
  *   hist   uint32 [nseg][nbins] from ts_histogram;
  *   nq, q  [host] nq (1..TS_MAX_Q) entropic indices (the paper's alpha),
  *          each finite and > 0; q = 1 selects the Shannon limit (below);
@@ -318,9 +319,10 @@ ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bi
 #define TS_MAX_LABEL_SETS 4
 
 /* ts_label_sets -- ts_label for several threshold sets of one batch (e.g.
- * the thresholds found for several entropic indices q, Section 4), in one
- * pass over the voxels: each voxel is read once and one label is written
- * per set.  Labels are bit-identical to nsets separate ts_label calls.
+ * the thresholds found for several values of the tunable entropic index,
+ * Tsallis-entropy section), in one pass over the voxels: each voxel is read
+ * once and one label is written per set.  Labels are bit-identical to nsets
+ * separate ts_label calls (Algorithm 1 applied once per set).
  *   nsets  1..TS_MAX_LABEL_SETS;
  *   thr    [host] array of nsets device pointers, each int32 [nseg][k]
  *          (same rules as ts_label's thr);
