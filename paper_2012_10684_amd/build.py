@@ -1,13 +1,15 @@
 """Build libts.so (the HIP library behind include/ts.h) for gfx950 in-tree.
 
-Every kernel and the C ABI are compiled by hipcc into one shared library next
-to this file.  Packed-FP32 instructions are disabled (-packed-fp32-ops) and
+Every kernel source and the C ABI are compiled by hipcc into objects (one
+hipcc process per source, in parallel) and linked into one shared library
+next to this file.  Packed-FP32 instructions are disabled (-packed-fp32-ops) and
 floating-point contraction is off, so each FP32 expression is evaluated
 exactly as written (the search re-evaluates FP32 keys and relies on
 getting the same bits).
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import shutil
@@ -20,13 +22,15 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libts.so")
 ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+COMPILE = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
+LINK = ["-shared", "-fPIC", f"--offload-arch={ARCH}"]
+OBJDIR = os.path.join(HERE, "_build")
 
 
 def hipcc() -> str:
@@ -40,18 +44,38 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libts.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + sources()
+def _filter(stderr: str) -> str:
+    return "\n".join(l for l in stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src).replace(".hip", ".o"))
+    cmd = [hipcc()] + COMPILE + ["-c", "-o", obj, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     p = subprocess.run(cmd, capture_output=True, text=True)
-    err = "\n".join(l for l in p.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
+    err = _filter(p.stderr)
     if p.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({p.returncode}):\n{err}")
+        raise RuntimeError(f"hipcc failed on {os.path.basename(src)} ({p.returncode}):\n{err}")
     if verbose and err:
         print(err, file=sys.stderr)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP source (always recompiles) and link libts.so."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = sources()
+    n = jobs or max(1, min(len(srcs), 8, len(os.sched_getaffinity(0))))
+    with concurrent.futures.ThreadPoolExecutor(n) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    tmp = LIB + ".tmp"
+    cmd = [hipcc()] + LINK + ["-o", tmp] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"hipcc link failed ({p.returncode}):\n{_filter(p.stderr)}")
     os.replace(tmp, LIB)
     return LIB
 
