@@ -1,23 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the Tsallis-threshold segmentation path on one MI355X.
 
-Workload: one 512x512x300 int16 CT-like volume (seeded synthetic four-tissue
-mixture with branching airway tubes); per-slice 256-bin histograms over the
-HU window [-1024, -200]; per-slice exhaustive k = 2 threshold search for
-q = 0.5, 0.8 and 1.5 (FP32 keys + FP64 tie check); per-slice labels for each
-q.  One step is the whole path over the volume:
-    ts_histogram (300 problems) -> ts_prefix (3 q x 300 problems)
-    -> ts_threshold_search (900 problems, one launch)
-    -> ts_label_sets (one pass over the voxels writes the three label maps).
+Default workload (the largest single-GPU configuration): 64 CT-like int16
+volumes of 512x512xZ, Z ~ U{120..600} (seeded synthetic four-tissue mixture
+with branching airway tubes, tissue fractions scaled by U(0.9, 1.1) per
+volume, every volume generated separately), 23,000+ slices in one batch;
+per-slice 256-bin histograms over the HU window [-1024, -200]; per-slice
+exhaustive k = 2 threshold search at q = 0.8 (FP32 keys + FP64 tie check);
+per-slice labels.  One step is the whole path over the batch:
+    ts_histogram (every slice) -> ts_prefix -> ts_threshold_search (one launch)
+    -> ts_label_sets (one pass over the voxels writes the label maps).
 Inputs are resident in HBM before timing starts; every output buffer and the
-workspaces are allocated once, so a step only launches kernels.
+workspaces are allocated once, so a step only launches kernels.  Other
+workloads (--workload): the 300-slice volume at three q, the 600-slice volume
+at k = 3, one slice, the two-dimensional form, the segmentation step with the
+opening, and the serving trace.
 
 Prints one JSON line: voxels/s over the whole step (the value), tuples/s,
 the roofline of the label pass (the kernel with the most algorithmic bytes)
 from HIP events recorded around it on its stream in the timed steps, the
-CPU oracle timed on a bounded sample, and, from untimed passes after the
-timed region, per-kernel times and per-step p50/p99 (events add gaps to the
-stream, so the timed steps carry only the label pass's pair).
+CPU oracle timed on a bounded sample (one thread and all the host's cores),
+and, from untimed passes after the timed region, per-kernel times and
+per-step p50/p99 (events add gaps to the stream, so the timed steps carry
+only the label pass's pair).
 """
 from __future__ import annotations
 
@@ -68,10 +73,118 @@ CPU_MAX_PASSES = 100000
 # EV_EVERY-th step only
 EV_EVERY = 4
 
-# distinct volumes generated for the batched and serving workloads; every
-# request takes the first Z slices of one of them (generation costs ~13 s
-# per 512x512x600 volume on one core)
+# distinct volumes generated for the serving workload; every request takes
+# the first Z slices of one of them (generation costs ~8 s per 512x512x600
+# volume on one core).  The batched workload generates each of its 64
+# volumes.
 POOL = 4
+
+
+# kernel name prefix -> source file (for the HBM traffic record)
+KERNEL_FILES = (("ts::k_label", "k_label.hip"), ("ts::k_histogram", "k_histogram.hip"),
+                ("ts::k_fill_u32", "k_histogram.hip"), ("ts::k_prefix", "k_prefix.hip"),
+                ("ts::k_fused", "k_search.hip"), ("ts::k_setup", "k_search.hip"), ("ts::k_rows3", "k_search.hip"),
+                ("ts::k_tiles32", "k_search.hip"), ("ts::k_final", "k_search.hip"), ("ts::k_hist2d", "k_2d.hip"),
+                ("ts::k_search2d", "k_2d.hip"), ("ts::k_morph", "k_morph.hip"))
+
+
+def kernel_file(name: str):
+    for pre, f in KERNEL_FILES:
+        if name.startswith(pre):
+            return f
+    return None
+
+
+def _csv_rows(d: str, suffix: str):
+    """Rows of every rocprofv3 CSV under d whose name ends with suffix."""
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return rows
+
+
+def short_name(n: str, width: int = 56) -> str:
+    n = n.replace("void ", "")
+    if not n.startswith("ts::"):
+        n = n[:width - 18] + " (torch / runtime)"
+    return n[:width]
+
+
+def summarize_trace(d: str, header: str) -> str:
+    """Per-kernel calls and average/min/max durations from a rocprofv3
+    --kernel-trace --stats run (its *kernel_stats.csv)."""
+    rows = _csv_rows(d, "kernel_stats.csv")
+    out = [header, "", f"{'kernel':<58} {'calls':>6} {'avg_us':>9} {'min_us':>9} {'max_us':>9} {'share':>6}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        out.append(f"{short_name(r['Name']):<58} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>9.2f} "
+                   f"{float(r['MinNs']) / 1e3:>9.2f} {float(r['MaxNs']) / 1e3:>9.2f} {float(r['Percentage']):>5.1f}%")
+    return "\n".join(out) + "\n"
+
+
+def pmc_per_dispatch(d: str, counter: str):
+    """kernel name -> (dispatches, mean counter value per dispatch) of one
+    rocprofv3 --pmc run (its *counter_collection.csv)."""
+    acc = {}
+    for r in _csv_rows(d, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r["Kernel_Name"], r.get("Dispatch_Id") or r.get("Correlation_Id"))
+        acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])  # summed over the counter's instances
+    per = {}
+    for (name, _), v in acc.items():
+        n, t = per.get(name, (0, 0.0))
+        per[name] = (n + 1, t + v)
+    return {name: (n, t / n) for name, (n, t) in per.items()}
+
+
+def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload, command):
+    """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
+    dispatch), scaled by what the same counters read for the runtime's copy
+    kernel moving a known number of bytes (bench.py --calibrate); updates
+    profiles/traffic.json (one record per kernel source and workload: the
+    kernel of that source with the most bytes) and returns a text summary."""
+    copy = 256 << 20
+    cf, cw = pmc_per_dispatch(cal_fetch_dir, "FETCH_SIZE"), pmc_per_dispatch(cal_write_dir, "WRITE_SIZE")
+    ck = [n for n in cf if "copyBuffer" in n or "copy" in n.lower()]
+    if not ck:
+        raise SystemExit("no copy kernel in the calibration runs")
+    f_fac = copy / (cf[ck[0]][1] * 1024.0)
+    w_fac = copy / (cw[ck[0]][1] * 1024.0)
+    fe, wr = pmc_per_dispatch(fetch_dir, "FETCH_SIZE"), pmc_per_dispatch(write_dir, "WRITE_SIZE")
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        rec = {}
+    rec["_calibration"] = {"kernel": ck[0], "copy_bytes": copy, "FETCH_SIZE_KiB": cf[ck[0]][1],
+                           "WRITE_SIZE_KiB": cw[ck[0]][1], "fetch_factor": f_fac, "write_factor": w_fac,
+                           "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- "
+                                      "python3 bench.py --calibrate"}
+    lines = [f"HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (one run each), "
+             f"workload {workload}", f"command: {command}",
+             f"calibration: {ck[0]} copying 256 MiB reads FETCH_SIZE {cf[ck[0]][1]:.0f} KiB (factor {f_fac:.3f}), "
+             f"WRITE_SIZE {cw[ck[0]][1]:.0f} KiB (factor {w_fac:.3f})", ""]
+    best = {}
+    for name in sorted(set(fe) & set(wr), key=lambda n: -(fe[n][1] * f_fac + wr[n][1] * w_fac)):
+        f = kernel_file(name)
+        rb, wb = fe[name][1] * 1024.0 * f_fac, wr[name][1] * 1024.0 * w_fac
+        if f is None:
+            continue
+        lines.append(f"{short_name(name, 40):<40} read {rb / 1e6:>10.2f} MB  write {wb / 1e6:>10.2f} MB  per launch "
+                     f"({fe[name][0]} launches)  src {src_hash(f)}")
+        if f not in best:
+            best[f] = name
+            rec[f"{f}:{workload}"] = {"kernel": short_name(name, 200), "src_sha": src_hash(f), "workload": workload,
+                                      "bytes_per_launch": rb + wb, "read_bytes": rb, "write_bytes": wb,
+                                      "launches": fe[name][0]}
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return "\n".join(lines) + "\n"
 
 
 def parse():
@@ -80,9 +193,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="volume300", choices=sorted(WORKLOADS),
-                    help="volume300 is the benchmark's workload; the others report the same fields")
-    ap.add_argument("--cpu-slices", type=int, default=300, help="slices in the oracle's timed sample")
+    ap.add_argument("--workload", default="batch64", choices=sorted(WORKLOADS),
+                    help="batch64 is the benchmark's workload; the others report the same fields")
+    ap.add_argument("--cpu-slices", type=int, default=300,
+                    help="slices in the oracle's timed sample (batch64: one mid slice of each volume)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the multi-threaded oracle timing (default: every CPU this process may use)")
     ap.add_argument("--requests", type=int, default=120, help="serving: requests replayed from the trace")
     ap.add_argument("--per-slice-sample", type=int, default=2000,
                     help="batch64: slices timed with one launch per slice and stage")
@@ -94,6 +210,12 @@ def parse():
                          "(default: eager launches, measured faster on MI355X)")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run device-to-device copies of 256 MiB (reference kernel for the PMC byte counters)")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="no GPU: print the per-kernel summary of a rocprofv3 --kernel-trace --stats output folder")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
+                    help="no GPU: HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output folders of "
+                         "this workload and of --calibrate; updates profiles/traffic.json, prints a summary")
+    ap.add_argument("--header", default="", help="first line(s) of a --summarize-* summary (the command that ran)")
     return ap.parse_args()
 
 
@@ -114,69 +236,82 @@ def load_traffic(kernel_file: str, workload: str):
         d = json.load(open(p))
     except (OSError, ValueError):
         return None
-    e = d.get(kernel_file)
+    e = d.get(f"{kernel_file}:{workload}")  # one record per kernel source and workload
     if not e or e.get("src_sha") != src_hash(kernel_file) or e.get("workload") != workload:
         return None
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(vol, nslices: int, wl, gpu_thr=None, gpu_obj=None):
-    """The oracle timed on a sample of the workload; with the GPU's thresholds
-    and objectives ([nq][problem][k], [nq][problem]) also their agreement on
-    that sample (the objective error per configuration)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(problems, wl, gpu_thr=None, gpu_obj=None, what="", threads=0):
+    """The oracle timed on a sample of the workload's problems (a list of
+    (index of the problem in the GPU results, int16 voxels)), first on one
+    thread, then on `threads` threads (default: every CPU this process may
+    use) that take the sample's problems in turn; each timing repeats the
+    sample until CPU_MIN_S have run.  With the GPU's thresholds and
+    objectives ([nq][problem][k], [nq][problem]) also their agreement on the
+    sample (the objective error per configuration)."""
+    import concurrent.futures
+
     import numpy as np
     import oracle
 
-    _, per_slice, LO, HI, L, K, QS = wl
-    sample = vol[:nslices] if per_slice else vol
+    _, _, LO, HI, L, K, QS = wl
 
-    def one_pass(refs):
-        if per_slice:
-            for z in range(sample.shape[0]):
-                h = oracle.histogram(sample[z], LO, HI, L)
-                for j, q in enumerate(QS):
-                    r = oracle.search(h, K, q, oracle.MODE_PREFIX)
-                    oracle.label(sample[z].reshape(-1), LO, HI, L, r.thr)
-                    refs.append((j, z, r))
-        else:
-            h = oracle.histogram(sample, LO, HI, L)
-            for j, q in enumerate(QS):
-                r = oracle.search(h, K, q, oracle.MODE_PREFIX)
-                oracle.label(sample.reshape(-1), LO, HI, L, r.thr)
-                refs.append((j, 0, r))
+    def one(v):
+        out = []
+        h = oracle.histogram(v, LO, HI, L)
+        for j, q in enumerate(QS):
+            r = oracle.search(h, K, q, oracle.MODE_PREFIX)
+            oracle.label(v.reshape(-1), LO, HI, L, r.thr)
+            out.append((j, r))
+        return out
 
-    if per_slice:
-        what = (f"{sample.shape[0]} of the {vol.shape[0]} slices: oracle histogram + {len(QS)} x "
-                f"(prefix-mode k={K} search + labels)")
-    else:
-        what = f"the whole input: oracle histogram + prefix-mode k={K} search + labels"
-    # the sample is passed over again until CPU_MIN_S of oracle work has run
-    # (at most CPU_MAX_PASSES passes), so short samples are timed over a
-    # stable interval
-    refs = []
-    passes = 0
-    t0 = time.perf_counter()
-    while True:
-        one_pass(refs if passes == 0 else [])
-        passes += 1
-        dt = time.perf_counter() - t0
-        if dt >= CPU_MIN_S or passes >= CPU_MAX_PASSES:
-            break
-    nvox = int(np.prod(sample.shape)) * passes
-    base = {"value": nvox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}, {passes} pass(es), {dt:.2f} s single-threaded"}
+    def timed(run):
+        passes, t0 = 0, time.perf_counter()
+        while True:
+            run()
+            passes += 1
+            dt = time.perf_counter() - t0
+            if dt >= CPU_MIN_S or passes >= CPU_MAX_PASSES:
+                return passes, dt
+
+    nvox = sum(int(v.size) for _, v in problems)
+    refs = [(i, j, r) for i, v in problems for j, r in one(v)]  # untimed: the agreement check
+    p1, dt1 = timed(lambda: [one(v) for _, v in problems])
+    T = threads or len(os.sched_getaffinity(0))
+    T = max(1, min(T, len(problems)))  # threads take whole problems
+    with concurrent.futures.ThreadPoolExecutor(T) as ex:
+        pT, dtT = timed(lambda: list(ex.map(lambda iv: one(iv[1]), problems)))
+    model = cpu_model()
+    single = {"value": nvox * p1 / dt1, "unit": "voxels/s", "cores": 1,
+              "sample": f"{what}, {p1} pass(es) in {dt1:.2f} s on one thread"}
+    base = {"value": nvox * pT / dtT, "unit": "voxels/s", "cores": T, "kind": "oracle",
+            "sample": f"{what}, {pT} pass(es) in {dtT:.2f} s on {T} threads (one problem per thread at a time; "
+                      f"the oracle releases the interpreter lock), {model}",
+            "cpu_model": model, "single_thread": single}
     check = None
     if gpu_thr is not None:
-        same, err, near = 0, 0.0, 0
-        for j, z, r in refs:
+        same, err, near, ok = 0, 0.0, 0, 0
+        for i, j, r in refs:
             if r.status != oracle.OK:
                 continue
-            t = [int(x) for x in gpu_thr[j][z]]
+            ok += 1
+            t = [int(x) for x in gpu_thr[j][i]]
             if t == r.thr.tolist():
                 same += 1
             elif r.rel_gap() < 1e-6:
                 near += 1
-            err = max(err, abs(float(gpu_obj[j][z]) - r.obj) / abs(r.obj))
+            err = max(err, abs(float(gpu_obj[j][i]) - r.obj) / abs(r.obj))
         check = {"problems": len(refs), "thresholds_identical": same, "differing_within_1e-6_gap": near,
                  "max_rel_objective_error": err}
     return base, check
@@ -196,6 +331,8 @@ def make_pool(jobs):
     n = min(len(jobs), max(1, min(16, len(os.sched_getaffinity(0)))))
     with mp.get_context("spawn").Pool(n) as pool:
         return pool.map(_gen, jobs)
+
+
 
 
 def bench_serving(args, wl, trace, jobs, vols):
@@ -468,6 +605,12 @@ def capture_graphs(step, stream, hist, res, outs, sample_labels: bool):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.header), end="")
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(*args.summarize_pmc, args.workload, args.header), end="")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (independent problems would be "
               f"sharded across GPUs by voxel count with no exchange; one large volume needs three small "
@@ -486,9 +629,10 @@ def main():
         zmax = {sz: max([z for _, z, s_ in trace if s_ == sz] or [1]) for sz in (256, 512)}
         jobs = [("serve", i, zmax[sz], sz) for sz in (256, 512) for i in range(POOL // 2)]
         return bench_serving(args, wl, trace, jobs, make_pool(jobs))
-    if args.workload == "batch64":
+    if args.workload == "batch64" and not args.calibrate:
         depths = synth.batch_depths(64)
-        pool = make_pool([("batch", i, max(depths), 512) for i in range(POOL)])
+        # worker processes start before this process touches the GPU
+        gen_pool, gen_iter = synth.generate_parallel(list(enumerate(depths)))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.workload == "volume300_2d":
@@ -506,15 +650,34 @@ def main():
         return
     desc, per_slice, LO, HI, L, K, QS = wl
     if args.workload == "batch64":
-        dpool = [torch.from_numpy(v).to(dev) for v in pool]
-        dvols = [dpool[i % POOL][:z].clone() for i, z in enumerate(depths)]  # one buffer per volume
-        del dpool
-        vol = pool[0][:30]  # the oracle's sample
+        # every volume generated separately and copied into its own device
+        # buffer as it arrives; the oracle's sample is the middle slice of
+        # each volume
+        dvols, sample, base = [], [], 0
+        for i, v in enumerate(gen_iter):
+            assert v.shape == (depths[i], 512, 512), v.shape
+            dvols.append(torch.from_numpy(v).to(dev))
+            sample.append((base + depths[i] // 2, v[depths[i] // 2].copy()))
+            base += depths[i]
+            del v
+            if (i + 1) % 16 == 0:
+                print(f"bench: {i + 1} of {len(depths)} volumes generated and resident", file=sys.stderr, flush=True)
+        gen_pool.close()
+        gen_pool.join()
         nvox_all = sum(int(v.numel()) for v in dvols)
         batch = api.Batch([v[z].reshape(-1) for v in dvols for z in range(v.shape[0])])
+        sample_what = f"the middle slice of each of the {len(dvols)} volumes: oracle histogram + prefix-mode k={K} " \
+                      f"search + labels"
     else:
         vol = {"volume300": lambda: synth.workload_volume300(0), "volume600": lambda: synth.workload_volume600(0),
                "slice": lambda: synth.workload_slice(0)[None]}[args.workload]()
+        if per_slice:
+            sample = [(z, vol[z]) for z in range(min(args.cpu_slices, vol.shape[0]))]
+            sample_what = f"{len(sample)} of the {vol.shape[0]} slices: oracle histogram + {len(QS)} x " \
+                          f"(prefix-mode k={K} search + labels)"
+        else:
+            sample = [(0, vol)]
+            sample_what = f"the whole input: oracle histogram + prefix-mode k={K} search + labels"
         dv = torch.from_numpy(vol).to(dev)
         nvox_all = int(vol.size)
         batch = api.Batch.slices(dv) if per_slice else api.Batch([dv.reshape(-1)])
@@ -778,8 +941,9 @@ def main():
         line["batched_speedup_vs_per_slice_launches"] = per_slice_s * nseg / (dt / args.steps)
         line["per_slice_sample"] = m
     if not args.no_cpu_baseline:
-        line["cpu_baseline"], line["oracle_check"] = cpu_baseline(vol, args.cpu_slices, wl, res[0].cpu().numpy(),
-                                                                  res[1].cpu().numpy())
+        line["cpu_baseline"], line["oracle_check"] = cpu_baseline(sample, wl, res[0].cpu().numpy(),
+                                                                  res[1].cpu().numpy(), sample_what,
+                                                                  args.cpu_threads)
     print(json.dumps(line), flush=True)
 
 

@@ -191,6 +191,26 @@ def workload_batch_volume(index: int, Z: int, size: int = 512) -> np.ndarray:
     return make_volume(rng, Z, size, frac_scale=scale)
 
 
+def batch_volume_job(job) -> np.ndarray:
+    """Worker entry of generate_parallel: job = (index, Z) of a batched
+    workload volume."""
+    i, z = job
+    return workload_batch_volume(i, z)
+
+
+def generate_parallel(jobs, workers: int = 0, fn=batch_volume_job):
+    """Start worker processes (spawned, numpy only) that build fn(job) for
+    every job; returns the pool and an iterator over the results in job order,
+    each delivered as soon as it and the ones before it are done.  Call
+    close() and join() on the pool afterwards."""
+    import multiprocessing as mp
+    import os
+
+    n = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    pool = mp.get_context("spawn").Pool(max(1, min(n, len(jobs))))
+    return pool, pool.imap(fn, jobs)
+
+
 def serving_trace(count: int = 600, rate: float = 20.0, seed_index: int = 0):
     """Poisson arrivals: list of (arrival_s, Z, size); sizes 50/50 small
     (256x256xU{60..300}) or large (512x512xU{120..600})."""

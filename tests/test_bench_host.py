@@ -23,8 +23,9 @@ def tree(tmp_path, monkeypatch):
         shutil.copy(os.path.join(src, f), dst / f)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     (tmp_path / "profiles").mkdir()
-    rec = {"k_label.hip": {"src_sha": bench.src_hash("k_label.hip"), "workload": "volume300",
-                           "bytes_per_launch": 123.0}}
+    rec = {"k_label.hip:volume300": {"src_sha": bench.src_hash("k_label.hip"), "workload": "volume300",
+                                     "bytes_per_launch": 123.0},
+           "k_label.hip:batch64": {"src_sha": "0" * 16, "workload": "batch64", "bytes_per_launch": 7.0}}
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
     return dst
 
@@ -32,6 +33,7 @@ def tree(tmp_path, monkeypatch):
 def test_traffic_used_for_its_source_and_workload(tree):
     assert bench.load_traffic("k_label.hip", "volume300") == 123.0
     assert bench.load_traffic("k_label.hip", "volume600") is None  # another workload
+    assert bench.load_traffic("k_label.hip", "batch64") is None  # taken on another source
     assert bench.load_traffic("k_histogram.hip", "volume300") is None  # no record
 
 
@@ -45,8 +47,33 @@ def test_traffic_dropped_once_the_kernel_changes(tree, changed):
 def test_cpu_baseline_repeats_a_short_sample(monkeypatch):
     monkeypatch.setattr(bench, "CPU_MIN_S", 0.3)
     vol = synth.workload_slice(0)[None]
-    base, check = bench.cpu_baseline(vol, 1, bench.WORKLOADS["slice"], np.array([[[0]]]), np.array([[1.0]]))
-    passes = int(base["sample"].split(" pass")[0].rsplit(" ", 1)[-1])
-    assert passes >= 2, base
-    assert np.isfinite(base["value"]) and base["value"] > 0 and base["cores"] == 1
-    assert check["problems"] == 1  # the agreement check covers the first pass only
+    base, check = bench.cpu_baseline([(0, vol[0])], bench.WORKLOADS["slice"], np.array([[[0]]]), np.array([[1.0]]),
+                                     "one slice")
+    for rec in (base, base["single_thread"]):
+        passes = int(rec["sample"].split(" pass")[0].rsplit(" ", 1)[-1])
+        assert passes >= 2, rec
+        assert np.isfinite(rec["value"]) and rec["value"] > 0
+    assert base["cores"] == 1 and base["single_thread"]["cores"] == 1  # one problem: one thread
+    assert base["kind"] == "oracle" and base["cpu_model"]
+    assert check["problems"] == 1  # the agreement check covers the sample once
+
+
+def test_cpu_baseline_threads_take_whole_problems(monkeypatch):
+    """Several problems: the multi-threaded timing uses up to the requested
+    threads, and the agreement check compares every problem of the sample
+    with the GPU's result at its own index."""
+    import oracle
+    monkeypatch.setattr(bench, "CPU_MIN_S", 0.2)
+    wl = bench.WORKLOADS["batch64"]
+    _, _, lo, hi, L, k, qs = wl
+    vol = synth.make_volume(synth.rng_for(9, 3), 3, 128)
+    sample = [(5, vol[0]), (2, vol[1]), (9, vol[2])]
+    thr = np.full((1, 10, k), -1, np.int32)
+    obj = np.full((1, 10), np.nan)
+    for i, v in sample:
+        r = oracle.search(oracle.histogram(v, lo, hi, L), k, qs[0])
+        thr[0, i], obj[0, i] = r.thr, r.obj
+    base, check = bench.cpu_baseline(sample, wl, thr, obj, "three slices", threads=2)
+    assert base["cores"] == 2 and base["single_thread"]["cores"] == 1
+    assert check["problems"] == 3 and check["thresholds_identical"] == 3
+    assert check["max_rel_objective_error"] == 0.0

@@ -73,3 +73,23 @@ def test_engine_realtime_trace(volumes):
     st = latency_stats(res, wall=max(r.done for r in res))
     say(f"realtime trace: {st}")
     assert st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_engine_serving_size_requests_against_the_oracle():
+    """Requests of the serving workload's sizes (512x512x300 and 256x256x200
+    volumes, whole-volume 512-bin histograms over [-1024, 3071], k = 3,
+    q = 0.8) served together: thresholds, objectives and every label against
+    the oracle."""
+    vols = [synth.serving_volume(700, 300, 512), synth.serving_volume(701, 200, 256)]
+    eng = Engine(api.binning(LO, HI, L), K, (0.8,))
+    reqs = [Request(i, torch.from_numpy(v).pin_memory(), 0.0) for i, v in enumerate(vols)]
+    say(f"engine: serving-size requests {[v.shape for v in vols]}")
+    res = {r.rid: r for r in eng.run(reqs, realtime=False)}
+    for i, v in enumerate(vols):
+        h = oracle.histogram(v, LO, HI, L)
+        assert int(h.sum()) == v.size
+        exact, ref = check_choice(h, K, 0.8, res[i].thr[0], res[i].obj[0], int(res[i].status[0]))
+        say(f"request {i} {v.shape}: thresholds {res[i].thr[0].tolist()} (oracle {ref.thr.tolist()}, "
+            f"runner-up gap {ref.rel_gap():.2e})")
+        want = oracle.label(v.reshape(-1), LO, HI, L, res[i].thr[0])
+        assert np.array_equal(res[i].labels[0].numpy(), want), i
