@@ -63,16 +63,32 @@ def test_engine_batched_equals_alone(volumes, max_batch_voxels, max_inflight):
 
 
 def test_engine_realtime_trace(volumes):
-    eng = Engine(api.binning(LO, HI, L), K, QS, max_batch_voxels=300_000)
+    """Arrivals spread in time, label buffers from the pinned pool given back
+    as each result is seen: every result is still bit-identical to the
+    request served alone, and the device-side times are measured."""
+    nmax = max(v.size for v in volumes)
+    eng = Engine(api.binning(LO, HI, L), K, QS, max_batch_voxels=300_000, max_request_voxels=nmax, pool_slots=64)
     reqs = [Request(i, torch.from_numpy(volumes[i % len(volumes)]).pin_memory(), 0.004 * i) for i in range(20)]
-    res = eng.run(reqs, realtime=True)
-    assert len(res) == 20
+    alone = {i: _alone(v) for i, v in enumerate(volumes)}
+    checked = []
+
+    def check(r):
+        thr, obj, st, labs = alone[r.rid % len(volumes)]
+        assert r.error is None and np.array_equal(r.thr, thr) and np.array_equal(r.status, st), r.rid
+        for j in range(len(QS)):
+            assert torch.equal(r.labels[j], labs[j]), (r.rid, j)
+        checked.append(r.rid)
+        eng.release(r)  # the buffers go back to the pool
+
+    res = eng.run(reqs, realtime=True, on_result=check)
+    assert sorted(checked) == list(range(20))
     for r in res:
         assert r.done >= r.admitted >= r.arrival - 1e-9
-        assert (r.status == 0).all()
+        assert 0 < r.kernels_s <= r.device_s <= r.done - r.admitted + 1e-3
     st = latency_stats(res, wall=max(r.done for r in res))
-    say(f"realtime trace: {st}")
-    assert st["p99_s"] >= st["p50_s"] > 0
+    say(f"realtime trace: {st}; pinned buffers allocated outside the pool: {eng.backend.pool.extra}")
+    assert st["p99_s"] >= st["p50_s"] > 0 and st["device_p99_s"] >= st["device_p50_s"] > 0
+    assert eng.backend.pool.extra == 0
 
 
 def test_engine_serving_size_requests_against_the_oracle():

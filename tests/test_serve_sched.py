@@ -83,4 +83,20 @@ def test_latency_stats():
     assert st["p99_s"] == pytest.approx(np.percentile(np.arange(1, 101) * 0.01, 99))
     assert st["max_s"] == pytest.approx(1.0)
     assert st["voxels_per_s"] == pytest.approx(100 * 100 / 2.0)
-    assert latency_stats([]) == {"n": 0}
+    assert latency_stats([]) == {"n": 0, "errors": 0}
+    # failed requests are counted, not timed
+    bad = Result(7, None, None, None, [], arrival=0.0, admitted=0.0, done=9.0, nvox=100, error="refused")
+    st2 = latency_stats(rs + [bad], wall=2.0)
+    assert st2["n"] == 100 and st2["errors"] == 1 and st2["max_s"] == pytest.approx(1.0)
+
+
+def test_admission_by_free_device_bytes():
+    """Without a fixed budget the requests admitted together must fit in the
+    device bytes free at that moment."""
+    s = Scheduler(3, None, max_batch_voxels=10_000)
+    for i in range(4):
+        s.submit(req(i, 400, 0.0))  # 1200 bytes each
+    assert [r.rid for r in s.admit(0, free_bytes=2500)] == [0, 1]
+    assert s.admit(0, free_bytes=1000) == []
+    assert [r.rid for r in s.admit(0, free_bytes=1200)] == [2]
+    assert [r.rid for r in s.admit(0)] == [3]  # no figure: only the other budgets
