@@ -38,8 +38,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# transcendental (v_log_f32) issue peak: a quarter of the FP32 lanes, 256 CUs x 4 SIMDs x 4 lanes x 2.4 GHz
+# transcendental (v_log_f32) issue peak assumed where none is measured: a
+# quarter of the FP32 lanes, 256 CUs x 4 SIMDs x 4 lanes x 2.4 GHz; the
+# search lines carry the rate measured by the issue-rate probe as well
 TRANS_PEAK_TOPS = 256 * 4 * 4 * 2.4e9 / 1e12
+# instructions per lane and block of the issue-rate probe, per op
+ISSUE_OPS = {0: ("v_add_f32", 8, 0), 1: ("v_log_f32", 8, 8), 2: ("class-term mix", 14, 2)}
+
+
+def measure_issue_rates(api, torch, dev, stream, blocks=4096, iters=4000):
+    """Lane instructions per second of the issue-rate probe (best of 3
+    launches, event-timed on `stream`): plain FP32 adds, v_log_f32 alone, and
+    the search's class-term mix (2 v_log_f32 + 12 FP32 ops)."""
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    res = {}
+    for op, (name, per, logs) in ISSUE_OPS.items():
+        api.issue_rate(op, blocks, 16, out, stream=stream)  # warm-up
+        best = None
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            api.issue_rate(op, blocks, iters, out, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3
+            best = t if best is None else min(best, t)
+        lanes = blocks * 256 * iters
+        res[name] = {"lane_instr_per_s": lanes * per / best, "blocks_per_s": lanes / best,
+                     "log2_per_s": lanes * logs / best, "us": best * 1e6}
+    return res
+
+
+def search_roofline(rates, tuples, logs_per_tuple, search_s):
+    """The search against the measured issue rates: transcendental ops per
+    second against v_log_f32's rate, and tuples per second against the
+    class-term mix's rate (one class term per tuple for k <= 2)."""
+    logs = tuples * logs_per_tuple / search_s
+    peak = rates["v_log_f32"]["log2_per_s"]
+    return {"bound": "alu", "kernel": "search", "achieved": logs / 1e12, "peak": peak / 1e12, "unit": "Tlog2/s",
+            "frac": logs / peak, "peak_source": "issue-rate probe (v_log_f32, measured in this run)",
+            "tuples_per_s": tuples / search_s,
+            "class_term_mix_per_s": rates["class-term mix"]["blocks_per_s"],
+            "frac_of_class_term_mix": (tuples / search_s) / rates["class-term mix"]["blocks_per_s"],
+            "fp32_add_lane_instr_per_s": rates["v_add_f32"]["lane_instr_per_s"]}
 
 # name -> (description, per-slice?, window lo, hi, bins, k, q values)
 WORKLOADS = {
@@ -868,6 +909,11 @@ def main():
     steps_us = sorted(e["step"][0].elapsed_time(e["step"][1]) * 1e3 for e in sev)
     line["step_us_p50"] = float(np.percentile(steps_us, 50))
     line["step_us_p99"] = float(np.percentile(steps_us, 99))
+    rates = measure_issue_rates(api, torch, dev, stream)
+    line["issue_rates"] = {k: {kk: (round(vv, 3) if kk == "us" else float(f"{vv:.4g}")) for kk, vv in v.items()}
+                           for k, v in rates.items()}
+    if K <= 2:
+        line["search_roofline"] = search_roofline(rates, tuples, 2, per["search"])
     if args.workload == "volume600":
         # the plain GPU form (one thread per tuple, FP64, one launch per
         # problem) and the FP64 exhaustive mode, for the speed-up of the search

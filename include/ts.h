@@ -342,6 +342,20 @@ ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int
  * Errors: TS_ERR_INVALID_ARG for n < 0 or null pointers when n > 0. */
 ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream);
 
+/* ts_issue_rate -- diagnostic: one launch of `blocks` workgroups of 256
+ * threads in which every lane issues `iters` blocks of independent FP32
+ * vector instructions: op 0 eight v_add_f32 (plain FP32 issue), op 1 eight
+ * v_log_f32 (the transcendental unit the FP32 search keys use), op 2 two
+ * v_log_f32 and twelve v_add_f32 (one class term of the search).  The caller
+ * times the launch; instructions per lane / time gives the issue peaks that
+ * the search's throughput is compared with (its class terms are the O(1)
+ * evaluation of the Tsallis objective, Tsallis-entropy section).
+ *   out    device float [blocks * 256], overwritten with values that keep
+ *          the instructions live (no meaning).
+ * Errors: TS_ERR_INVALID_ARG for op outside 0..2, blocks or iters < 1, or a
+ * null out. */
+ts_status ts_issue_rate(int32_t op, int32_t blocks, int32_t iters, float *out, ts_stream_t stream);
+
 /* [host] Text describing the last non-OK status returned on this thread
  * ("" if none).  The pointer stays valid until the next call on this thread. */
 const char *ts_last_error(void);

@@ -81,6 +81,7 @@ def _load():
     lib.ts_label.argtypes = [_Batch, Binning, P, i32, P, P, P]
     lib.ts_label_sets.argtypes = [_Batch, Binning, i32, P, i32, P, P, P]
     lib.ts_log2_f32.argtypes = [P, P, i64, P]
+    lib.ts_issue_rate.argtypes = [i32, i32, i32, P, P]
     lib.ts_histogram2d.argtypes = [_Batch, i32, i32, Binning, P, P]
     lib.ts_search2d_workspace_bytes.argtypes = [i32, i32, i32]
     lib.ts_search2d_workspace_bytes.restype = sz
@@ -93,7 +94,7 @@ def _load():
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
     for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets,
               lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d, lib.ts_threshold_search_dp,
-              lib.ts_open2d):
+              lib.ts_open2d, lib.ts_issue_rate):
         f.restype = ctypes.c_int
     lib.ts_last_error.argtypes = []
     lib.ts_last_error.restype = ctypes.c_char_p
@@ -452,6 +453,14 @@ def log2_f32(x: torch.Tensor, stream=None) -> torch.Tensor:
         y = torch.empty_like(x)
     _check(_lib.ts_log2_f32(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
     return y
+
+
+def issue_rate(op: int, blocks: int, iters: int, out: torch.Tensor, stream=None) -> None:
+    """One launch of the issue-rate probe (diagnostic): op 0 plain FP32 adds,
+    1 v_log_f32, 2 the search's class-term mix; out: float32 [blocks * 256]."""
+    if out.dtype != torch.float32 or not out.is_cuda or out.numel() < blocks * 256:
+        raise ValueError("out must be a float32 CUDA tensor of at least blocks * 256 elements")
+    _check(_lib.ts_issue_rate(op, blocks, iters, _ptr(out), _stream(stream)))
 
 
 def histogram2d(batch: Batch, height: int, width: int, bin: Binning, out: Optional[torch.Tensor] = None,

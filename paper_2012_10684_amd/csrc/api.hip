@@ -487,4 +487,15 @@ ts_status ts_log2_f32(const float *x, float *y, int64_t n, ts_stream_t stream)
     return launch_log2_f32(x, y, n, (hipStream_t)stream);
 }
 
+ts_status ts_issue_rate(int32_t op, int32_t blocks, int32_t iters, float *out, ts_stream_t stream)
+{
+    if (op < 0 || op > 2)
+        return fail(TS_ERR_INVALID_ARG, "ts_issue_rate: op must be 0, 1 or 2");
+    if (blocks < 1 || iters < 1)
+        return fail(TS_ERR_INVALID_ARG, "ts_issue_rate: blocks and iters must be >= 1");
+    if (!out)
+        return fail(TS_ERR_INVALID_ARG, "ts_issue_rate: null pointer");
+    return launch_issue_rate(op, blocks, iters, out, (hipStream_t)stream);
+}
+
 } // extern "C"

@@ -195,6 +195,7 @@ ts_status launch_dp(const double *P, const double *Q, int nseg, int L, int k, in
 ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const double *q, void *ws, int32_t *thr,
                           double *obj, int32_t *status, hipStream_t st);
 ts_status launch_log2_f32(const float *x, float *y, int64_t n, hipStream_t st);
+ts_status launch_issue_rate(int op, int blocks, int iters, float *out, hipStream_t st);
 ts_status launch_label(const ts_batch &b, const BinMap &bm, const LabelSets &sets, int nsets, int k, const Tune &t,
                        hipStream_t st);
 

@@ -61,6 +61,7 @@ def _bind(lib):
     lib.ts_label.argtypes = [Batch, Binning, P, i32, P, P, P]
     lib.ts_label_sets.argtypes = [Batch, Binning, i32, P, i32, P, P, P]
     lib.ts_log2_f32.argtypes = [P, P, ctypes.c_int64, P]
+    lib.ts_issue_rate.argtypes = [i32, i32, i32, P, P]
     lib.ts_histogram2d.argtypes = [Batch, i32, i32, Binning, P, P]
     lib.ts_search2d_workspace_bytes.argtypes = [i32, i32, i32]
     lib.ts_search2d_workspace_bytes.restype = sz
@@ -114,7 +115,7 @@ def test_workspace_sizes(lib):
     ("search_bins_lt_k1", 1), ("search_null", 1), ("search_nq0", 1), ("search_nq9", 1), ("search_qnan_in_batch", 1),
     ("label_k", 1), ("label_null", 1), ("label_total_without_seg", 1),
     ("sets_zero", 1), ("sets_five", 1), ("sets_null_array", 1), ("sets_null_entry", 1), ("sets_k", 1),
-    ("log2_neg", 1), ("log2_null", 1),
+    ("log2_neg", 1), ("log2_null", 1), ("issue_op", 1), ("issue_blocks", 1), ("issue_null", 1),
     ("h2d_bins", 1), ("h2d_width", 1), ("h2d_total", 1), ("h2d_null", 1),
     ("s2d_bins", 1), ("s2d_q", 1), ("s2d_ws", 3), ("s2d_null", 1),
     ("open_bins", 1), ("open_radius", 1), ("open_radius_neg", 1), ("open_total", 1), ("open_no_output", 1),
@@ -206,6 +207,12 @@ def test_argument_errors(lib, case, expect):
         st = lib.ts_log2_f32(FAKE, FAKE, -1, sx)
     elif case == "log2_null":
         st = lib.ts_log2_f32(None, FAKE, 10, sx)
+    elif case == "issue_op":
+        st = lib.ts_issue_rate(3, 8, 8, FAKE, sx)
+    elif case == "issue_blocks":
+        st = lib.ts_issue_rate(0, 0, 8, FAKE, sx)
+    elif case == "issue_null":
+        st = lib.ts_issue_rate(1, 8, 8, None, sx)
     elif case.startswith("sets_"):
         n = {"sets_zero": 0, "sets_five": 5}.get(case, 2)
         thr = (T * 5)(*([FAKE.value] * 5))
