@@ -101,6 +101,11 @@ WORKLOADS = {
                        "[-1024,-200] (256), opening by a flat disk of radius 10 (erosion, then dilation), residue "
                        "gray - opened, Tsallis threshold (k=1) of the residue for q in {0.5,0.8,1.5}, residue labels",
                        True, -1024, -200, 256, 1, (0.5, 0.8, 1.5)),
+    "volume300_open2d": ("volume 512x512x300 int16, the paper's whole segmentation step per slice: gray levels over "
+                         "[-1024,-200] (256), opening by a flat disk of radius 10, residue gray - opened, 2D histogram "
+                         "of (residue level, 3x3 average residue level), FP32 + FP64 arg max over threshold pairs "
+                         "(t, s) for q in {0.5,0.8,1.5}, residue labelled by t", True, -1024, -200, 256, 1,
+                         (0.5, 0.8, 1.5)),
     "serving": ("Poisson trace, 20 volumes/s, half 256x256xU{60..300} and half 512x512xU{120..600}; per volume "
                 "512-bin histogram over [-1024,3071], k=3, q=0.8, labels back in host memory",
                 False, -1024, 3071, 512, 3, (0.8,)),
@@ -124,7 +129,7 @@ POOL = 4
 # kernel name prefix -> source file (for the HBM traffic record)
 KERNEL_FILES = (("ts::k_label", "k_label.hip"), ("ts::k_histogram", "k_histogram.hip"),
                 ("ts::k_fill_u32", "k_histogram.hip"), ("ts::k_prefix", "k_prefix.hip"),
-                ("ts::k_fused", "k_search.hip"), ("ts::k_setup", "k_search.hip"), ("ts::k_rows3", "k_search.hip"),
+                ("ts::k_fused", "k_search.hip"), ("ts::k_segment", "k_search.hip"), ("ts::k_setup", "k_search.hip"), ("ts::k_rows3", "k_search.hip"),
                 ("ts::k_tiles32", "k_search.hip"), ("ts::k_final", "k_search.hip"), ("ts::k_hist2d", "k_2d.hip"),
                 ("ts::k_search2d", "k_2d.hip"), ("ts::k_morph", "k_morph.hip"))
 
@@ -246,6 +251,9 @@ def parse():
     ap.add_argument("--inputs", type=int, default=None,
                     help="resident copies of the input the steps cycle through (default: 4 for volume300 and "
                          "volume600, whose volume would otherwise sit in the memory-side cache; else 1)")
+    ap.add_argument("--path", default="fused", choices=("fused", "steps"),
+                    help="fused: one ts_segment call per step; steps: ts_histogram, ts_prefix, "
+                         "ts_threshold_search, ts_label_sets")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured as HIP graphs, checked against an eager step "
                          "(default: eager launches, measured faster on MI355X)")
@@ -261,10 +269,10 @@ def parse():
 
 
 def src_hash(name: str) -> str:
-    """Hash of a kernel's source file and the header every kernel includes."""
+    """Hash of a kernel's source file and every header of the kernels."""
     d = os.path.join(ROOT, "paper_2012_10684_amd", "csrc")
     h = hashlib.sha256()
-    for f in (name, "common.h"):
+    for f in [name] + sorted(f for f in os.listdir(d) if f.endswith(".h")):
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -426,10 +434,13 @@ def bench_serving(args, wl, trace, jobs, vols):
     print(json.dumps(line), flush=True)
 
 
-def bench_open(args, wl, dev):
+def bench_open(args, wl, dev, two_d=False):
     """The paper's segmentation step per slice: opening by the disk of radius
     10 (residue = gray - opened), then the Tsallis threshold selected on the
-    residue's gray levels for each q (one threshold) and the residue labelled."""
+    residue's gray levels for each q and the residue labelled: one threshold
+    from the one-dimensional histogram, or (two_d) the pair (t, s) from the 2D
+    histogram of (level, 3x3 average level), labels from t (the paper's
+    form)."""
     import numpy as np
     import torch
 
@@ -451,14 +462,21 @@ def bench_open(args, wl, dev):
     hist = torch.empty((Z, L), dtype=torch.int32, device=dev)
     P = torch.empty((Z, L), dtype=torch.float64, device=dev)
     Q = torch.empty((nq, Z, L), dtype=torch.float64, device=dev)
-    wss = torch.empty(api.workspace_bytes(Z, L, K, api.SEARCH_FP32_TIECHECK, nq), dtype=torch.uint8, device=dev)
-    res = (torch.empty((nq, Z, K), dtype=torch.int32, device=dev), torch.empty((nq, Z), dtype=torch.float64, device=dev),
-           torch.empty((nq, Z), dtype=torch.int32, device=dev))
-    thrs = [res[0][j] for j in range(nq)]
+    if two_d:
+        hist = torch.empty((Z, L, L), dtype=torch.int32, device=dev)
+        wss = torch.empty(api.workspace2d_bytes(Z, L, nq), dtype=torch.uint8, device=dev)
+        res = (torch.empty((nq, 2, Z), dtype=torch.int32, device=dev),
+               torch.empty((nq, Z), dtype=torch.float64, device=dev), torch.empty((nq, Z), dtype=torch.int32, device=dev))
+        thrs = [res[0][j, 0] for j in range(nq)]  # t of each pair
+    else:
+        wss = torch.empty(api.workspace_bytes(Z, L, K, api.SEARCH_FP32_TIECHECK, nq), dtype=torch.uint8, device=dev)
+        res = (torch.empty((nq, Z, K), dtype=torch.int32, device=dev),
+               torch.empty((nq, Z), dtype=torch.float64, device=dev), torch.empty((nq, Z), dtype=torch.int32, device=dev))
+        thrs = [res[0][j] for j in range(nq)]
     outs = [[torch.empty(H * W, dtype=torch.uint8, device=dev) for _ in range(Z)] for _ in QS]
     optrs = [api.device_table([o.data_ptr() for o in oq], dev) for oq in outs]
     stream = torch.cuda.current_stream()
-    names = ["opening", "histogram", "prefix", "search", "label"]
+    names = ["opening", "histogram", "search", "label"] if two_d else ["opening", "histogram", "prefix", "search", "label"]
 
     def step(ev=None):
         ev = ev or {}
@@ -471,13 +489,20 @@ def bench_open(args, wl, dev):
         api.open2d(batch, H, W, binn, R, ws=ws, opened=opened, residue16=r16, want=(), stream=stream)
         mark("opening", 1)
         mark("histogram", 0)
-        api.histogram(rb, ident, out=hist, tune="auto", stream=stream)
+        if two_d:
+            api.histogram2d(rb, H, W, ident, out=hist, stream=stream)
+        else:
+            api.histogram(rb, ident, out=hist, tune="auto", stream=stream)
         mark("histogram", 1)
-        mark("prefix", 0)
-        api.prefix(hist, QS, P=P, Q=Q, stream=stream)
-        mark("prefix", 1)
+        if not two_d:
+            mark("prefix", 0)
+            api.prefix(hist, QS, P=P, Q=Q, stream=stream)
+            mark("prefix", 1)
         mark("search", 0)
-        api.threshold_search(P, Q, K, QS, ws=wss, out=res, tune="auto", stream=stream)
+        if two_d:
+            api.threshold_search2d(hist, QS, ws=wss, out=res, stream=stream)
+        else:
+            api.threshold_search(P, Q, K, QS, ws=wss, out=res, tune="auto", stream=stream)
         mark("search", 1)
         mark("label", 0)
         api.label_sets(rb, ident, thrs, K, outs=outs, out_ptrs=optrs, tune="auto", stream=stream)
@@ -508,11 +533,13 @@ def bench_open(args, wl, dev):
     # opened + int16 residue out
     line = {
         "metric": "voxels/s (the paper's segmentation step: opening by a disk of radius 10, Tsallis threshold "
-                  "of the residue, labels)",
+                  + ("pair (t, s) of the residue's 2D histogram, labels from t)" if two_d
+                     else "of the residue, labels)"),
         "value": nvox * args.steps / dt, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": desc, "images": Z, "voxels": nvox, "radius": R, "k": K, "q": list(QS)},
+        "config": {"workload": desc, "images": Z, "voxels": nvox, "radius": R, "k": K, "q": list(QS),
+                   "form": "2d" if two_d else "1d"},
         "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
         "kernel_us_note": "from an untimed pass with events around every stage (each event adds a gap)",
         "roofline": {"bound": "hbm", "kernel": "k_morph (erosion + dilation)", "achieved": alg / avg / 1e9,
@@ -695,8 +722,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "volume300_2d":
         return bench_2d(args, WORKLOADS[args.workload], dev)
-    if args.workload == "volume300_open":
-        return bench_open(args, WORKLOADS[args.workload], dev)
+    if args.workload in ("volume300_open", "volume300_open2d"):
+        return bench_open(args, WORKLOADS[args.workload], dev, two_d=args.workload == "volume300_open2d")
     if args.calibrate:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -769,12 +796,20 @@ def main():
     optrs = [torch.tensor([o.data_ptr() for o in oq], dtype=torch.int64).to(dev) for oq in outs]
     stream = torch.cuda.current_stream()
     names = ["histogram", "prefix", "search", "label"]
+    fused = args.path == "fused"
+    if fused and args.graph:
+        raise SystemExit("--graph replays the separate steps: use it with --path steps")
+    # ts_segment's workspace (contents ignored)
+    seg_ws = torch.empty(max(api.segment_workspace_bytes(nseg, L, K, nq), 1), dtype=torch.uint8, device=dev)
+    # the roofline kernel: the fused segmentation kernel, or the label pass
+    rk = "segment" if fused else "label"
 
-    def step(ev=None, st=None, parts=("pre", "label"), i=0):
+    def step(ev=None, st=None, parts=("pre", "label"), i=0, path=None):
         """One pass of the path over input copy i on stream st (default: the
         current stream); ev maps kernel names (or "step") to a (start, end)
-        pair of events recorded around that kernel; parts selects histogram +
-        prefix + search ("pre") and labels ("label")."""
+        pair of events recorded around that kernel; path "fused" (one
+        ts_segment call) or "steps" (default: --path); for the steps, parts
+        selects histogram + prefix + search ("pre") and labels ("label")."""
         ev = ev or {}
         st = st or stream
         batch = batches[i % n_in]
@@ -784,6 +819,12 @@ def main():
                 ev[name][i].record(st)
 
         mark("step", 0)
+        if (path or args.path) == "fused":
+            mark("segment", 0)
+            api.segment(batch, binn, K, QS, hist=hist, out=res, out_ptrs=optrs, ws=seg_ws, tune="auto", stream=st)
+            mark("segment", 1)
+            mark("step", 1)
+            return
         if "pre" in parts:
             mark("histogram", 0)
             api.histogram(batch, binn, out=hist, tune="auto", stream=st)
@@ -821,7 +862,7 @@ def main():
     # histogram's 2), and only in every EV_EVERY-th step: each recorded event
     # adds a few us of gap to the stream
     sampled = list(range(0, args.steps, EV_EVERY))
-    roof_ev = {s: p for s, p in zip(sampled, pairs(len(sampled), ["label"]))}
+    roof_ev = {s: p for s, p in zip(sampled, pairs(len(sampled), [rk]))}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if graphs is not None:
@@ -841,7 +882,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
-    label_t = avg_us(list(roof_ev.values()), "label") * 1e-6
+    roof_t = avg_us(list(roof_ev.values()), rk) * 1e-6
     if graphs is not None:
         # the same steps launched eagerly (untimed for the record)
         torch.cuda.synchronize()
@@ -855,12 +896,18 @@ def main():
     nb = min(args.steps, 20)
     kev = pairs(nb, names)
     for s in range(nb):
-        step(kev[s], i=s)
+        step(kev[s], i=s, path="steps")
     sev = pairs(args.steps, ["step"])
     for s in range(args.steps):
         step(sev[s], i=s)
+    fev = pairs(nb, ["segment"])
+    for s in range(nb):
+        step(fev[s], i=s, path="fused")
     torch.cuda.synchronize()
     per = {n: avg_us(kev, n) * 1e-6 for n in names}
+    per["segment (fused, one call)"] = avg_us(fev, "segment") * 1e-6
+    step(i=0)  # the results reported below come from the timed path
+    torch.cuda.synchronize()
 
     nvox = nvox_all
     n = L - 1
@@ -868,9 +915,11 @@ def main():
     tuples = len(QS) * nseg * per_problem
     hist_t = per["histogram"]
     label_bytes = (2 + nq) * nvox  # int16 in, one uint8 label per q out
-    avg = label_t
+    avg = roof_t
+    # algorithmic bytes: the int16 input once and one label byte per q (the
+    # fused kernel's second read of each problem is not algorithmic)
     alg = label_bytes
-    src = "k_label.hip"
+    src = "k_search.hip" if fused else "k_label.hip"
     achieved = alg / avg / 1e9
     traffic = load_traffic(src, args.workload)
     # correctness guard: every problem found a valid tuple, every label pass wrote labels in [0, K]
@@ -893,12 +942,13 @@ def main():
         "tuples_per_s": tuples * args.steps / dt,
         "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
         "kernel_us_note": "from an untimed pass with events around every kernel (each event adds a gap)",
-        "roofline": {"bound": "hbm", "kernel": src.replace(".hip", ""), "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_segment" if fused else "k_label", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6},
+        "path": args.path,
         "histogram_gbs": 2 * nvox / hist_t / 1e9,
-        "label_gbs": achieved,
+        "label_gbs": label_bytes / per["label"] / 1e9,
         "all_problems_ok": bool(st_ok),
     }
     line["launch"] = "hip_graph_replay" if graphs is not None else "eager"

@@ -123,6 +123,10 @@ typedef struct {
     int32_t search_path;     /* 1: one workgroup per problem (k <= 2, nbins <= 1024, or k = 1),
                                 2: one launch per search phase; 0: chosen from the sizes */
     int32_t search_block;    /* threads per workgroup on the one-workgroup path: 256, 512 or 1024 */
+    int32_t segment_parts;   /* ts_segment: workgroups per problem, 1..64 (1: the whole path of a
+                                problem in one workgroup and one launch) */
+    int32_t segment_block;   /* ts_segment: threads per workgroup: 256, 512 or 1024 (raised to what
+                                the prefix scan of nbins needs) */
 } ts_tuning;
 
 /* ts_histogram -- per-problem histograms of gray levels (Thresholding
@@ -192,6 +196,37 @@ size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t
 ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
                               int32_t nq, const double *q, int32_t mode, void *ws, size_t ws_bytes, int32_t *thr,
                               double *obj, int32_t *status, const ts_tuning *tune, ts_stream_t stream);
+
+/* [host] Bytes of workspace ts_segment needs for these sizes (labels: whether
+ * it writes labels); 0 if the sizes are invalid. */
+size_t ts_segment_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq, int32_t mode, int32_t labels);
+
+/* ts_segment -- the whole path in one call: per problem the histogram of
+ * gray levels (as ts_histogram), the prefix sums (as ts_prefix), the arg max
+ * threshold tuple for every q (as ts_threshold_search) and the labels (as
+ * ts_label_sets).  Every output is bit-identical to those calls'.  For
+ * k <= 2 in the FP32 modes (nbins <= 4096 for k = 1, <= 1024 for k = 2;
+ * nq <= TS_MAX_LABEL_SETS when labelling) the steps run fused: with one
+ * workgroup per problem the whole path of a problem is one workgroup of one
+ * launch (its voxels read twice, nothing else leaves the chip but the
+ * histogram and the results); with several workgroups per problem (few
+ * problems), the last one to finish counting does the prefix sums and the
+ * search, then one label launch.  Other sizes and modes run the separate
+ * passes.
+ *   batch, bin, k, nq, q, mode   as for ts_histogram / ts_threshold_search;
+ *   hist    out: uint32 [nseg][L];
+ *   thr, obj, status   out: as ts_threshold_search ([nq][nseg][k], [nq][nseg]);
+ *   out     [host] array [nq] of device tables of [nseg] device pointers (as
+ *           ts_label_sets), or NULL for no labels;
+ *   ws      device workspace of ws_bytes >= ts_segment_workspace_bytes(...);
+ *           its contents on entry are ignored (the per-problem tickets that
+ *           find the last workgroup of a problem are tagged with a value
+ *           that changes with every call).  Concurrent calls must not share
+ *           a workspace.
+ * Errors: as the separate calls; TS_ERR_WORKSPACE for a workspace too small. */
+ts_status ts_segment(ts_batch batch, ts_binning bin, int32_t k, int32_t nq, const double *q, int32_t mode,
+                     uint32_t *hist, int32_t *thr, double *obj, int32_t *status, uint8_t *const *const *out,
+                     void *ws, size_t ws_bytes, const ts_tuning *tune, ts_stream_t stream);
 
 /* Largest number of thresholds ts_threshold_search_dp finds and ts_label /
  * ts_label_sets apply. */
@@ -363,7 +398,7 @@ const char *ts_last_error(void);
 /* [host] ABI version of this header (increments on incompatible change). */
 int32_t ts_abi_version(void);
 
-#define TS_ABI_VERSION 2
+#define TS_ABI_VERSION 3
 
 #ifdef __cplusplus
 }

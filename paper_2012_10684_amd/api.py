@@ -27,7 +27,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TS_LIBRARY", os.path.join(_HERE, "libts.so"))
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_Q = 8
 TS_OK, TS_ERR_INVALID_ARG, TS_ERR_UNSUPPORTED, TS_ERR_WORKSPACE, TS_ERR_HIP = 0, 1, 2, 3, 4
 SEARCH_FP32_TIECHECK, SEARCH_FP32_ONLY, SEARCH_FP64, SEARCH_PLAIN, SEARCH_SUMPROD = 0, 1, 2, 3, 4
@@ -49,7 +49,8 @@ class _Batch(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "hist_block", "hist_replicas", "hist_wg_per_cu", "label_block", "label_vecs",
-        "search_cols", "search_rows", "min_chunk", "search_path", "search_block")]
+        "search_cols", "search_rows", "min_chunk", "search_path", "search_block", "segment_parts",
+        "segment_block")]
 
     @classmethod
     def from_dict(cls, d: Optional[dict]):
@@ -78,6 +79,9 @@ def _load():
     lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
     lib.ts_search_workspace_bytes.restype = sz
     lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, sz, P, P, P, P, P]
+    lib.ts_segment_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.ts_segment_workspace_bytes.restype = sz
+    lib.ts_segment.argtypes = [_Batch, Binning, i32, i32, P, i32, P, P, P, P, P, P, sz, P, P]
     lib.ts_label.argtypes = [_Batch, Binning, P, i32, P, P, P]
     lib.ts_label_sets.argtypes = [_Batch, Binning, i32, P, i32, P, P, P]
     lib.ts_log2_f32.argtypes = [P, P, i64, P]
@@ -92,7 +96,7 @@ def _load():
     lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
     lib.ts_search_dp_workspace_bytes.restype = sz
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
-    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_label, lib.ts_label_sets,
+    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_segment, lib.ts_label, lib.ts_label_sets,
               lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d, lib.ts_threshold_search_dp,
               lib.ts_open2d, lib.ts_issue_rate):
         f.restype = ctypes.c_int
@@ -360,9 +364,51 @@ def label_sets(batch: Batch, bin: Binning, thrs: Sequence[torch.Tensor], k: int,
     return outs
 
 
-def segment(batch: Batch, bin: Binning, k: int, q: float, mode: int = SEARCH_FP32_TIECHECK, tune=None,
-            stream=None):
-    """histogram -> prefix -> search -> label for every problem of the batch."""
+def segment_workspace_bytes(nseg: int, nbins: int, k: int, nq: int = 1, mode: int = SEARCH_FP32_TIECHECK,
+                            labels: bool = True) -> int:
+    return int(_lib.ts_segment_workspace_bytes(nseg, nbins, k, nq, mode, 1 if labels else 0))
+
+
+def segment(batch: Batch, bin: Binning, k: int, q, mode: int = SEARCH_FP32_TIECHECK, labels: bool = True,
+            hist=None, out=None, label_outs=None, out_ptrs=None, ws=None, tune=None, stream=None):
+    """The whole path in one call (ts_segment): histograms [nseg, L], (thr,
+    obj, status) as threshold_search ([nq] leading when q is a sequence) and,
+    with labels, per q a list of per-problem uint8 label tensors (None when
+    out_ptrs are given).  ws: a workspace of segment_workspace_bytes (any
+    contents), allocated here by default."""
+    qs, batched = _qs(q)
+    nq, nseg, L = len(qs), batch.nseg, bin.nbins
+    dev = batch.ptrs.device
+    lead = (nq,) if batched else ()
+    need = segment_workspace_bytes(nseg, L, k, nq, mode, labels)
+    with _on(stream):
+        if hist is None:
+            hist = torch.empty((nseg, L), dtype=torch.int32, device=dev)
+        if out is None:
+            out = (torch.empty(lead + (nseg, k), dtype=torch.int32, device=dev),
+                   torch.empty(lead + (nseg,), dtype=torch.float64, device=dev),
+                   torch.empty(lead + (nseg,), dtype=torch.int32, device=dev))
+        if ws is None:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        if labels and out_ptrs is None:
+            if label_outs is None:
+                label_outs = [[torch.empty(int(n), dtype=torch.uint8, device=dev) for n in batch.sizes] for _ in qs]
+            out_ptrs = [device_table([o.data_ptr() for o in oq], dev, stream) for oq in label_outs]
+    thr, obj, status = out
+    arr = None
+    if labels:
+        arr = (ctypes.c_void_p * nq)(*[p.data_ptr() for p in out_ptrs])
+    t = _tune(tune, lambda a: a.key_segment(nseg, batch.total, L, k, nq))
+    _check(_lib.ts_segment(batch._c, bin, int(k), nq, _qarr(qs), int(mode), _ptr(hist), _ptr(thr), _ptr(obj),
+                           _ptr(status), ctypes.cast(arr, ctypes.c_void_p) if labels else None, _ptr(ws),
+                           ws.numel(), t, _stream(stream)))
+    return hist, out, label_outs
+
+
+def segment_steps(batch: Batch, bin: Binning, k: int, q: float, mode: int = SEARCH_FP32_TIECHECK, tune=None,
+                  stream=None):
+    """histogram -> prefix -> search -> label for every problem of the batch,
+    as four separate calls."""
     h = histogram(batch, bin, tune=tune, stream=stream)
     P, Q = prefix(h, q, stream=stream)
     thr, obj, status = threshold_search(P, Q, k, q, mode, tune=tune, stream=stream)
@@ -387,12 +433,15 @@ def batch_segment(volumes: Sequence[torch.Tensor], bin: Binning, k: int, q, per:
     stage: one problem per slice (per="slice") or per volume
     (per="volume"); q a value or a sequence of up to MAX_LABEL_SETS values
     (all q searched in one launch, labelled in one pass); method "exhaustive"
-    (ts_threshold_search with `mode`), "dp" (ts_threshold_search_dp) or
-    "auto" (exhaustive for k <= 3, dp beyond).  With open_radius (per="slice"
-    only), each slice is first opened by that disk and the threshold is
-    selected and applied on the residue (the paper's segmentation order;
-    gray levels through the identity binning).  Only marshalling: every step
-    runs in libts."""
+    (ts_threshold_search with `mode`), "dp" (ts_threshold_search_dp), "2d"
+    (the two-dimensional form: per="slice", k = 1, every volume with the same
+    slice shape; 2D histograms of (gray level, 3x3 average gray level), the
+    arg max pair (t, s), labels from t alone; hist is then [nseg, L, L] and
+    thr an [nq, nseg, 2] view holding (t, s)) or "auto" (exhaustive for
+    k <= 3, dp beyond).  With open_radius (per="slice" only), each slice is
+    first opened by that disk and the threshold is selected and applied on the
+    residue (the paper's segmentation order; gray levels through the identity
+    binning).  Only marshalling: every step runs in libts."""
     if per not in ("slice", "volume"):
         raise ValueError("per must be 'slice' or 'volume'")
     # every tensor this call makes (copies, outputs) is allocated on the
@@ -428,6 +477,19 @@ def _batch_segment(volumes, bin, k, q, per, mode, method, open_radius, tune, str
     else:
         segs = [v.reshape(-1) for v in src]
     batch = Batch(segs, stream=stream)
+    if method == "2d":
+        if per != "slice" or k != 1:
+            raise ValueError("the two-dimensional form takes per='slice' and k = 1")
+        shapes = {tuple(v.shape[1:]) for v in src}
+        if len(shapes) != 1 or any(v.dim() != 3 for v in src):
+            raise ValueError("the two-dimensional form needs (Z, H, W) volumes of one slice shape")
+        (Hh, Ww), = shapes
+        h = histogram2d(batch, Hh, Ww, bin, stream=stream)
+        thr2, obj, status = threshold_search2d(h, list(qs), stream=stream)  # [nq, 2, nseg]
+        labels = [[torch.empty(v.shape, dtype=torch.uint8, device=v.device) for v in src] for _ in qs]
+        outs = [[lv[z].reshape(-1) for lv in lj for z in range(lv.shape[0])] for lj in labels]
+        label_sets(batch, bin, [thr2[j, 0] for j in range(len(qs))], 1, outs=outs, tune=tune, stream=stream)
+        return Segmentation(h, thr2.transpose(1, 2), obj, status, labels, residues)
     h = histogram(batch, bin, tune=tune, stream=stream)
     P, Q = prefix(h, list(qs), stream=stream)
     if method == "dp":

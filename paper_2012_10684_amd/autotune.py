@@ -76,6 +76,10 @@ def key_search(nseg: int, L: int, k: int, mode: int) -> str:
     return f"{_arch()}|search|L={L}|k={k}|mode={mode}|nseg=2^{_p2(nseg)}"
 
 
+def key_segment(nseg: int, total: int, L: int, k: int, nq: int) -> str:
+    return f"{_arch()}|segment|L={L}|k={k}|nq={nq}|nseg=2^{_p2(nseg)}|vox=2^{_p2(total)}"
+
+
 def histogram_space(L: int) -> Iterable[dict]:
     # min_chunk bounds the workgroup count from below in voxels per workgroup:
     # large chunks pay off when each workgroup flushes many bins

@@ -71,6 +71,8 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
     o->min_chunk = t->min_chunk ? t->min_chunk : 8192;
     o->search_path = t->search_path;
     o->search_block = t->search_block ? t->search_block : 512;
+    o->segment_parts = t->segment_parts;
+    o->segment_block = t->segment_block;
     if (o->hist_block < 64 || o->hist_block > 1024 || o->hist_block % 64)
         return fail(TS_ERR_INVALID_ARG, "tuning: hist_block must be a multiple of 64 in [64, 1024]");
     if (!pow2(o->hist_replicas) || o->hist_replicas > 32)
@@ -93,6 +95,10 @@ ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *o)
         return fail(TS_ERR_INVALID_ARG, "tuning: search_path must be 0, 1 or 2");
     if (o->search_block != 256 && o->search_block != 512 && o->search_block != 1024)
         return fail(TS_ERR_INVALID_ARG, "tuning: search_block must be 256, 512 or 1024");
+    if (o->segment_parts < 0 || o->segment_parts > 64)
+        return fail(TS_ERR_INVALID_ARG, "tuning: segment_parts must be in [1, 64]");
+    if (o->segment_block != 0 && o->segment_block != 256 && o->segment_block != 512 && o->segment_block != 1024)
+        return fail(TS_ERR_INVALID_ARG, "tuning: segment_block must be 256, 512 or 1024");
     return TS_OK;
 }
 
@@ -348,6 +354,56 @@ ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int
                         uint8_t *const *const *out, const ts_tuning *tune, ts_stream_t stream)
 {
     return label_common("ts_label_sets", batch, bin, nsets, thr, k, out, tune, stream);
+}
+
+size_t ts_segment_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq, int32_t mode, int32_t labels)
+{
+    if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || nbins < k + 1 || k < 1 || k > 3 || nq < 1 || nq > TS_MAX_Q ||
+        mode < 0 || mode > TS_SEARCH_SUMPROD || (labels && nq > TS_MAX_LABEL_SETS))
+        return 0;
+    return segment_workspace_bytes(nseg, nbins, k, nq, mode, labels != 0);
+}
+
+ts_status ts_segment(ts_batch batch, ts_binning bin, int32_t k, int32_t nq, const double *q, int32_t mode,
+                     uint32_t *hist, int32_t *thr, double *obj, int32_t *status, uint8_t *const *const *out,
+                     void *ws, size_t ws_bytes, const ts_tuning *tune, ts_stream_t stream)
+{
+    ts_status st = check_batch(batch);
+    if (st != TS_OK)
+        return st;
+    BinMap bm;
+    if ((st = make_binmap(bin, &bm)) != TS_OK)
+        return st;
+    const int32_t nseg = batch.nseg;
+    // the search's checks (P and Q stand in for pointers the call makes itself)
+    const double *nn = (const double *)1;
+    if ((st = check_search_args("ts_segment", nn, nn, nseg, bin.nbins, k, nq, q, mode, thr, obj, status)) != TS_OK)
+        return st;
+    if (out && nq > TS_MAX_LABEL_SETS)
+        return fail(TS_ERR_INVALID_ARG, "ts_segment: labels for at most " + std::to_string(TS_MAX_LABEL_SETS) +
+                                            " values of q");
+    LabelSets sets = {};
+    if (out && nseg > 0) {
+        for (int u = 0; u < nq; ++u) {
+            if (!out[u])
+                return fail(TS_ERR_INVALID_ARG, "ts_segment: null pointer");
+            sets.thr[u] = thr + (int64_t)u * nseg * k;
+            sets.out[u] = out[u];
+        }
+    }
+    if (nseg > 0 && !hist)
+        return fail(TS_ERR_INVALID_ARG, "ts_segment: null pointer");
+    Tune t;
+    if ((st = resolve_tuning(tune, bin.nbins, &t)) != TS_OK)
+        return st;
+    const size_t need = segment_workspace_bytes(nseg, bin.nbins, k, nq, mode, out != nullptr);
+    if (nseg > 0 && (ws_bytes < need || !ws))
+        return fail(TS_ERR_WORKSPACE, "ts_segment: workspace too small (need " + std::to_string(need) +
+                                          " bytes, got " + std::to_string(ws_bytes) + ")");
+    if (nseg == 0)
+        return TS_OK;
+    return launch_segment(batch, bm, k, nq, q, mode, hist, thr, obj, status, out ? &sets : nullptr, ws, t,
+                          (hipStream_t)stream);
 }
 
 ts_status ts_histogram2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, uint32_t *hist,

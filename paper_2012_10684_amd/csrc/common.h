@@ -30,6 +30,7 @@ struct Tune {
     int search_cols, search_rows;
     int min_chunk;
     int search_path, search_block;
+    int segment_parts, segment_block;
 };
 ts_status resolve_tuning(const ts_tuning *t, int nbins, Tune *out);
 
@@ -210,5 +211,9 @@ ts_status check_search_args(const char *fn, const double *P, const double *Q, in
 ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k, int nq, const double *q, int mode,
                         void *ws, size_t ws_bytes, int32_t *thr, double *obj, int32_t *status, const Tune &t,
                         hipStream_t st);
+size_t segment_workspace_bytes(int nseg, int L, int k, int nq, int mode, bool labels);
+ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, const double *q, int mode,
+                         uint32_t *hist, int32_t *thr, double *obj, int32_t *status, const LabelSets *sets, void *ws,
+                         const Tune &t, hipStream_t st);
 
 } // namespace ts

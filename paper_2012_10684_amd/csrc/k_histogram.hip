@@ -19,10 +19,9 @@
 #include <algorithm>
 
 #include "common.h"
+#include "hist_dev.h"
 
 namespace ts {
-
-typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Zero n words: the words before the first 16-byte boundary, then 16-byte
 // stores, then the last n mod 4 words (p is 4-byte aligned).
@@ -49,19 +48,6 @@ ts_status launch_fill_u32(uint32_t *p, int64_t n, hipStream_t st)
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ((n >> 2) + 255) / 256));
     hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, p, n);
     return check_launch("zero fill");
-}
-
-template <int R, int MAP>
-__device__ __forceinline__ void count8(uint32_t *lds, const v4i &w, const BinMap &bm, uint32_t rep)
-{
-    const uint32_t u[4] = {(uint32_t)w.x, (uint32_t)w.y, (uint32_t)w.z, (uint32_t)w.w};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        int v0 = (int)(int16_t)(u[j] & 0xffffu);
-        int v1 = (int)(int16_t)(u[j] >> 16);
-        atomicAdd(&lds[bin_of_t<MAP>(v0, bm) * R + rep], 1u);
-        atomicAdd(&lds[bin_of_t<MAP>(v1, bm) * R + rep], 1u);
-    }
 }
 
 template <int R>

@@ -47,8 +47,13 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 
 #include "common.h"
+#include "hist_dev.h"
+#include "label_dev.h"
+#include "prefix_dev.h"
 
 namespace ts {
 
@@ -1050,19 +1055,19 @@ __global__ void __launch_bounds__(K3_THREADS) k_rows3(Args a)
         rows3_body<0, PHASE>(a, Arow, wm);
 }
 
-// Write one problem's result from its best candidate.
-// Write problem s's result from its best candidate.
-__device__ __forceinline__ void write_result(const Cand &b, const Args &a, int s, int32_t *thr, double *obj,
-                                             int32_t *status)
+// Write problem s's result from its best candidate (plast = P(L-1) of the
+// problem: 1, or 0 when it holds no voxel).
+__device__ __forceinline__ void write_result(const Cand &b, const Args &a, int s, double plast, int32_t *thr,
+                                             double *obj, int32_t *status)
 {
-    const int k = a.k, L = a.L;
+    const int k = a.k;
     const QConst &qc = a.qc[s / a.nseg];
     const double q = qc.q, sgn = qc.sgn;
     if (b.r == -INFINITY) {
         for (int j = 0; j < k; ++j)
             thr[(int64_t)s * k + j] = -1;
         obj[s] = NAN;
-        status[s] = a.P[(int64_t)(s % a.nseg) * L + L - 1] > 0.0 ? TS_PROBLEM_DEGENERATE : TS_PROBLEM_EMPTY;
+        status[s] = plast > 0.0 ? TS_PROBLEM_DEGENERATE : TS_PROBLEM_EMPTY;
     } else {
         long long c = b.c;
         for (int j = k - 1; j >= 0; --j) {
@@ -1091,7 +1096,8 @@ struct FusedLds {
     double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
     long long wc[FUSED_THREADS / 64];
     float sdelta;
-    int next; // next tile to hand out in phase 1
+    int next;       // next tile to hand out in phase 1
+    long long code; // the result's tuple code (-1: none)
 };
 
 static size_t fused_lds_bytes(int Lp, int k, int tiles)
@@ -1100,26 +1106,30 @@ static size_t fused_lds_bytes(int Lp, int k, int tiles)
            (size_t)tiles * sizeof(float);
 }
 
+// The whole search of problem s by the calling workgroup, from its prefix
+// sums P, Q [L] (global memory, or LDS); stage: copy them to LDS for phase 2
+// (k = 2 from global memory).  Writes the result and returns its tuple code
+// (-1: no valid tuple) in every thread.
 template <int SGN, int COLS, int K>
-__device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t *__restrict__ thr_out,
-                                           double *__restrict__ obj, int32_t *__restrict__ status)
+__device__ __forceinline__ long long fused_body(const Args &a, FusedLds &sh, int s, const double *P, const double *Q,
+                                                bool stage, int32_t *__restrict__ thr_out, double *__restrict__ obj,
+                                                int32_t *__restrict__ status)
 {
     float *hd = sh.hd, *tr = sh.tr, *tmax = sh.tmax, *wmax = sh.wmax;
     float4 *hls = sh.hls;
-    const int s = blockIdx.x;
     const QConst &qc = a.qc[s / a.nseg];
-    const double *P = a.P + (int64_t)(s % a.nseg) * a.L;
-    const double *Q = a.Q + (int64_t)s * a.L;
-    // k = 2: split prefixes and FP64 prefixes in LDS
+    // k = 2: split prefixes (and FP64 prefixes, when staged) in LDS
     const Steps stp = head_tail32<SGN>(a, qc, P, Q, hd, tr, K == 2 ? hls : nullptr, sh.red,
-                                       K == 2 ? sh.pd : nullptr, K == 2 ? sh.qd : nullptr);
+                                       K == 2 && stage ? sh.pd : nullptr, K == 2 && stage ? sh.qd : nullptr);
     if (threadIdx.x == 0) {
         sh.sdelta = problem_delta(a, qc, stp, Q[a.L - 1]);
         sh.next = 0;
     }
     __syncthreads();
     TileCtx x = make_ctx(a, s, hd, tr, hls);
-    if (K == 2) { // phase 2 reads the prefixes from LDS
+    x.P = P;
+    x.Q = Q;
+    if (K == 2 && stage) { // phase 2 reads the prefixes from LDS
         x.P = sh.pd;
         x.Q = sh.qd;
     }
@@ -1189,8 +1199,11 @@ __device__ __forceinline__ void fused_body(const Args &a, FusedLds &sh, int32_t 
                 best.l = sh.wl[i];
                 best.c = sh.wc[i];
             }
-        write_result(best, a, s, thr_out, obj, status);
+        write_result(best, a, s, P[a.L - 1], thr_out, obj, status);
+        sh.code = best.r == -INFINITY ? -1LL : best.c;
     }
+    __syncthreads();
+    return sh.code;
 }
 
 template <int COLS, int K>
@@ -1205,13 +1218,16 @@ __global__ void __launch_bounds__(FUSED_THREADS) k_fused(Args a, int32_t *__rest
     sh.hd = reinterpret_cast<float *>(sh.qd + (K == 2 ? a.Lp : 0));
     sh.tr = sh.hd + a.Lp;
     sh.tmax = sh.tr + a.Lp;
-    const double sgn = a.qc[blockIdx.x / a.nseg].sgn;
+    const int s = blockIdx.x;
+    const double sgn = a.qc[s / a.nseg].sgn;
+    const double *P = a.P + (int64_t)(s % a.nseg) * a.L;
+    const double *Q = a.Q + (int64_t)s * a.L;
     if (sgn > 0)
-        fused_body<1, COLS, K>(a, sh, thr_out, obj, status);
+        fused_body<1, COLS, K>(a, sh, s, P, Q, true, thr_out, obj, status);
     else if (sgn < 0)
-        fused_body<-1, COLS, K>(a, sh, thr_out, obj, status);
+        fused_body<-1, COLS, K>(a, sh, s, P, Q, true, thr_out, obj, status);
     else
-        fused_body<0, COLS, K>(a, sh, thr_out, obj, status);
+        fused_body<0, COLS, K>(a, sh, s, P, Q, true, thr_out, obj, status);
 }
 
 // FP64 mode: exhaustive FP64 keys with the lexicographic tie rule.
@@ -1336,7 +1352,7 @@ __global__ void __launch_bounds__(1024) k_final(Args a, const Best *__restrict__
                 bl = sl[j];
                 bc = sc[j];
             }
-        write_result(Cand{br, bl, bc}, a, s, thr, obj, status);
+        write_result(Cand{br, bl, bc}, a, s, a.P[(int64_t)(s % a.nseg) * a.L + a.L - 1], thr, obj, status);
     }
 }
 
@@ -1488,6 +1504,479 @@ __global__ void __launch_bounds__(256) k_sumprod(Args a, int64_t ntup, int per, 
             }
         out[blockIdx.x] = Best{br, br, bc, 0};
     }
+}
+
+QConst make_qconst(double q, int L);
+
+// ---------------------------------------------------------------- whole path
+
+// ts_segment: histogram, prefix sums, search and labels of every problem in
+// one launch (one workgroup per problem), or in two (P workgroups per problem
+// counting parts of it, the last of them to finish doing the prefix sums and
+// the search; then the label pass).  The steps are the device code of the
+// separate passes (count8_rt, prefix_row with the same bins per thread,
+// fused_body, lab8), so every output is bit-identical to theirs.
+//
+// LDS: area A (the histogram replicas; later the prefix scan's scratch; then
+// the search's rows) | counts [Lp] | P [Lp] | Q [Lp] of the current q.
+
+constexpr int SEG_COLS = 2;            // search columns per lane
+constexpr int SEG_MAX_PARTS = 64;      // workgroups per problem
+constexpr int SEG_MAX_PART_WG = 1024;  // problems x parts when parts > 1
+constexpr int SEG_MIN_PART = 16384;    // voxels per part (parts > 1)
+constexpr size_t SEG_MAX_LDS = 150 * 1024; // dynamic LDS of one workgroup (160 KiB per CU, static part aside)
+
+struct SegArgs {
+    const int16_t *const *vox;
+    const int64_t *offs;
+    int nseg, parts, lr, nq, E;
+    BinMap bm;
+    uint32_t *hist;        // out [nseg][L]
+    uint32_t *partial;            // [nseg][parts][L] when parts > 1
+    unsigned long long *tickets;  // [nseg] when parts > 1 (any initial contents)
+    unsigned int epoch;           // this call's tag of the tickets (never 0)
+    LabelSets sets;        // label sets written by this kernel (label = 1)
+    int label;
+    int areaA; // bytes of LDS area A (a multiple of 16)
+};
+
+// The part's ticket for its problem: the word holds (call tag << 32 | parts
+// counted so far); a word left by another call, or any other contents, is
+// restarted for this call.  Returns 1 for the first part to arrive, parts for
+// the last.  Each failed exchange means another part got in, so the loop
+// ends after at most parts + 1 rounds.
+__device__ __forceinline__ unsigned int take_ticket(unsigned long long *t, unsigned int epoch)
+{
+    unsigned long long old = __hip_atomic_load(t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const unsigned long long nw =
+            (unsigned int)(old >> 32) == epoch ? old + 1ull : (((unsigned long long)epoch << 32) | 1ull);
+        unsigned long long seen = old;
+        if (__hip_atomic_compare_exchange_strong(t, &seen, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return (unsigned int)(nw & 0xffffffffull);
+        old = seen;
+    }
+}
+
+// Count the voxels [i0, i1) of one problem into the LDS replicas: scalar head
+// up to the first 16-byte boundary, 16-byte vectors with the next four in
+// flight while four are counted, scalar tail.  Ordinary loads: the label
+// pass of the same workgroup reads these bytes again.
+template <int MAP>
+__device__ __forceinline__ void seg_count(uint32_t *lds, int lr, const TS_GLOBAL int16_t *base, int64_t i0, int64_t i1,
+                                          const BinMap &bm)
+{
+    const uint32_t rep = threadIdx.x & ((1u << lr) - 1u);
+    int64_t head = (int64_t)(((16u - ((uintptr_t)(base + i0) & 15u)) & 15u) >> 1);
+    if (head > i1 - i0)
+        head = i1 - i0;
+    if (threadIdx.x < head)
+        atomicAdd(&lds[(bin_of_t<MAP>(base[i0 + threadIdx.x], bm) << lr) + rep], 1u);
+    const int64_t vb = i0 + head;
+    const int64_t nvec = (i1 - vb) >> 3;
+    const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(base + vb);
+    const int64_t st = blockDim.x;
+    int64_t j = threadIdx.x;
+    bool have = j + 3 * st < nvec;
+    v4i a0 = {0, 0, 0, 0}, a1 = a0, a2 = a0, a3 = a0;
+    if (have) {
+        a0 = vp[j];
+        a1 = vp[j + st];
+        a2 = vp[j + 2 * st];
+        a3 = vp[j + 3 * st];
+    }
+    while (have) {
+        const int64_t jn = j + 4 * st;
+        const bool nxt = jn + 3 * st < nvec;
+        v4i b0 = a0, b1 = a1, b2 = a2, b3 = a3;
+        if (nxt) {
+            b0 = vp[jn];
+            b1 = vp[jn + st];
+            b2 = vp[jn + 2 * st];
+            b3 = vp[jn + 3 * st];
+        }
+        count8_rt<MAP>(lds, a0, bm, lr, rep);
+        count8_rt<MAP>(lds, a1, bm, lr, rep);
+        count8_rt<MAP>(lds, a2, bm, lr, rep);
+        count8_rt<MAP>(lds, a3, bm, lr, rep);
+        a0 = b0;
+        a1 = b1;
+        a2 = b2;
+        a3 = b3;
+        j = jn;
+        have = nxt;
+    }
+    for (; j < nvec; j += st) {
+        const v4i w = vp[j];
+        count8_rt<MAP>(lds, w, bm, lr, rep);
+    }
+    const int64_t tb = vb + (nvec << 3);
+    if (threadIdx.x < i1 - tb)
+        atomicAdd(&lds[(bin_of_t<MAP>(base[tb + threadIdx.x], bm) << lr) + rep], 1u);
+}
+
+// Labels of one whole problem for nq threshold sets (thresholds in LDS), the
+// rules of the label pass: 16-byte loads of 8 voxels and 8-byte stores per
+// set where the input and outputs share the alignment phase, else voxel by
+// voxel.
+template <int K>
+__device__ __forceinline__ void seg_label(const SegArgs &g, int s, const TS_GLOBAL int16_t *src, int64_t n,
+                                          const int (*tsh)[K])
+{
+    Cuts<K> cu[TS_MAX_LABEL_SETS];
+    PCuts<K> pc[TS_MAX_LABEL_SETS];
+    TS_GLOBAL uint8_t *dst[TS_MAX_LABEL_SETS];
+    int64_t head = (int64_t)(((16u - ((uintptr_t)src & 15u)) & 15u) >> 1);
+    if (head > n)
+        head = n;
+    bool vec = true;
+#pragma unroll
+    for (int u = 0; u < TS_MAX_LABEL_SETS; ++u) {
+        if (u < g.nq) {
+            cu[u] = make_cuts<K>(tsh[u], K, g.bm);
+            pc[u] = pack_cuts(cu[u]);
+            dst[u] = gpw(g.sets.out[u][s]);
+            vec = vec && (((uintptr_t)(dst[u] + head)) & 7u) == 0;
+        }
+    }
+    const int64_t bd = blockDim.x;
+    if (!vec) {
+        for (int64_t i = threadIdx.x; i < n; i += bd) {
+            const int v = src[i];
+#pragma unroll
+            for (int u = 0; u < TS_MAX_LABEL_SETS; ++u)
+                if (u < g.nq)
+                    dst[u][i] = (uint8_t)lab1(v, cu[u]);
+        }
+        return;
+    }
+    if (threadIdx.x < head) {
+        const int v = src[threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < TS_MAX_LABEL_SETS; ++u)
+            if (u < g.nq)
+                dst[u][threadIdx.x] = (uint8_t)lab1p(v, pc[u]);
+    }
+    const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(src + head);
+    const int64_t nvec = (n - head) >> 3;
+    for (int64_t i0 = threadIdx.x; i0 < nvec; i0 += 4 * bd) {
+        v4i w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + e * bd;
+            w[e] = i < nvec ? __builtin_nontemporal_load(vp + i) : v4i{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + e * bd;
+            if (i < nvec) {
+#pragma unroll
+                for (int u = 0; u < TS_MAX_LABEL_SETS; ++u)
+                    if (u < g.nq)
+                        __builtin_nontemporal_store(lab8(w[e], pc[u]),
+                                                    reinterpret_cast<TS_GLOBAL v2u *>(dst[u] + head) + i);
+            }
+        }
+    }
+    const int64_t tb = head + (nvec << 3);
+    if (threadIdx.x < n - tb) {
+        const int v = src[tb + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < TS_MAX_LABEL_SETS; ++u)
+            if (u < g.nq)
+                dst[u][tb + threadIdx.x] = (uint8_t)lab1p(v, pc[u]);
+    }
+}
+
+template <int K, int MAP>
+__global__ void __launch_bounds__(1024) k_segment(SegArgs g, Args a, int32_t *__restrict__ thr_out,
+                                                  double *__restrict__ obj, int32_t *__restrict__ status)
+{
+    extern __shared__ float4 dyn[];
+    __shared__ FusedLds sh;
+    __shared__ PrefixLds ps;
+    __shared__ unsigned int tk;
+    __shared__ int tsh[TS_MAX_LABEL_SETS][K];
+    const int L = g.bm.L, Lp = a.Lp;
+    char *area = reinterpret_cast<char *>(dyn);
+    uint32_t *rl = reinterpret_cast<uint32_t *>(area);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(area + g.areaA);
+    double *Pl = reinterpret_cast<double *>(area + g.areaA + (size_t)4 * Lp);
+    double *Ql = Pl + Lp;
+    const int s = blockIdx.x / g.parts, part = blockIdx.x % g.parts;
+    const int lr = g.lr;
+
+    for (int i = threadIdx.x; i < (L << lr); i += blockDim.x)
+        rl[i] = 0u;
+    __syncthreads();
+    const int64_t o0 = g.offs[s], n = g.offs[s + 1] - o0;
+    const TS_GLOBAL int16_t *src = gp(g.vox[s]);
+    {
+        const int64_t per = ((n + g.parts - 1) / g.parts + 7) & ~(int64_t)7;
+        const int64_t i0 = min(n, (int64_t)part * per), i1 = min(n, i0 + per);
+        if (i0 < i1)
+            seg_count<MAP>(rl, lr, src, i0, i1, g.bm);
+    }
+    __syncthreads();
+    const int R = 1 << lr;
+    if (g.parts == 1) {
+        for (int b = threadIdx.x; b < L; b += blockDim.x) {
+            uint32_t c = 0;
+            for (int r = 0; r < R; ++r)
+                c += rl[(b << lr) + r];
+            cnt[b] = c;
+            g.hist[(int64_t)s * L + b] = c;
+        }
+    } else {
+        // the part's counts go out as device-coherent stores; once every
+        // store is acknowledged the part takes a ticket, and the part that
+        // takes the last one adds all parts up (device-coherent loads) and
+        // goes on.  No cache-wide fence is needed: only these stores and
+        // loads cross workgroups.
+        uint32_t *mine = g.partial + ((int64_t)s * g.parts + part) * L;
+        for (int b = threadIdx.x; b < L; b += blockDim.x) {
+            uint32_t c = 0;
+            for (int r = 0; r < R; ++r)
+                c += rl[(b << lr) + r];
+            __hip_atomic_store(mine + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            tk = take_ticket(g.tickets + s, g.epoch);
+        __syncthreads();
+        if (tk != (unsigned int)g.parts)
+            return;
+        const uint32_t *pp = g.partial + (int64_t)s * g.parts * L;
+        const int bd = blockDim.x;
+        for (int b0 = threadIdx.x; b0 < L; b0 += 4 * bd) {
+            uint32_t c[4] = {0u, 0u, 0u, 0u};
+            for (int p0 = 0; p0 < g.parts; p0 += 8) { // 32 loads in flight
+                uint32_t v[4][8];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int b = b0 + i * bd, p = p0 + u;
+                        v[i][u] = (b < L && p < g.parts)
+                                      ? __hip_atomic_load(pp + (int64_t)p * L + b, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : 0u;
+                    }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        c[i] += v[i][u];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int b = b0 + i * bd;
+                if (b < L) {
+                    cnt[b] = c[i];
+                    g.hist[(int64_t)s * L + b] = c[i];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // prefix sums and search, one q at a time (P once, Q per q, in LDS)
+    double *qs = reinterpret_cast<double *>(area);
+    int *lastocc = reinterpret_cast<int *>(area + (size_t)8 * L);
+    sh.hls = reinterpret_cast<float4 *>(area);
+    sh.pd = nullptr;
+    sh.qd = nullptr;
+    sh.hd = reinterpret_cast<float *>(area + (K == 2 ? (size_t)16 * Lp : 0));
+    sh.tr = sh.hd + Lp;
+    sh.tmax = sh.tr + Lp;
+    for (int j = 0; j < g.nq; ++j) {
+        prefix_row([cnt](int b) { return cnt[b]; }, L, g.E, a.qc[j].q, j == 0 ? Pl : nullptr, Ql, qs, lastocc, ps);
+        const int sj = j * g.nseg + s;
+        const double sgn = a.qc[j].sgn;
+        long long code;
+        if (sgn > 0)
+            code = fused_body<1, SEG_COLS, K>(a, sh, sj, Pl, Ql, false, thr_out, obj, status);
+        else if (sgn < 0)
+            code = fused_body<-1, SEG_COLS, K>(a, sh, sj, Pl, Ql, false, thr_out, obj, status);
+        else
+            code = fused_body<0, SEG_COLS, K>(a, sh, sj, Pl, Ql, false, thr_out, obj, status);
+        if (threadIdx.x == 0 && j < TS_MAX_LABEL_SETS) {
+            for (int i = K - 1; i >= 0; --i) {
+                tsh[j][i] = code < 0 ? -1 : (int)(code & 4095);
+                code = code < 0 ? code : code >> 12;
+            }
+        }
+    }
+    if (!g.label)
+        return;
+    __syncthreads();
+    seg_label<K>(g, s, src, n, tsh);
+}
+
+static bool seg_fusable(int L, int k, int mode, int nq, bool labels)
+{
+    if (mode != TS_SEARCH_FP32_TIECHECK && mode != TS_SEARCH_FP32_ONLY)
+        return false;
+    if (labels && nq > TS_MAX_LABEL_SETS)
+        return false;
+    if (!((k == 1 && L <= FUSED_MAX_L) || (k == 2 && L <= FUSED_MAX_L2)))
+        return false;
+    return make_plan(1, L, k, mode, SEG_COLS, 16).tiles <= FUSED_MAX_TILES;
+}
+
+static int seg_log2_replicas(const Tune &t)
+{
+    int lr = 0;
+    while ((1 << lr) < t.hist_replicas)
+        ++lr;
+    return lr;
+}
+
+static size_t seg_areaA(int L, int Lp, int k, int tiles, int lr)
+{
+    size_t a = ((size_t)L << lr) * sizeof(uint32_t);
+    a = std::max(a, (size_t)L * (sizeof(double) + sizeof(int)));
+    a = std::max(a, fused_lds_bytes(Lp, k, tiles));
+    return (a + 15) & ~(size_t)15;
+}
+
+size_t segment_workspace_bytes(int nseg, int L, int k, int nq, int mode, bool labels)
+{
+    if (seg_fusable(L, k, mode, nq, labels))
+        return align256((size_t)nseg * sizeof(unsigned long long)) +
+               (size_t)L * sizeof(uint32_t) * (size_t)std::min<int64_t>(SEG_MAX_PART_WG, (int64_t)nseg * SEG_MAX_PARTS);
+    // the separate passes: P, Q and the search workspace
+    return align256((size_t)nseg * L * sizeof(double)) + align256((size_t)nq * nseg * L * sizeof(double)) +
+           search_workspace_bytes(nseg * nq, L, k, mode, 4);
+}
+
+// Workgroups per problem: one when the problems alone fill the chip twice;
+// else enough to, with at least SEG_MIN_PART voxels each.
+static int seg_parts(int nseg, int64_t total, const Tune &t)
+{
+    if (t.segment_parts) // within what the workspace holds
+        return t.segment_parts == 1 ? 1 : std::max(1, std::min(t.segment_parts, SEG_MAX_PART_WG / std::max(nseg, 1)));
+    const int cus = device_cu_count();
+    if (nseg >= 2 * cus)
+        return 1;
+    int p = (2 * cus + nseg - 1) / nseg;
+    const int64_t avg = total / std::max(nseg, 1);
+    p = (int)std::min<int64_t>(p, std::max<int64_t>(1, avg / SEG_MIN_PART));
+    p = std::min(p, SEG_MAX_PARTS);
+    p = std::min(p, std::max(1, SEG_MAX_PART_WG / std::max(nseg, 1)));
+    return std::max(p, 1);
+}
+
+template <int K, int MAP>
+static void launch_seg_km(dim3 g, dim3 b, size_t lds, hipStream_t st, const SegArgs &sa, const Args &a, int32_t *thr,
+                          double *obj, int32_t *status)
+{
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_segment<K, MAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipLaunchKernelGGL((k_segment<K, MAP>), g, b, lds, st, sa, a, thr, obj, status);
+}
+
+ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, const double *q, int mode,
+                         uint32_t *hist, int32_t *thr, double *obj, int32_t *status, const LabelSets *sets, void *ws,
+                         const Tune &t, hipStream_t st)
+{
+    const int L = bm.L, nseg = b.nseg;
+    char *wb = (char *)ws;
+    if (!seg_fusable(L, k, mode, nq, sets != nullptr)) {
+        double *P = (double *)wb;
+        double *Q = (double *)(wb + align256((size_t)nseg * L * sizeof(double)));
+        char *sw = wb + align256((size_t)nseg * L * sizeof(double)) + align256((size_t)nq * nseg * L * sizeof(double));
+        ts_status e;
+        if ((e = launch_histogram(b, bm, hist, t, st)) != TS_OK)
+            return e;
+        if ((e = launch_prefix(hist, nseg, L, nq, q, P, Q, st)) != TS_OK)
+            return e;
+        if ((e = launch_search(P, Q, nseg, L, k, nq, q, mode, sw, search_workspace_bytes(nseg * nq, L, k, mode, 4),
+                               thr, obj, status, t, st)) != TS_OK)
+            return e;
+        return sets ? launch_label(b, bm, *sets, nq, k, t, st) : TS_OK;
+    }
+    const int parts = seg_parts(nseg, b.total, t);
+    const Plan p = make_plan(nseg * nq, L, k, mode, SEG_COLS, t.search_rows);
+    Args a = {};
+    a.P = nullptr;
+    a.Q = nullptr;
+    a.nseg = nseg;
+    a.nprob = nseg * nq;
+    a.L = L;
+    a.Lp = p.Lp;
+    a.k = k;
+    a.mode = mode;
+    for (int j = 0; j < TS_MAX_Q; ++j)
+        a.qc[j] = make_qconst(q[j < nq ? j : 0], L);
+    a.CW = p.CW;
+    a.NB = p.NB;
+    a.NC = p.NC;
+    a.T1 = p.T1;
+    a.tiles = p.tiles;
+    SegArgs sa = {};
+    sa.vox = b.vox;
+    sa.offs = b.offs;
+    sa.nseg = nseg;
+    sa.parts = parts;
+    sa.lr = seg_log2_replicas(t);
+    sa.nq = nq;
+    sa.E = prefix_bins_per_thread(L);
+    sa.bm = bm;
+    sa.hist = hist;
+    sa.tickets = (unsigned long long *)wb;
+    sa.partial = (uint32_t *)(wb + align256((size_t)nseg * sizeof(unsigned long long)));
+    {
+        // a tag per call (never 0), starting from a value of this process's
+        // clock so that words left in reused memory are unlikely to match
+        static std::atomic<unsigned int> seq{(unsigned int)std::chrono::steady_clock::now().time_since_epoch().count()};
+        unsigned int e;
+        do
+            e = ++seq;
+        while (e == 0);
+        sa.epoch = e;
+    }
+    sa.label = sets != nullptr && parts == 1;
+    if (sets)
+        sa.sets = *sets;
+    // fewer histogram replicas if the LDS would not hold them (replicas
+    // change no result)
+    size_t lds;
+    for (;;) {
+        sa.areaA = (int)seg_areaA(L, p.Lp, k, p.tiles, sa.lr);
+        lds = (size_t)sa.areaA + (size_t)p.Lp * (sizeof(uint32_t) + 2 * sizeof(double));
+        if (lds <= SEG_MAX_LDS || sa.lr == 0)
+            break;
+        --sa.lr;
+    }
+    if (lds > SEG_MAX_LDS)
+        return fail(TS_ERR_UNSUPPORTED, "ts_segment: sizes beyond the LDS of one workgroup");
+    // the prefix scan needs blockDim * E >= L
+    int block = t.segment_block ? t.segment_block : (parts > 1 || L >= 1024 ? 1024 : 512);
+    while (block * sa.E < L)
+        block *= 2;
+    const dim3 g((unsigned)((int64_t)nseg * parts)), blk((unsigned)block);
+#define TS_SEG(K)                                                                                                    \
+    switch (map_kind(bm)) {                                                                                          \
+    case 0: launch_seg_km<K, 0>(g, blk, lds, st, sa, a, thr, obj, status); break;                                   \
+    case 1: launch_seg_km<K, 1>(g, blk, lds, st, sa, a, thr, obj, status); break;                                   \
+    case 2: launch_seg_km<K, 2>(g, blk, lds, st, sa, a, thr, obj, status); break;                                   \
+    default: launch_seg_km<K, 3>(g, blk, lds, st, sa, a, thr, obj, status); break;                                  \
+    }
+    if (k == 1) {
+        TS_SEG(1)
+    } else {
+        TS_SEG(2)
+    }
+#undef TS_SEG
+    ts_status e = check_launch("ts_segment");
+    if (e != TS_OK)
+        return e;
+    if (sets && parts > 1)
+        return launch_label(b, bm, *sets, nq, k, t, st);
+    return TS_OK;
 }
 
 // ---------------------------------------------------------------- dispatch

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_path():
     names = declared_functions()
     for n in ("ts_histogram", "ts_prefix", "ts_threshold_search", "ts_label", "ts_label_sets",
-              "ts_search_workspace_bytes",
+              "ts_search_workspace_bytes", "ts_segment", "ts_segment_workspace_bytes",
               "ts_last_error", "ts_abi_version"):
         assert n in names, names
 
@@ -72,6 +72,9 @@ def _bind(lib):
     lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
     lib.ts_search_dp_workspace_bytes.restype = sz
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
+    lib.ts_segment_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.ts_segment_workspace_bytes.restype = sz
+    lib.ts_segment.argtypes = [Batch, Binning, i32, i32, P, i32, P, P, P, P, P, P, sz, P, P]
     lib.ts_last_error.restype = ctypes.c_char_p
     return lib
 
@@ -86,7 +89,7 @@ def qs(*v):
 
 def test_abi_version(lib):
     lib.ts_abi_version.restype = ctypes.c_int32
-    assert lib.ts_abi_version() == 2
+    assert lib.ts_abi_version() == 3
 
 
 def test_workspace_sizes(lib):
@@ -121,6 +124,8 @@ def test_workspace_sizes(lib):
     ("open_bins", 1), ("open_radius", 1), ("open_radius_neg", 1), ("open_total", 1), ("open_no_output", 1),
     ("open_ws", 3), ("open_height", 1),
     ("dp_k0", 1), ("dp_k17", 1), ("dp_bins_lt_k1", 1), ("dp_q", 1), ("dp_ws", 3), ("dp_null", 1), ("dp_misaligned", 1),
+    ("seg_k4", 1), ("seg_ws", 3), ("seg_nq5_labels", 1), ("seg_null_hist", 1), ("seg_null_out_entry", 1),
+    ("seg_bad_parts", 1), ("seg_bad_block", 1), ("seg_q", 1), ("seg_bins", 3),
 ])
 def test_argument_errors(lib, case, expect):
     _bind(lib)
@@ -137,7 +142,7 @@ def test_argument_errors(lib, case, expect):
     elif case == "hist_null":
         st = lib.ts_histogram(Batch(None, FAKE, 1, 10), ok_bin, FAKE, None, sx)
     elif case == "hist_bad_tune":
-        tune = (ctypes.c_int32 * 10)(100, 0, 0, 0, 0, 0, 0, 0, 0, 0)  # block not a multiple of 64
+        tune = (ctypes.c_int32 * 12)(100, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0)  # block not a multiple of 64
         st = lib.ts_histogram(b1, ok_bin, FAKE, ctypes.cast(tune, T), sx)
     elif case == "prefix_q0":
         st = lib.ts_prefix(FAKE, 1, 256, 1, qs(0.0), FAKE, FAKE, sx)
@@ -203,6 +208,23 @@ def test_argument_errors(lib, case, expect):
         ws = ctypes.c_void_p(0x1004) if case == "dp_misaligned" else FAKE
         st = lib.ts_threshold_search_dp(None if case == "dp_null" else FAKE, FAKE, 2, L, k, 1, q, ws, ws_bytes, FAKE,
                                         FAKE, FAKE, sx)
+    elif case.startswith("seg_"):
+        k = 4 if case == "seg_k4" else 2
+        nq = 5 if case == "seg_nq5_labels" else 2
+        q = qs(*([0.8] * nq)) if case != "seg_q" else qs(0.8, 0.0)
+        binning = Binning(-1024, 3071, 2000 if case == "seg_bins" else 256)
+        tune = None
+        if case in ("seg_bad_parts", "seg_bad_block"):
+            vals = [0] * 12
+            vals[10 if case == "seg_bad_parts" else 11] = 65 if case == "seg_bad_parts" else 384
+            tune = ctypes.cast((ctypes.c_int32 * 12)(*vals), T)
+        outp = (T * 5)(*([FAKE.value] * 5))
+        if case == "seg_null_out_entry":
+            outp[1] = None
+        # 2000 bins with k = 2 run the separate passes: valid sizes, the workspace too small
+        ws_bytes = 16 if case in ("seg_ws", "seg_bins") else 1 << 40
+        st = lib.ts_segment(b1, binning, k, nq, q, 0, None if case == "seg_null_hist" else FAKE, FAKE, FAKE, FAKE,
+                            ctypes.cast(outp, T), FAKE, ws_bytes, tune, sx)
     elif case == "log2_neg":
         st = lib.ts_log2_f32(FAKE, FAKE, -1, sx)
     elif case == "log2_null":
@@ -240,3 +262,19 @@ def test_empty_batch_is_a_no_op(lib):
     assert lib.ts_prefix(None, 0, 256, 1, qs(0.8), None, None, None) == 0
     assert lib.ts_threshold_search(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, 0, None, None, None, None,
                                    None) == 0
+    assert lib.ts_segment(Batch(None, None, 0, 0), ok_bin, 2, 1, qs(0.8), 0, None, None, None, None, None, None, 0,
+                          None, None) == 0
+
+
+def test_segment_workspace_sizes(lib):
+    _bind(lib)
+    ws = lib.ts_segment_workspace_bytes
+    # fused (k <= 2): tickets + partial histograms of at most 1024 workgroups
+    assert ws(1, 4096, 1, 1, 0, 1) == 256 + 4096 * 4 * 64
+    assert ws(22844, 256, 2, 1, 0, 1) == ((22844 * 8 + 255) // 256) * 256 + 256 * 4 * 1024
+    # separate passes (k = 3, or FP64): P, Q and the search workspace
+    assert ws(1, 1024, 3, 1, 0, 1) >= 2 * 1024 * 8 + lib.ts_search_workspace_bytes(1, 1024, 3, 1, 0)
+    assert ws(2, 256, 2, 1, 2, 1) >= 2 * 2 * 256 * 8
+    for bad in [(-1, 256, 2, 1, 0, 1), (1, 1, 1, 1, 0, 1), (1, 256, 4, 1, 0, 1), (1, 256, 2, 5, 0, 1),
+                (1, 256, 2, 9, 0, 0), (1, 256, 2, 1, 9, 1)]:
+        assert ws(*bad) == 0, bad
