@@ -228,6 +228,29 @@ ts_status ts_segment(ts_batch batch, ts_binning bin, int32_t k, int32_t nq, cons
                      uint32_t *hist, int32_t *thr, double *obj, int32_t *status, uint8_t *const *const *out,
                      void *ws, size_t ws_bytes, const ts_tuning *tune, ts_stream_t stream);
 
+/* Bytes of the library-owned device scratch behind
+ * ts_threshold_search_noalloc (one array per GPU, held until the process
+ * ends). */
+#define TS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* ts_threshold_search_noalloc -- ts_threshold_search for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * ts_threshold_search, without the workspace: the kernels that need one use
+ * a fixed library-owned device array of TS_NOALLOC_SCRATCH_BYTES per GPU.
+ * Nothing is allocated by this call (no hipMalloc, no library allocator).
+ * The scratch is shared by every call on one GPU and keeps the last call's
+ * contents (the kernels initialise every word they read); calls that overlap
+ * on one GPU (different streams or threads) race on it and must be
+ * serialised by the caller.
+ * Errors: as ts_threshold_search, and TS_ERR_WORKSPACE when these sizes need
+ * more than TS_NOALLOC_SCRATCH_BYTES of scratch (the one-workgroup-per-problem
+ * path needs none), TS_ERR_HIP when the scratch's device address cannot be
+ * obtained. */
+ts_status ts_threshold_search_noalloc(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
+                                      int32_t nq, const double *q, int32_t mode, int32_t *thr, double *obj,
+                                      int32_t *status, const ts_tuning *tune, ts_stream_t stream);
+
 /* Largest number of thresholds ts_threshold_search_dp finds and ts_label /
  * ts_label_sets apply. */
 #define TS_DP_MAX_K 16

@@ -79,6 +79,7 @@ def _load():
     lib.ts_search_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
     lib.ts_search_workspace_bytes.restype = sz
     lib.ts_threshold_search.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, sz, P, P, P, P, P]
+    lib.ts_threshold_search_noalloc.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, P, P, P, P]
     lib.ts_segment_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
     lib.ts_segment_workspace_bytes.restype = sz
     lib.ts_segment.argtypes = [_Batch, Binning, i32, i32, P, i32, P, P, P, P, P, P, sz, P, P]
@@ -96,7 +97,7 @@ def _load():
     lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
     lib.ts_search_dp_workspace_bytes.restype = sz
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
-    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_segment, lib.ts_label, lib.ts_label_sets,
+    for f in (lib.ts_histogram, lib.ts_prefix, lib.ts_threshold_search, lib.ts_threshold_search_noalloc, lib.ts_segment, lib.ts_label, lib.ts_label_sets,
               lib.ts_log2_f32, lib.ts_histogram2d, lib.ts_threshold_search2d, lib.ts_threshold_search_dp,
               lib.ts_open2d, lib.ts_issue_rate):
         f.restype = ctypes.c_int
@@ -267,6 +268,31 @@ def threshold_search(P: torch.Tensor, Q: torch.Tensor, k: int, q, mode: int = SE
     t = _tune(tune, lambda a: a.key_search(nseg * nq, L, k, mode))
     _check(_lib.ts_threshold_search(_ptr(P), _ptr(Q), nseg, L, int(k), nq, _qarr(qs), int(mode), _ptr(ws),
                                     ws.numel(), _ptr(thr), _ptr(obj), _ptr(status), t, _stream(stream)))
+    return thr, obj, status
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def threshold_search_noalloc(P: torch.Tensor, Q: torch.Tensor, k: int, q, mode: int = SEARCH_FP32_TIECHECK,
+                             out=None, tune=None, stream=None):
+    """threshold_search without a workspace: the library's fixed per-GPU
+    scratch is used (calls that overlap on one GPU race on it).  With `out`
+    (thr, obj, status) nothing is allocated here either."""
+    nseg, L = P.shape
+    qs, batched = _qs(q)
+    nq = len(qs)
+    lead = (nq,) if batched else ()
+    if out is None:
+        with _on(stream):
+            thr = torch.empty(lead + (nseg, k), dtype=torch.int32, device=P.device)
+            obj = torch.empty(lead + (nseg,), dtype=torch.float64, device=P.device)
+            status = torch.empty(lead + (nseg,), dtype=torch.int32, device=P.device)
+    else:
+        thr, obj, status = out
+    t = _tune(tune, lambda a: a.key_search(nseg * nq, L, k, mode))
+    _check(_lib.ts_threshold_search_noalloc(_ptr(P), _ptr(Q), nseg, L, int(k), nq, _qarr(qs), int(mode),
+                                            _ptr(thr), _ptr(obj), _ptr(status), t, _stream(stream)))
     return thr, obj, status
 
 

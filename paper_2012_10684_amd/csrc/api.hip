@@ -311,6 +311,69 @@ ts_status ts_threshold_search(const double *P, const double *Q, int32_t nseg, in
     return launch_search(P, Q, nseg, nbins, k, nq, q, mode, ws, ws_bytes, thr, obj, status, t, (hipStream_t)stream);
 }
 
+} // extern "C"
+
+namespace ts {
+
+// Scratch of ts_threshold_search_noalloc.  Every GPU holds its own copy of
+// this array; in host code its name is only a host-side stand-in, so the
+// device address is looked up once per device (with that device current)
+// and only that address is handed to kernels.
+__device__ __align__(256) unsigned char scratch[TS_NOALLOC_SCRATCH_BYTES];
+
+static ts_status scratch_address(void **out)
+{
+    static std::mutex mu;
+    static std::unordered_map<int, void *> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(TS_ERR_HIP, std::string("ts_threshold_search_noalloc: hipGetDevice: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) {
+        *out = it->second;
+        return TS_OK;
+    }
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(TS_ERR_HIP, std::string("ts_threshold_search_noalloc: hipGetSymbolAddress: ") +
+                                    (e != hipSuccess ? hipGetErrorString(e) : "null address"));
+    addr[dev] = p;
+    *out = p;
+    return TS_OK;
+}
+
+} // namespace ts
+
+extern "C" {
+
+ts_status ts_threshold_search_noalloc(const double *P, const double *Q, int32_t nseg, int32_t nbins, int32_t k,
+                                      int32_t nq, const double *q, int32_t mode, int32_t *thr, double *obj,
+                                      int32_t *status, const ts_tuning *tune, ts_stream_t stream)
+{
+    ts_status st;
+    if ((st = check_search_args("ts_threshold_search_noalloc", P, Q, nseg, nbins, k, nq, q, mode, thr, obj,
+                                status)) != TS_OK)
+        return st;
+    Tune t;
+    if ((st = resolve_tuning(tune, nbins, &t)) != TS_OK)
+        return st;
+    if (nseg == 0)
+        return TS_OK;
+    const size_t need = search_need_bytes(nseg * nq, nbins, k, mode, t);
+    if (need > TS_NOALLOC_SCRATCH_BYTES)
+        return fail(TS_ERR_WORKSPACE, "ts_threshold_search_noalloc: these sizes need " + std::to_string(need) +
+                                          " bytes of scratch, more than the fixed " +
+                                          std::to_string(TS_NOALLOC_SCRATCH_BYTES));
+    void *ws = nullptr;
+    if ((st = scratch_address(&ws)) != TS_OK)
+        return st;
+    return launch_search(P, Q, nseg, nbins, k, nq, q, mode, ws, TS_NOALLOC_SCRATCH_BYTES, thr, obj, status, t,
+                         (hipStream_t)stream);
+}
+
 static ts_status label_common(const char *fn, ts_batch batch, ts_binning bin, int32_t nsets,
                               const int32_t *const *thr, int32_t k, uint8_t *const *const *out, const ts_tuning *tune,
                               ts_stream_t stream)

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_path():
     names = declared_functions()
     for n in ("ts_histogram", "ts_prefix", "ts_threshold_search", "ts_label", "ts_label_sets",
-              "ts_search_workspace_bytes", "ts_segment", "ts_segment_workspace_bytes",
+              "ts_search_workspace_bytes", "ts_segment", "ts_segment_workspace_bytes", "ts_threshold_search_noalloc",
               "ts_last_error", "ts_abi_version"):
         assert n in names, names
 
@@ -72,6 +72,7 @@ def _bind(lib):
     lib.ts_search_dp_workspace_bytes.argtypes = [i32, i32, i32, i32]
     lib.ts_search_dp_workspace_bytes.restype = sz
     lib.ts_threshold_search_dp.argtypes = [P, P, i32, i32, i32, i32, P, P, sz, P, P, P, P]
+    lib.ts_threshold_search_noalloc.argtypes = [P, P, i32, i32, i32, i32, P, i32, P, P, P, P, P]
     lib.ts_segment_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
     lib.ts_segment_workspace_bytes.restype = sz
     lib.ts_segment.argtypes = [Batch, Binning, i32, i32, P, i32, P, P, P, P, P, P, sz, P, P]
@@ -126,6 +127,7 @@ def test_workspace_sizes(lib):
     ("dp_k0", 1), ("dp_k17", 1), ("dp_bins_lt_k1", 1), ("dp_q", 1), ("dp_ws", 3), ("dp_null", 1), ("dp_misaligned", 1),
     ("seg_k4", 1), ("seg_ws", 3), ("seg_nq5_labels", 1), ("seg_null_hist", 1), ("seg_null_out_entry", 1),
     ("seg_bad_parts", 1), ("seg_bad_block", 1), ("seg_q", 1), ("seg_bins", 3),
+    ("noalloc_k0", 1), ("noalloc_null", 1), ("noalloc_beyond_scratch", 3),
 ])
 def test_argument_errors(lib, case, expect):
     _bind(lib)
@@ -225,6 +227,13 @@ def test_argument_errors(lib, case, expect):
         ws_bytes = 16 if case in ("seg_ws", "seg_bins") else 1 << 40
         st = lib.ts_segment(b1, binning, k, nq, q, 0, None if case == "seg_null_hist" else FAKE, FAKE, FAKE, FAKE,
                             ctypes.cast(outp, T), FAKE, ws_bytes, tune, sx)
+    elif case.startswith("noalloc_"):
+        k = 0 if case == "noalloc_k0" else 2
+        P = None if case == "noalloc_null" else FAKE
+        n = 20000 if case == "noalloc_beyond_scratch" else 2
+        tune = (ctypes.c_int32 * 12)(0, 0, 0, 0, 0, 0, 0, 0, 2, 0, 0, 0)  # one launch per phase: uses scratch
+        st = lib.ts_threshold_search_noalloc(P, FAKE, n, 256, k, 1, qs(0.8), 0, FAKE, FAKE, FAKE,
+                                             ctypes.cast(tune, T), sx)
     elif case == "log2_neg":
         st = lib.ts_log2_f32(FAKE, FAKE, -1, sx)
     elif case == "log2_null":
@@ -262,6 +271,8 @@ def test_empty_batch_is_a_no_op(lib):
     assert lib.ts_prefix(None, 0, 256, 1, qs(0.8), None, None, None) == 0
     assert lib.ts_threshold_search(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, 0, None, None, None, None,
                                    None) == 0
+    assert lib.ts_threshold_search_noalloc(None, None, 0, 256, 2, 2, qs(0.8, 1.5), 0, None, None, None, None,
+                                           None) == 0
     assert lib.ts_segment(Batch(None, None, 0, 0), ok_bin, 2, 1, qs(0.8), 0, None, None, None, None, None, None, 0,
                           None, None) == 0
 
