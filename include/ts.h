@@ -206,13 +206,14 @@ size_t ts_segment_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_
  * threshold tuple for every q (as ts_threshold_search) and the labels (as
  * ts_label_sets).  Every output is bit-identical to those calls'.  For
  * k <= 2 in the FP32 modes (nbins <= 4096 for k = 1, <= 1024 for k = 2;
- * nq <= TS_MAX_LABEL_SETS when labelling) the steps run fused: with one
- * workgroup per problem the whole path of a problem is one workgroup of one
- * launch (its voxels read twice, nothing else leaves the chip but the
- * histogram and the results); with several workgroups per problem (few
- * problems), the last one to finish counting does the prefix sums and the
- * search, then one label launch.  Other sizes and modes run the separate
- * passes.
+ * nq <= TS_MAX_LABEL_SETS when labelling) and at least twice as many
+ * problems as the GPU has compute units (or tune->segment_parts >= 1) the
+ * steps run fused: with one workgroup per problem the whole path of a
+ * problem is one workgroup of one launch (its voxels read twice, nothing
+ * else leaves the chip but the histogram and the results); with several
+ * workgroups per problem (tune->segment_parts > 1) the last one to finish
+ * counting does the prefix sums and the search, then one label launch.
+ * Otherwise the separate passes run, in this one call.
  *   batch, bin, k, nq, q, mode   as for ts_histogram / ts_threshold_search;
  *   hist    out: uint32 [nseg][L];
  *   thr, obj, status   out: as ts_threshold_search ([nq][nseg][k], [nq][nseg]);

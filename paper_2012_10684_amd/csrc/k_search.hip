@@ -1523,8 +1523,8 @@ QConst make_qconst(double q, int L);
 constexpr int SEG_COLS = 2;            // search columns per lane
 constexpr int SEG_MAX_PARTS = 64;      // workgroups per problem
 constexpr int SEG_MAX_PART_WG = 1024;  // problems x parts when parts > 1
-constexpr int SEG_MIN_PART = 16384;    // voxels per part (parts > 1)
 constexpr size_t SEG_MAX_LDS = 150 * 1024; // dynamic LDS of one workgroup (160 KiB per CU, static part aside)
+constexpr int SEG_SEPARATE_BELOW = 1024;   // problems below which a call may take the separate passes
 
 struct SegArgs {
     const int16_t *const *vox;
@@ -1841,31 +1841,42 @@ static size_t seg_areaA(int L, int Lp, int k, int tiles, int lr)
     return (a + 15) & ~(size_t)15;
 }
 
-size_t segment_workspace_bytes(int nseg, int L, int k, int nq, int mode, bool labels)
+static size_t seg_separate_bytes(int nseg, int L, int k, int nq, int mode)
 {
-    if (seg_fusable(L, k, mode, nq, labels))
-        return align256((size_t)nseg * sizeof(unsigned long long)) +
-               (size_t)L * sizeof(uint32_t) * (size_t)std::min<int64_t>(SEG_MAX_PART_WG, (int64_t)nseg * SEG_MAX_PARTS);
-    // the separate passes: P, Q and the search workspace
+    // P, Q and the search workspace of the separate passes
     return align256((size_t)nseg * L * sizeof(double)) + align256((size_t)nq * nseg * L * sizeof(double)) +
            search_workspace_bytes(nseg * nq, L, k, mode, 4);
 }
 
-// Workgroups per problem: one when the problems alone fill the chip twice;
-// else enough to, with at least SEG_MIN_PART voxels each.
-static int seg_parts(int nseg, int64_t total, const Tune &t)
+size_t segment_workspace_bytes(int nseg, int L, int k, int nq, int mode, bool labels)
 {
-    if (t.segment_parts) // within what the workspace holds
-        return t.segment_parts == 1 ? 1 : std::max(1, std::min(t.segment_parts, SEG_MAX_PART_WG / std::max(nseg, 1)));
-    const int cus = device_cu_count();
-    if (nseg >= 2 * cus)
+    if (!seg_fusable(L, k, mode, nq, labels))
+        return seg_separate_bytes(nseg, L, k, nq, mode);
+    const size_t fused = align256((size_t)nseg * sizeof(unsigned long long)) +
+                         (size_t)L * sizeof(uint32_t) *
+                             (size_t)std::min<int64_t>(SEG_MAX_PART_WG, (int64_t)nseg * SEG_MAX_PARTS);
+    // below SEG_SEPARATE_BELOW problems the call may take the separate passes
+    return nseg < SEG_SEPARATE_BELOW ? std::max(fused, seg_separate_bytes(nseg, L, k, nq, mode)) : fused;
+}
+
+// Whether a fusable call takes the fused kernel: with one workgroup per
+// problem when the problems fill the chip twice over (fewer problems leave
+// compute units idle, and the separate passes, which split every problem
+// over many workgroups, are faster there), or as the tuning asks.
+static bool seg_use_fused(int nseg, const Tune &t)
+{
+    if (t.segment_parts)
+        return true;
+    return nseg >= SEG_SEPARATE_BELOW || nseg >= 2 * device_cu_count();
+}
+
+// Workgroups per problem: one unless the tuning asks for more (within what
+// the workspace holds).
+static int seg_parts(int nseg, const Tune &t)
+{
+    if (t.segment_parts <= 1)
         return 1;
-    int p = (2 * cus + nseg - 1) / nseg;
-    const int64_t avg = total / std::max(nseg, 1);
-    p = (int)std::min<int64_t>(p, std::max<int64_t>(1, avg / SEG_MIN_PART));
-    p = std::min(p, SEG_MAX_PARTS);
-    p = std::min(p, std::max(1, SEG_MAX_PART_WG / std::max(nseg, 1)));
-    return std::max(p, 1);
+    return std::max(1, std::min(t.segment_parts, SEG_MAX_PART_WG / std::max(nseg, 1)));
 }
 
 template <int K, int MAP>
@@ -1884,7 +1895,7 @@ ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, con
 {
     const int L = bm.L, nseg = b.nseg;
     char *wb = (char *)ws;
-    if (!seg_fusable(L, k, mode, nq, sets != nullptr)) {
+    if (!seg_fusable(L, k, mode, nq, sets != nullptr) || !seg_use_fused(nseg, t)) {
         double *P = (double *)wb;
         double *Q = (double *)(wb + align256((size_t)nseg * L * sizeof(double)));
         char *sw = wb + align256((size_t)nseg * L * sizeof(double)) + align256((size_t)nq * nseg * L * sizeof(double));
@@ -1898,7 +1909,7 @@ ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, con
             return e;
         return sets ? launch_label(b, bm, *sets, nq, k, t, st) : TS_OK;
     }
-    const int parts = seg_parts(nseg, b.total, t);
+    const int parts = seg_parts(nseg, t);
     const Plan p = make_plan(nseg * nq, L, k, mode, SEG_COLS, t.search_rows);
     Args a = {};
     a.P = nullptr;

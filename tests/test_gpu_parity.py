@@ -425,8 +425,8 @@ def test_determinism_and_batch_invariance():
     dv = to_dev(vol)
     binn = api.binning(-1024, -200, 256)
     whole = api.Batch.slices(dv)
-    r1 = api.segment(whole, binn, 2, 0.8)
-    r2 = api.segment(whole, binn, 2, 0.8)
+    r1 = api.segment_steps(whole, binn, 2, 0.8)
+    r2 = api.segment_steps(whole, binn, 2, 0.8)
     torch.cuda.synchronize()
     assert torch.equal(r1[0], r2[0]) and torch.equal(r1[2][0], r2[2][0])
     assert torch.equal(r1[2][1], r2[2][1])
@@ -434,10 +434,17 @@ def test_determinism_and_batch_invariance():
         assert torch.equal(a, b)
     # each slice alone gives the same bits as inside the batch
     for z in (0, 7, 23):
-        one = api.segment(api.Batch([dv[z].reshape(-1)]), binn, 2, 0.8)
+        one = api.segment_steps(api.Batch([dv[z].reshape(-1)]), binn, 2, 0.8)
         assert torch.equal(one[0][0], r1[0][z])
         assert torch.equal(one[2][0][0], r1[2][0][z]) and torch.equal(one[2][1][0], r1[2][1][z])
         assert torch.equal(one[3][0], r1[3][z])
+    # the whole path in one call (one workgroup per slice) gives the same bits
+    f = api.segment(whole, binn, 2, 0.8, tune={"segment_parts": 1})
+    torch.cuda.synchronize()
+    assert torch.equal(f[0], r1[0]) and torch.equal(f[1][0], r1[2][0])
+    assert torch.equal(f[1][1].view(torch.int64), r1[2][1].view(torch.int64))
+    for a, b in zip(f[2][0], r1[3]):
+        assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("q", [0.5, 1.5])

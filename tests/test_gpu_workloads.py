@@ -21,7 +21,8 @@ def test_single_slice_4096_bins_k1():
     for idx in range(3):
         s = synth.workload_slice(idx)
         binn = api.binning(-1024, 3071, 4096)
-        h, _, (thr, obj, st), labels = api.segment(api.Batch([to_dev(s.reshape(-1))]), binn, 1, 0.8)
+        h, (thr, obj, st), labels = api.segment(api.Batch([to_dev(s.reshape(-1))]), binn, 1, 0.8)
+        labels = labels[0]
         torch.cuda.synchronize()
         hh = oracle.histogram(s, -1024, 3071, 4096)
         assert np.array_equal(u32(h)[0], hh)
@@ -44,7 +45,8 @@ def test_volume300_per_slice_k2(volume300, q):
     dv = to_dev(vol)
     b = api.Batch.slices(dv)
     binn = api.binning(-1024, -200, 256)
-    h, _, (thr, obj, st), labels = api.segment(b, binn, 2, q)
+    h, (thr, obj, st), labels = api.segment(b, binn, 2, q)
+    labels = labels[0]
     torch.cuda.synchronize()
     H = u32(h)
     thr, obj, st = thr.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
@@ -73,7 +75,8 @@ def test_volume600_whole_k3():
     dv = to_dev(vol)
     b = api.Batch([dv.reshape(-1)])
     binn = api.binning(-1024, 3071, 1024)
-    h, _, (thr, obj, st), labels = api.segment(b, binn, 3, 0.8)
+    h, (thr, obj, st), labels = api.segment(b, binn, 3, 0.8)
+    labels = labels[0]
     torch.cuda.synchronize()
     hh = oracle.histogram(vol, -1024, 3071, 1024)
     assert np.array_equal(u32(h)[0], hh)
@@ -145,3 +148,14 @@ def test_batch64_full_size():
             check_choice(want_h, 2, q, thr_h[j, i], obj_h[j, i], st_h[j, i])
             want = oracle.label(sl, -1024, -200, 256, thr_h[j, i])
             assert np.array_equal(flat[j][i].cpu().numpy(), want), (i, q)
+    # the benchmark's launch: q = 0.8 through ts_segment (one workgroup per
+    # slice, the whole path in one launch): every output bit-identical to the
+    # separate passes above
+    say("the same batch at q = 0.8 through ts_segment")
+    fl = torch.empty((nseg, S), dtype=torch.uint8, device=dvols[0].device)
+    hf, (tf, of, sf), _ = api.segment(b, binn, 2, 0.8, label_outs=[[fl[i] for i in range(nseg)]], tune="auto")
+    torch.cuda.synchronize()
+    assert torch.equal(hf, h)
+    assert torch.equal(tf, thr[1]) and torch.equal(sf, st[1])
+    assert torch.equal(of.view(torch.int64), obj[1].view(torch.int64))
+    assert torch.equal(fl, flat[1])
