@@ -15,16 +15,20 @@
 // one hot address.  At the end the non-zero cells are added to the global 2D
 // histogram.
 //
-// k_search2d: one workgroup per (q index, problem), one thread per column s.
-// Class 2 sums are accumulated bottom-up over rows and its log term
-// sgn(1-q) (ln Q_2 - q ln w_2) is stored per cell in the workspace (FP64);
-// then class 1 sums are accumulated top-down, the stored class 2 term of
-// (t+1, s+1) is added and the first best pair is kept (t outermost).  Row
-// sums along s are fixed-order block scans, and an empty cell takes the row
-// sum of the last (first, for suffixes) occupied cell, so a whole empty
-// column or row leaves every class sum unchanged bit for bit and the pairs
-// it separates tie exactly.  FP64 throughout: the reported pair is the FP64
-// arg max.  q = 1 is the Shannon limit, as in the one-dimensional search.
+// k_search2d: one workgroup of four wavefronts per (q index, problem); the
+// rows holding counts are split into four blocks, one per wavefront, four
+// columns per lane.  Class 2 sums are accumulated bottom-up over rows and
+// class 1 sums top-down; a wavefront starts its block from the carried sums
+// of the blocks before it in that direction (each block's column totals,
+// summed along s, exchanged through LDS), so the four walk their rows at
+// once.  FP32 keys of every pair, then an FP64 re-check of the rows whose
+// best key is within the keys' error bound of the maximum, from the same
+// sums; the first best FP64 pair wins (t outermost).  Sums along s are
+// fixed-order scans, and an empty cell (or an empty column of a block's
+// totals) takes the sum of the last occupied one, so a whole empty column or
+// row leaves every class sum unchanged bit for bit and the pairs it
+// separates tie exactly.  q = 1 is the Shannon limit, as in the
+// one-dimensional search.
 #include <math.h>
 
 #include <algorithm>
@@ -40,7 +44,8 @@ constexpr int H2_THREADS = 1024;
 constexpr int H2_MAX_W = 4096;    // row length held in the LDS ring
 constexpr int H2_MAX_L = 256;     // 2D histograms up to 256 x 256
 constexpr int H2_LDS = 160 * 1024; // LDS of one workgroup: the plane (128 KiB at L = 256) and staged rows
-constexpr int S2_THREADS = 64;    // one wavefront per (q, image)
+constexpr int S2_WAVES = 4;       // wavefronts per (q, image), each a block of the rows
+constexpr int S2_THREADS = 64 * S2_WAVES;
 constexpr int S2_CPL = 4;         // columns per lane (L <= 256)
 constexpr int S2_TAB = 2048;      // p^q (or p ln p) of counts below this from an LDS table
 constexpr int S2_RING = 4;        // rows of counts in flight ahead of the row being summed
@@ -342,6 +347,43 @@ __device__ __forceinline__ void row_sums(const uint32_t (&c)[S2_CPL], const doub
     }
 }
 
+// The same scan for per-position values given directly (cc counts, cq sums
+// of cterm; a block's column totals): exact count prefix, FP64 prefix in
+// the lane then after its exclusive base, an empty position taking the
+// value at the nearest occupied position before it.
+__device__ __forceinline__ void pos_sums(const uint64_t (&cc)[S2_CPL], const double (&cq)[S2_CPL],
+                                         uint64_t (&rc)[S2_CPL], double (&rq)[S2_CPL])
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t lc = 0;
+    double lq = 0.0;
+    int first = S2_CPL;
+    uint64_t pc[S2_CPL];
+    double pq[S2_CPL];
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        lc += cc[u];
+        lq = lq + cq[u];
+        pc[u] = lc;
+        pq[u] = lq;
+        if (cc[u] && first == S2_CPL)
+            first = u;
+    }
+    const uint64_t occ = __ballot(lc != 0);
+    const uint64_t bc = wave_excl_sum<uint64_t>(lc);
+    const double bq = wave_excl_sum<double>(lq);
+    const double last = bq + lq;
+    const uint64_t before = occ & ((1ull << lane) - 1ull);
+    const int src = before ? 63 - __clzll((long long)before) : lane;
+    const double prev_raw = __shfl(last, src, 64);
+    const double prev = before ? prev_raw : 0.0;
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        rc[u] = bc + pc[u];
+        rq[u] = u >= first ? bq + pq[u] : prev;
+    }
+}
+
 // FP64 class term from the class sums: sgn(1-q) (ln S - q ln C) for Tsallis,
 // ln C - S / C for q = 1 (S = sum of cterm, C = pixels); -inf for an empty
 // class; clamped to [0, hmax].  Called only for the few rows the FP64
@@ -493,6 +535,57 @@ __device__ __forceinline__ void for_rows(const S2 &p, const int *rows, int k0, i
     }
 }
 
+// Column totals of the listed rows rows[k0], rows[k0 + DIR], ... (n >= 0 of
+// them) in DIR's scan positions: count sums and sums of cterm, added in
+// walking order; the next S2_RING rows' loads in flight.
+template <int DIR>
+__device__ __forceinline__ void block_totals(const S2 &p, const int *rows, int k0, int n, uint64_t (&cc)[S2_CPL],
+                                             double (&cq)[S2_CPL])
+{
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        cc[u] = 0;
+        cq[u] = 0.0;
+    }
+    if (n <= 0)
+        return;
+    uint32_t ring[S2_RING][S2_CPL];
+#pragma unroll
+    for (int d = 0; d < S2_RING; ++d)
+        load_row<DIR>(p.h, p.L, p.vec, rows[k0 + DIR * min(d, n - 1)], ring[d]);
+    for (int i0 = 0; i0 < n; i0 += S2_RING) {
+#pragma unroll
+        for (int d = 0; d < S2_RING; ++d) {
+            const int i = i0 + d;
+            uint32_t c[S2_CPL];
+#pragma unroll
+            for (int u = 0; u < S2_CPL; ++u)
+                c[u] = ring[d][u];
+            load_row<DIR>(p.h, p.L, p.vec, rows[k0 + DIR * min(i + S2_RING, n - 1)], ring[d]);
+            if (i < n) {
+                double t[S2_CPL];
+                bool big = false;
+#pragma unroll
+                for (int u = 0; u < S2_CPL; ++u) {
+                    t[u] = p.tab[min(c[u], (uint32_t)S2_TAB - 1u)];
+                    big |= c[u] >= (uint32_t)S2_TAB;
+                }
+                if (__ballot(big)) {
+#pragma unroll
+                    for (int u = 0; u < S2_CPL; ++u)
+                        if (c[u] >= (uint32_t)S2_TAB)
+                            t[u] = cterm_big(c[u], p.q);
+                }
+#pragma unroll
+                for (int u = 0; u < S2_CPL; ++u) {
+                    cc[u] += c[u];
+                    cq[u] = cq[u] + t[u];
+                }
+            }
+        }
+    }
+}
+
 // Maximum over the wavefront by DPP moves (no LDS round trips): within rows
 // of 16 lanes, then carried by the broadcasts of lanes 15 and 31; lanes
 // without a source read -inf.  The result is read from lane 63.
@@ -515,30 +608,92 @@ __device__ __forceinline__ float wave_max_f32(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// One (q index, problem) per wavefront; CT is the type of in-row count sums
-// (uint32_t when the image holds fewer than 2^32 pixels).  R >= 1 rows hold
-// counts, listed in rows[] in increasing order.  A row without counts
-// (t >= 1) leaves the class 1 sums unchanged and B(t+1, .) = B(t, .): its
-// pairs tie exactly with those of row t-1, which come first, so only listed
-// rows are visited, and the class 2 partner of the listed row rows[k] is
-// rows[k+1].
+// LDS of one (q index, problem).
+struct S2Lds {
+    double tab[S2_TAB];                   // cterm of counts below S2_TAB
+    int rows[H2_MAX_L];                   // rows holding counts, increasing
+    float rmax[H2_MAX_L];                 // best pair key of each listed row
+    uint64_t tc[2][S2_WAVES][H2_MAX_L];   // block totals along s: [0] class 2 blocks, [1] class 1 blocks
+    double tq[2][S2_WAVES][H2_MAX_L];
+    float wm[S2_WAVES];                   // per-wavefront maxima
+    double wb[S2_WAVES];                  // per-wavefront best FP64 pair
+    long long wcode[S2_WAVES];
+};
+
+// Block w of n listed rows starting at k0 in one of S2_WAVES equal parts.
+__device__ __forceinline__ int s2_block(int k0, int n, int w) { return k0 + (int)(((int64_t)n * w) / S2_WAVES); }
+
+// This wavefront's block totals along s (its lane's scan positions) into
+// LDS, from its rows rows[k0], rows[k0 + DIR], ... (n of them).
+template <int DIR>
+__device__ __forceinline__ void store_block_totals(const S2 &p, const int *rows, int k0, int n, uint64_t *tc,
+                                                   double *tq)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t cc[S2_CPL], rc[S2_CPL];
+    double cq[S2_CPL], rq[S2_CPL];
+    block_totals<DIR>(p, rows, k0, n, cc, cq);
+    pos_sums(cc, cq, rc, rq);
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        const int pos = S2_CPL * lane + u;
+        if (pos < H2_MAX_L) {
+            tc[pos] = rc[u];
+            tq[pos] = rq[u];
+        }
+    }
+}
+
+// The sums carried into block w: the block totals of blocks v0, v0 + dv, ...
+// up to (not including) w, added in that order.
+template <typename CT>
+__device__ __forceinline__ void carry_in(const uint64_t (*tc)[H2_MAX_L], const double (*tq)[H2_MAX_L], int v0,
+                                         int dv, int w, CT (&ac)[S2_CPL], double (&aq)[S2_CPL])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < S2_CPL; ++u) {
+        ac[u] = 0;
+        aq[u] = 0.0;
+    }
+    for (int v = v0; v != w; v += dv) {
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u) {
+            const int pos = min(S2_CPL * lane + u, H2_MAX_L - 1);
+            ac[u] += (CT)tc[v][pos];
+            aq[u] = aq[u] + tq[v][pos];
+        }
+    }
+}
+
+// One (q index, problem) per workgroup of S2_WAVES wavefronts; CT is the type
+// of in-row count sums (uint32_t when the image holds fewer than 2^32
+// pixels).  R >= 1 rows hold counts, listed in rows[] in increasing order.
+// A row without counts (t >= 1) leaves the class 1 sums unchanged and
+// B(t+1, .) = B(t, .): its pairs tie exactly with those of row t-1, which
+// come first, so only listed rows are visited, and the class 2 partner of
+// the listed row rows[k] is rows[k+1].
 //  1. class 2 keys, bottom-up: B(t, s) = sums over {i >= t, j >= s} (scan
-//     position p is column L-1-p); FP32 key of every listed row t >= 1 into
-//     k2 (workspace, [L][L] floats);
-//  2. class 1, top-down: A(t, s) = sums over {i <= t, j <= s}; the pair key
-//     is the FP32 class 1 key plus k2 at (rows[k+1], s+1); row maxima rmax[k]
-//     and the maximum M;
+//     position p is column L-1-p); the listed rows kB .. R-1 in S2_WAVES
+//     blocks, each started from the totals of the blocks below it; FP32 key
+//     of every listed row t >= 1 into k2 (workspace, [L][L] floats);
+//  2. class 1, top-down: A(t, s) = sums over {i <= t, j <= s}, the listed
+//     rows 0 .. R-2 in blocks, each started from the totals of the blocks
+//     above it; the pair key is the FP32 class 1 key plus k2 at
+//     (rows[k+1], s+1); row maxima rmax[k] and the maximum M;
 //  3. rows with rmax >= M - 2 delta (the FP64 arg max is among them): the
 //     FP64 class 2 terms of their partner rows into t2 (workspace, doubles),
-//     by the bottom-up sums again;
-//  4. top-down again: the FP64 value of every pair of those rows whose key
-//     is >= M - 2 delta; the first best pair (t outermost).
+//     from the same sums as in 1;
+//  4. the FP64 value of every pair of those rows whose key is >= M - 2
+//     delta, from the same sums as in 2; the first best pair (t outermost).
 template <typename CT>
-__device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, const int *rows, float *rmax, float *k2,
-                                              double *t2, int32_t *thr_t, int32_t *thr_s, double *obj_p,
-                                              int32_t *status_p)
+__device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, S2Lds &sh, float *k2, double *t2,
+                                              int32_t *thr_t, int32_t *thr_s, double *obj_p, int32_t *status_p)
 {
     const int lane = threadIdx.x & 63, L = p.L;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int *rows = sh.rows;
+    float *rmax = sh.rmax;
     int colB[S2_CPL], colA[S2_CPL];
 #pragma unroll
     for (int u = 0; u < S2_CPL; ++u) {
@@ -548,6 +703,10 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
     const int kB = rows[0] == 0 ? 1 : 0; // class 2 starts at row 1 at the earliest
     // pairs exist for listed rows k with k + 1 < R (rows[k] <= L - 2 follows)
     const int npair = R - 1;
+    // this wavefront's blocks: [b0, b1) of kB .. R-1 (class 2), [a0, a1) of
+    // 0 .. npair-1 (class 1)
+    const int b0 = s2_block(kB, R - kB, w), b1 = s2_block(kB, R - kB, w + 1);
+    const int a0 = s2_block(0, npair, w), a1 = s2_block(0, npair, w + 1);
     auto none = [](int, float(&)[S2_CPL]) {};
     // the stored class 2 keys at (rows[k + 1], s + 1) for the lane's columns s
     auto partner = [&](int k, float(&x)[S2_CPL]) {
@@ -559,12 +718,26 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
         }
     };
 
+    // block totals of both directions, then the carries into this block
+    store_block_totals<-1>(p, rows, b1 - 1, b1 - b0, sh.tc[0][w], sh.tq[0][w]);
+    store_block_totals<1>(p, rows, a0, a1 - a0, sh.tc[1][w], sh.tq[1][w]);
+    __syncthreads();
+    CT cB[S2_CPL], cA[S2_CPL];
+    double qB[S2_CPL], qA[S2_CPL];
+    carry_in<CT>(sh.tc[0], sh.tq[0], S2_WAVES - 1, -1, w, cB, qB); // the blocks below
+    carry_in<CT>(sh.tc[1], sh.tq[1], 0, 1, w, cA, qA);             // the blocks above
+
     // 1. class 2 keys
     {
-        CT bc[S2_CPL] = {};
-        double bq[S2_CPL] = {};
-        for_rows<-1, CT>(p, rows, R - 1, R - kB, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
-                                                           const float(&)[S2_CPL]) {
+        CT bc[S2_CPL];
+        double bq[S2_CPL];
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u) {
+            bc[u] = cB[u];
+            bq[u] = qB[u];
+        }
+        for_rows<-1, CT>(p, rows, b1 - 1, b1 - b0, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
+                                                            const float(&)[S2_CPL]) {
             float *row = k2 + (int64_t)rows[k] * L;
 #pragma unroll
             for (int u = 0; u < S2_CPL; ++u) {
@@ -577,12 +750,17 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
     }
     __syncthreads();
     // 2. pair keys, row maxima
-    float M = -INFINITY;
     {
-        CT ac[S2_CPL] = {};
-        double aq[S2_CPL] = {};
-        for_rows<1, CT>(p, rows, 0, npair, partner, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
-                                                        const float(&x)[S2_CPL]) {
+        float M = -INFINITY;
+        CT ac[S2_CPL];
+        double aq[S2_CPL];
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u) {
+            ac[u] = cA[u];
+            aq[u] = qA[u];
+        }
+        for_rows<1, CT>(p, rows, a0, a1 - a0, partner, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
+                                                          const float(&x)[S2_CPL]) {
             float m = -INFINITY;
 #pragma unroll
             for (int u = 0; u < S2_CPL; ++u) {
@@ -596,11 +774,17 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
                 rmax[k] = m;
             M = fmaxf(M, m);
         });
+        if (lane == 0)
+            sh.wm[w] = M;
     }
+    __syncthreads();
+    float M = -INFINITY;
+    for (int v = 0; v < S2_WAVES; ++v)
+        M = fmaxf(M, sh.wm[v]);
     const double delta = s2_delta(p, N);
     const bool all = !(delta < INFINITY);
     if (!all && !(M > -INFINITY)) { // every key finite for a valid pair: none is valid
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             *thr_t = *thr_s = -1;
             *obj_p = NAN;
             *status_p = TS_PROBLEM_DEGENERATE;
@@ -608,75 +792,93 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
         return;
     }
     const double T = all ? -INFINITY : (double)M - 2.0 * delta;
-    __syncthreads();
-    // candidate rows: kc0 .. kc1 (listed-row indices)
-    int kc0 = npair, kc1 = -1;
-    for (int k = lane; k < npair; k += 64)
-        if (all || (double)rmax[k] >= T) {
-            kc0 = min(kc0, k);
-            kc1 = max(kc1, k);
-        }
+    // 3. FP64 class 2 terms of the partner rows rows[k], k - 1 a candidate,
+    // k in this wavefront's class 2 block: walked from the block's bottom up
+    // to the highest such row
+    {
+        int kmin = b1;
+        for (int k = b0 + lane; k < b1; k += 64)
+            if (k >= 1 && (all || (double)rmax[k - 1] >= T))
+                kmin = min(kmin, k);
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        kc0 = min(kc0, __shfl_xor(kc0, o, 64));
-        kc1 = max(kc1, __shfl_xor(kc1, o, 64));
-    }
-    // 3. FP64 class 2 terms of the partner rows rows[k + 1], k a candidate
-    if (kc1 >= 0) {
-        CT bc[S2_CPL] = {};
-        double bq[S2_CPL] = {};
-        for_rows<-1, CT>(p, rows, R - 1, R - 1 - kc0, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
-                                                                 const float(&)[S2_CPL]) {
+        for (int o = 32; o >= 1; o >>= 1)
+            kmin = min(kmin, __shfl_xor(kmin, o, 64));
+        if (kmin < b1) {
+            CT bc[S2_CPL];
+            double bq[S2_CPL];
 #pragma unroll
             for (int u = 0; u < S2_CPL; ++u) {
-                bc[u] += rc[u];
-                bq[u] = bq[u] + rq[u];
+                bc[u] = cB[u];
+                bq[u] = qB[u];
             }
-            if (all || (double)rmax[k - 1] >= T) {
-                double *row = t2 + (int64_t)rows[k] * L;
+            for_rows<-1, CT>(p, rows, b1 - 1, b1 - kmin, none,
+                             [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL], const float(&)[S2_CPL]) {
 #pragma unroll
-                for (int u = 0; u < S2_CPL; ++u)
-                    if (colB[u] >= 0)
-                        row[colB[u]] = class_term2(bc[u], bq[u], p.q, p.sgn, p.hmax);
-            }
-        });
+                                 for (int u = 0; u < S2_CPL; ++u) {
+                                     bc[u] += rc[u];
+                                     bq[u] = bq[u] + rq[u];
+                                 }
+                                 if (k >= 1 && (all || (double)rmax[k - 1] >= T)) {
+                                     double *row = t2 + (int64_t)rows[k] * L;
+#pragma unroll
+                                     for (int u = 0; u < S2_CPL; ++u)
+                                         if (colB[u] >= 0)
+                                             row[colB[u]] = class_term2(bc[u], bq[u], p.q, p.sgn, p.hmax);
+                                 }
+                             });
+        }
     }
     __syncthreads();
-    // 4. FP64 values of the candidate pairs
+    // 4. FP64 values of the candidate pairs of this wavefront's class 1 block
     double best = -INFINITY;
     long long code = 0x7fffffffffffffffLL;
-    if (kc1 >= 0) {
-        CT ac[S2_CPL] = {};
-        double aq[S2_CPL] = {};
-        for_rows<1, CT>(p, rows, 0, kc1 + 1, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
-                                                       const float(&)[S2_CPL]) {
+    {
+        int kmax = a0 - 1;
+        for (int k = a0 + lane; k < a1; k += 64)
+            if (all || (double)rmax[k] >= T)
+                kmax = max(kmax, k);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+            kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        if (kmax >= a0) {
+            CT ac[S2_CPL];
+            double aq[S2_CPL];
 #pragma unroll
             for (int u = 0; u < S2_CPL; ++u) {
-                ac[u] += rc[u];
-                aq[u] = aq[u] + rq[u];
+                ac[u] = cA[u];
+                aq[u] = qA[u];
             }
-            if (!(all || (double)rmax[k] >= T))
-                return;
-            const int t = rows[k], r2 = rows[k + 1];
-            const float *row2 = k2 + (int64_t)r2 * L;
-            const double *row2d = t2 + (int64_t)r2 * L;
+            for_rows<1, CT>(p, rows, a0, kmax - a0 + 1, none,
+                            [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL], const float(&)[S2_CPL]) {
 #pragma unroll
-            for (int u = 0; u < S2_CPL; ++u) {
-                if (colA[u] <= L - 2) {
-                    const float key = class_key32(ac[u], aq[u], p) + row2[colA[u] + 1];
-                    if (all || (double)key >= T) {
-                        const double lam = class_term2(ac[u], aq[u], p.q, p.sgn, p.hmax) + row2d[colA[u] + 1];
-                        const long long cd = ((long long)t << 12) | colA[u];
-                        if (lam > -INFINITY && (lam > best || (lam == best && cd < code))) {
-                            best = lam;
-                            code = cd;
-                        }
-                    }
-                }
-            }
-        });
+                                for (int u = 0; u < S2_CPL; ++u) {
+                                    ac[u] += rc[u];
+                                    aq[u] = aq[u] + rq[u];
+                                }
+                                if (!(all || (double)rmax[k] >= T))
+                                    return;
+                                const int t = rows[k], r2 = rows[k + 1];
+                                const float *row2 = k2 + (int64_t)r2 * L;
+                                const double *row2d = t2 + (int64_t)r2 * L;
+#pragma unroll
+                                for (int u = 0; u < S2_CPL; ++u) {
+                                    if (colA[u] <= L - 2) {
+                                        const float key = class_key32(ac[u], aq[u], p) + row2[colA[u] + 1];
+                                        if (all || (double)key >= T) {
+                                            const double lam = class_term2(ac[u], aq[u], p.q, p.sgn, p.hmax) +
+                                                               row2d[colA[u] + 1];
+                                            const long long cd = ((long long)t << 12) | colA[u];
+                                            if (lam > -INFINITY && (lam > best || (lam == best && cd < code))) {
+                                                best = lam;
+                                                code = cd;
+                                            }
+                                        }
+                                    }
+                                }
+                            });
+        }
     }
-    // first best pair of the wavefront
+    // first best pair of the wavefront, then of the workgroup
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         const double b2 = __shfl_xor(best, o, 64);
@@ -687,6 +889,16 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, cons
         }
     }
     if (lane == 0) {
+        sh.wb[w] = best;
+        sh.wcode[w] = code;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < S2_WAVES; ++v)
+            if (sh.wb[v] > best || (sh.wb[v] == best && sh.wcode[v] < code)) {
+                best = sh.wb[v];
+                code = sh.wcode[v];
+            }
         if (!(best > -INFINITY)) {
             *thr_t = *thr_s = -1;
             *obj_p = NAN;
@@ -742,9 +954,8 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
                                                          const uint64_t *__restrict__ cnt, int32_t *__restrict__ thr,
                                                          double *__restrict__ obj, int32_t *__restrict__ status)
 {
-    __shared__ double tab[S2_TAB];
-    __shared__ int rows[H2_MAX_L];
-    __shared__ float rmax[H2_MAX_L];
+    __shared__ S2Lds sh;
+    __shared__ int nrows;
     const int lane = threadIdx.x & 63;
     const int prob = blockIdx.x, s0 = prob % nseg, j = prob / nseg;
     S2 p;
@@ -757,45 +968,50 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
     p.mq = (float)(-p.q);
     p.sg = p.q < 1.0 ? 1.0f : -1.0f;
     p.gmax = (float)(p.hmax * 1.4426950408889634 * (1.0 + 0x1p-20));
-    p.tab = tab;
-    // the image's pixel count and its rows holding counts, in increasing
-    // order: lane l looks at rows 4l .. 4l+3 (groups past the last hold no
-    // rows below L)
+    p.tab = sh.tab;
+    // the image's pixel count (every wavefront) and its rows holding counts,
+    // in increasing order (wavefront 0): lane l looks at rows 4l .. 4l+3
+    // (groups past the last hold no rows below L)
     const int groups = (L + 15) / 16;
     uint64_t n = lane < groups ? cnt[(int64_t)s0 * 16 + lane] : 0;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
         n += __shfl_xor(n, o, 64);
-    const uint32_t g16 = (4 * lane) / 16 < groups ? mask[(int64_t)s0 * 16 + (4 * lane) / 16] : 0u;
-    uint32_t nib = (g16 >> ((4 * lane) % 16)) & 0xfu;
-    if (4 * lane + 4 > L)
-        nib &= (4 * lane < L) ? (1u << (L - 4 * lane)) - 1u : 0u;
-    const uint32_t pos = wave_excl_sum<uint32_t>((uint32_t)__popc(nib));
-    uint32_t w = pos;
+    if (threadIdx.x < 64) {
+        const uint32_t g16 = (4 * lane) / 16 < groups ? mask[(int64_t)s0 * 16 + (4 * lane) / 16] : 0u;
+        uint32_t nib = (g16 >> ((4 * lane) % 16)) & 0xfu;
+        if (4 * lane + 4 > L)
+            nib &= (4 * lane < L) ? (1u << (L - 4 * lane)) - 1u : 0u;
+        const uint32_t pos = wave_excl_sum<uint32_t>((uint32_t)__popc(nib));
+        uint32_t w = pos;
 #pragma unroll
-    for (int d = 0; d < 4; ++d)
-        if (nib & (1u << d))
-            rows[w++] = 4 * lane + d;
-    const int R = __shfl(w, 63, 64);
+        for (int d = 0; d < 4; ++d)
+            if (nib & (1u << d))
+                sh.rows[w++] = 4 * lane + d;
+        const int R = __shfl(w, 63, 64);
+        if (lane == 0)
+            nrows = R;
+    }
     // thr is [nq][2][nseg]: t at row 0, s at row 1 of this q
     int32_t *thr_t = thr + (int64_t)(2 * j) * nseg + s0, *thr_s = thr_t + nseg;
     if (n == 0) {
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             *thr_t = *thr_s = -1;
             obj[prob] = NAN;
             status[prob] = TS_PROBLEM_EMPTY;
         }
         return;
     }
-    for (int i = lane; i < S2_TAB; i += 64)
-        tab[i] = cterm((uint32_t)i, p.q);
+    for (int i = threadIdx.x; i < S2_TAB; i += blockDim.x)
+        sh.tab[i] = cterm((uint32_t)i, p.q);
     __syncthreads();
+    const int R = nrows;
     float *k2 = k2all + (int64_t)prob * L * L;
     double *t2 = t2all + (int64_t)prob * L * L;
     if (n >> 32)
-        search2d_body<uint64_t>(p, (double)n, R, rows, rmax, k2, t2, thr_t, thr_s, obj + prob, status + prob);
+        search2d_body<uint64_t>(p, (double)n, R, sh, k2, t2, thr_t, thr_s, obj + prob, status + prob);
     else
-        search2d_body<uint32_t>(p, (double)n, R, rows, rmax, k2, t2, thr_t, thr_s, obj + prob, status + prob);
+        search2d_body<uint32_t>(p, (double)n, R, sh, k2, t2, thr_t, thr_s, obj + prob, status + prob);
 }
 
 // Workspace: FP64 terms [nprob][L][L], FP32 keys [nprob][L][L], row masks
