@@ -135,6 +135,7 @@ KERNEL_FILES = (("ts::k_label", "k_label.hip"), ("ts::k_histogram", "k_histogram
 
 
 def kernel_file(name: str):
+    name = name[5:] if name.startswith("void ") else name  # template kernels carry their return type
     for pre, f in KERNEL_FILES:
         if name.startswith(pre):
             return f

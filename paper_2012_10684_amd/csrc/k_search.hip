@@ -1518,7 +1518,7 @@ QConst make_qconst(double q, int L);
 // fused_body, lab8), so every output is bit-identical to theirs.
 //
 // LDS: area A (the histogram replicas; later the prefix scan's scratch; then
-// the search's rows) | counts [Lp] | P [Lp] | Q [Lp] of the current q.
+// the search's rows) | counts [Lp] | P [Lp] | Q [nq][Lp].
 
 constexpr int SEG_COLS = 2;            // search columns per lane
 constexpr int SEG_MAX_PARTS = 64;      // workgroups per problem
@@ -1702,8 +1702,7 @@ __global__ void __launch_bounds__(1024) k_segment(SegArgs g, Args a, int32_t *__
     char *area = reinterpret_cast<char *>(dyn);
     uint32_t *rl = reinterpret_cast<uint32_t *>(area);
     uint32_t *cnt = reinterpret_cast<uint32_t *>(area + g.areaA);
-    double *Pl = reinterpret_cast<double *>(area + g.areaA + (size_t)4 * Lp);
-    double *Ql = Pl + Lp;
+    double *Pl = reinterpret_cast<double *>(area + g.areaA + (size_t)4 * Lp); // then Q of each q, [Lp] each
     const int s = blockIdx.x / g.parts, part = blockIdx.x % g.parts;
     const int lr = g.lr;
 
@@ -1790,9 +1789,15 @@ __global__ void __launch_bounds__(1024) k_segment(SegArgs g, Args a, int32_t *__
     sh.hd = reinterpret_cast<float *>(area + (K == 2 ? (size_t)16 * Lp : 0));
     sh.tr = sh.hd + Lp;
     sh.tmax = sh.tr + Lp;
+    // every q's prefix sums first, then the searches: the scan's constants
+    // are then dead before the search starts (a loop over both held them in
+    // registers across the search and spilled them to scratch)
+    for (int j = 0; j < g.nq; ++j)
+        prefix_row([cnt](int b) { return cnt[b]; }, L, g.E, a.qc[j].q, j == 0 ? Pl : nullptr, Pl + (size_t)(1 + j) * Lp,
+                   qs, lastocc, ps);
     for (int j = 0; j < g.nq; ++j) {
-        prefix_row([cnt](int b) { return cnt[b]; }, L, g.E, a.qc[j].q, j == 0 ? Pl : nullptr, Ql, qs, lastocc, ps);
         const int sj = j * g.nseg + s;
+        const double *Ql = Pl + (size_t)(1 + j) * Lp;
         const double sgn = a.qc[j].sgn;
         long long code;
         if (sgn > 0)
@@ -1814,6 +1819,13 @@ __global__ void __launch_bounds__(1024) k_segment(SegArgs g, Args a, int32_t *__
     seg_label<K>(g, s, src, n, tsh);
 }
 
+static size_t seg_areaA(int L, int Lp, int k, int tiles, int lr);
+
+static size_t seg_lds_bytes(int L, int Lp, int k, int tiles, int lr, int nq)
+{
+    return seg_areaA(L, Lp, k, tiles, lr) + (size_t)Lp * (sizeof(uint32_t) + (size_t)(1 + nq) * sizeof(double));
+}
+
 static bool seg_fusable(int L, int k, int mode, int nq, bool labels)
 {
     if (mode != TS_SEARCH_FP32_TIECHECK && mode != TS_SEARCH_FP32_ONLY)
@@ -1822,7 +1834,10 @@ static bool seg_fusable(int L, int k, int mode, int nq, bool labels)
         return false;
     if (!((k == 1 && L <= FUSED_MAX_L) || (k == 2 && L <= FUSED_MAX_L2)))
         return false;
-    return make_plan(1, L, k, mode, SEG_COLS, 16).tiles <= FUSED_MAX_TILES;
+    // the search's tiles (any tuning: the fewest rows per tile) and the LDS
+    // with one histogram replica
+    const Plan p = make_plan(1, L, k, mode, SEG_COLS, 16);
+    return p.tiles <= FUSED_MAX_TILES && seg_lds_bytes(L, p.Lp, k, p.tiles, 0, nq) <= SEG_MAX_LDS;
 }
 
 static int seg_log2_replicas(const Tune &t)
@@ -1957,7 +1972,7 @@ ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, con
     size_t lds;
     for (;;) {
         sa.areaA = (int)seg_areaA(L, p.Lp, k, p.tiles, sa.lr);
-        lds = (size_t)sa.areaA + (size_t)p.Lp * (sizeof(uint32_t) + 2 * sizeof(double));
+        lds = seg_lds_bytes(L, p.Lp, k, p.tiles, sa.lr, nq);
         if (lds <= SEG_MAX_LDS || sa.lr == 0)
             break;
         --sa.lr;
