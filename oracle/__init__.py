@@ -108,6 +108,9 @@ def _bind(lib):
     lib.or_objective_c.restype = f64
     lib.or_label.argtypes = [P, i64, i32, i32, i32, P, i32, P]
     lib.or_label.restype = None
+    if hasattr(lib, "or_search_dp"):
+        lib.or_search_dp.argtypes = [P, i32, i32, f64, i32, P, P]
+        lib.or_search_dp.restype = i32
     if hasattr(lib, "or2_search"):  # mutated copies of oracle.c alone lack the 2-D part
         lib.or2_mean3x3.argtypes = [P, i32, i32, P]
         lib.or2_mean3x3.restype = None
@@ -205,6 +208,19 @@ def search(hist: np.ndarray, k: int, q: float, mode: int = MODE_PREFIX, lib=None
     if st == BADARG:
         raise ValueError(f"oracle.search: bad arguments L={h.size} k={k} q={q} mode={mode}")
     return SearchResult(thr, best.value, second.value, st)
+
+
+def search_dp(hist: np.ndarray, k: int, q: float, mode: int = MODE_PREFIX, lib=None) -> SearchResult:
+    """Arg max by dynamic programming over class boundaries (prefix or Kapur
+    mode): the same objective and tie rule as search(), for numbers of
+    thresholds the exhaustive search cannot reach; second is not computed."""
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    thr = np.empty(k, dtype=np.int32)
+    best = ctypes.c_double()
+    st = (lib or _load()).or_search_dp(_ptr(h), h.size, int(k), float(q), int(mode), _ptr(thr), ctypes.byref(best))
+    if st == BADARG:
+        raise ValueError(f"oracle.search_dp: bad arguments L={h.size} k={k} q={q} mode={mode}")
+    return SearchResult(thr, best.value, float("nan"), st)
 
 
 def objective(hist: np.ndarray, thr, q: float, mode: int = MODE_PREFIX, lib=None,

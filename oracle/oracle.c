@@ -371,6 +371,83 @@ double or_objective(const uint32_t *hist, int32_t L, int32_t k, double q, int32_
     return or_objective_c(hist, L, k, q, mode, OR_COMP_RECURSIVE, thr);
 }
 
+/* Dynamic programme for many thresholds, where the exhaustive search cannot
+   finish (e.g. four thresholds over 1024 levels: 4.5e10 tuples).  The
+   recursive composition T <- T + S_j + (1-q) T S_j multiplies the factors
+   1 + (1-q) S_j (1 + (1-q) T' = (1 + (1-q) T)(1 + (1-q) S_j)), so phi is a
+   strictly increasing function of F = sum_j f_j with
+   f_j = sgn(1-q) ln(1 + (1-q) S_j) (for the Kapur limit f_j = S_j and F = T):
+   the arg max of phi over the tuples is the arg max of F, a sum over
+   consecutive classes.  With W_m(a) the best F of the bins a..L-1 split into
+   m + 1 classes,
+       W_0(a) = f(a, L-1),   W_m(a) = max_t [ f(a, t) + W_{m-1}(t + 1) ],
+   the maximum is W_k(0), and the first tuple attaining it (t_1 outermost) is
+   rebuilt forward by taking the smallest t whose term equals the table value
+   exactly (the same sums in the same order).  S_j are the class entropies of
+   the prefix mode (or the literal Shannon sums); an empty class is invalid.
+   Outputs thr[k] and *best = phi at the optimum (expm1(sgn F) / (1 - q), or F
+   for Kapur).  Returns OR_OK, OR_DEGENERATE, OR_EMPTY or OR_BADARG. */
+int32_t or_search_dp(const uint32_t *hist, int32_t L, int32_t k, double q, int32_t mode, int32_t *thr,
+                     double *best)
+{
+    for (int32_t j = 0; j < k && j < 16; ++j)
+        thr[j] = -1;
+    *best = NAN;
+    if (!args_ok(L, k, q, mode) || mode == OR_MODE_DIRECT)
+        return OR_BADARG;
+    if (k > L - 1)
+        return OR_DEGENERATE;
+    ctx_t cx;
+    int st = ctx_init(&cx, hist, L, 2, q, mode); /* every class (a, b) memoised (prefix mode) */
+    if (st != OR_OK) {
+        ctx_free(&cx);
+        return st;
+    }
+    const int kapur = mode == OR_MODE_KAPUR;
+    const double sgn = q < 1.0 ? 1.0 : -1.0;
+    double *f = (double *)malloc(sizeof(double) * (size_t)L * (size_t)L); /* f[a * L + b], a <= b */
+    double *W = (double *)malloc(sizeof(double) * (size_t)(k + 1) * (size_t)L);
+    for (int32_t a = 0; a < L; ++a)
+        for (int32_t b = a; b < L; ++b) {
+            const double S = class_entropy(&cx, a, b);
+            f[(int64_t)a * L + b] = isnan(S) ? -INFINITY : (kapur ? S : sgn * log(1.0 + (1.0 - q) * S));
+        }
+    for (int32_t a = 0; a < L; ++a)
+        W[a] = f[(int64_t)a * L + (L - 1)];
+    for (int32_t m = 1; m <= k; ++m)
+        for (int32_t a = 0; a < L; ++a) {
+            double v = -INFINITY;
+            /* class [a, t], then m more classes of at least one bin each */
+            for (int32_t t = a; t <= L - 1 - m; ++t) {
+                const double x = f[(int64_t)a * L + t] + W[(size_t)(m - 1) * L + t + 1];
+                if (x > v)
+                    v = x;
+            }
+            W[(size_t)m * L + a] = v;
+        }
+    const double F = W[(size_t)k * L];
+    if (!(F > -INFINITY)) {
+        free(f);
+        free(W);
+        ctx_free(&cx);
+        return OR_DEGENERATE;
+    }
+    int32_t a = 0;
+    for (int32_t m = k; m >= 1; --m) {
+        const double want = W[(size_t)m * L + a];
+        int32_t t = a;
+        while (t <= L - 1 - m && !(f[(int64_t)a * L + t] + W[(size_t)(m - 1) * L + t + 1] == want))
+            ++t;
+        thr[k - m] = t;
+        a = t + 1;
+    }
+    *best = kapur ? F : expm1(sgn * F) / (1.0 - q);
+    free(f);
+    free(W);
+    ctx_free(&cx);
+    return OR_OK;
+}
+
 /* Thresholding kernel function (Algorithm 1) generalised to k thresholds:
    label = number of thresholds strictly below the voxel's bin.  A tuple
    whose first entry is negative (no valid tuple) labels everything 0. */

@@ -232,6 +232,47 @@ def pin_dp(lib=None, mode=oracle.MODE_PREFIX):
         assert abs(r.obj - want) <= 1e-11 * max(1.0, abs(want)), (L, k, q, r, want)
 
 
+def pin_search_dp(lib=None):
+    """The oracle's dynamic-programming search: the same maximum as the
+    independent numpy dynamic programme over the log form (k up to 5, 40
+    levels, beyond the exhaustive search's reach at these sizes), the same
+    tuple and value as the exhaustive search on small histograms, and the
+    uniform closed form with its first-tuple tie rule (20 equal bins, four
+    thresholds: classes of 4 bins, S = ln_q(4^5), tuple (3, 7, 11, 15))."""
+    rng = np.random.default_rng(17)
+    for L, k, q in [(40, 4, 0.8), (36, 5, 1.5), (30, 4, 0.5)]:
+        h = rng.integers(0, 500, L).astype(np.uint32)
+        h[rng.integers(0, L, 3)] = 0
+        r = oracle.search_dp(h, k, q, lib=lib)
+        want = _dp_max(h, k, q)
+        assert r.status == oracle.OK and abs(r.obj - want) <= 1e-11 * max(1.0, abs(want)), (L, k, q, r, want)
+        assert abs(oracle.objective(h, r.thr, q, lib=lib) - r.obj) <= 1e-11 * max(1.0, abs(r.obj)), (L, k, q, r)
+    for L, k, q in [(14, 2, 0.8), (16, 3, 1.5), (18, 4, 0.5)]:
+        h = rng.integers(0, 40, L).astype(np.uint32)
+        h[rng.integers(0, L, 2)] = 0
+        ex = oracle.search(h, k, q, lib=lib)
+        r = oracle.search_dp(h, k, q, lib=lib)
+        assert r.thr.tolist() == ex.thr.tolist() or ex.rel_gap() < 1e-9, (L, k, q, ex, r)
+        assert abs(r.obj - ex.obj) <= 1e-12 * max(1.0, abs(ex.obj)), (L, k, q, ex, r)
+    u = oracle.search_dp(np.full(20, 5, dtype=np.uint32), 4, 0.8, lib=lib)
+    assert u.thr.tolist() == [3, 7, 11, 15], u
+    assert abs(u.obj - ln_q(4.0 ** 5, 0.8)) <= 1e-12 * abs(u.obj), u
+    # runs of empty bins: thresholds anywhere in a run tie exactly; the first
+    # tuple wins, as in the exhaustive search
+    h = np.array([7, 3, 0, 0, 0, 9, 2, 0, 0, 4, 6, 0, 0, 5], dtype=np.uint32)
+    for k in (1, 2, 3):
+        ex = oracle.search(h, k, 0.8, lib=lib)
+        r = oracle.search_dp(h, k, 0.8, lib=lib)
+        assert r.thr.tolist() == ex.thr.tolist(), (k, ex, r)
+    # the last k + 1 bins occupied, one per class: the only valid tuple is
+    # (L-k-1, ..., L-2), every class boundary at its upper limit
+    L, k = 15, 4
+    h = np.zeros(L, dtype=np.uint32)
+    h[L - k - 1:] = 5
+    r = oracle.search_dp(h, k, 0.8, lib=lib)
+    assert r.status == oracle.OK and r.thr.tolist() == list(range(L - k - 1, L - 1)), r
+
+
 def pin_symmetry(lib=None, mode=oracle.MODE_PREFIX):
     rng = np.random.default_rng(17)
     for L, k, q in [(16, 1, 0.8), (14, 2, 0.5), (12, 3, 1.5)]:
@@ -414,7 +455,7 @@ def pin_sumprod_symmetry(lib=None, mode=oracle.MODE_PREFIX):
 
 ALL_PINS = [
     pin_binmap_identity, pin_binmap_edges, pin_histogram, pin_uniform_closed_form, pin_uniform_argmax,
-    pin_separated_bins, pin_q2_gini_simpson, pin_kapur_limit, pin_dp, pin_symmetry, pin_invariances,
+    pin_separated_bins, pin_q2_gini_simpson, pin_kapur_limit, pin_dp, pin_search_dp, pin_symmetry, pin_invariances,
     pin_direct_vs_prefix, pin_prefix, pin_labels, pin_sumprod_uniform_closed_form, pin_sumprod_k1_is_paper,
     pin_sumprod_q2, pin_sumprod_kapur_limit, pin_sumprod_symmetry,
 ]

@@ -146,10 +146,17 @@ def test_dp_k4_whole_volume_histogram(q):
     H = h.cpu().numpy().view(np.uint32)
     thr, obj, st = _dp(H, 4, q)
     assert st[0] == 0
+    # the oracle's own dynamic programme (pinned against the exhaustive
+    # oracle and an independent numpy programme): same tuple, same value
+    r = oracle.search_dp(H[0], 4, q)
+    assert r.status == oracle.OK
+    assert abs(obj[0] - r.obj) <= 1e-9 * abs(r.obj), (obj[0], r)
+    s_or = oracle.objective(H[0], thr[0], q, oracle.MODE_PREFIX)
+    assert abs(s_or - r.obj) <= 1e-9 * abs(r.obj), (thr[0], s_or, r)
+    if thr[0].tolist() != r.thr.tolist():  # only a tie within FP64 rounding may differ
+        assert abs(s_or - r.obj) <= 1e-12 * abs(r.obj), (thr[0].tolist(), r)
     want = _numpy_dp_max(H[0], 4, q)
     assert abs(obj[0] - want) <= 1e-9 * abs(want), (obj[0], want)
-    s_or = oracle.objective(H[0], thr[0], q, oracle.MODE_PREFIX)
-    assert abs(s_or - want) <= 1e-9 * abs(want), (thr[0], s_or, want)
     # the four thresholds label the volume (labels 0..4)
     dv = to_dev(vol).reshape(-1)
     lab = api.label(api.Batch([dv]), binn, to_dev(thr), 4)[0]

@@ -39,6 +39,11 @@ MUTANTS = {
     "sumprod_product_sign": ("return kapur ? sum : sum + (1.0 - q) * prod;", "return kapur ? sum : sum + (q - 1.0) * prod;"),
     "sumprod_product_skips_first": ("        prod *= S[j];\n", "        prod *= (j ? S[j] : 1.0);\n"),
     "sumprod_composes_recursively": ("    if (cx->comp == OR_COMP_SUMPROD)\n", "    if (0)\n"),
+    "dp_sum_of_entropies": ("f[(int64_t)a * L + b] = isnan(S) ? -INFINITY : (kapur ? S : sgn * log(1.0 + (1.0 - q) * S));",
+                            "f[(int64_t)a * L + b] = isnan(S) ? -INFINITY : S;"),
+    "dp_short_range": ("for (int32_t t = a; t <= L - 1 - m; ++t) {", "for (int32_t t = a; t < L - 1 - m; ++t) {"),
+    "dp_last_tuple": ("        int32_t t = a;\n        while (t <= L - 1 - m && !(f[(int64_t)a * L + t] + W[(size_t)(m - 1) * L + t + 1] == want))\n            ++t;",
+                      "        int32_t t = L - 1 - m;\n        while (t > a && !(f[(int64_t)a * L + t] + W[(size_t)(m - 1) * L + t + 1] == want))\n            --t;"),
     "empty_class_allowed": ("    if (!(w > 0.0))\n        return NAN;\n    double s = 0.0;\n    for (int32_t i = a; i <= b; ++i)\n        if (p[i] > 0.0)\n            s += pow",
                             "    if (!(w > 0.0))\n        return 0.0;\n    double s = 0.0;\n    for (int32_t i = a; i <= b; ++i)\n        if (p[i] > 0.0)\n            s += pow"),
 }
