@@ -722,20 +722,15 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, S2Ld
     store_block_totals<-1>(p, rows, b1 - 1, b1 - b0, sh.tc[0][w], sh.tq[0][w]);
     store_block_totals<1>(p, rows, a0, a1 - a0, sh.tc[1][w], sh.tq[1][w]);
     __syncthreads();
-    CT cB[S2_CPL], cA[S2_CPL];
-    double qB[S2_CPL], qA[S2_CPL];
-    carry_in<CT>(sh.tc[0], sh.tq[0], S2_WAVES - 1, -1, w, cB, qB); // the blocks below
-    carry_in<CT>(sh.tc[1], sh.tq[1], 0, 1, w, cA, qA);             // the blocks above
+    // the sums carried into this wavefront's blocks (the blocks below it for
+    // class 2, above it for class 1) are re-read from LDS at the start of
+    // each walk rather than held in registers across the passes
 
     // 1. class 2 keys
     {
         CT bc[S2_CPL];
         double bq[S2_CPL];
-#pragma unroll
-        for (int u = 0; u < S2_CPL; ++u) {
-            bc[u] = cB[u];
-            bq[u] = qB[u];
-        }
+        carry_in<CT>(sh.tc[0], sh.tq[0], S2_WAVES - 1, -1, w, bc, bq);
         for_rows<-1, CT>(p, rows, b1 - 1, b1 - b0, none, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
                                                             const float(&)[S2_CPL]) {
             float *row = k2 + (int64_t)rows[k] * L;
@@ -754,11 +749,7 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, S2Ld
         float M = -INFINITY;
         CT ac[S2_CPL];
         double aq[S2_CPL];
-#pragma unroll
-        for (int u = 0; u < S2_CPL; ++u) {
-            ac[u] = cA[u];
-            aq[u] = qA[u];
-        }
+        carry_in<CT>(sh.tc[1], sh.tq[1], 0, 1, w, ac, aq);
         for_rows<1, CT>(p, rows, a0, a1 - a0, partner, [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL],
                                                           const float(&x)[S2_CPL]) {
             float m = -INFINITY;
@@ -806,11 +797,7 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, S2Ld
         if (kmin < b1) {
             CT bc[S2_CPL];
             double bq[S2_CPL];
-#pragma unroll
-            for (int u = 0; u < S2_CPL; ++u) {
-                bc[u] = cB[u];
-                bq[u] = qB[u];
-            }
+            carry_in<CT>(sh.tc[0], sh.tq[0], S2_WAVES - 1, -1, w, bc, bq);
             for_rows<-1, CT>(p, rows, b1 - 1, b1 - kmin, none,
                              [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL], const float(&)[S2_CPL]) {
 #pragma unroll
@@ -843,11 +830,7 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, S2Ld
         if (kmax >= a0) {
             CT ac[S2_CPL];
             double aq[S2_CPL];
-#pragma unroll
-            for (int u = 0; u < S2_CPL; ++u) {
-                ac[u] = cA[u];
-                aq[u] = qA[u];
-            }
+            carry_in<CT>(sh.tc[1], sh.tq[1], 0, 1, w, ac, aq);
             for_rows<1, CT>(p, rows, a0, kmax - a0 + 1, none,
                             [&](int k, const CT(&rc)[S2_CPL], const double(&rq)[S2_CPL], const float(&)[S2_CPL]) {
 #pragma unroll
