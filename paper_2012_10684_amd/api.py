@@ -136,9 +136,10 @@ def _ptr(t: Optional[torch.Tensor]):
 _TUNED: dict = {}  # size-class key -> Tuning or None, for "auto" (the default cache is read once)
 
 
-def _tune(tune, key_fn=None):
+def _tune(tune, key_fn=None, lookup_fn=None):
     """None: library defaults; "auto": the autotuner's cached shapes for this
-    size class (defaults if none), resolved once per size class; a dict or
+    size class (defaults if none; lookup_fn(autotune) in place of the cache
+    entry of the key when given), resolved once per size class; a dict or
     Tuning: those shapes."""
     if tune is None:
         return None
@@ -150,7 +151,7 @@ def _tune(tune, key_fn=None):
         from . import autotune
         key = key_fn(autotune)
         if key not in _TUNED:
-            d = autotune.lookup(key)
+            d = lookup_fn(autotune) if lookup_fn else autotune.lookup(key)
             _TUNED[key] = Tuning.from_dict(d) if d else None
         t = _TUNED[key]
         return ctypes.byref(t) if t is not None else None
@@ -424,7 +425,8 @@ def segment(batch: Batch, bin: Binning, k: int, q, mode: int = SEARCH_FP32_TIECH
     arr = None
     if labels:
         arr = (ctypes.c_void_p * nq)(*[p.data_ptr() for p in out_ptrs])
-    t = _tune(tune, lambda a: a.key_segment(nseg, batch.total, L, k, nq))
+    t = _tune(tune, lambda a: a.key_segment(nseg, batch.total, L, k, nq),
+              lambda a: a.lookup_segment(nseg, batch.total, L, k, nq, mode))
     _check(_lib.ts_segment(batch._c, bin, int(k), nq, _qarr(qs), int(mode), _ptr(hist), _ptr(thr), _ptr(obj),
                            _ptr(status), ctypes.cast(arr, ctypes.c_void_p) if labels else None, _ptr(ws),
                            ws.numel(), t, _stream(stream)))

@@ -202,6 +202,20 @@ def lookup(key: str) -> Optional[dict]:
     return _default.lookup(key)
 
 
+def lookup_segment(nseg: int, total: int, L: int, k: int, nq: int, mode: int) -> Optional[dict]:
+    """Tuning of a ts_segment call: its own cache entry if there is one, else
+    the entries of the separate steps it may run (histogram, search of nseg x
+    nq problems, labels of nq sets), whose fields do not overlap; None if none
+    is cached."""
+    own = lookup(key_segment(nseg, total, L, k, nq))
+    if own is not None:
+        return own
+    merged = {}
+    for key in (key_histogram(nseg, total, L), key_search(nseg * nq, L, k, mode), key_label(nseg, total, k, nq)):
+        merged.update(lookup(key) or {})
+    return merged or None
+
+
 # ---------------------------------------------------------------------------- CLI
 
 def _tune_workload(name: str, tuner: Autotuner):

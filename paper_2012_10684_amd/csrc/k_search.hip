@@ -316,6 +316,7 @@ __device__ __forceinline__ void wave_best(double &r, double &l, long long &c)
 struct QConst {
     double q, sgn, hmax; // hmax = |1-q| ln L
     float mq, gmax;      // mq = -sgn * fl32(q), gmax = |1-q| log2 L (rounded up)
+    float cw;            // |1-q| (1 for q = 1) rounded up: a class of n bins has g <= cw log2 n
 };
 
 // Problem p of a launch uses index q_{p / nseg}, P row p % nseg and Q row p;
@@ -577,9 +578,10 @@ struct TileCtx {
     const float *hd, *tr; // head / tail rows (LDS or global)
     const float4 *hl;     // split prefixes (LDS or global)
     const float *A, *R;   // k = 3 rows of the problem (global)
+    const unsigned long long *prune; // k = 2: rows skipped in phase 1, [NB][Lp / 64] bit words (or null)
     int L, Lp, mode, CW, T1;
     double q, sgn, hmax;
-    float mq, gmax;
+    float mq, gmax, cw;
 };
 
 __device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *hd, const float *tr,
@@ -604,6 +606,8 @@ __device__ __forceinline__ TileCtx make_ctx(const Args &a, int s, const float *h
     x.hmax = c.hmax;
     x.mq = c.mq;
     x.gmax = c.gmax;
+    x.cw = c.cw;
+    x.prune = nullptr;
     return x;
 }
 
@@ -716,20 +720,43 @@ __device__ __forceinline__ void rows_k2_group(const TileCtx &x, int t1, const fl
     }
 }
 
+// Whether every row of [t1, t1 + R) is marked in a column block's prune
+// words pw (null: no row is).  The words are the same in every lane.
+template <int R>
+__device__ __forceinline__ bool rows_marked(const unsigned long long *pw, int t1)
+{
+    if (!pw)
+        return false;
+    const int o = t1 & 63, wi = t1 >> 6;
+    unsigned long long m = pw[wi] >> o;
+    if (o + R > 64)
+        m |= pw[wi + 1] << (64 - o);
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)m);
+    constexpr unsigned long long want = (1ull << R) - 1ull;
+    if (R <= 32)
+        return (lo & (unsigned int)want) == (unsigned int)want;
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)(m >> 32));
+    return ((((unsigned long long)hi << 32) | lo) & want) == want;
+}
+
+// pw: the column block's prune words (phase 1), or null.
 template <int SGN, int COLS, int PHASE, bool MASK, int V0 = 0>
 __device__ __forceinline__ void rows_k2(const TileCtx &x, int t1b, int t1e, const float4 (&hc)[COLS],
                                         const float (&tc)[COLS], const int (&t2v)[COLS], float thr, float &acc,
-                                        Cand &best)
+                                        Cand &best, const unsigned long long *pw)
 {
     int t1 = t1b;
     for (; t1 + 8 <= t1e; t1 += 8)
-        rows_k2_group<SGN, COLS, PHASE, MASK, 8, V0>(x, t1, hc, tc, t2v, thr, acc, best);
+        if (!rows_marked<8>(pw, t1))
+            rows_k2_group<SGN, COLS, PHASE, MASK, 8, V0>(x, t1, hc, tc, t2v, thr, acc, best);
     if (t1 + 4 <= t1e) {
-        rows_k2_group<SGN, COLS, PHASE, MASK, 4, V0>(x, t1, hc, tc, t2v, thr, acc, best);
+        if (!rows_marked<4>(pw, t1))
+            rows_k2_group<SGN, COLS, PHASE, MASK, 4, V0>(x, t1, hc, tc, t2v, thr, acc, best);
         t1 += 4;
     }
     for (; t1 < t1e; ++t1)
-        rows_k2_group<SGN, COLS, PHASE, MASK, 1, V0>(x, t1, hc, tc, t2v, thr, acc, best);
+        if (!rows_marked<1>(pw, t1))
+            rows_k2_group<SGN, COLS, PHASE, MASK, 1, V0>(x, t1, hc, tc, t2v, thr, acc, best);
 }
 
 // Rows [rb, re) on the diagonal of a tile whose columns start at cbase: rows
@@ -738,13 +765,13 @@ __device__ __forceinline__ void rows_k2(const TileCtx &x, int t1b, int t1e, cons
 template <int SGN, int COLS, int PHASE, int V = 0>
 __device__ __forceinline__ void rows_k2_diag(const TileCtx &x, int rb, int re, int cbase, const float4 (&hc)[COLS],
                                              const float (&tc)[COLS], const int (&t2v)[COLS], float thr,
-                                             float &acc, Cand &best)
+                                             float &acc, Cand &best, const unsigned long long *pw)
 {
     if constexpr (V < COLS) {
         const int lo = max(rb, cbase + 64 * V), hi = min(re, cbase + 64 * (V + 1));
         if (lo < hi)
-            rows_k2<SGN, COLS, PHASE, true, V>(x, lo, hi, hc, tc, t2v, thr, acc, best);
-        rows_k2_diag<SGN, COLS, PHASE, V + 1>(x, rb, re, cbase, hc, tc, t2v, thr, acc, best);
+            rows_k2<SGN, COLS, PHASE, true, V>(x, lo, hi, hc, tc, t2v, thr, acc, best, pw);
+        rows_k2_diag<SGN, COLS, PHASE, V + 1>(x, rb, re, cbase, hc, tc, t2v, thr, acc, best, pw);
     }
 }
 
@@ -788,8 +815,9 @@ __device__ __forceinline__ void tile_k2(const TileCtx &x, int b, int c, float th
         return;
     }
     const int ra = min(r1, cbase);
-    rows_k2<SGN, COLS, PHASE, false>(x, r0, ra, hc, tc, t2v, thr, acc, best); // every t2 > t1
-    rows_k2_diag<SGN, COLS, PHASE>(x, max(r0, cbase), r1, cbase, hc, tc, t2v, thr, acc, best);
+    const unsigned long long *pw = x.prune ? x.prune + b * (x.Lp >> 6) : nullptr;
+    rows_k2<SGN, COLS, PHASE, false>(x, r0, ra, hc, tc, t2v, thr, acc, best, pw); // every t2 > t1
+    rows_k2_diag<SGN, COLS, PHASE>(x, max(r0, cbase), r1, cbase, hc, tc, t2v, thr, acc, best, pw);
 }
 
 template <int SGN, int COLS, int PHASE, int K>
@@ -1087,12 +1115,16 @@ __device__ __forceinline__ void write_result(const Cand &b, const Args &a, int s
 // of P, Q [Lp] (k = 2; phase 2 reads them), the rows hd, tr [Lp] and the tile
 // maxima tmax [tiles] are carved from dynamic LDS sized for the launch
 // (fused_lds_bytes); the rest is static.
+constexpr int PRUNE_WORDS = 16 * 16; // k = 2: column blocks (<= 16) x Lp / 64 (<= 16)
+
 struct FusedLds {
     float *hd, *tr, *tmax;
     float4 *hls;
     double *pd, *qd;
     double red[2 * (FUSED_THREADS / 64)];
     float wmax[FUSED_THREADS / 64];
+    float wseed[FUSED_THREADS / 64];
+    unsigned long long prune[PRUNE_WORDS];
     double wr[FUSED_THREADS / 64], wl[FUSED_THREADS / 64];
     long long wc[FUSED_THREADS / 64];
     float sdelta;
@@ -1104,6 +1136,86 @@ static size_t fused_lds_bytes(int Lp, int k, int tiles)
 {
     return (size_t)Lp * (2 * sizeof(float) + (k == 2 ? sizeof(float4) + 2 * sizeof(double) : 0)) +
            (size_t)tiles * sizeof(float);
+}
+
+// k = 2, rows of phase 1 that cannot hold the arg max.  For a row t1 and a
+// column block [c0, c1] (c1 <= L - 2) every tuple (t1, t2) of the block has
+//   key <= head(t1) + gb + max over the block of tail(t2),
+// where gb bounds the middle class term g(t1, t2) (Tsallis-entropy section:
+// the class terms of the objective).  A class of n bins has, by the power
+// mean inequality, sum p^q <= n^(1-q) (sum p)^q for q < 1 and >= for q > 1,
+// so g <= |1-q| log2 n (q = 1: the class entropy, <= log2 n); for t1 < c0
+// its masses also lie between those of (t1, c0] and (t1, c1], so g <=
+// log2 dQ(t1, c1) - q log2 dP(t1, c0) for q < 1 and q log2 dP(t1, c1) -
+// log2 dQ(t1, c0) for q > 1.  The bound U is formed in FP32 like the keys;
+// with E = delta / 2 the per-key error bound, U is within E of its FP64 value.
+//
+// Given the largest FP32 key Ms of some tuples sigma, a row with U < Ms -
+// 3 delta has every FP64 key below key64(sigma) - delta: none of its tuples
+// is the arg max or ties with it, while the row of sigma is kept.  Phase 1
+// then skips groups of rows that are all marked; phase 2 is unchanged (its
+// threshold comes from the keys phase 1 did evaluate, and the arg max is
+// among them).  The seeds sigma are a coarse grid of tuples, one per thread.
+template <int SGN>
+__device__ __forceinline__ float seed_key(const TileCtx &x)
+{
+    int G = 1;
+    while ((G + 1) * (G + 1) <= (int)blockDim.x)
+        ++G;
+    const int S = (x.L - 1 + G - 1) / G; // G positions over [0, L - 2]
+    const int i = threadIdx.x / G, j = threadIdx.x % G;
+    const int t1 = min(i * S + S / 2, x.L - 2), t2 = min(j * S + S / 2, x.L - 2);
+    if (i >= G || !(t1 < t2))
+        return -INFINITY;
+    return (x.hd[t1] + cls32<SGN>(x.hl[t2], x.hl[t1], x.mq, x.gmax)) + x.tr[t2]; // as in phase 1
+}
+
+// Ms - 3 delta rounded down; -inf (nothing pruned) unless both are finite.
+__device__ __forceinline__ float prune_threshold(float Ms, float delta)
+{
+    if (!(Ms > -INFINITY) || !(delta < INFINITY))
+        return -INFINITY;
+    const double t64 = (double)Ms - 3.0 * (double)delta;
+    float t = (float)t64;
+    if ((double)t > t64)
+        t = nextafterf(t, -INFINITY);
+    return t;
+}
+
+// Bit t1 % 64 of words[b * (Lp / 64) + t1 / 64] set: row t1 of column block b
+// is skipped (rows without a tuple in the block are marked too).  One
+// wavefront per word, lanes over rows.
+template <int SGN>
+__device__ __forceinline__ void prune_rows(const TileCtx &x, int NB, float pthr, unsigned long long *words)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int PW = x.Lp >> 6, L = x.L;
+    for (int idx = w; idx < NB * PW; idx += nw) {
+        const int b = idx / PW, t1 = (idx % PW) * 64 + lane;
+        const int c0 = b * x.CW, c1 = min(c0 + x.CW - 1, L - 2);
+        float tm = -INFINITY;
+        for (int t2 = c0 + lane; t2 <= c1; t2 += 64)
+            tm = fmaxf(tm, x.tr[t2]);
+        tm = wave_max(tm);
+        bool skip = true;
+        if (t1 < c1) {
+            float gb = x.cw * __builtin_amdgcn_logf((float)(c1 - t1)); // the widest class (t1, c1]
+            if (SGN != 0 && t1 < c0) {
+                const float4 hr = x.hl[t1], h0 = x.hl[c0], h1 = x.hl[c1];
+                const float4 hp = SGN > 0 ? h0 : h1, hq = SGN > 0 ? h1 : h0;
+                const float dp = (hp.x - hr.x) + (hp.y - hr.y);
+                const float dq = (hq.z - hr.z) + (hq.w - hr.w);
+                const float lx = __builtin_amdgcn_logf(dq), ly = __builtin_amdgcn_logf(dp);
+                gb = fminf(gb, fmaf(x.mq, ly, SGN > 0 ? lx : -lx)); // NaN (empty classes) keeps gb
+            }
+            gb = __builtin_amdgcn_fmed3f(gb, 0.0f, x.gmax);
+            skip = (x.hd[t1] + gb) + tm < pthr;
+        }
+        const unsigned long long m = __ballot(skip);
+        if (lane == 0)
+            words[idx] = m;
+    }
 }
 
 // The whole search of problem s by the calling workgroup, from its prefix
@@ -1121,21 +1233,38 @@ __device__ __forceinline__ long long fused_body(const Args &a, FusedLds &sh, int
     // k = 2: split prefixes (and FP64 prefixes, when staged) in LDS
     const Steps stp = head_tail32<SGN>(a, qc, P, Q, hd, tr, K == 2 ? hls : nullptr, sh.red,
                                        K == 2 && stage ? sh.pd : nullptr, K == 2 && stage ? sh.qd : nullptr);
+    TileCtx x = make_ctx(a, s, hd, tr, hls);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nw = blockDim.x >> 6;
+    const bool prune = K == 2 && a.mode == TS_SEARCH_FP32_TIECHECK && a.NB * (a.Lp >> 6) <= PRUNE_WORDS;
+    if (prune) { // the rows are in LDS (head_tail32 ends with a barrier)
+        const float sk = wave_max(seed_key<SGN>(x));
+        if (lane == 0)
+            sh.wseed[w] = sk;
+    }
     if (threadIdx.x == 0) {
         sh.sdelta = problem_delta(a, qc, stp, Q[a.L - 1]);
         sh.next = 0;
     }
     __syncthreads();
-    TileCtx x = make_ctx(a, s, hd, tr, hls);
+    if (prune) {
+        float ms = -INFINITY;
+        for (int i = 0; i < nw; ++i)
+            ms = fmaxf(ms, sh.wseed[i]);
+        const float pthr = prune_threshold(ms, sh.sdelta); // the same in every thread
+        if (pthr > -INFINITY) {
+            prune_rows<SGN>(x, a.NB, pthr, sh.prune);
+            __syncthreads();
+            x.prune = sh.prune;
+        }
+    }
     x.P = P;
     x.Q = Q;
     if (K == 2 && stage) { // phase 2 reads the prefixes from LDS
         x.P = sh.pd;
         x.Q = sh.qd;
     }
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int nw = blockDim.x >> 6;
     Cand best = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL};
     float wm = -INFINITY;
     // tiles are handed out one at a time from an LDS counter, heaviest first
@@ -2053,6 +2182,11 @@ QConst make_qconst(double q, int L)
     if ((double)g < gm)
         g = nextafterf(g, INFINITY);
     c.gmax = g;
+    const double cw = shannon ? 1.0 : fabs(1.0 - q);
+    float w = (float)cw;
+    if ((double)w < cw)
+        w = nextafterf(w, INFINITY);
+    c.cw = w;
     return c;
 }
 
