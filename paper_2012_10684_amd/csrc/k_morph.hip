@@ -6,31 +6,48 @@
 //
 // One workgroup per 64 x 64 output tile of one image.  The tile and a halo of
 // r pixels are staged in LDS (gray levels; outside the image the neutral
-// value, 255 for the minimum and 0 for the maximum).  The disk is the union
-// over row offsets dy of horizontal runs of half-width w(dy) =
-// floor(sqrt(r^2 - dy^2)); w grows as |dy| falls, so a row buffer H holds
-// the horizontal minimum (maximum) of half-width w for every staged row and
-// is widened in place, one distinct w at a time, and each output takes the
-// minimum (maximum) of H at rows y - |dy| and y + |dy| when w = w(dy).  Per
-// output pixel: about 2r (1 + 2r / 64) LDS reads to widen H and 2r + 1 to
-// combine, for each of the two passes.
+// value, 255 for the minimum and 0 for the maximum) with a fixed row stride,
+// so that a thread's staged rows sit at constant offsets from each other.
+// The disk is the union over row offsets dy of horizontal runs of half-width
+// w(dy) = floor(sqrt(r^2 - dy^2)); w grows as |dy| falls, so each thread
+// holds the horizontal minimum (maximum) of its staged rows in registers and
+// widens them one distinct w at a time (two LDS byte reads and one min3 per
+// row and unit of width), then publishes them in a row buffer H; each output
+// takes the minimum (maximum) of H at rows y - |dy| and y + |dy| when w =
+// w(dy).  Per output pixel and pass: about 2r (1 + 2r / 64) LDS reads to
+// widen and 2r + 2 to combine.
 #include "common.h"
 
 namespace ts {
 
 constexpr int MO_TX = 64, MO_TY = 64, MO_THREADS = 256;
 constexpr int MO_PER = MO_TX * MO_TY / MO_THREADS; // outputs per thread
-constexpr int MO_SW = MO_TX + 2 * TS_MORPH_MAX_RADIUS;  // largest staged row
+constexpr int MO_SW = MO_TX + 2 * TS_MORPH_MAX_RADIUS;  // staged row stride (the largest staged row)
 constexpr int MO_SH = MO_TY + 2 * TS_MORPH_MAX_RADIUS;  // largest staged column
+constexpr int MO_PH = MO_THREADS / MO_TX;               // row phases: thread rows yb, yb + 4, ...
+constexpr int MO_ROWS = MO_SH / MO_PH;                  // staged rows per thread, at most
 
-__device__ __forceinline__ int isqrt_floor(int n)
+// min (MAXOP: max) of three values as one v_min3_u32 / v_max3_u32 (the
+// compiler would split it into a 16-bit and a 32-bit operation)
+template <bool MAXOP>
+__device__ __forceinline__ unsigned op3(unsigned a, unsigned b, unsigned c)
 {
-    int w = (int)sqrt((double)n);
-    while (w * w > n)
-        --w;
-    while ((w + 1) * (w + 1) <= n)
-        ++w;
-    return w;
+    unsigned r;
+    if (MAXOP)
+        asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    else
+        asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// floor(sqrt(n)) from a guess g >= 0 (wavefront-uniform integers: scalar code)
+__device__ __forceinline__ int isqrt_from(int n, int g)
+{
+    while (g * g > n)
+        --g;
+    while ((g + 1) * (g + 1) <= n)
+        ++g;
+    return g;
 }
 
 // MAXOP = false: erosion of the gray levels of the int16 images (src16,
@@ -55,7 +72,7 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
     const TS_GLOBAL int16_t *img16 = gp(src16[s]);
     const int c = threadIdx.x % MO_TX, yb = threadIdx.x / MO_TX; // lane column, row phase (0..3)
     // stage the tile and its halo: rows yb, yb + 4, ..., columns c, c + 64
-    for (int row = yb; row < sh; row += MO_THREADS / MO_TX) {
+    for (int row = yb; row < sh; row += MO_PH) {
         const int y = y0 - r + row;
         const bool yin = y >= 0 && y < H;
         for (int col = c; col < sw; col += MO_TX) {
@@ -67,34 +84,58 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
                 else
                     v = bin_of_t<MAP>(img16[(int64_t)y * W + x], bm);
             }
-            in[row * sw + col] = (uint8_t)v;
+            in[row * MO_SW + col] = (uint8_t)v;
         }
     }
+    // this thread's staged rows yb + 4 i, i < nr, in groups of four (rows of
+    // the last group past sh read staged memory that is never used)
+    const int nr = __builtin_amdgcn_readfirstlane((sh - yb + MO_PH - 1) / MO_PH); // the same in the wavefront
+    const uint8_t *cin = in + yb * MO_SW + c + r; // row yb, column c of the tile
+    unsigned hv[MO_ROWS];
     __syncthreads();
-    // half-width 0: the staged pixel itself
-    for (int row = yb; row < sh; row += MO_THREADS / MO_TX)
-        hr[row * MO_TX + c] = in[row * sw + c + r];
+#pragma unroll
+    for (int i0 = 0; i0 < MO_ROWS; i0 += 4)
+        if (i0 < nr) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                hv[i0 + u] = cin[(i0 + u) * MO_PH * MO_SW]; // half-width 0: the staged pixel itself
+        }
+    // publish the rows at their current half-width into hr
+    auto publish = [&]() {
+#pragma unroll
+        for (int i0 = 0; i0 < MO_ROWS; i0 += 4)
+            if (i0 < nr) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u < nr)
+                        hr[(yb + (i0 + u) * MO_PH) * MO_TX + c] = (uint8_t)hv[i0 + u];
+            }
+    };
+    publish();
     // outputs (yb + 4 i, c), i < MO_PER
     int out[MO_PER];
 #pragma unroll
     for (int i = 0; i < MO_PER; ++i)
         out[i] = neutral;
-    int cur = 0;
+    int cur = 0, wg = 0;
     __syncthreads(); // hr at half-width 0
     for (int a = r; a >= 0; --a) {
-        const int w = isqrt_floor(r * r - a * a);
-        if (w > cur) { // widen every staged row from half-width cur to w
-            __syncthreads(); // the combine steps before have read hr
-            for (int row = yb; row < sh; row += MO_THREADS / MO_TX) {
-                const uint8_t *rin = in + row * sw + c + r;
-                int v = hr[row * MO_TX + c];
-#pragma unroll 4
-                for (int d = cur + 1; d <= w; ++d) {
-                    const int lft = rin[-d], rgt = rin[d];
-                    v = MAXOP ? max(v, max(lft, rgt)) : min(v, min(lft, rgt));
-                }
-                hr[row * MO_TX + c] = (uint8_t)v;
+        const int w = wg = isqrt_from(r * r - a * a, wg);
+        if (w > cur) { // widen every staged row of the thread from half-width cur to w
+            for (int d = cur + 1; d <= w; ++d) {
+                const uint8_t *pl = cin - d, *pr = cin + d;
+#pragma unroll
+                for (int i0 = 0; i0 < MO_ROWS; i0 += 4)
+                    if (i0 < nr) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int o = (i0 + u) * MO_PH * MO_SW;
+                            hv[i0 + u] = op3<MAXOP>(hv[i0 + u], pl[o], pr[o]);
+                        }
+                    }
             }
+            __syncthreads(); // the combine steps before have read hr
+            publish();
             cur = w;
             __syncthreads();
         }
