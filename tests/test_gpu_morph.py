@@ -34,7 +34,7 @@ def _check(imgs, lo, hi, L, r, want=("opened", "residue")):
             assert np.array_equal(r16[i].cpu().numpy().astype(np.int32), rr), (H, W, r, i)
 
 
-@pytest.mark.parametrize("r", [0, 1, 3, 10, 17, 32])
+@pytest.mark.parametrize("r", [0, 1, 2, 3, 5, 10, 17, 31, 32])
 def test_open2d_random_images(r):
     rng = np.random.default_rng(r + 1)
     for H, W in [(1, 1), (3, 200), (64, 64), (70, 129), (130, 65)]:
