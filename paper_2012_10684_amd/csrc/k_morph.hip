@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
     // stage word j of row rho: pixels x = x0 - R + 2j and x + 1 of row y0 - r
     // + rho; every load of the thread is issued before the first is used
     {
-        const int j = threadIdx.x & 63, rw = threadIdx.x >> 6; // rows rw, rw + 4, ...
+        const int j = threadIdx.x & 63, rw = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); // rows rw, rw + 4, ...
         const int x = x0 - R + 2 * j;
         const bool xin0 = j < nw && x >= 0 && x < W, xin1 = j < nw && x + 1 >= 0 && x + 1 < W;
         uint32_t stg[MO_STG][2];
@@ -92,13 +92,15 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
         for (int i = 0; i < MO_STG; ++i) {
             const int y = y0 - r + rw + 4 * i;
             const bool yin = rw + 4 * i < sh && y >= 0 && y < H;
-            const int64_t o = (int64_t)y * W + x;
+            // the row's base is the same in the wavefront; the column a 32-bit offset
             if (MAXOP) {
-                stg[i][0] = yin && xin0 ? (uint32_t)src8[img_off + o] : neutral;
-                stg[i][1] = yin && xin1 ? (uint32_t)src8[img_off + o + 1] : neutral;
+                const uint8_t *row8 = src8 + img_off + (int64_t)y * W;
+                stg[i][0] = yin && xin0 ? (uint32_t)row8[x] : neutral;
+                stg[i][1] = yin && xin1 ? (uint32_t)row8[x + 1] : neutral;
             } else {
-                stg[i][0] = yin && xin0 ? (uint32_t)(int)img16[o] : 0u;
-                stg[i][1] = yin && xin1 ? (uint32_t)(int)img16[o + 1] : 0u;
+                const TS_GLOBAL int16_t *row16 = img16 + (int64_t)y * W;
+                stg[i][0] = yin && xin0 ? (uint32_t)(int)row16[x] : 0u;
+                stg[i][1] = yin && xin1 ? (uint32_t)(int)row16[x + 1] : 0u;
             }
         }
 #pragma unroll
