@@ -48,7 +48,7 @@ constexpr int S2_WAVES = 4;       // wavefronts per (q, image), each a block of 
 constexpr int S2_THREADS = 64 * S2_WAVES;
 constexpr int S2_CPL = 4;         // columns per lane (L <= 256)
 constexpr int S2_TAB = 2048;      // p^q (or p ln p) of counts below this from an LDS table
-constexpr int S2_RING = 4;        // rows of counts in flight ahead of the row being summed
+constexpr int S2_RING = 3;        // rows of counts in flight ahead of the row being summed
 
 // ------------------------------------------------------------------ histogram
 
@@ -405,6 +405,7 @@ struct S2 {
     bool vec;          // rows load as 16-byte vectors (L % 4 == 0, aligned)
     double q, sgn, hmax;
     const double *tab; // cterm of counts below S2_TAB
+    const uint32_t *band; // per row: lowest | highest column holding counts << 16 (LDS)
     float mq;          // -q rounded to FP32 (Tsallis)
     float sg;          // sgn(1-q) as +-1 (Tsallis)
     float gmax;        // hmax / ln 2 rounded up
@@ -466,29 +467,30 @@ __device__ __forceinline__ double s2_delta(const S2 &p, double N)
 // (clamped addresses, masked values) so that several rows' loads can be in
 // flight at once.
 template <int DIR>
-__device__ __forceinline__ void load_row(const uint32_t *h, int L, bool vec, int t, uint32_t (&c)[S2_CPL])
+__device__ __forceinline__ void load_row(const uint32_t *h, int L, bool vec, int t, uint32_t (&c)[S2_CPL],
+                                         const uint32_t *band)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t *row = h + (int64_t)t * L;
+    // columns outside the row's band hold no counts: those lanes load nothing
+    // (band null: every column)
+    const uint32_t bd = band ? band[t] : 0xffff0000u;
+    const int jlo = (int)(bd & 0xffffu), jhi = (int)(bd >> 16);
+    const int c0 = DIR > 0 ? S2_CPL * lane : L - S2_CPL - S2_CPL * lane; // the lane's lowest column (vec)
     if (vec) {
-        const bool ok = S2_CPL * lane < L;
-        const int off = ok ? (DIR > 0 ? S2_CPL * lane : L - S2_CPL - S2_CPL * lane) : 0;
-        const uint4 v = *reinterpret_cast<const uint4 *>(row + off);
+        const bool ok = S2_CPL * lane < L && c0 <= jhi && c0 + S2_CPL - 1 >= jlo;
+        const uint4 v = ok ? *reinterpret_cast<const uint4 *>(row + c0) : make_uint4(0u, 0u, 0u, 0u);
         if (DIR > 0) {
             c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
         } else {
             c[0] = v.w; c[1] = v.z; c[2] = v.y; c[3] = v.x;
         }
-#pragma unroll
-        for (int u = 0; u < S2_CPL; ++u)
-            c[u] = ok ? c[u] : 0u;
     } else {
 #pragma unroll
         for (int u = 0; u < S2_CPL; ++u) {
             const int col = DIR > 0 ? S2_CPL * lane + u : L - 1 - (S2_CPL * lane + u);
-            const bool ok = col >= 0 && col < L;
-            const uint32_t v = row[ok ? col : 0];
-            c[u] = ok ? v : 0u;
+            const bool ok = col >= 0 && col < L && col >= jlo && col <= jhi;
+            c[u] = ok ? row[col] : 0u;
         }
     }
 }
@@ -509,7 +511,7 @@ __device__ __forceinline__ void for_rows(const S2 &p, const int *rows, int k0, i
 #pragma unroll
     for (int d = 0; d < S2_RING; ++d) {
         const int kk = k0 + DIR * min(d, n - 1);
-        load_row<DIR>(p.h, p.L, p.vec, rows[kk], ring[d]);
+        load_row<DIR>(p.h, p.L, p.vec, rows[kk], ring[d], p.band);
         aux(kk, xr[d]);
     }
     for (int i0 = 0; i0 < n; i0 += S2_RING) {
@@ -524,7 +526,7 @@ __device__ __forceinline__ void for_rows(const S2 &p, const int *rows, int k0, i
                 x[u] = xr[d][u];
             }
             const int kk = k0 + DIR * min(i + S2_RING, n - 1);
-            load_row<DIR>(p.h, p.L, p.vec, rows[kk], ring[d]);
+            load_row<DIR>(p.h, p.L, p.vec, rows[kk], ring[d], p.band);
             aux(kk, xr[d]);
             CT rc[S2_CPL];
             double rq[S2_CPL];
@@ -552,7 +554,7 @@ __device__ __forceinline__ void block_totals(const S2 &p, const int *rows, int k
     uint32_t ring[S2_RING][S2_CPL];
 #pragma unroll
     for (int d = 0; d < S2_RING; ++d)
-        load_row<DIR>(p.h, p.L, p.vec, rows[k0 + DIR * min(d, n - 1)], ring[d]);
+        load_row<DIR>(p.h, p.L, p.vec, rows[k0 + DIR * min(d, n - 1)], ring[d], p.band);
     for (int i0 = 0; i0 < n; i0 += S2_RING) {
 #pragma unroll
         for (int d = 0; d < S2_RING; ++d) {
@@ -561,7 +563,7 @@ __device__ __forceinline__ void block_totals(const S2 &p, const int *rows, int k
 #pragma unroll
             for (int u = 0; u < S2_CPL; ++u)
                 c[u] = ring[d][u];
-            load_row<DIR>(p.h, p.L, p.vec, rows[k0 + DIR * min(i + S2_RING, n - 1)], ring[d]);
+            load_row<DIR>(p.h, p.L, p.vec, rows[k0 + DIR * min(i + S2_RING, n - 1)], ring[d], p.band);
             if (i < n) {
                 double t[S2_CPL];
                 bool big = false;
@@ -611,6 +613,7 @@ __device__ __forceinline__ float wave_max_f32(float v)
 // LDS of one (q index, problem).
 struct S2Lds {
     double tab[S2_TAB];                   // cterm of counts below S2_TAB
+    uint32_t band[H2_MAX_L];              // each row's band of columns holding counts
     int rows[H2_MAX_L];                   // rows holding counts, increasing
     float rmax[H2_MAX_L];                 // best pair key of each listed row
     uint64_t tc[2][S2_WAVES][H2_MAX_L];   // block totals along s: [0] class 2 blocks, [1] class 1 blocks
@@ -895,19 +898,22 @@ __device__ __forceinline__ void search2d_body(const S2 &p, double N, int R, S2Ld
     }
 }
 
-// Which rows of each image hold counts, and the image's pixel count: one
-// wavefront per group of 16 rows, all 16 rows' loads in flight together.
-// mask[s][g] bit d: row 16 g + d holds counts; cnt[s][g]: its pixels.
+// Which rows of each image hold counts, the image's pixel count and each
+// row's band of columns holding counts: one wavefront per group of 16 rows,
+// all 16 rows' loads in flight together.  mask[s][g] bit d: row 16 g + d
+// holds counts; cnt[s][g]: its pixels; band[s][t]: the lowest column holding
+// counts in row t | the highest << 16 (0xffff | 0 << 16 for an empty row).
 __global__ void __launch_bounds__(64) k_rows2d(const uint32_t *__restrict__ hist, int L, int groups,
-                                               uint16_t *__restrict__ mask, uint64_t *__restrict__ cnt)
+                                               uint16_t *__restrict__ mask, uint64_t *__restrict__ cnt,
+                                               uint32_t *__restrict__ band)
 {
-    const int s0 = blockIdx.x / groups, g = blockIdx.x % groups;
+    const int s0 = blockIdx.x / groups, g = blockIdx.x % groups, lane = threadIdx.x & 63;
     const uint32_t *h = hist + (int64_t)s0 * L * L;
     const bool vec = (L % S2_CPL) == 0 && ((uintptr_t)h & 15) == 0;
     uint32_t c[16][S2_CPL];
 #pragma unroll
     for (int d = 0; d < 16; ++d) // rows past L reload row L-1 and count as empty
-        load_row<1>(h, L, vec, min(16 * g + d, L - 1), c[d]);
+        load_row<1>(h, L, vec, min(16 * g + d, L - 1), c[d], nullptr);
     uint32_t bits = 0;
     uint64_t n = 0;
 #pragma unroll
@@ -921,6 +927,22 @@ __global__ void __launch_bounds__(64) k_rows2d(const uint32_t *__restrict__ hist
         n += r;
         if (__ballot(r != 0))
             bits |= 1u << d;
+        int lo = 0xffff, hi = 0;
+#pragma unroll
+        for (int u = S2_CPL - 1; u >= 0; --u)
+            if (c[d][u])
+                lo = S2_CPL * lane + u;
+#pragma unroll
+        for (int u = 0; u < S2_CPL; ++u)
+            if (c[d][u])
+                hi = S2_CPL * lane + u;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, 64));
+            hi = max(hi, __shfl_xor(hi, o, 64));
+        }
+        if (lane == 0 && 16 * g + d < L)
+            band[(int64_t)s0 * L + 16 * g + d] = (bits >> d) & 1u ? (uint32_t)lo | ((uint32_t)hi << 16) : 0xffffu;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
@@ -931,16 +953,24 @@ __global__ void __launch_bounds__(64) k_rows2d(const uint32_t *__restrict__ hist
     }
 }
 
-__global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restrict__ hist, int nseg, int L, Q2List ql,
-                                                         float *__restrict__ k2all, double *__restrict__ t2all,
-                                                         const uint16_t *__restrict__ mask,
-                                                         const uint64_t *__restrict__ cnt, int32_t *__restrict__ thr,
+// Workgroup b takes image s0 = 8 (b / 8 / nq) + b % 8 and q index (b / 8) %
+// nq: the nq workgroups of an image are 8 apart, so they land on the same XCD
+// (workgroups go to the 8 XCDs in turn) and share its L2 for the image's
+// rows; workgroups with s0 >= nseg do nothing.
+__global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restrict__ hist, int nseg, int nq, int L,
+                                                         Q2List ql, float *__restrict__ k2all,
+                                                         double *__restrict__ t2all, const uint16_t *__restrict__ mask,
+                                                         const uint64_t *__restrict__ cnt,
+                                                         const uint32_t *__restrict__ band, int32_t *__restrict__ thr,
                                                          double *__restrict__ obj, int32_t *__restrict__ status)
 {
     __shared__ S2Lds sh;
     __shared__ int nrows;
     const int lane = threadIdx.x & 63;
-    const int prob = blockIdx.x, s0 = prob % nseg, j = prob / nseg;
+    const int slot = blockIdx.x >> 3, s0 = (slot / nq) * 8 + (blockIdx.x & 7), j = slot % nq;
+    if (s0 >= nseg)
+        return;
+    const int prob = j * nseg + s0;
     S2 p;
     p.h = hist + (int64_t)s0 * L * L;
     p.L = L;
@@ -952,6 +982,7 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
     p.sg = p.q < 1.0 ? 1.0f : -1.0f;
     p.gmax = (float)(p.hmax * 1.4426950408889634 * (1.0 + 0x1p-20));
     p.tab = sh.tab;
+    p.band = sh.band;
     // the image's pixel count (every wavefront) and its rows holding counts,
     // in increasing order (wavefront 0): lane l looks at rows 4l .. 4l+3
     // (groups past the last hold no rows below L)
@@ -987,6 +1018,8 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
     }
     for (int i = threadIdx.x; i < S2_TAB; i += blockDim.x)
         sh.tab[i] = cterm((uint32_t)i, p.q);
+    for (int i = threadIdx.x; i < L; i += blockDim.x)
+        sh.band[i] = band[(int64_t)s0 * L + i];
     __syncthreads();
     const int R = nrows;
     float *k2 = k2all + (int64_t)prob * L * L;
@@ -998,15 +1031,16 @@ __global__ void __launch_bounds__(S2_THREADS) k_search2d(const uint32_t *__restr
 }
 
 // Workspace: FP64 terms [nprob][L][L], FP32 keys [nprob][L][L], row masks
-// uint16 [nseg][16] and pixel counts uint64 [nseg][16], each part starting
-// 256-byte aligned (the workspace itself must be 8-byte aligned).
+// uint16 [nseg][16], pixel counts uint64 [nseg][16] and row bands uint32
+// [nseg][L], each part starting 256-byte aligned (the workspace itself must
+// be 8-byte aligned).
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t search2d_workspace_bytes(int nseg, int nq, int L)
 {
     const size_t cells = (size_t)nseg * nq * L * L;
     return up256(cells * sizeof(double)) + up256(cells * sizeof(float)) + up256((size_t)nseg * 16 * 2) +
-           (size_t)nseg * 16 * 8;
+           up256((size_t)nseg * 16 * 8) + (size_t)nseg * L * 4;
 }
 
 ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const double *q, void *ws, int32_t *thr,
@@ -1021,10 +1055,12 @@ ts_status launch_search2d(const uint32_t *hist, int nseg, int L, int nq, const d
     float *k2 = (float *)(w + up256(cells * sizeof(double)));
     uint16_t *mask = (uint16_t *)(w + up256(cells * sizeof(double)) + up256(cells * sizeof(float)));
     uint64_t *cnt = (uint64_t *)((char *)mask + up256((size_t)nseg * 16 * 2));
+    uint32_t *band = (uint32_t *)((char *)cnt + up256((size_t)nseg * 16 * 8));
     const int groups = (L + 15) / 16;
-    hipLaunchKernelGGL(k_rows2d, dim3((unsigned)(nseg * groups)), dim3(64), 0, st, hist, L, groups, mask, cnt);
-    hipLaunchKernelGGL(k_search2d, dim3((unsigned)(nseg * nq)), dim3(S2_THREADS), 0, st, hist, nseg, L, ql, k2, t2, mask,
-                       cnt, thr, obj, status);
+    hipLaunchKernelGGL(k_rows2d, dim3((unsigned)(nseg * groups)), dim3(64), 0, st, hist, L, groups, mask, cnt, band);
+    const unsigned nblk = (unsigned)((nseg + 7) / 8 * 8 * nq);
+    hipLaunchKernelGGL(k_search2d, dim3(nblk), dim3(S2_THREADS), 0, st, hist, nseg, nq, L, ql, k2, t2, mask, cnt, band,
+                       thr, obj, status);
     return check_launch("ts_threshold_search2d");
 }
 
