@@ -252,9 +252,11 @@ def parse():
     ap.add_argument("--inputs", type=int, default=None,
                     help="resident copies of the input the steps cycle through (default: 4 for volume300 and "
                          "volume600, whose volume would otherwise sit in the memory-side cache; else 1)")
-    ap.add_argument("--path", default="fused", choices=("fused", "steps"),
+    ap.add_argument("--path", default="auto", choices=("auto", "fused", "steps"),
                     help="fused: one ts_segment call per step; steps: ts_histogram, ts_prefix, "
-                         "ts_threshold_search, ts_label_sets")
+                         "ts_threshold_search, ts_label_sets; auto: fused where ts_segment runs its one-kernel "
+                         "path (problems filling the chip twice over), else steps (the same kernels ts_segment "
+                         "would launch, with the label pass timed as the roofline kernel)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured as HIP graphs, checked against an eager step "
                          "(default: eager launches, measured faster on MI355X)")
@@ -797,6 +799,9 @@ def main():
     optrs = [torch.tensor([o.data_ptr() for o in oq], dtype=torch.int64).to(dev) for oq in outs]
     stream = torch.cuda.current_stream()
     names = ["histogram", "prefix", "search", "label"]
+    if args.path == "auto":  # ts_segment's own rule for its one-kernel path
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        args.path = "fused" if nseg >= 1024 or nseg >= 2 * cus else "steps"
     fused = args.path == "fused"
     if fused and args.graph:
         raise SystemExit("--graph replays the separate steps: use it with --path steps")

@@ -82,25 +82,48 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
     const int64_t img_off = (int64_t)s * H * W;
     const TS_GLOBAL int16_t *img16 = gp(src16[s]);
     // stage word j of row rho: pixels x = x0 - R + 2j and x + 1 of row y0 - r
-    // + rho; every load of the thread is issued before the first is used
+    // + rho; every load of the thread is issued before the first is used.
+    // With an even width and aligned rows (pairs) the two pixels of a word are
+    // both inside or both outside the image and load as one access.
+    const bool pairs = (W & 1) == 0 && (MAXOP ? ((uintptr_t)(src8 + img_off) & 1) == 0 : ((uintptr_t)img16 & 3) == 0);
     {
         const int j = threadIdx.x & 63, rw = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); // rows rw, rw + 4, ...
         const int x = x0 - R + 2 * j;
         const bool xin0 = j < nw && x >= 0 && x < W, xin1 = j < nw && x + 1 >= 0 && x + 1 < W;
         uint32_t stg[MO_STG][2];
+        if (pairs) {
 #pragma unroll
-        for (int i = 0; i < MO_STG; ++i) {
-            const int y = y0 - r + rw + 4 * i;
-            const bool yin = rw + 4 * i < sh && y >= 0 && y < H;
-            // the row's base is the same in the wavefront; the column a 32-bit offset
-            if (MAXOP) {
-                const uint8_t *row8 = src8 + img_off + (int64_t)y * W;
-                stg[i][0] = yin && xin0 ? (uint32_t)row8[x] : neutral;
-                stg[i][1] = yin && xin1 ? (uint32_t)row8[x + 1] : neutral;
-            } else {
-                const TS_GLOBAL int16_t *row16 = img16 + (int64_t)y * W;
-                stg[i][0] = yin && xin0 ? (uint32_t)(int)row16[x] : 0u;
-                stg[i][1] = yin && xin1 ? (uint32_t)(int)row16[x + 1] : 0u;
+            for (int i = 0; i < MO_STG; ++i) {
+                const int y = y0 - r + rw + 4 * i;
+                const bool in2 = rw + 4 * i < sh && y >= 0 && y < H && xin0;
+                if (MAXOP) {
+                    const uint16_t *row8 = reinterpret_cast<const uint16_t *>(src8 + img_off + (int64_t)y * W);
+                    const uint32_t v = in2 ? (uint32_t)row8[x >> 1] : neutral | (neutral << 8);
+                    stg[i][0] = v & 0xffu;
+                    stg[i][1] = v >> 8;
+                } else {
+                    const TS_GLOBAL uint32_t *row16 =
+                        reinterpret_cast<const TS_GLOBAL uint32_t *>(img16 + (int64_t)y * W);
+                    const uint32_t v = in2 ? row16[x >> 1] : 0u;
+                    stg[i][0] = v & 0xffffu;
+                    stg[i][1] = v >> 16;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < MO_STG; ++i) {
+                const int y = y0 - r + rw + 4 * i;
+                const bool yin = rw + 4 * i < sh && y >= 0 && y < H;
+                // the row's base is the same in the wavefront; the column a 32-bit offset
+                if (MAXOP) {
+                    const uint8_t *row8 = src8 + img_off + (int64_t)y * W;
+                    stg[i][0] = yin && xin0 ? (uint32_t)row8[x] : neutral;
+                    stg[i][1] = yin && xin1 ? (uint32_t)row8[x + 1] : neutral;
+                } else {
+                    const TS_GLOBAL int16_t *row16 = img16 + (int64_t)y * W;
+                    stg[i][0] = yin && xin0 ? (uint32_t)(uint16_t)row16[x] : 0u;
+                    stg[i][1] = yin && xin1 ? (uint32_t)(uint16_t)row16[x + 1] : 0u;
+                }
             }
         }
 #pragma unroll
@@ -201,14 +224,47 @@ __global__ void __launch_bounds__(MO_THREADS) k_morph(const int16_t *const *__re
     // the residue's input values are all loaded before the first store (the
     // outputs may alias the input as far as the compiler knows)
     int f[MO_PER][2];
+    const bool opairs = (W & 1) == 0 && ((uintptr_t)img16 & 3) == 0 && ((uintptr_t)dst & 1) == 0 &&
+                        ((uintptr_t)res & 1) == 0 && ((uintptr_t)res16 & 3) == 0;
     if (MAXOP && (res || res16)) {
+        if (opairs) {
 #pragma unroll
-        for (int i = 0; i < MO_PER; ++i)
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int y = y0 + yb + MO_PH * i, x = x0 + 2 * l + e;
-                f[i][e] = y < H && x < W ? (int)img16[(int64_t)y * W + x] : 0;
+            for (int i = 0; i < MO_PER; ++i) {
+                const int y = y0 + yb + MO_PH * i, x = x0 + 2 * l;
+                const uint32_t v =
+                    y < H && x < W ? reinterpret_cast<const TS_GLOBAL uint32_t *>(img16 + (int64_t)y * W)[x >> 1] : 0u;
+                f[i][0] = (int)(int16_t)(v & 0xffffu);
+                f[i][1] = (int)(int16_t)(v >> 16);
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < MO_PER; ++i)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int y = y0 + yb + MO_PH * i, x = x0 + 2 * l + e;
+                    f[i][e] = y < H && x < W ? (int)img16[(int64_t)y * W + x] : 0;
+                }
+        }
+    }
+    if (opairs) { // both pixels of a pair inside or both outside: one store per output and pair
+#pragma unroll
+        for (int i = 0; i < MO_PER; ++i) {
+            const int y = y0 + yb + MO_PH * i, x = x0 + 2 * l;
+            if (y >= H || x >= W)
+                continue;
+            const uint32_t v0 = out[i] & 0xffffu, v1 = out[i] >> 16;
+            const int64_t o = img_off + (int64_t)y * W + x;
+            if (dst)
+                *reinterpret_cast<uint16_t *>(dst + o) = (uint16_t)(v0 | (v1 << 8));
+            if (MAXOP && (res || res16)) {
+                const int g0 = bin_of_t<MAP>(f[i][0], bm) - (int)v0, g1 = bin_of_t<MAP>(f[i][1], bm) - (int)v1;
+                if (res)
+                    *reinterpret_cast<uint16_t *>(res + o) = (uint16_t)((g0 & 0xff) | ((g1 & 0xff) << 8));
+                if (res16)
+                    *reinterpret_cast<uint32_t *>(res16 + o) = (uint32_t)(g0 & 0xffff) | ((uint32_t)(g1 & 0xffff) << 16);
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int i = 0; i < MO_PER; ++i) {

@@ -65,6 +65,26 @@ def test_open2d_single_outputs():
     _check(imgs, -1024, 3071, 256, 6, want=("residue16",))
 
 
+@pytest.mark.parametrize("r", [2, 10])
+def test_open2d_misaligned_images(r):
+    """Even widths (pixel pairs load and store as one access) with images at
+    odd int16 offsets of one buffer (2-byte aligned): the per-pixel path."""
+    rng = np.random.default_rng(40 + r)
+    H, W, n = 66, 130, 3
+    buf = rng.integers(-1100, 400, n * H * W + 1).astype(np.int16)
+    dbuf = to_dev(buf)
+    imgs = [dbuf[1 + i * H * W: 1 + (i + 1) * H * W] for i in range(n)]
+    o, res, r16 = api.open2d(api.Batch(imgs), H, W, api.binning(-1024, 3071, 256), r,
+                             want=("opened", "residue", "residue16"))
+    torch.cuda.synchronize()
+    for i in range(n):
+        g = oracle.gray(buf[1 + i * H * W: 1 + (i + 1) * H * W].reshape(H, W), -1024, 3071, 256)
+        oo, rr = oracle.opening(g, r)
+        assert np.array_equal(o[i].cpu().numpy().astype(np.int32), oo), (r, i)
+        assert np.array_equal(res[i].cpu().numpy().astype(np.int32), rr), (r, i)
+        assert np.array_equal(r16[i].cpu().numpy().astype(np.int32), rr), (r, i)
+
+
 @pytest.mark.parametrize("q", [0.5, 1.5])
 def test_segmentation_after_the_opening(q):
     """The paper's segmentation step on workload slices: opening by the
