@@ -189,6 +189,34 @@ def pmc_per_dispatch(d: str, counter: str):
     return {name: (n, t / n) for name, (n, t) in per.items()}
 
 
+def summarize_sq(dirs, header: str) -> str:
+    """Per-kernel SQ counters per dispatch (summed over the counter's
+    instances, averaged over the kernel's dispatches) from one or more
+    rocprofv3 --pmc runs (their *counter_collection.csv), ts:: kernels only,
+    with VALU and LDS instructions per wavefront."""
+    acc, disp = {}, {}
+    for d in dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            name = r["Kernel_Name"]
+            if not short_name(name).startswith("ts::") or "k_issue" in name:
+                continue
+            key = (name, r.get("Dispatch_Id") or r.get("Correlation_Id"))
+            disp.setdefault(name, {}).setdefault(r["Counter_Name"], set()).add(key[1])
+            acc.setdefault(name, {}).setdefault(r["Counter_Name"], 0.0)
+            acc[name][r["Counter_Name"]] += float(r["Counter_Value"])
+    counters = sorted({c for v in acc.values() for c in v})
+    out = [header, "", "per dispatch; wave-level instruction counts (x 64 for lane operations)", ""]
+    for name in sorted(acc, key=lambda n: -acc[n].get("SQ_INSTS_VALU", 0.0) / max(1, len(disp[n].get("SQ_INSTS_VALU", [1])))):
+        vals = {c: acc[name][c] / len(disp[name][c]) for c in acc[name]}
+        out.append(short_name(name, 70))
+        out.append("  " + "  ".join(f"{c}={vals[c]:.4g}" for c in counters if c in vals))
+        if vals.get("SQ_WAVES"):
+            w = vals["SQ_WAVES"]
+            out.append("  per wavefront: " + "  ".join(f"{c[len('SQ_INSTS_'):]}={vals[c] / w:.1f}" for c in counters
+                                                       if c.startswith("SQ_INSTS_") and c in vals))
+    return "\n".join(out) + "\n"
+
+
 def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload, command):
     """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
     dispatch), scaled by what the same counters read for the runtime's copy
@@ -267,6 +295,8 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
                     help="no GPU: HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output folders of "
                          "this workload and of --calibrate; updates profiles/traffic.json, prints a summary")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="DIR",
+                    help="print per-kernel SQ counters per dispatch from rocprofv3 --pmc runs")
     ap.add_argument("--header", default="", help="first line(s) of a --summarize-* summary (the command that ran)")
     return ap.parse_args()
 
@@ -698,6 +728,9 @@ def main():
         return
     if args.summarize_pmc:
         print(summarize_pmc(*args.summarize_pmc, args.workload, args.header), end="")
+        return
+    if args.summarize_sq:
+        print(summarize_sq(args.summarize_sq, args.header), end="")
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (independent problems would be "

@@ -77,3 +77,24 @@ def test_cpu_baseline_threads_take_whole_problems(monkeypatch):
     assert base["cores"] == 2 and base["single_thread"]["cores"] == 1
     assert check["problems"] == 3 and check["thresholds_identical"] == 3
     assert check["max_rel_objective_error"] == 0.0
+
+
+def test_summarize_sq_per_dispatch_and_per_wavefront(tmp_path):
+    """SQ counters: summed over a counter's instances within a dispatch,
+    averaged over dispatches; runtime kernels and the issue-rate probe left
+    out; instructions per wavefront from SQ_WAVES."""
+    rows = ["Correlation_Id,Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    for disp, scale in ((1, 1.0), (2, 3.0)):
+        for inst in range(2):  # two instances of each counter per dispatch
+            rows.append(f"{disp},{disp},\"ts::k_morph<false, 0>(int)\",SQ_INSTS_VALU,{500 * scale}")
+            rows.append(f"{disp},{disp},\"ts::k_morph<false, 0>(int)\",SQ_WAVES,{5 * scale}")
+    rows.append("3,3,void ts::k_issue<1>(float),SQ_INSTS_VALU,7")
+    rows.append("4,4,__amd_rocclr_copyBuffer,SQ_INSTS_VALU,9")
+    d = tmp_path / "sq"
+    d.mkdir()
+    (d / "pmc_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    out = bench.summarize_sq([str(d)], "hdr")
+    assert out.startswith("hdr\n")
+    assert "k_issue" not in out and "copyBuffer" not in out
+    assert "SQ_INSTS_VALU=2000" in out and "SQ_WAVES=20" in out  # (1000 + 3000) / 2, (10 + 30) / 2
+    assert "per wavefront: VALU=100.0" in out
