@@ -280,11 +280,9 @@ def parse():
     ap.add_argument("--inputs", type=int, default=None,
                     help="resident copies of the input the steps cycle through (default: 4 for volume300 and "
                          "volume600, whose volume would otherwise sit in the memory-side cache; else 1)")
-    ap.add_argument("--path", default="auto", choices=("auto", "fused", "steps"),
+    ap.add_argument("--path", default="fused", choices=("fused", "steps"),
                     help="fused: one ts_segment call per step; steps: ts_histogram, ts_prefix, "
-                         "ts_threshold_search, ts_label_sets; auto: fused where ts_segment runs its one-kernel "
-                         "path (problems filling the chip twice over), else steps (the same kernels ts_segment "
-                         "would launch, with the label pass timed as the roofline kernel)")
+                         "ts_threshold_search, ts_label_sets")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured as HIP graphs, checked against an eager step "
                          "(default: eager launches, measured faster on MI355X)")
@@ -832,16 +830,19 @@ def main():
     optrs = [torch.tensor([o.data_ptr() for o in oq], dtype=torch.int64).to(dev) for oq in outs]
     stream = torch.cuda.current_stream()
     names = ["histogram", "prefix", "search", "label"]
-    if args.path == "auto":  # ts_segment's own rule for its one-kernel path
-        cus = torch.cuda.get_device_properties(dev).multi_processor_count
-        args.path = "fused" if nseg >= 1024 or nseg >= 2 * cus else "steps"
     fused = args.path == "fused"
+    # whether ts_segment runs its one-kernel path (its own rule: the problems
+    # fill the chip twice over); otherwise it launches the separate passes
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    kseg = fused and (nseg >= 1024 or nseg >= 2 * cus)
     if fused and args.graph:
         raise SystemExit("--graph replays the separate steps: use it with --path steps")
     # ts_segment's workspace (contents ignored)
     seg_ws = torch.empty(max(api.segment_workspace_bytes(nseg, L, K, nq), 1), dtype=torch.uint8, device=dev)
     # the roofline kernel: the fused segmentation kernel, or the label pass
-    rk = "segment" if fused else "label"
+    # (timed inside the step with --path steps; from the untimed per-kernel
+    # pass when the timed ts_segment call runs it among the separate passes)
+    rk = "segment" if kseg else "label"
 
     def step(ev=None, st=None, parts=("pre", "label"), i=0, path=None):
         """One pass of the path over input copy i on stream st (default: the
@@ -901,7 +902,7 @@ def main():
     # histogram's 2), and only in every EV_EVERY-th step: each recorded event
     # adds a few us of gap to the stream
     sampled = list(range(0, args.steps, EV_EVERY))
-    roof_ev = {s: p for s, p in zip(sampled, pairs(len(sampled), [rk]))}
+    roof_ev = {s: p for s, p in zip(sampled, pairs(len(sampled), [rk]))} if kseg or not fused else {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if graphs is not None:
@@ -921,7 +922,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
-    roof_t = avg_us(list(roof_ev.values()), rk) * 1e-6
+    roof_t = avg_us(list(roof_ev.values()), rk) * 1e-6 if roof_ev else None
     if graphs is not None:
         # the same steps launched eagerly (untimed for the record)
         torch.cuda.synchronize()
@@ -955,11 +956,11 @@ def main():
     tuples = len(QS) * nseg * per_problem
     hist_t = per["histogram"]
     label_bytes = (2 + nq) * nvox  # int16 in, one uint8 label per q out
-    avg = roof_t
+    avg = roof_t if roof_t is not None else per["label"]
     # algorithmic bytes: the int16 input once and one label byte per q (the
     # fused kernel's second read of each problem is not algorithmic)
     alg = label_bytes
-    src = "k_search.hip" if fused else "k_label.hip"
+    src = "k_search.hip" if kseg else "k_label.hip"
     achieved = alg / avg / 1e9
     traffic = load_traffic(src, args.workload)
     # correctness guard: every problem found a valid tuple, every label pass wrote labels in [0, K]
@@ -982,10 +983,14 @@ def main():
         "tuples_per_s": tuples * args.steps / dt,
         "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
         "kernel_us_note": "from an untimed pass with events around every kernel (each event adds a gap)",
-        "roofline": {"bound": "hbm", "kernel": "k_segment" if fused else "k_label", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_segment" if kseg else "k_label", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6},
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6,
+                     "timing": ("events around the ts_segment call in every fourth timed step" if kseg else
+                                "events around the label pass in every fourth timed step" if not fused else
+                                "events around the label pass in the untimed per-kernel pass (the timed "
+                                "ts_segment call runs it among the separate passes)")},
         "path": args.path,
         "histogram_gbs": 2 * nvox / hist_t / 1e9,
         "label_gbs": label_bytes / per["label"] / 1e9,

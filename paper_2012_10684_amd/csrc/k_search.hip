@@ -71,7 +71,8 @@ constexpr int FUSED_MAX_TILES = 4096;
 struct Meta {
     int menc;    // ordered-int encoding of the problem's FP32 max key
     float delta; // bound on |key32 - key64 / ln 2|
-    int pad0, pad1;
+    float pthr;  // k = 3: phase 1 skips row groups whose key bound is below this (-inf: none)
+    int pad1;
 };
 
 struct Best {
@@ -475,6 +476,18 @@ __device__ __forceinline__ Steps head_tail32(const Args &a, const QConst &c, con
     return r;
 }
 
+// Ms - 3 delta rounded down; -inf (nothing pruned) unless both are finite.
+__device__ __forceinline__ float prune_threshold(float Ms, float delta)
+{
+    if (!(Ms > -INFINITY) || !(delta < INFINITY))
+        return -INFINITY;
+    const double t64 = (double)Ms - 3.0 * (double)delta;
+    float t = (float)t64;
+    if ((double)t > t64)
+        t = nextafterf(t, -INFINITY);
+    return t;
+}
+
 __global__ void __launch_bounds__(256) k_setup(Args a)
 {
     const int s = blockIdx.x; // problem
@@ -495,11 +508,47 @@ __global__ void __launch_bounds__(256) k_setup(Args a)
     else
         stp = head_tail32<0>(a, c, P, Q, (float *)a.head + (int64_t)s * Lp, (float *)a.tail + (int64_t)s * Lp,
                              a.hl + (int64_t)s * Lp, red);
+    // k = 3 with the FP64 re-check: the largest FP32 key of a coarse grid of
+    // tuples (seeds) gives the threshold below which k_rows3 skips row groups
+    // (rows3_body); the rows written above are visible after the barrier
+    float ms = -INFINITY;
+    if (a.k == 3 && a.mode == TS_SEARCH_FP32_TIECHECK) {
+        __syncthreads();
+        const float *hd = (const float *)a.head + (int64_t)s * Lp, *tl = (const float *)a.tail + (int64_t)s * Lp;
+        const float4 *hl = a.hl + (int64_t)s * Lp;
+        constexpr int G = 16; // grid positions over [0, L - 2]
+        const int S = (L - 1 + G - 1) / G;
+        const int i = threadIdx.x / G, j = threadIdx.x % G;
+        const int t1 = min(i * S + S / 2, L - 2), t2 = min(j * S + S / 2, L - 2);
+        if (i < G && t1 < t2) {
+            const float4 h1 = hl[t1], h2 = hl[t2];
+            const float ar = hd[t1] + (c.sgn > 0 ? cls32<1>(h2, h1, c.mq, c.gmax)
+                                                  : (c.sgn < 0 ? cls32<-1>(h2, h1, c.mq, c.gmax)
+                                                               : cls32<0>(h2, h1, c.mq, c.gmax)));
+            for (int m = j + 1; m < G; ++m) {
+                const int t3 = min(m * S + S / 2, L - 2);
+                if (t3 <= t2)
+                    continue;
+                const float4 h3 = hl[t3];
+                const float g3 = c.sgn > 0 ? cls32<1>(h3, h2, c.mq, c.gmax)
+                                           : (c.sgn < 0 ? cls32<-1>(h3, h2, c.mq, c.gmax)
+                                                        : cls32<0>(h3, h2, c.mq, c.gmax));
+                ms = fmaxf(ms, ar + (g3 + tl[t3])); // the A row term plus the column term, as in phase 1
+            }
+        }
+        ms = wave_max(ms);
+        if ((threadIdx.x & 63) == 0)
+            red[threadIdx.x >> 6] = (double)ms;
+        __syncthreads();
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            ms = fmaxf(ms, (float)red[w]);
+    }
     if (threadIdx.x == 0) {
         Meta m;
         m.menc = float_to_ordered(-INFINITY);
-        m.pad0 = m.pad1 = 0;
+        m.pad1 = 0;
         m.delta = problem_delta(a, c, stp, Q[L - 1]);
+        m.pthr = a.k == 3 && a.mode == TS_SEARCH_FP32_TIECHECK ? prune_threshold(ms, m.delta) : -INFINITY;
         a.meta[s] = m;
     }
     if (a.mode == TS_SEARCH_FP64) {
@@ -1028,10 +1077,31 @@ __device__ __forceinline__ void rows3_body(const Args &a, float *Arow, float *wm
     __syncthreads();
     Cand best = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL};
     float wmax = -INFINITY;
+    // phase 1 skips a group when the largest A of its rows plus the largest
+    // column term of this wavefront is below the seeds' threshold: that sum
+    // bounds every FP32 key of the block (rounded addition is monotone), and
+    // no tuple of it is the arg max or ties with it (the argument of the k = 2
+    // row pruning, k_setup)
+    float pthr = -INFINITY, rmx = -INFINITY;
+    if (PHASE == 1) {
+        pthr = a.meta[s].pthr;
+#pragma unroll
+        for (int v = 0; v < K3_COLS; ++v)
+            rmx = fmaxf(rmx, r[v]);
+        rmx = wave_max(rmx);
+    }
     for (int g = 0; g < ngr; ++g) {
         const int g0 = g * K3_GROUP, g1 = min(n1, g0 + K3_GROUP);
         if (PHASE == 2 && !(gmax_w[g] >= thr))
             continue;
+        if (PHASE == 1 && pthr > -INFINITY) {
+            const float ga = wave_max(lane < K3_GROUP && g0 + lane < g1 ? Arow[g0 + lane] : -INFINITY);
+            if (ga + rmx < pthr) {
+                if (lane == 0)
+                    gmax_w[g] = -INFINITY;
+                continue;
+            }
+        }
         float acc = -INFINITY;
         if (nv > 2)
             rows3_loop<4, PHASE>(x, Arow, g0, g1, r, t2, t3v, thr, acc, best);
@@ -1170,17 +1240,6 @@ __device__ __forceinline__ float seed_key(const TileCtx &x)
     return (x.hd[t1] + cls32<SGN>(x.hl[t2], x.hl[t1], x.mq, x.gmax)) + x.tr[t2]; // as in phase 1
 }
 
-// Ms - 3 delta rounded down; -inf (nothing pruned) unless both are finite.
-__device__ __forceinline__ float prune_threshold(float Ms, float delta)
-{
-    if (!(Ms > -INFINITY) || !(delta < INFINITY))
-        return -INFINITY;
-    const double t64 = (double)Ms - 3.0 * (double)delta;
-    float t = (float)t64;
-    if ((double)t > t64)
-        t = nextafterf(t, -INFINITY);
-    return t;
-}
 
 // Bit t1 % 64 of words[b * (Lp / 64) + t1 / 64] set: row t1 of column block b
 // is skipped (rows without a tuple in the block are marked too).  One

@@ -78,3 +78,22 @@ def test_pruned_on_ct_slices():
         for i in range(H.shape[0]):
             exact, _ = check_choice(H[i], 2, q, t1[i], o1[i], s1[i])
             assert exact
+
+
+@pytest.mark.parametrize("L", [4, 5, 17, 64, 65, 200, 300])
+def test_k3_group_pruning(L):
+    """k = 3: k_rows3 skips row groups whose bound (largest A of the group +
+    largest column term) is below the seeds' threshold; the thresholds must
+    equal those of the FP64 exhaustive mode (no pruning) and the oracle's."""
+    H = np.stack(_shapes(L, 3000 + L))
+    for q in QS:
+        say(f"k=3 pruning L={L} q={q}: {H.shape[0]} histograms")
+        P, Q = api.prefix(to_dev(H.view(np.int32)), q)
+        t1, o1, s1 = (x.cpu().numpy() for x in api.threshold_search(P, Q, 3, q, api.SEARCH_FP32_TIECHECK))
+        t2, o2, s2 = (x.cpu().numpy() for x in api.threshold_search(P, Q, 3, q, api.SEARCH_FP64))
+        torch.cuda.synchronize()
+        assert np.array_equal(t1, t2), (q, t1, t2)
+        assert np.array_equal(s1, s2)
+        mode = oracle.MODE_KAPUR if q == 1.0 else oracle.MODE_PREFIX
+        for i in range(H.shape[0]):
+            check_choice(H[i], 3, q, t1[i], o1[i], s1[i], mode=mode)
