@@ -1,0 +1,13 @@
+// k_morph_r31.hip -- the opening's kernels for disk radii 31..32 (the
+// kernels are in morph_dev.h; one source file per range of radii so that the
+// fully unrolled kernels compile in parallel).
+#include "morph_dev.h"
+
+namespace ts {
+
+bool launch_morph_31_32(int r, dim3 grid, hipStream_t st, const MorphArgs &ero, const MorphArgs &dil)
+{
+    return launch_morph_range<31, 32>(r, grid, st, ero, dil);
+}
+
+} // namespace ts

@@ -1,6 +1,7 @@
 """GPU parity of the morphology step (ts_open2d) against the oracle: the
 opened image and the residue gray - opened bit-exact, for radii 0..32,
 images smaller than a tile or than the disk, sizes that leave ragged tiles,
+images wider than a tile,
 narrow and wide windows, CT-like slices of the workload, and each output
 requested alone."""
 import numpy as np
@@ -38,6 +39,16 @@ def _check(imgs, lo, hi, L, r, want=("opened", "residue")):
 def test_open2d_random_images(r):
     rng = np.random.default_rng(r + 1)
     for H, W in [(1, 1), (3, 200), (64, 64), (70, 129), (130, 65)]:
+        imgs = rng.integers(-1100, 400, (2, H, W)).astype(np.int16)
+        _check(imgs, -1024, 3071, 256, r)
+
+
+@pytest.mark.parametrize("r", [1, 4, 10, 32])
+def test_open2d_wide_images(r):
+    """Images wider than one tile (512 columns): tiles with halo columns on
+    both sides, odd and even widths."""
+    rng = np.random.default_rng(70 + r)
+    for H, W in [(20, 513), (17, 1100), (5, 1026)]:
         imgs = rng.integers(-1100, 400, (2, H, W)).astype(np.int16)
         _check(imgs, -1024, 3071, 256, r)
 
