@@ -844,6 +844,8 @@ def main():
     # fill the chip twice over); otherwise it launches the separate passes
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     kseg = fused and (nseg >= 1024 or nseg >= 2 * cus)
+    # one problem, k = 1, one q: ts_segment's one-launch path (k_small)
+    ksmall = fused and nseg == 1 and K == 1 and nq == 1 and nvox_all <= 4194304
     if fused and args.graph:
         raise SystemExit("--graph replays the separate steps: use it with --path steps")
     # ts_segment's workspace (contents ignored)
@@ -851,7 +853,7 @@ def main():
     # the roofline kernel: the fused segmentation kernel, or the label pass
     # (timed inside the step with --path steps; from the untimed per-kernel
     # pass when the timed ts_segment call runs it among the separate passes)
-    rk = "segment" if kseg else "label"
+    rk = "segment" if kseg or ksmall else "label"
 
     def step(ev=None, st=None, parts=("pre", "label"), i=0, path=None):
         """One pass of the path over input copy i on stream st (default: the
@@ -911,7 +913,7 @@ def main():
     # histogram's 2), and only in every EV_EVERY-th step: each recorded event
     # adds a few us of gap to the stream
     sampled = list(range(0, args.steps, EV_EVERY))
-    roof_ev = {s: p for s, p in zip(sampled, pairs(len(sampled), [rk]))} if kseg or not fused else {}
+    roof_ev = {s: p for s, p in zip(sampled, pairs(len(sampled), [rk]))} if kseg or ksmall or not fused else {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if graphs is not None:
@@ -969,7 +971,7 @@ def main():
     # algorithmic bytes: the int16 input once and one label byte per q (the
     # fused kernel's second read of each problem is not algorithmic)
     alg = label_bytes
-    src = "k_search.hip" if kseg else "k_label.hip"
+    src = "k_search.hip" if kseg or ksmall else "k_label.hip"
     achieved = alg / avg / 1e9
     traffic = load_traffic(src, args.workload)
     # correctness guard: every problem found a valid tuple, every label pass wrote labels in [0, K]
@@ -992,11 +994,12 @@ def main():
         "tuples_per_s": tuples * args.steps / dt,
         "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
         "kernel_us_note": "from an untimed pass with events around every kernel (each event adds a gap)",
-        "roofline": {"bound": "hbm", "kernel": "k_segment" if kseg else "k_label", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_segment" if kseg else "k_small" if ksmall else "k_label",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6,
-                     "timing": ("events around the ts_segment call in every fourth timed step" if kseg else
+                     "timing": ("events around the ts_segment call in every fourth timed step" if kseg or ksmall else
                                 "events around the label pass in every fourth timed step" if not fused else
                                 "events around the label pass in the untimed per-kernel pass (the timed "
                                 "ts_segment call runs it among the separate passes)")},

@@ -106,7 +106,9 @@ enum {
 enum {
     TS_PROBLEM_OK = 0,
     TS_PROBLEM_DEGENERATE = 1, /* no valid tuple: fewer than k+1 occupied bins */
-    TS_PROBLEM_EMPTY = 2       /* the problem has no voxels */
+    TS_PROBLEM_EMPTY = 2,      /* the problem has no voxels */
+    TS_PROBLEM_SYNC_FAILED = 3 /* ts_segment's one-problem path: a wait between its workgroups gave up
+                                  (never expected: the launch keeps them all resident); outputs invalid */
 };
 
 /* [host] Optional launch shapes (NULL, or 0 in a field, selects the built-in
@@ -213,7 +215,14 @@ size_t ts_segment_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_
  * else leaves the chip but the histogram and the results); with several
  * workgroups per problem (tune->segment_parts > 1) the last one to finish
  * counting does the prefix sums and the search, then one label launch.
- * Otherwise the separate passes run, in this one call.
+ * One problem with k = 1, one q and FP32_TIECHECK (up to 4,194,304 voxels,
+ * nbins <= 4096, no tune->segment_parts) runs as one launch of up to 64
+ * workgroups that share the histogram, the prefix sums (each computing one
+ * 64-thread group of the scan in the prefix pass's summation order), the
+ * FP64 objective of every threshold and the labels, with three grid-wide
+ * waits between the stages; status TS_PROBLEM_SYNC_FAILED reports a wait
+ * that gave up (not expected: the workgroups are few enough to be resident
+ * at once).  Otherwise the separate passes run, in this one call.
  *   batch, bin, k, nq, q, mode   as for ts_histogram / ts_threshold_search;
  *   hist    out: uint32 [nseg][L];
  *   thr, obj, status   out: as ts_threshold_search ([nq][nseg][k], [nq][nseg]);

@@ -2051,8 +2051,15 @@ static size_t seg_separate_bytes(int nseg, int L, int k, int nq, int mode)
            search_workspace_bytes(nseg * nq, L, k, mode, 4);
 }
 
+static size_t small_bytes(int L);
+static bool small_path(const ts_batch &b, int L, int k, int nq, int mode, const Tune &t);
+static ts_status launch_small(const ts_batch &b, const BinMap &bm, const double *q, uint32_t *hist, int32_t *thr,
+                              double *obj, int32_t *status, const LabelSets *sets, void *ws, hipStream_t st);
+
 size_t segment_workspace_bytes(int nseg, int L, int k, int nq, int mode, bool labels)
 {
+    if (nseg == 1 && k == 1 && nq == 1 && mode == TS_SEARCH_FP32_TIECHECK && L <= FUSED_MAX_L)
+        return std::max(small_bytes(L), seg_separate_bytes(nseg, L, k, nq, mode));
     if (!seg_fusable(L, k, mode, nq, labels))
         return seg_separate_bytes(nseg, L, k, nq, mode);
     const size_t fused = align256((size_t)nseg * sizeof(unsigned long long)) +
@@ -2098,6 +2105,8 @@ ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, con
 {
     const int L = bm.L, nseg = b.nseg;
     char *wb = (char *)ws;
+    if (small_path(b, L, k, nq, mode, t))
+        return launch_small(b, bm, q, hist, thr, obj, status, sets, ws, st);
     if (!seg_fusable(L, k, mode, nq, sets != nullptr) || !seg_use_fused(nseg, t)) {
         double *P = (double *)wb;
         double *Q = (double *)(wb + align256((size_t)nseg * L * sizeof(double)));
@@ -2191,6 +2200,474 @@ ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, con
     if (sets && parts > 1)
         return launch_label(b, bm, *sets, nq, k, t, st);
     return TS_OK;
+}
+
+// ---------------------------------------------------------------- one small problem
+
+// ts_segment for one problem with one threshold (k = 1, one q) and few
+// voxels, e.g. one slice at 4096 levels: the per-bin work (p^q of every bin,
+// the scans, the objective of every threshold) is spread over many compute
+// units instead of one workgroup.  One cooperative launch of G workgroups
+// (all resident at once) with three grid barriers:
+//   1. each workgroup counts its share of the voxels into LDS and stores its
+//      partial histogram;
+//   2. virtual wavefront v of the prefix scan (the 64 threads of bins
+//      [64 v E, 64 (v + 1) E) in prefix_row's layout, E bins per thread) runs
+//      as wavefront 0 of workgroup v: it adds up the partials of its bins,
+//      forms p^q (the voxel count N is known up front: every voxel falls in
+//      a bin) and the wavefront's part of the scans, and publishes its totals;
+//   3. every virtual wavefront takes the exclusive bases from the totals of
+//      the ones before it in prefix_row's order (so P and Q are the same bits
+//      as the prefix pass), evaluates the FP64 objective of each of its
+//      thresholds with the re-check's own function, and publishes its best;
+// then every workgroup takes the best of the bests (first threshold among
+// equals) and labels its share of the voxels.  The FP64 arg max over every
+// threshold is the tuple the FP32 search with its FP64 re-check returns, and
+// the objective written is computed from the same Lambda by the same code,
+// so every output is bit-identical to the separate passes.  A barrier wait
+// gives up after about a quarter of a second (a cooperative launch keeps
+// every workgroup resident, so it never should) and the problem's status
+// then reports it.
+
+constexpr int SMALL_THREADS = 256;
+constexpr int SMALL_MAX_G = 64;                        // workgroups of one launch
+constexpr int SMALL_MIN_VOX_PER_WG = 8192;             // voxels per workgroup, at least
+constexpr int64_t SMALL_MAX_VOX = (int64_t)SMALL_MAX_G * 65536; // larger problems take the other paths
+constexpr int SMALL_REC = 16;                          // 8-byte words per virtual-wavefront record
+
+struct SmallArgs {
+    const int16_t *const *vox;    // the batch's table (one problem)
+    uint8_t *const *labtab;       // its label table (or null)
+    int64_t n;
+    BinMap bm;
+    int G, E, NWV, lr;
+    uint32_t *hist;          // out [L]
+    uint32_t *part;          // [G][L] partial histograms
+    unsigned long long *rec; // [NWV][SMALL_REC]
+    unsigned long long *bar; // barrier word: (call tag << 32) | arrivals
+    unsigned int epoch;
+};
+
+// Grid barrier number `round` (1, 2, 3) of the launch: every workgroup's
+// device-coherent stores are complete before it arrives; returns false if
+// the wait gave up.
+__device__ __forceinline__ bool small_sync(const SmallArgs &g, int round, int *ok)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // arrival: one fetch-add on (call tag << 32 | arrivals); before the
+        // first barrier a word left by another call (or any contents) is
+        // restarted at (tag, 0) by one exchange, which fails harmlessly once
+        // some workgroup has restarted it (its tag then matches)
+        if (round == 1) {
+            unsigned long long v = __hip_atomic_load(g.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((v >> 32) != (unsigned long long)g.epoch)
+                (void)__hip_atomic_compare_exchange_strong(g.bar, &v, (unsigned long long)g.epoch << 32,
+                                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+        }
+        (void)__hip_atomic_fetch_add(g.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long want = ((unsigned long long)g.epoch << 32) | (unsigned long long)(round * g.G);
+        int spins = 0;
+        for (;;) {
+            const unsigned long long v = __hip_atomic_load(g.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((v >> 32) == (unsigned long long)g.epoch && v >= want)
+                break;
+            if (++spins > (1 << 22)) {
+                *ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    return *ok != 0;
+}
+
+__device__ __forceinline__ void small_put(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long small_get(const unsigned long long *p)
+{
+    return __hip_atomic_load(const_cast<unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Labels of voxels [i0, i1) of the problem (the rules of the label pass).
+__device__ __forceinline__ void small_label(const TS_GLOBAL int16_t *src, TS_GLOBAL uint8_t *dst, int64_t i0,
+                                            int64_t i1, const PCuts<1> &pc)
+{
+    int64_t head = (int64_t)(((16u - ((uintptr_t)(src + i0) & 15u)) & 15u) >> 1);
+    if (head > i1 - i0)
+        head = i1 - i0;
+    const bool vec = (((uintptr_t)(dst + i0 + head)) & 7u) == 0;
+    if (!vec) {
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
+            dst[i] = (uint8_t)lab1p(src[i], pc);
+        return;
+    }
+    if (threadIdx.x < head)
+        dst[i0 + threadIdx.x] = (uint8_t)lab1p(src[i0 + threadIdx.x], pc);
+    const int64_t vb = i0 + head, nvec = (i1 - vb) >> 3;
+    const TS_GLOBAL v4i *vp = reinterpret_cast<const TS_GLOBAL v4i *>(src + vb);
+    TS_GLOBAL v2u *op = reinterpret_cast<TS_GLOBAL v2u *>(dst + vb);
+    const int64_t bd = blockDim.x;
+    for (int64_t i0 = threadIdx.x; i0 < nvec; i0 += 4 * bd) { // four vectors in flight
+        v4i x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            x[e] = i0 + e * bd < nvec ? __builtin_nontemporal_load(vp + i0 + e * bd) : v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (i0 + e * bd < nvec)
+                __builtin_nontemporal_store(lab8(x[e], pc), op + i0 + e * bd);
+    }
+    const int64_t tb = vb + (nvec << 3);
+    if (threadIdx.x < i1 - tb)
+        dst[tb + threadIdx.x] = (uint8_t)lab1p(src[tb + threadIdx.x], pc);
+}
+
+// 64-bit readlane (lane u uniform)
+__device__ __forceinline__ unsigned long long small_rl(unsigned long long v, int u)
+{
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(v & 0xffffffffull), u);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(v >> 32), u);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double small_rlf(double v, int u)
+{
+    return __longlong_as_double((long long)small_rl((unsigned long long)__double_as_longlong(v), u));
+}
+
+template <int MAP>
+__global__ void __launch_bounds__(SMALL_THREADS) k_small(SmallArgs g, Args a, int32_t *__restrict__ thr_out,
+                                                        double *__restrict__ obj, int32_t *__restrict__ status)
+{
+    // LDS: the histogram replicas; after barrier 1: P, Q [L], then for this
+    // virtual wavefront qs, p^q [64 E] and the counts [64 E]
+    extern __shared__ double sdyn[];
+    __shared__ int ok, tstar;
+    __shared__ double wr[SMALL_THREADS / 64], wl[SMALL_THREADS / 64];
+    __shared__ long long wc[SMALL_THREADS / 64];
+    static_assert(SMALL_THREADS / 64 == PREFIX_MAX_E, "one wavefront per bin slot of a prefix thread");
+    const int L = g.bm.L, w = blockIdx.x, lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); // the bin slot e of stages 2 and 3
+    if (threadIdx.x == 0)
+        ok = 1;
+    const TS_GLOBAL int16_t *src = gp(g.vox[0]);
+    // ---- 1. partial histogram of this workgroup's voxels
+    uint32_t *rl = reinterpret_cast<uint32_t *>(sdyn);
+    for (int i = threadIdx.x; i < (L << g.lr); i += blockDim.x)
+        rl[i] = 0u;
+    __syncthreads();
+    const int64_t per = ((g.n + g.G - 1) / g.G + 7) & ~(int64_t)7;
+    const int64_t v0 = min(g.n, (int64_t)w * per), v1 = min(g.n, v0 + per);
+    if (v0 < v1)
+        seg_count<MAP>(rl, g.lr, src, v0, v1, g.bm);
+    __syncthreads();
+    for (int b = threadIdx.x; b < L; b += blockDim.x) {
+        uint32_t c = 0;
+        for (int r = 0; r < (1 << g.lr); ++r)
+            c += rl[(b << g.lr) + r];
+        __hip_atomic_store(g.part + (int64_t)w * L + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    small_sync(g, 1, &ok);
+    const int E = g.E, wb = w * 64 * E;
+    double *Pl = sdyn, *Ql = sdyn + L, *qsl = sdyn + 2 * L, *pql = qsl + 64 * E;
+    uint32_t *cl = reinterpret_cast<uint32_t *>(pql + 64 * E);
+    const QConst &qc = a.qc[0];
+    const double q = qc.q;
+    const uint64_t N = (uint64_t)g.n;
+    const double Nd = (double)N;
+    const bool vw = w < g.NWV;          // workgroup w is virtual wavefront w of the scan (uniform)
+    const int b0 = (w * 64 + lane) * E; // this lane's prefix-thread bins [b0, b0 + E)
+    uint32_t c[PREFIX_MAX_E];
+    double pq[PREFIX_MAX_E];
+    uint64_t cincl = 0;
+    double qincl = 0.0;
+    int oincl = -1;
+    if (vw) {
+        // ---- 2a. wavefront e adds up the partials of bin b0 + e of every
+        // lane (every load in flight at once) and forms its p^q
+        if (wv < E) {
+            const int b = b0 + wv;
+            uint32_t ce = 0;
+            if (b < L) {
+                for (int p0 = 0; p0 < g.G; p0 += 32) {
+                    uint32_t v[32];
+#pragma unroll
+                    for (int u = 0; u < 32; ++u)
+                        v[u] = p0 + u < g.G ? __hip_atomic_load(g.part + (int64_t)(p0 + u) * L + b, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT)
+                                            : 0u;
+#pragma unroll
+                    for (int u = 0; u < 32; ++u)
+                        ce += v[u];
+                }
+                g.hist[b] = ce;
+            }
+            const double pe = (double)ce / Nd;
+            cl[lane * E + wv] = ce;
+            pql[lane * E + wv] = ce ? (q == 1.0 ? pe * log(pe) : pow(pe, q)) : 0.0; // q = 1: the Shannon limit
+        }
+        __syncthreads();
+        // ---- 2b. wavefront 0 is the virtual wavefront: the thread totals of
+        // prefix_row, the wavefront's part of the scans, its record
+        if (wv == 0) {
+            uint64_t csum = 0;
+            int occ = -1;
+            double qloc = 0.0;
+#pragma unroll
+            for (int e = 0; e < PREFIX_MAX_E; ++e) {
+                c[e] = e < E ? cl[lane * E + e] : 0u;
+                pq[e] = e < E ? pql[lane * E + e] : 0.0;
+                csum += c[e];
+                if (c[e])
+                    occ = b0 + e;
+                qloc += pq[e]; // left to right
+            }
+            cincl = csum;
+            qincl = qloc;
+            oincl = occ;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint64_t cv = __shfl_up(cincl, o, 64);
+                const double qv = __shfl_up(qincl, o, 64);
+                const int ov = __shfl_up(oincl, o, 64);
+                if (lane >= o) {
+                    cincl = cv + cincl;
+                    qincl = qv + qincl;
+                    oincl = ov > oincl ? ov : oincl;
+                }
+            }
+            // the record: totals, and what another wavefront needs to rebuild
+            // qs at this wavefront's last occupied bin
+            const unsigned long long occmask = __ballot(occ >= 0);
+            unsigned long long *rv = g.rec + (int64_t)w * SMALL_REC;
+            const double qprev = __shfl_up(qincl, 1, 64); // inclusive q of the lane before
+            const int jl = occmask ? 63 - __builtin_clzll(occmask) : -1; // lane of the last occupied bin
+            if (lane == 63) {
+                small_put(rv + 0, cincl);
+                small_put(rv + 1, (unsigned long long)__double_as_longlong(qincl));
+                small_put(rv + 2, (unsigned long long)(long long)oincl);
+            }
+            if (lane == jl) {
+                double loc = 0.0;
+#pragma unroll
+                for (int e = 0; e < PREFIX_MAX_E; ++e)
+                    if (e < E && b0 + e < L && b0 + e <= occ)
+                        loc += pq[e];
+                small_put(rv + 3, (unsigned long long)jl);
+                small_put(rv + 4, (unsigned long long)__double_as_longlong(qprev));
+                small_put(rv + 5, (unsigned long long)__double_as_longlong(loc));
+            }
+        }
+    }
+    small_sync(g, 2, &ok);
+    if (vw) {
+        if (wv == 0) {
+            // ---- 3a. bases from the virtual wavefronts before this one (lane
+            // u < NWV loads record u; the sequential sums run over readlanes),
+            // P and Q of the wavefront's bins
+            uint64_t rc = 0, r3 = 0, r4 = 0, r5 = 0;
+            long long r2 = -1;
+            double rq = 0.0;
+            if (lane < g.NWV) {
+                const unsigned long long *ru = g.rec + (int64_t)lane * SMALL_REC;
+                rc = small_get(ru + 0);
+                rq = __longlong_as_double((long long)small_get(ru + 1));
+                r2 = (long long)small_get(ru + 2);
+                r3 = small_get(ru + 3);
+                r4 = small_get(ru + 4);
+                r5 = small_get(ru + 5);
+            }
+            const int om = (int)r2;
+            // excl_u = ((0 + t_0) + t_1) + ... + t_(u-1): the scan's sequential order
+            double run = 0.0, excl_mine = 0.0;
+            uint64_t cbase = 0;
+            int obase = -1, lastw = -1;
+            for (int u = 0; u < g.NWV; ++u) {
+                if (lane == u)
+                    excl_mine = run;
+                run = run + small_rlf(rq, u);
+                const int omu = __builtin_amdgcn_readlane(om, u);
+                if (u < w) {
+                    cbase += small_rl(rc, u);
+                    obase = omu > obase ? omu : obase;
+                }
+                if (omu >= 0)
+                    lastw = u;
+            }
+            // qs at the last occupied bin of virtual wavefront u (lane u's view)
+            const double qs_last_mine =
+                ((int)r3 == 0 ? excl_mine : excl_mine + __longlong_as_double((long long)r4)) +
+                __longlong_as_double((long long)r5);
+            const double qbase_w = small_rlf(excl_mine, w);
+            const double qs_before = obase >= 0 ? small_rlf(qs_last_mine, obase / (64 * E)) : 0.0;
+            const double qs_end = lastw >= 0 ? small_rlf(qs_last_mine, lastw) : 0.0;
+            // exclusive lane prefixes within the wavefront
+            const uint64_t cex = __shfl_up(cincl, 1, 64);
+            const double qex = __shfl_up(qincl, 1, 64);
+            const int oex = __shfl_up(oincl, 1, 64);
+            const double qb = lane == 0 ? qbase_w : qbase_w + qex;
+            int last = lane == 0 ? obase : (oex > obase ? oex : obase);
+            uint64_t C = cbase + (lane == 0 ? 0 : cex);
+            double loc = 0.0;
+            int lastocc[PREFIX_MAX_E];
+#pragma unroll
+            for (int e = 0; e < PREFIX_MAX_E; ++e) {
+                lastocc[e] = -1;
+                if (e < E && b0 + e < L) {
+                    const int t = b0 + e;
+                    C += c[e];
+                    loc += pq[e];
+                    if (c[e])
+                        last = t;
+                    Pl[t] = (double)C / Nd;
+                    qsl[t - wb] = qb + loc;
+                    lastocc[e] = last;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+            for (int e = 0; e < PREFIX_MAX_E; ++e) {
+                if (e < E && b0 + e < L) { // Q of the last occupied bin at or before t
+                    const int t = b0 + e, lt = lastocc[e];
+                    Ql[t] = lt < 0 ? 0.0 : (lt >= wb ? qsl[lt - wb] : qs_before);
+                }
+            }
+            if (lane == 0) { // P and Q at L - 1: the whole problem
+                Pl[L - 1] = 1.0;
+                Ql[L - 1] = qs_end;
+            }
+        }
+        __syncthreads();
+        // ---- 3b. wavefront e evaluates threshold b0 + e of every lane with
+        // the re-check's FP64 function; the best of the workgroup
+        double r = -INFINITY, lm = -INFINITY;
+        long long cd = 0x7fffffffffffffffLL;
+        const int t = b0 + wv;
+        if (wv < E && t <= L - 2) {
+            r = lambda64_k<1>(Pl, Ql, L, &t, q, qc.sgn, qc.hmax);
+            lm = r;
+            cd = t;
+        }
+        wave_best(r, lm, cd);
+        if (lane == 0) {
+            wr[wv] = r;
+            wl[wv] = lm;
+            wc[wv] = cd;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Cand best = {-INFINITY, -INFINITY, 0x7fffffffffffffffLL};
+            for (int i = 0; i < SMALL_THREADS / 64; ++i)
+                if (better(wr[i], wc[i], best.r, best.c)) {
+                    best.r = wr[i];
+                    best.l = wl[i];
+                    best.c = wc[i];
+                }
+            unsigned long long *rv = g.rec + (int64_t)w * SMALL_REC;
+            small_put(rv + 6, (unsigned long long)__double_as_longlong(best.r));
+            small_put(rv + 7, (unsigned long long)__double_as_longlong(best.l));
+            small_put(rv + 8, (unsigned long long)best.c);
+        }
+    }
+    const bool synced = small_sync(g, 3, &ok);
+    // ---- the best of the bests (lane u of wavefront 0 loads the best of
+    // virtual wavefront u), the result, the labels
+    if (threadIdx.x < 64) {
+        double r = -INFINITY, l = -INFINITY;
+        long long cd = 0x7fffffffffffffffLL;
+        if (lane < g.NWV) {
+            const unsigned long long *ru = g.rec + (int64_t)lane * SMALL_REC;
+            r = __longlong_as_double((long long)small_get(ru + 6));
+            l = __longlong_as_double((long long)small_get(ru + 7));
+            cd = (long long)small_get(ru + 8);
+        }
+        wave_best(r, l, cd);
+        if (threadIdx.x == 0) {
+            const Cand best = {r, l, cd};
+            tstar = r == -INFINITY ? -1 : (int)cd;
+            if (w == 0) {
+                write_result(best, a, 0, 1.0, thr_out, obj, status);
+                if (!synced)
+                    status[0] = TS_PROBLEM_SYNC_FAILED;
+            }
+        }
+    }
+    __syncthreads();
+    if (g.labtab && v0 < v1) {
+        const int32_t tv[1] = {tstar};
+        const PCuts<1> pc = pack_cuts(make_cuts<1>(tv, 1, g.bm));
+        small_label(src, gpw(g.labtab[0]), v0, v1, pc);
+    }
+}
+
+static size_t small_bytes(int L) { return align256((size_t)SMALL_MAX_G * L * sizeof(uint32_t)) + align256((size_t)16 * SMALL_REC * 8) + 256; }
+
+// Whether ts_segment takes the one-problem cooperative path.
+static bool small_path(const ts_batch &b, int L, int k, int nq, int mode, const Tune &t)
+{
+    return b.nseg == 1 && k == 1 && nq == 1 && mode == TS_SEARCH_FP32_TIECHECK && L <= FUSED_MAX_L &&
+           b.total > 0 && b.total <= SMALL_MAX_VOX && !t.segment_parts;
+}
+
+static ts_status launch_small(const ts_batch &b, const BinMap &bm, const double *q, uint32_t *hist, int32_t *thr,
+                              double *obj, int32_t *status, const LabelSets *sets, void *ws, hipStream_t st)
+{
+    const int L = bm.L;
+    SmallArgs g = {};
+    g.vox = b.vox;
+    g.labtab = sets ? sets->out[0] : nullptr;
+    g.n = b.total;
+    g.bm = bm;
+    g.E = prefix_bins_per_thread(L);
+    g.NWV = prefix_threads(L) / 64;
+    g.G = (int)std::max<int64_t>(g.NWV, std::min<int64_t>(SMALL_MAX_G, (b.total + SMALL_MIN_VOX_PER_WG - 1) /
+                                                                              SMALL_MIN_VOX_PER_WG));
+    g.lr = L <= 1024 ? 2 : 0;
+    g.hist = hist;
+    char *wb = (char *)ws;
+    g.part = (uint32_t *)wb;
+    g.rec = (unsigned long long *)(wb + align256((size_t)SMALL_MAX_G * L * sizeof(uint32_t)));
+    g.bar = g.rec + 16 * SMALL_REC;
+    {
+        static std::atomic<unsigned int> seq{(unsigned int)std::chrono::steady_clock::now().time_since_epoch().count() ^
+                                             0x5a5a5a5au};
+        unsigned int e;
+        do
+            e = ++seq;
+        while (e == 0);
+        g.epoch = e;
+    }
+    Args a = {};
+    a.nseg = 1;
+    a.nprob = 1;
+    a.L = L;
+    a.Lp = L;
+    a.k = 1;
+    a.mode = TS_SEARCH_FP32_TIECHECK;
+    for (int j = 0; j < TS_MAX_Q; ++j)
+        a.qc[j] = make_qconst(q[0], L);
+    const size_t lds = std::max((size_t)(L << g.lr) * sizeof(uint32_t),
+                                (size_t)(2 * L + 2 * 64 * g.E) * sizeof(double) + (size_t)64 * g.E * sizeof(uint32_t));
+    const dim3 grid((unsigned)g.G), blk(SMALL_THREADS);
+#define TS_SMALL(M)                                                                                                 \
+    if (lds > 64 * 1024)                                                                                            \
+        (void)hipFuncSetAttribute((const void *)k_small<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    hipLaunchKernelGGL(k_small<M>, grid, blk, lds, st, g, a, thr, obj, status)
+    switch (map_kind(bm)) {
+    case 0: TS_SMALL(0); break;
+    case 1: TS_SMALL(1); break;
+    case 2: TS_SMALL(2); break;
+    default: TS_SMALL(3); break;
+    }
+#undef TS_SMALL
+    return check_launch("ts_segment");
 }
 
 // ---------------------------------------------------------------- dispatch

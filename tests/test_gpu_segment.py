@@ -166,3 +166,66 @@ def test_without_labels(slices):
     torch.cuda.synchronize()
     assert got[2] is None
     _same(got, want, "no labels")
+
+
+def _one_problem_inputs():
+    """One problem per entry: a workload slice, a constant image, tiny and
+    ragged sizes at odd element offsets (2-byte aligned), four slices."""
+    rng = np.random.default_rng(11)
+    img = synth.workload_slice(0).reshape(-1)
+    buf = rng.normal(-300, 700, 70000).clip(-1024, 3071).astype(np.int16)
+    buf[::97] = -32768
+    buf[5::101] = 32767
+    four = synth.workload_volume300(0)[:4].reshape(-1)
+    return [("slice", img), ("constant", np.full(5000, -600, np.int16)), ("one", buf[3:4]),
+            ("nine", buf[3:12]), ("ragged", buf[3:65542]), ("four slices", four)]
+
+
+@pytest.mark.parametrize("L,lo,hi", [(4096, -1024, 3071), (1000, -1024, 3071), (256, -1024, -200), (13, -5, 7),
+                                     (2, -1024, 3071)])
+@pytest.mark.parametrize("q", [0.5, 0.8, 1.0, 3.0])
+def test_one_problem_path(L, lo, hi, q):
+    """ts_segment for one problem, k = 1, one q (the cooperative path that
+    spreads the prefix sums and the search over many workgroups) against the
+    separate calls bit for bit, labels included; with and without labels."""
+    binn = api.binning(lo, hi, L)
+    for name, v in _one_problem_inputs():
+        dv = to_dev(np.ascontiguousarray(v))
+        b = api.Batch([dv])
+        say(f"one-problem path L={L} q={q} {name} ({v.size} voxels)")
+        got = api.segment(b, binn, 1, q)
+        want = _steps(b, binn, 1, [q])
+        torch.cuda.synchronize()
+        want = (want[0], tuple(x[0] for x in want[1]), want[2])
+        _same(got, want, (L, q, name))
+        nolab = api.segment(b, binn, 1, q, labels=False)
+        torch.cuda.synchronize()
+        assert nolab[2] is None
+        _same((nolab[0], nolab[1], None), (want[0], want[1], None), (L, q, name, "no labels"))
+        if name == "constant":
+            assert got[1][2].item() == api.PROBLEM_DEGENERATE
+
+
+def test_one_problem_path_oracle_and_reuse():
+    """The one-problem path against the oracle, and one workspace of any
+    contents reused over calls of different sizes (the barrier word carries
+    each call's tag)."""
+    img = synth.workload_slice(1)
+    binn = api.binning(-1024, 3071, 4096)
+    dv = to_dev(img.reshape(-1))
+    need = api.segment_workspace_bytes(1, 4096, 1, 1)
+    ws = torch.full((need,), 0xFF, dtype=torch.uint8, device=dv.device)
+    h = oracle.histogram(img, -1024, 3071, 4096)
+    for n, junk in [(img.size, False), (1000, True), (img.size, True), (77777, False), (img.size, False)]:
+        say(f"one-problem path reuse: {n} voxels, junk {junk}")
+        if junk:
+            ws.random_(0, 256)
+        b = api.Batch([dv[:n]])
+        got = api.segment(b, binn, 1, 0.8, ws=ws)
+        want = _steps(b, binn, 1, [0.8])
+        torch.cuda.synchronize()
+        _same(got, (want[0], tuple(x[0] for x in want[1]), want[2]), (n, junk))
+    got = api.segment(api.Batch([dv]), binn, 1, 0.8, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(got[0].cpu().numpy().view(np.uint32)[0], h)
+    check_choice(h, 1, 0.8, got[1][0].cpu().numpy()[0], got[1][1].item(), got[1][2].item())
