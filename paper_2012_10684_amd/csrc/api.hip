@@ -29,6 +29,23 @@ ts_status check_launch(const char *what)
     return TS_OK;
 }
 
+void allow_dynamic_lds(const void *fn, size_t bytes)
+{
+    if (bytes <= 64 * 1024)
+        return;
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, size_t> set; // (device, kernel) -> bytes allowed
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const uint64_t key = ((uint64_t)(uint32_t)dev << 48) ^ (uint64_t)(uintptr_t)fn;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = set.find(key);
+    if (it != set.end() && it->second >= bytes)
+        return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        set[key] = bytes;
+}
+
 int device_cu_count()
 {
     static std::mutex mu;

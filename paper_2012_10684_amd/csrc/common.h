@@ -22,6 +22,10 @@ void set_error(const std::string &msg);
 ts_status fail(ts_status st, const std::string &msg);
 ts_status check_launch(const char *what);
 int device_cu_count();
+// Let kernel fn use `bytes` of dynamic LDS (more than the default 64 KiB) on
+// the current device: the attribute is set once per kernel and device and
+// kept (setting it on every launch stalled the host behind queued work).
+void allow_dynamic_lds(const void *fn, size_t bytes);
 
 // ---------------------------------------------------------------- tuning
 struct Tune {

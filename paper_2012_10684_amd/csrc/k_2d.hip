@@ -218,7 +218,7 @@ ts_status launch_hist2d(const ts_batch &b, int H, int W, const BinMap &bm, uint3
     const int bands = (H + rows - 1) / rows;
     const dim3 g((unsigned)((int64_t)b.nseg * bands)), blk(H2_THREADS);
 #define TS_H2(M)                                                                                                    \
-    (void)hipFuncSetAttribute((const void *)k_hist2d<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+    allow_dynamic_lds((const void *)k_hist2d<M>, lds);                                                            \
     hipLaunchKernelGGL(k_hist2d<M>, g, blk, lds, st, b.vox, b.nseg, H, W, rows, chunk, bm, hist)
     switch (map_kind(bm)) {
     case 0: TS_H2(0); break;

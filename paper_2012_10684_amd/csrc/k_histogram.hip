@@ -155,9 +155,7 @@ template <int R, int MAP>
 static void launch_rm(int grid, int block, size_t lds, hipStream_t st, const ts_batch &b, int64_t chunk,
                       const BinMap &bm, uint32_t *hist)
 {
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_histogram<R, MAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+    allow_dynamic_lds((const void *)k_histogram<R, MAP>, lds);
     hipLaunchKernelGGL((k_histogram<R, MAP>), dim3(grid), dim3(block), lds, st, b.vox, b.offs, b.nseg, b.total,
                        chunk, bm, hist);
 }

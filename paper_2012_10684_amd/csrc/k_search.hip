@@ -2093,9 +2093,7 @@ template <int K, int MAP>
 static void launch_seg_km(dim3 g, dim3 b, size_t lds, hipStream_t st, const SegArgs &sa, const Args &a, int32_t *thr,
                           double *obj, int32_t *status)
 {
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_segment<K, MAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+    allow_dynamic_lds((const void *)k_segment<K, MAP>, lds);
     hipLaunchKernelGGL((k_segment<K, MAP>), g, b, lds, st, sa, a, thr, obj, status);
 }
 
@@ -2231,7 +2229,7 @@ ts_status launch_segment(const ts_batch &b, const BinMap &bm, int k, int nq, con
 
 constexpr int SMALL_THREADS = 256;
 constexpr int SMALL_MAX_G = 64;                        // workgroups of one launch
-constexpr int SMALL_MIN_VOX_PER_WG = 8192;             // voxels per workgroup, at least
+constexpr int SMALL_MIN_VOX_PER_WG = 16384;            // voxels per workgroup, at least
 constexpr int64_t SMALL_MAX_VOX = (int64_t)SMALL_MAX_G * 65536; // larger problems take the other paths
 constexpr int SMALL_REC = 16;                          // 8-byte words per virtual-wavefront record
 
@@ -2657,8 +2655,7 @@ static ts_status launch_small(const ts_batch &b, const BinMap &bm, const double 
                                 (size_t)(2 * L + 2 * 64 * g.E) * sizeof(double) + (size_t)64 * g.E * sizeof(uint32_t));
     const dim3 grid((unsigned)g.G), blk(SMALL_THREADS);
 #define TS_SMALL(M)                                                                                                 \
-    if (lds > 64 * 1024)                                                                                            \
-        (void)hipFuncSetAttribute((const void *)k_small<M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    allow_dynamic_lds((const void *)k_small<M>, lds);                                                              \
     hipLaunchKernelGGL(k_small<M>, grid, blk, lds, st, g, a, thr, obj, status)
     switch (map_kind(bm)) {
     case 0: TS_SMALL(0); break;
