@@ -355,6 +355,8 @@ ts_status ts_threshold_search_dp(const double *P, const double *Q, int32_t nseg,
 
 /* Largest disk radius ts_open2d takes. */
 #define TS_MORPH_MAX_RADIUS 32
+/* Largest image ts_open2d takes, in pixels (its int16 bytes fit a signed 32-bit offset). */
+#define TS_MORPH_MAX_PIXELS 1073741823
 
 /* [host] Bytes of workspace ts_open2d needs: one byte per pixel. */
 size_t ts_open2d_workspace_bytes(int32_t nseg, int32_t height, int32_t width);
@@ -379,7 +381,8 @@ size_t ts_open2d_workspace_bytes(int32_t nseg, int32_t height, int32_t width);
  *             binning {0, nbins-1, nbins} (each level its own bin), so the
  *             threshold is selected on the image after the morphology step,
  *             as the paper's segmentation does (at least one output).
- * Errors: TS_ERR_INVALID_ARG, TS_ERR_WORKSPACE. */
+ * Errors: TS_ERR_INVALID_ARG (also for an image of more than
+ * TS_MORPH_MAX_PIXELS pixels), TS_ERR_WORKSPACE. */
 ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bin, int32_t radius, void *ws,
                     size_t ws_bytes, uint8_t *opened, uint8_t *residue, int16_t *residue16, ts_stream_t stream);
 

@@ -598,6 +598,9 @@ ts_status ts_open2d(ts_batch batch, int32_t height, int32_t width, ts_binning bi
         return fail(TS_ERR_INVALID_ARG, "ts_open2d: radius must be in 0.." + std::to_string(TS_MORPH_MAX_RADIUS));
     if (height < 1 || width < 1)
         return fail(TS_ERR_INVALID_ARG, "ts_open2d: need height >= 1 and width >= 1");
+    if ((int64_t)height * width > TS_MORPH_MAX_PIXELS)
+        return fail(TS_ERR_INVALID_ARG, "ts_open2d: more than " + std::to_string((long long)TS_MORPH_MAX_PIXELS) +
+                                            " pixels in one image");
     if (batch.total != (int64_t)batch.nseg * height * width)
         return fail(TS_ERR_INVALID_ARG, "ts_open2d: total must be nseg * height * width");
     if (batch.nseg > 0 && !opened && !residue && !residue16)

@@ -123,7 +123,7 @@ def test_workspace_sizes(lib):
     ("h2d_bins", 1), ("h2d_width", 1), ("h2d_total", 1), ("h2d_null", 1),
     ("s2d_bins", 1), ("s2d_q", 1), ("s2d_ws", 3), ("s2d_null", 1),
     ("open_bins", 1), ("open_radius", 1), ("open_radius_neg", 1), ("open_total", 1), ("open_no_output", 1),
-    ("open_ws", 3), ("open_height", 1),
+    ("open_ws", 3), ("open_height", 1), ("open_huge", 1),
     ("dp_k0", 1), ("dp_k17", 1), ("dp_bins_lt_k1", 1), ("dp_q", 1), ("dp_ws", 3), ("dp_null", 1), ("dp_misaligned", 1),
     ("seg_k4", 1), ("seg_ws", 3), ("seg_nq5_labels", 1), ("seg_null_hist", 1), ("seg_null_out_entry", 1),
     ("seg_bad_parts", 1), ("seg_bad_block", 1), ("seg_q", 1), ("seg_bins", 3),
@@ -199,9 +199,13 @@ def test_argument_errors(lib, case, expect):
         if case == "open_total":
             b = Batch(FAKE, FAKE, 2, 83)
         Hh = 0 if case == "open_height" else 6
-        ws_bytes = 10 if case == "open_ws" else 1 << 30
+        Ww = 7
+        if case == "open_huge":  # one image of 2^30 pixels: beyond TS_MORPH_MAX_PIXELS
+            Hh, Ww = 1 << 15, 1 << 15
+            b = Batch(FAKE, FAKE, 1, Hh * Ww)
+        ws_bytes = 10 if case == "open_ws" else 1 << 31
         outs = (None, None) if case == "open_no_output" else (FAKE, None)
-        st = lib.ts_open2d(b, Hh, 7, binning, r, FAKE, ws_bytes, outs[0], outs[1], None, sx)
+        st = lib.ts_open2d(b, Hh, Ww, binning, r, FAKE, ws_bytes, outs[0], outs[1], None, sx)
     elif case.startswith("dp_"):
         k = {"dp_k0": 0, "dp_k17": 17}.get(case, 5)
         L = 5 if case == "dp_bins_lt_k1" else 512
