@@ -94,6 +94,15 @@ __device__ __forceinline__ TS_GLOBAL T *gpw(T *p)
     return (TS_GLOBAL T *)p;
 }
 
+// Workgroup barrier that orders LDS accesses only: global stores and atomics
+// issued before it stay in flight (__syncthreads also waits for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------- batch walk
 // Index of the problem containing flattened position pos: the largest s with
 // offs[s] <= pos (binary search; offs non-decreasing, nseg >= 1).

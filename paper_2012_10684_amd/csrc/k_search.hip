@@ -1390,7 +1390,7 @@ __device__ __forceinline__ long long fused_body(const Args &a, FusedLds &sh, int
         write_result(best, a, s, P[a.L - 1], thr_out, obj, status);
         sh.code = best.r == -INFINITY ? -1LL : best.c;
     }
-    __syncthreads();
+    lds_barrier(); // the result's global stores need not land before the workgroup goes on
     return sh.code;
 }
 
