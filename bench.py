@@ -1022,9 +1022,11 @@ def main():
     if K <= 2:
         line["search_roofline"] = search_roofline(rates, tuples, 2, per["search"])
     if args.workload == "volume600":
-        # the plain GPU form (one thread per tuple, FP64, one launch per
-        # problem) and the FP64 exhaustive mode, for the speed-up of the search
-        for name, mode in (("plain_fp64", api.SEARCH_PLAIN), ("fp64", api.SEARCH_FP64)):
+        # the plain GPU form (one thread per tuple, one launch per problem, in
+        # FP64 and in FP32) and the FP64 exhaustive mode, for the speed-up of
+        # the search
+        for name, mode in (("plain_fp64", api.SEARCH_PLAIN), ("plain_fp32", api.SEARCH_PLAIN_FP32),
+                           ("fp64", api.SEARCH_FP64)):
             ws2 = torch.empty(api.workspace_bytes(nseg, L, K, mode, nq), dtype=torch.uint8, device=dev)
             out2 = tuple(torch.empty_like(r) for r in res)
             api.threshold_search(P, Q, K, QS, mode, ws=ws2, out=out2, stream=stream)

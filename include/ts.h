@@ -96,10 +96,15 @@ enum {
     TS_SEARCH_FP64 = 2,          /* FP64 exhaustive keys */
     TS_SEARCH_PLAIN = 3,         /* one thread per tuple, all classes evaluated directly in
                                     FP64, one launch per problem: the simple GPU form */
-    TS_SEARCH_SUMPROD = 4        /* a different objective: the multilevel form
+    TS_SEARCH_SUMPROD = 4,       /* a different objective: the multilevel form
                                     sum_j S_j + (1-q) prod_j S_j of the class entropies
                                     (equal to the paper's for k = 1), FP64 exhaustive, all
                                     problems in one launch; obj is that value */
+    TS_SEARCH_PLAIN_FP32 = 5     /* one thread per tuple, every class term evaluated directly in
+                                    FP32 (the keys of TS_SEARCH_FP32_ONLY, from the prefix sums
+                                    split into two floats), one launch per problem: the simple
+                                    GPU form in single precision; the first tuple with the
+                                    largest key; obj is its FP64 objective */
 };
 
 /* Per-problem outcome written by ts_threshold_search. */

@@ -30,7 +30,7 @@ LIB_PATH = os.environ.get("TS_LIBRARY", os.path.join(_HERE, "libts.so"))
 ABI_VERSION = 3
 MAX_Q = 8
 TS_OK, TS_ERR_INVALID_ARG, TS_ERR_UNSUPPORTED, TS_ERR_WORKSPACE, TS_ERR_HIP = 0, 1, 2, 3, 4
-SEARCH_FP32_TIECHECK, SEARCH_FP32_ONLY, SEARCH_FP64, SEARCH_PLAIN, SEARCH_SUMPROD = 0, 1, 2, 3, 4
+SEARCH_FP32_TIECHECK, SEARCH_FP32_ONLY, SEARCH_FP64, SEARCH_PLAIN, SEARCH_SUMPROD, SEARCH_PLAIN_FP32 = 0, 1, 2, 3, 4, 5
 PROBLEM_OK, PROBLEM_DEGENERATE, PROBLEM_EMPTY, PROBLEM_SYNC_FAILED = 0, 1, 2, 3
 
 

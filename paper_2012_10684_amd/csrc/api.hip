@@ -272,7 +272,7 @@ ts_status ts_prefix(const uint32_t *hist, int32_t nseg, int32_t nbins, int32_t n
 size_t ts_search_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq, int32_t mode)
 {
     if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || k < 1 || k > 3 || nq < 1 || nq > TS_MAX_Q || mode < 0 ||
-        mode > TS_SEARCH_SUMPROD)
+        mode > TS_SEARCH_PLAIN_FP32)
         return 0;
     return search_workspace_bytes(nseg * nq, nbins, k, mode, 4);
 }
@@ -293,7 +293,7 @@ ts_status check_search_args(const char *fn, const double *P, const double *Q, in
         return fail(TS_ERR_INVALID_ARG, f + ": k must be 1, 2 or 3");
     if (nbins < k + 1)
         return fail(TS_ERR_INVALID_ARG, f + ": nbins must be >= k + 1");
-    if (mode < 0 || mode > TS_SEARCH_SUMPROD)
+    if (mode < 0 || mode > TS_SEARCH_PLAIN_FP32)
         return fail(TS_ERR_INVALID_ARG, f + ": unknown mode");
     ts_status st;
     if ((st = check_q(fn, nq, q, true)) != TS_OK)
@@ -439,7 +439,7 @@ ts_status ts_label_sets(ts_batch batch, ts_binning bin, int32_t nsets, const int
 size_t ts_segment_workspace_bytes(int32_t nseg, int32_t nbins, int32_t k, int32_t nq, int32_t mode, int32_t labels)
 {
     if (nseg < 0 || nbins < 2 || nbins > MAX_BINS || nbins < k + 1 || k < 1 || k > 3 || nq < 1 || nq > TS_MAX_Q ||
-        mode < 0 || mode > TS_SEARCH_SUMPROD || (labels && nq > TS_MAX_LABEL_SETS))
+        mode < 0 || mode > TS_SEARCH_PLAIN_FP32 || (labels && nq > TS_MAX_LABEL_SETS))
         return 0;
     return segment_workspace_bytes(nseg, nbins, k, nq, mode, labels != 0);
 }

@@ -159,10 +159,10 @@ static Plan make_plan(int nseg, int L, int k, int mode, int cols, int T1)
     if (mode == TS_SEARCH_FP32_TIECHECK || mode == TS_SEARCH_FP32_ONLY)
         o = align256(o + (size_t)nseg * p.tiles * (k == 3 ? p.T1 : 1) * sizeof(float));
     p.off_best = o;
-    if (mode != TS_SEARCH_PLAIN && mode != TS_SEARCH_SUMPROD)
+    if (mode != TS_SEARCH_PLAIN && mode != TS_SEARCH_PLAIN_FP32 && mode != TS_SEARCH_SUMPROD)
         o = align256(o + (size_t)nseg * p.tiles * sizeof(Best));
     p.off_plain = o;
-    if (mode == TS_SEARCH_PLAIN)
+    if (mode == TS_SEARCH_PLAIN || mode == TS_SEARCH_PLAIN_FP32)
         o = align256(o + (size_t)PLAIN_BLOCKS * sizeof(Best));
     if (mode == TS_SEARCH_SUMPROD)
         o = align256(o + (size_t)nseg * sumprod_blocks(L, k) * sizeof(Best));
@@ -1618,6 +1618,67 @@ __global__ void __launch_bounds__(256) k_plain(const double *__restrict__ P, con
     }
 }
 
+// The plain GPU form in single precision: one thread per tuple (unranked as
+// in k_plain), every class term evaluated directly in FP32 from the prefix
+// sums split into two floats (cls32, the keys of the FP32 modes); the first
+// tuple with the largest key, and its FP64 Lambda beside it for the result.
+template <int SGN>
+__global__ void __launch_bounds__(256) k_plain32(const double *__restrict__ P, const double *__restrict__ Q, int L,
+                                                 int k, int64_t ntup, QConst c, Best *__restrict__ out)
+{
+    float bk = -INFINITY;
+    long long bc = 0x7fffffffffffffffLL;
+    int bt[3] = {0, 0, 0};
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ntup;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int t[3] = {0, 0, 0};
+        int64_t v = r;
+        for (int j = k; j >= 1; --j) {
+            const int64_t x = inv_binom(v, j);
+            t[j - 1] = (int)x;
+            v -= binom(x, j);
+        }
+        float key = 0.0f;
+        float4 ha = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int j = 0; j <= k; ++j) {
+            const int b = j == k ? L - 1 : t[j];
+            const float4 hb = split_hl(P[b], Q[b]);
+            key += cls32<SGN>(hb, ha, c.mq, c.gmax);
+            ha = hb;
+        }
+        const long long code = make_code(k, t);
+        if (key > bk || (key == bk && code < bc)) {
+            bk = key;
+            bc = code;
+            bt[0] = t[0];
+            bt[1] = t[1];
+            bt[2] = t[2];
+        }
+    }
+    double rank = (double)bk, lam = -INFINITY;
+    if (bk > -INFINITY)
+        lam = lambda64(P, Q, L, k, bt, c.q, c.sgn, c.hmax);
+    wave_best(rank, lam, bc);
+    __shared__ double sr[4], sl[4];
+    __shared__ long long sc[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sr[w] = rank;
+        sl[w] = lam;
+        sc[w] = bc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+            if (better(sr[i], sc[i], rank, bc)) {
+                rank = sr[i];
+                lam = sl[i];
+                bc = sc[i];
+            }
+        out[blockIdx.x] = Best{rank, lam, bc, 0};
+    }
+}
+
 // ---------------------------------------------------------------- sum-product variant
 
 // The multilevel variant sum_j S_j + (1-q) prod_j S_j of one tuple in FP64
@@ -2779,6 +2840,24 @@ ts_status launch_search(const double *P, const double *Q, int nseg, int L, int k
                            pb);
         hipLaunchKernelGGL(k_final, dim3((unsigned)nprob), dim3(1024), 0, st, a, pb, per, thr, obj, status, 0);
         return check_launch("ts_threshold_search (sum-product)");
+    }
+    if (mode == TS_SEARCH_PLAIN_FP32) {
+        const int64_t n = L - 1;
+        const int64_t ntup = k == 1 ? n : (k == 2 ? n * (n - 1) / 2 : n * (n - 1) * (n - 2) / 6);
+        const int blocks = (int)std::min<int64_t>(PLAIN_BLOCKS, std::max<int64_t>(1, (ntup + 255) / 256));
+        Best *pb = (Best *)(base + p.off_plain);
+        for (int s = 0; s < nprob; ++s) {
+            const QConst &c = a.qc[s / nseg];
+            const double *Ps = P + (int64_t)(s % nseg) * L, *Qs = Q + (int64_t)s * L;
+            if (c.sgn > 0)
+                hipLaunchKernelGGL(k_plain32<1>, dim3(blocks), dim3(256), 0, st, Ps, Qs, L, k, ntup, c, pb);
+            else if (c.sgn < 0)
+                hipLaunchKernelGGL(k_plain32<-1>, dim3(blocks), dim3(256), 0, st, Ps, Qs, L, k, ntup, c, pb);
+            else
+                hipLaunchKernelGGL(k_plain32<0>, dim3(blocks), dim3(256), 0, st, Ps, Qs, L, k, ntup, c, pb);
+            hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, st, a, pb, blocks, thr, obj, status, s);
+        }
+        return check_launch("ts_threshold_search (plain FP32)");
     }
     if (mode == TS_SEARCH_PLAIN) {
         const int64_t n = L - 1;

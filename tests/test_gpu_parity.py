@@ -261,6 +261,31 @@ def test_search_fp32_only_mode_is_close():
         assert abs(obj[i] - s) <= 1e-10 * abs(s)  # reported value is the FP64 objective of that tuple
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("q", [0.5, 1.0, 1.5])
+def test_search_plain_fp32_mode_is_close(k, q):
+    """The plain form in FP32 (one thread per tuple, every class term in
+    FP32): near-optimal against the oracle, its reported objective the FP64
+    value of its own tuple, and the statuses of the exact modes (an empty
+    and a one-bin histogram included)."""
+    rng = np.random.default_rng(31 + k + int(10 * q))
+    L = {1: 300, 2: 130, 3: 40}[k]
+    H = _random_hists(rng, 5, L, zero_frac=0.1, hi=10000)
+    H[3] = 0
+    H[4] = 0
+    H[4][7] = 50
+    thr, obj, st = _search_all(H, k, q, api.SEARCH_PLAIN_FP32)
+    _, _, st_ref = _search_all(H, k, q, api.SEARCH_PLAIN)
+    assert np.array_equal(st, st_ref), (st, st_ref)
+    assert st[3] == api.PROBLEM_EMPTY and st[4] == api.PROBLEM_DEGENERATE
+    om = oracle.MODE_KAPUR if q == 1.0 else oracle.MODE_PREFIX  # q = 1: the Shannon limit
+    for i in range(3):
+        r = oracle.search(H[i], k, q, mode=om)
+        s = oracle.objective(H[i], thr[i], q, mode=om)
+        assert s >= r.obj - 1e-4 * abs(r.obj), (k, q, i, thr[i], r.thr)
+        assert abs(obj[i] - s) <= 1e-10 * abs(s), (k, q, i)
+
+
 def test_label_ragged(ragged):
     host, base, segs = ragged
     rng = np.random.default_rng(3)
