@@ -102,8 +102,10 @@ def test_workspace_sizes(lib):
     assert ws(1, 1024, 3, 1, 2) >= 2 * 1024 * 1024 * 8  # FP64 rows
     assert ws(10, 256, 2, 1, 0) > ws(5, 256, 2, 1, 0)
     assert ws(100, 256, 2, 3, 0) == ws(300, 256, 2, 1, 0)  # nq x nseg problems
+    # the plain forms (FP64: mode 3, FP32: mode 5) keep one best per block of tuples
+    assert ws(1, 1024, 3, 1, 5) == ws(1, 1024, 3, 1, 3) > 0
     for bad in [(-1, 256, 1, 1, 0), (1, 1, 1, 1, 0), (1, 4097, 1, 1, 0), (1, 256, 0, 1, 0), (1, 256, 4, 1, 0),
-                (1, 256, 1, 1, 7), (1, 256, 1, 0, 0), (1, 256, 1, 9, 0)]:
+                (1, 256, 1, 1, 6), (1, 256, 1, 1, 7), (1, 256, 1, 0, 0), (1, 256, 1, 9, 0)]:
         assert ws(*bad) == 0, bad
     dpws = lib.ts_search_dp_workspace_bytes
     assert dpws(1, 1024, 4, 1) == 4 * 1024 * 8 and dpws(300, 256, 2, 3) == 2 * 900 * 256 * 8
