@@ -31,6 +31,7 @@ import hashlib
 import math
 import json
 import os
+import re
 import sys
 import time
 
@@ -244,12 +245,13 @@ def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload, 
              f"workload {workload}", f"command: {command}",
              f"calibration: {ck[0]} copying 256 MiB reads FETCH_SIZE {cf[ck[0]][1]:.0f} KiB (factor {f_fac:.3f}), "
              f"WRITE_SIZE {cw[ck[0]][1]:.0f} KiB (factor {w_fac:.3f})", ""]
-    best = {}
+    best, every = {}, {}
     for name in sorted(set(fe) & set(wr), key=lambda n: -(fe[n][1] * f_fac + wr[n][1] * w_fac)):
         f = kernel_file(name)
         rb, wb = fe[name][1] * 1024.0 * f_fac, wr[name][1] * 1024.0 * w_fac
         if f is None:
             continue
+        every.setdefault(f, {})[short_name(name, 200)] = rb + wb
         lines.append(f"{short_name(name, 40):<40} read {rb / 1e6:>10.2f} MB  write {wb / 1e6:>10.2f} MB  per launch "
                      f"({fe[name][0]} launches)  src {src_hash(f)}")
         if f not in best:
@@ -257,6 +259,8 @@ def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload, 
             rec[f"{f}:{workload}"] = {"kernel": short_name(name, 200), "src_sha": src_hash(f), "workload": workload,
                                       "bytes_per_launch": rb + wb, "read_bytes": rb, "write_bytes": wb,
                                       "launches": fe[name][0]}
+    for f, kernels in every.items():  # bytes per launch of every kernel of that source
+        rec[f"{f}:{workload}"]["kernels"] = kernels
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return "\n".join(lines) + "\n"
@@ -299,18 +303,50 @@ def parse():
     return ap.parse_args()
 
 
+def src_files(name: str):
+    """A kernel source file and every file it includes with #include "...",
+    followed transitively (paths relative to the kernel sources' folder,
+    the source first, then the rest sorted)."""
+    d = os.path.join(ROOT, "paper_2012_10684_amd", "csrc")
+    seen, todo = set(), [os.path.normpath(name)]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        with open(os.path.join(d, f)) as fh:
+            for line in fh:
+                m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+                if m:
+                    todo.append(os.path.normpath(os.path.join(os.path.dirname(f), m.group(1))))
+    first = os.path.normpath(name)
+    return [first] + sorted(seen - {first})
+
+
+def code_text(text: str) -> str:
+    """C/C++ source without its comments and with every run of white space
+    made one blank: what the compiler sees of it (a // inside a string
+    literal also ends the text of its line; it only makes the hash blind to
+    the rest of that string)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def src_hash(name: str) -> str:
-    """Hash of a kernel's source file and every header of the kernels."""
+    """Hash of the code of a kernel's source file and of the files it
+    includes (a record stays valid while none of them changes, whatever else
+    is edited, comments included)."""
     d = os.path.join(ROOT, "paper_2012_10684_amd", "csrc")
     h = hashlib.sha256()
-    for f in [name] + sorted(f for f in os.listdir(d) if f.endswith(".h")):
-        h.update(open(os.path.join(d, f), "rb").read())
+    for f in src_files(name):
+        h.update(f.encode() + b"\0")
+        with open(os.path.join(d, f)) as fh:
+            h.update(code_text(fh.read()).encode() + b"\0")
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_file: str, workload: str):
-    """HBM traffic per launch from the committed PMC summary, if it was taken
-    on the current source of that kernel and on this workload (else None)."""
+def _traffic_record(kernel_file: str, workload: str):
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(p))
@@ -319,7 +355,30 @@ def load_traffic(kernel_file: str, workload: str):
     e = d.get(f"{kernel_file}:{workload}")  # one record per kernel source and workload
     if not e or e.get("src_sha") != src_hash(kernel_file) or e.get("workload") != workload:
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def load_traffic(kernel_file: str, workload: str):
+    """HBM traffic per launch from the committed PMC summary, if it was taken
+    on the current source of that kernel and on this workload (else None)."""
+    e = _traffic_record(kernel_file, workload)
+    return e.get("bytes_per_launch") if e else None
+
+
+def load_traffic_sum(kernel_file: str, workload: str, prefixes):
+    """Sum of the HBM bytes per launch of one kernel per name prefix (the
+    kernels of one source launched together), under the same conditions as
+    load_traffic; None unless every prefix matches exactly one kernel."""
+    e = _traffic_record(kernel_file, workload)
+    if not e or "kernels" not in e:
+        return None
+    total = 0.0
+    for pre in prefixes:
+        hit = [v for n, v in e["kernels"].items() if n.startswith(pre)]
+        if len(hit) != 1:
+            return None
+        total += hit[0]
+    return total
 
 
 def cpu_model() -> str:
@@ -583,11 +642,14 @@ def bench_open(args, wl, dev, two_d=False):
         "kernel_us": {n: round(v * 1e6, 2) for n, v in per.items()},
         "kernel_us_note": "from an untimed pass with events around every stage (each event adds a gap)",
         "roofline": {"bound": "hbm", "kernel": "k_morph (erosion + dilation)", "achieved": alg / avg / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
+                     "traffic": load_traffic_sum("k_morph.hip", args.workload,
+                                                 [f"ts::k_morph<{m}, {R}>" for m in ("false", "true")]),
                      "algorithmic_bytes_per_launch": alg, "avg_launch_us": avg * 1e6,
                      "note": "the HBM side of the opening (9 B per pixel over both passes: int16 in, eroded out and "
                              "in, int16 re-read, opened out, int16 residue out); the passes are bound by instruction "
-                             "issue (packed 16-bit min/max, LDS word reads), not by HBM"},
+                             "issue (packed 16-bit min/max, LDS word reads), not by HBM; a launch is one ts_open2d "
+                             "call, both passes, and traffic sums the PMC bytes of its two kernels"},
         "lds_word_reads_per_pixel": morph_lds_reads_per_pixel(R),
         "all_problems_ok": bool(int((res[2] != 0).sum()) == 0),
     }

@@ -40,7 +40,14 @@
 namespace ts {
 
 constexpr int MV_THREADS = 256; // threads per workgroup: one column pair each
-constexpr int MV_TY = 16;       // output rows per tile
+// Output rows per tile.  A thread holds its column pair over MV_TY + 2r rows
+// in registers; taller tiles load fewer halo rows per output row (the
+// neighbours' halo rows mostly come from L2) but hold more registers and fit
+// fewer wavefronts per SIMD.  Eight rows (68-76 VGPRs at r = 10, six or seven
+// wavefronts) measured never more than 8 % slower than the fastest of 4, 6,
+// 8, 12 and 16 rows at radii from 1 to 32 on 512- and 2048-wide images, and
+// up to 37 % faster than 16 rows.
+constexpr int MV_TY = 8;
 
 // floor(sqrt(n)), n >= 0, at compile time
 constexpr int mv_isqrt(int n)

@@ -19,15 +19,28 @@ def tree(tmp_path, monkeypatch):
     src = os.path.join(bench.ROOT, "paper_2012_10684_amd", "csrc")
     dst = tmp_path / "paper_2012_10684_amd" / "csrc"
     dst.mkdir(parents=True)
-    for f in ("k_label.hip", "common.h"):
+    for f in ("k_label.hip", "label_dev.h", "common.h", "morph_dev.h", "k_morph.hip"):
         shutil.copy(os.path.join(src, f), dst / f)
+    (tmp_path / "include").mkdir()
+    shutil.copy(os.path.join(bench.ROOT, "include", "ts.h"), tmp_path / "include" / "ts.h")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     (tmp_path / "profiles").mkdir()
     rec = {"k_label.hip:volume300": {"src_sha": bench.src_hash("k_label.hip"), "workload": "volume300",
                                      "bytes_per_launch": 123.0},
-           "k_label.hip:batch64": {"src_sha": "0" * 16, "workload": "batch64", "bytes_per_launch": 7.0}}
+           "k_label.hip:batch64": {"src_sha": "0" * 16, "workload": "batch64", "bytes_per_launch": 7.0},
+           "k_morph.hip:volume300_open": {"src_sha": bench.src_hash("k_morph.hip"), "workload": "volume300_open",
+                                          "bytes_per_launch": 5.0,
+                                          "kernels": {"ts::k_morph<true, 10>(ts::MorphArgs)": 5.0,
+                                                      "ts::k_morph<false, 10>(ts::MorphArgs)": 4.0}}}
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
     return dst
+
+
+def test_hash_covers_the_include_closure():
+    files = bench.src_files("k_label.hip")
+    assert files[0] == "k_label.hip"
+    assert set(files[1:]) == {"label_dev.h", "common.h", os.path.join("..", "..", "include", "ts.h")}
+    assert "morph_dev.h" not in bench.src_files("k_search.hip")
 
 
 def test_traffic_used_for_its_source_and_workload(tree):
@@ -37,11 +50,39 @@ def test_traffic_used_for_its_source_and_workload(tree):
     assert bench.load_traffic("k_histogram.hip", "volume300") is None  # no record
 
 
-@pytest.mark.parametrize("changed", ["k_label.hip", "common.h"])
+@pytest.mark.parametrize("changed", ["k_label.hip", "label_dev.h", "common.h", "../../include/ts.h"])
 def test_traffic_dropped_once_the_kernel_changes(tree, changed):
     with open(tree / changed, "a") as f:
-        f.write("\n// edited\n")
+        f.write("\nstatic const int edited = 1;\n")
     assert bench.load_traffic("k_label.hip", "volume300") is None
+
+
+@pytest.mark.parametrize("edit", ["\n// a comment\n", "\n/* a\n   block */\n", "\n\n   \n"])
+def test_traffic_kept_when_only_comments_or_blanks_change(tree, edit):
+    with open(tree / "label_dev.h", "a") as f:
+        f.write(edit)
+    assert bench.load_traffic("k_label.hip", "volume300") == 123.0
+
+
+def test_code_text_keeps_the_code():
+    a = bench.code_text("int a = 1; // one\n/* two */ int b =  2;")
+    assert a == "int a = 1; int b = 2;"
+    assert bench.code_text("x = 1 - 2;") != bench.code_text("x = 1 + 2;")
+
+
+def test_traffic_kept_when_a_header_it_does_not_include_changes(tree):
+    with open(tree / "morph_dev.h", "a") as f:
+        f.write("\nstatic const int edited = 1;\n")
+    assert bench.load_traffic("k_label.hip", "volume300") == 123.0
+    assert bench.load_traffic_sum("k_morph.hip", "volume300_open", ["ts::k_morph<false, 10>"]) is None
+
+
+def test_traffic_sum_of_the_two_passes(tree):
+    both = ["ts::k_morph<false, 10>", "ts::k_morph<true, 10>"]
+    assert bench.load_traffic_sum("k_morph.hip", "volume300_open", both) == 9.0
+    assert bench.load_traffic_sum("k_morph.hip", "volume300_open", ["ts::k_morph<true, 11>"]) is None  # no such kernel
+    assert bench.load_traffic_sum("k_morph.hip", "volume300_open", ["ts::k_morph<"]) is None  # ambiguous prefix
+    assert bench.load_traffic_sum("k_label.hip", "volume300", both) is None  # record without per-kernel bytes
 
 
 def test_cpu_baseline_repeats_a_short_sample(monkeypatch):
