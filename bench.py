@@ -305,9 +305,12 @@ def parse():
 
 def src_files(name: str):
     """A kernel source file and every file it includes with #include "...",
-    followed transitively (paths relative to the kernel sources' folder,
-    the source first, then the rest sorted)."""
+    followed transitively and found as the build finds them (beside the
+    including file, else in include/; a name found in neither is a system
+    header and left out).  Paths relative to the kernel sources' folder, the
+    source first, then the rest sorted."""
     d = os.path.join(ROOT, "paper_2012_10684_amd", "csrc")
+    inc = os.path.relpath(os.path.join(ROOT, "include"), d)
     seen, todo = set(), [os.path.normpath(name)]
     while todo:
         f = todo.pop()
@@ -317,8 +320,13 @@ def src_files(name: str):
         with open(os.path.join(d, f)) as fh:
             for line in fh:
                 m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
-                if m:
-                    todo.append(os.path.normpath(os.path.join(os.path.dirname(f), m.group(1))))
+                if not m:
+                    continue
+                for cand in (os.path.join(os.path.dirname(f), m.group(1)), os.path.join(inc, m.group(1))):
+                    cand = os.path.normpath(cand)
+                    if os.path.isfile(os.path.join(d, cand)):
+                        todo.append(cand)
+                        break
     first = os.path.normpath(name)
     return [first] + sorted(seen - {first})
 

@@ -36,6 +36,14 @@ def tree(tmp_path, monkeypatch):
     return dst
 
 
+def test_include_found_as_the_build_finds_it(tree):
+    with open(tree / "k_label.hip", "a") as f:
+        f.write('\n#include "ts.h"\n#include "hip/hip_runtime.h"\n')  # via -I include/; a system header
+    files = bench.src_files("k_label.hip")
+    assert os.path.join("..", "..", "include", "ts.h") in files
+    assert not any("hip_runtime" in f for f in files)
+
+
 def test_hash_covers_the_include_closure():
     files = bench.src_files("k_label.hip")
     assert files[0] == "k_label.hip"
