@@ -43,6 +43,17 @@ def test_open2d_random_images(r):
         _check(imgs, -1024, 3071, 256, r)
 
 
+@pytest.mark.parametrize("r", range(api.MORPH_MAX_RADIUS + 1))
+def test_open2d_every_radius(r):
+    """Every radius the entry point takes (each has a kernel of its own, in
+    one of several sources): images of one tile with ragged rows, and a wide
+    image of several tiles with halo columns."""
+    rng = np.random.default_rng(900 + r)
+    for n, H, W in [(2, 45, 70), (1, 11, 700)]:
+        imgs = rng.integers(-1100, 400, (n, H, W)).astype(np.int16)
+        _check(imgs, -1024, 3071, 256, r)
+
+
 @pytest.mark.parametrize("r", [1, 4, 10, 32])
 def test_open2d_wide_images(r):
     """Images wider than one tile (512 columns): tiles with halo columns on
